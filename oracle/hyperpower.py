@@ -1,0 +1,412 @@
+"""Literal CPU implementation of the hyperpower iterations (test infrastructure only).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may use this
+module; the product path never does.
+
+Citations name the paper's sections, equations (by their LaTeX labels, e.g.
+``(PM)``, ``(PM-modified)``, ``(stopreliable)``) and tables.
+
+Pins (what ties this file to something other than itself) live in
+``tests/test_oracle_pins.py``:
+  * the PM constants: the polynomial identity of Section 2, checked exactly;
+  * ``pm_step``: equals the 18-term definition (hyper18) and gives
+    F_{k+1} = F_k^18 (Theorem 3.1) in multiple precision;
+  * ``solve`` (loop, X0 rules, stop rule, iteration counting, COC): the paper's
+    worked Example 8.1 / Table 1 at 150 digits, for SM, CM, FM and PM;
+  * Moore-Penrose results: LAPACK SVD pseudo-inverse and closed forms from
+    the factors, plus the four Penrose equations;
+  * Drazin results: the Jordan-form closed form;
+  * the iteration limit: classical order-2 Newton-Schulz reaches the same X;
+  * Theorem 6.2 / 7.1: the E22 block grows 18x per plain loop and is removed by
+    the stabilising product.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+try:  # multiple precision is only needed for the 150-digit worked example
+    import mpmath
+except ImportError:  # pragma: no cover
+    mpmath = None
+
+
+# ---------------------------------------------------------------------------
+# Element arithmetic: IEEE binary64 or mpmath numbers in numpy object arrays.
+# ---------------------------------------------------------------------------
+
+class Arith:
+    """Scalar/array helpers for one element type."""
+
+    def __init__(self, name: str):
+        self.name = name
+
+    # scalars -----------------------------------------------------------
+    def num(self, v):
+        if self.name == "f64":
+            return float(v)
+        return mpmath.mpf(v)
+
+    def sqrt(self, v):
+        return math.sqrt(v) if self.name == "f64" else mpmath.sqrt(v)
+
+    def log(self, v):
+        return math.log(v) if self.name == "f64" else mpmath.log(v)
+
+    # arrays ------------------------------------------------------------
+    def asarray(self, a):
+        if self.name == "f64":
+            return np.asarray(a, dtype=np.float64)
+        a = np.asarray(a, dtype=object)
+        return np.vectorize(mpmath.mpf, otypes=[object])(a)
+
+    def eye(self, n):
+        if self.name == "f64":
+            return np.eye(n)
+        e = np.empty((n, n), dtype=object)
+        e[...] = mpmath.mpf(0)
+        for i in range(n):
+            e[i, i] = mpmath.mpf(1)
+        return e
+
+    def isfinite(self, a) -> bool:
+        if self.name == "f64":
+            return bool(np.all(np.isfinite(a)))
+        return all(mpmath.isfinite(x) for x in a.ravel())
+
+
+F64 = Arith("f64")
+MP = Arith("mp")
+
+
+# ---------------------------------------------------------------------------
+# Constants of the factored polynomial, Section 2.
+# ---------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class PMConstants:
+    c1: object
+    c2: object
+    c3: object
+    d1: object
+    d2: object
+    mu: object
+    psi: object
+
+
+def octic_constants(ar: Arith = F64) -> dict:
+    """a1, a2, a3, b1, b2, mu, psi: the solution of the seven-equation system
+    that splits the even-power sum of (hyper18-3) into two octics in R^2 plus
+    mu R^2 + psi R^4 (Section 2, (hyper18-33) and the closed forms after it)."""
+    n = ar.num
+    r93 = ar.sqrt(n(93))
+    return dict(
+        a1=n(5) / 496 * (31 + r93),
+        a2=(3 + r93) / 8,
+        a3=n(1) / 2,
+        b1=n(-5) / 496 * (r93 - 31),
+        b2=(3 - r93) / 8,
+        mu=n(3) / 8,
+        psi=n(321) / 1984,
+    )
+
+
+def pm_constants(ar: Arith = F64) -> PMConstants:
+    """c1, c2, c3 of (simplify1), d1, d2 of (simplify2), mu and psi of
+    (hyper18-33): the closed forms printed in Section 2, evaluated in the
+    arithmetic ``ar``."""
+    n = ar.num
+    r93 = ar.sqrt(n(93))
+    q = ar.sqrt(27 - 2 * r93)
+    return PMConstants(
+        c1=(q + 1) / 4,
+        c2=(1 - q) / 4,
+        c3=(5 * r93 - 93) / 496,
+        d1=(-93 - 5 * r93) / 496,
+        d2=-r93 / 4,
+        mu=n(3) / 8,
+        psi=n(321) / 1984,
+    )
+
+
+# ---------------------------------------------------------------------------
+# Norms (plain definitions).
+# ---------------------------------------------------------------------------
+
+def norm_1(a):
+    """Largest absolute column sum."""
+    return np.abs(a).sum(axis=0).max()
+
+
+def norm_inf(a):
+    """Largest absolute row sum."""
+    return np.abs(a).sum(axis=1).max()
+
+
+def norm_fro(a, ar: Arith = F64):
+    return ar.sqrt((a * a).sum())
+
+
+# ---------------------------------------------------------------------------
+# Initial approximations, Section 4.
+# ---------------------------------------------------------------------------
+
+def x0_moore_penrose(A, rule: str = "norm1inf", alpha=None, ar: Arith = F64):
+    """X0 = alpha * A^T for the Moore-Penrose inverse (real case: A* = A^T).
+
+    rule "norm1inf":   alpha = 1 / (||A||_1 ||A||_inf)          (Section 4)
+    rule "sigma_max2": alpha = 1 / sigma_1^2                    (scaling that
+                       keeps ||I - A X0||_2 < 1, condition of Theorem 3.1)
+    rule "sigma_opt":  alpha = 2 / (sigma_1^2 + sigma_r^2)       (Section 4, the
+                       Pan-Schreiber choice; sigma read as singular values of A)
+    rule "user":       alpha given.
+    Singular values come from LAPACK; that is allowed here (oracle only).
+    Returns (X0, alpha).
+    """
+    if rule == "norm1inf":
+        alpha = 1 / (norm_1(A) * norm_inf(A))
+    elif rule in ("sigma_max2", "sigma_opt"):
+        s = np.linalg.svd(np.asarray(A, dtype=np.float64), compute_uv=False)
+        s1 = s[0]
+        if rule == "sigma_max2":
+            alpha = 1.0 / (s1 * s1)
+        else:
+            sr = s[s > s1 * max(A.shape) * np.finfo(float).eps][-1]
+            alpha = 2.0 / (s1 * s1 + sr * sr)
+        alpha = ar.num(alpha)
+    elif rule == "user":
+        if alpha is None:
+            raise ValueError("rule 'user' needs alpha")
+        alpha = ar.num(alpha)
+    else:
+        raise ValueError(f"unknown alpha rule {rule!r}")
+    return alpha * A.T, alpha
+
+
+def x0_drazin(A, l: int, ar: Arith = F64):
+    """X0 = A^l / Tr(A^{l+1}) with l >= ind(A) (Section 4; Example 8.1).
+    Returns (X0, alpha) with alpha = 1 / Tr(A^{l+1})."""
+    n = A.shape[0]
+    Al = ar.eye(n)
+    for _ in range(l):
+        Al = Al @ A
+    tr = np.trace(Al @ A)
+    alpha = 1 / tr
+    return alpha * Al, alpha
+
+
+# ---------------------------------------------------------------------------
+# One loop of each iteration.
+# ---------------------------------------------------------------------------
+
+def pm_step(A, X, K: PMConstants, ar: Arith = F64):
+    """One loop of PM, Section 2, iteration (PM): seven products, in the
+    association the paper prints."""
+    I = ar.eye(A.shape[0])
+    R = I - A @ X                                   # product 1
+    R2 = R @ R                                      # product 2
+    R4 = R2 @ R2                                    # product 3
+    M = (I + K.c1 * R2 + R4) @ (I + K.c2 * R2 + R4)  # product 4
+    T = M + K.c3 * R2
+    S = M + K.d1 * R2 + K.d2 * R4
+    V = T @ S + K.mu * R2 + K.psi * R4              # product 5
+    return X @ ((I + R) @ V)                        # products 6 and 7
+
+
+def stabilise(A, Xh):
+    """The extra step of (PM-modified), Section 7: X_{k+1} = X_{k+1/2} A X_{k+1/2}."""
+    return Xh @ A @ Xh
+
+
+def hyperpower_direct_step(A, X, p: int, ar: Arith = F64):
+    """The hyperpower family (Hyperpower1), Section 1.3, by its definition:
+    X_{k+1} = X_k (I + R + R^2 + ... + R^{p-1}), R = I - A X_k."""
+    I = ar.eye(A.shape[0])
+    R = I - A @ X
+    P = I
+    acc = I
+    for _ in range(1, p):
+        P = P @ R
+        acc = acc + P
+    return X @ acc
+
+
+def sm_step(A, X, K=None, ar: Arith = F64):
+    """Newton-Schulz-Hotelling (schulz), Section 1.3: X (2I - A X)."""
+    I = ar.eye(A.shape[0])
+    return X @ (2 * I - A @ X)
+
+
+def cm_step(A, X, K=None, ar: Arith = F64):
+    """Chebyshev-Sen-Prabhu (chebyshev), Section 1.3: X (3I - A X (3I - A X))."""
+    I = ar.eye(A.shape[0])
+    AX = A @ X
+    return X @ (3 * I - AX @ (3 * I - AX))
+
+
+def fm_step(A, X, K=None, ar: Arith = F64):
+    """The seventh-order factorisation (SoleymaniN), Section 1.3."""
+    I = ar.eye(A.shape[0])
+    psi = I - A @ X
+    psi2 = psi @ psi
+    zeta = I + psi + psi2
+    ups = psi + psi2 @ psi2
+    return X @ (I + ups @ zeta)
+
+
+def hm_step(A, X, K=None, ar: Arith = F64):
+    """The 18th-order product of five factors (hyper18-2), Section 2."""
+    I = ar.eye(A.shape[0])
+    R = I - A @ X
+    R2 = R @ R
+    R3 = R2 @ R
+    R6 = R3 @ R3
+    return X @ (R + I) @ (R2 - R + I) @ (R2 + R + I) @ (R6 - R3 + I) @ (R6 + R3 + I)
+
+
+STEP_FUNCTIONS = {"pm": pm_step, "sm": sm_step, "cm": cm_step, "fm": fm_step, "hm": hm_step}
+ORDER = {"pm": 18, "sm": 2, "cm": 3, "fm": 7, "hm": 18}
+
+
+# ---------------------------------------------------------------------------
+# The iteration with its stopping rule, variant switch and guards.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Result:
+    X: object
+    status: str                 # ok | maxiter | stagnated | diverged | nonfinite
+    iters: int                  # loops run, including the one whose test passed
+    alpha: object
+    d_hist: list = field(default_factory=list)      # relative Frobenius changes
+    stop_hist: list = field(default_factory=list)   # the stopping rule's values
+    diff_inf_hist: list = field(default_factory=list)  # ||X_{k+1}-X_k||_inf
+    switch_iter: int = -1       # first loop run stabilised (-1: never)
+
+
+def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1inf",
+          alpha=None, X0=None, method: str = "pm", variant: str = "plain",
+          tau_switch: float = 0.1, stop: str = "rel_fro", tol: float = 1e-12,
+          max_iter: int = 100, diverge_limit: float = 1e6, ar: Arith = F64) -> Result:
+    """Run a hyperpower iteration to a generalized inverse of A.
+
+    kind      "mp": Moore-Penrose, X0 = alpha A^T (Section 4).
+              "drazin": X0 = A^l / Tr(A^{l+1}), l >= ind(A) (Section 4).
+    method    "pm" (the paper's 7-product scheme) or one of the comparison
+              schemes "sm", "cm", "fm", "hm" (Sections 1.3 and 2).
+    variant   "plain": (PM) every loop.
+              "stabilised": plain loops until the relative change first drops
+              below tau_switch, then (PM-modified) for every later loop -- the
+              switch recipe that closes Section 7.
+              "stab_always": (PM-modified) from X0 (kept for the test that
+              shows why the switch is needed).
+    stop      "rel_fro":  ||X_{k+1}-X_k||_F / ||X_k||_F < tol.
+              "abs_inf":  ||X_{k+1}-X_k||_inf <= tol (Example 8.1).
+              "paper_4_1": ||X_{k+1}-X_k||_F / (p^k alpha) < tol, rule
+              (stopreliable) of Section 4 with the Frobenius norm (Example 8.2).
+    Guards (the warning of Section 6 that looping past convergence can
+    diverge): a non-finite iterate ends with "nonfinite" and the last finite
+    iterate; once some relative change below tau_switch has been seen, a change
+    that does not decrease ends with "stagnated" and returns X_k, the input of
+    that loop; a relative change above diverge_limit before then ends with
+    "diverged"; max_iter loops end with "maxiter" (Section 8 uses 100).
+    The returned iterate on success is X_{k+1}, and iters counts the loops run.
+    """
+    if not (isinstance(A, np.ndarray) and (A.dtype == object) == (ar is MP)):
+        A = ar.asarray(A)
+    if X0 is not None:
+        X = X0
+        alpha = ar.num(alpha) if alpha is not None else ar.num(1)
+    elif kind == "mp":
+        X, alpha = x0_moore_penrose(A, alpha_rule, alpha, ar)
+    elif kind == "drazin":
+        if l is None:
+            raise ValueError("drazin needs l >= ind(A)")
+        X, alpha = x0_drazin(A, l, ar)
+    else:
+        raise ValueError(f"unknown kind {kind!r}")
+
+    step = STEP_FUNCTIONS[method]
+    p = ORDER[method]
+    K = pm_constants(ar)
+    res = Result(X=X, status="maxiter", iters=0, alpha=alpha)
+    stabilising = variant == "stab_always"
+    if stabilising:
+        res.switch_iter = 0
+    converging = False
+    for k in range(max_iter):
+        Xn = step(A, X, K, ar)
+        if stabilising:
+            Xn = stabilise(A, Xn)
+        res.iters = k + 1
+        if not ar.isfinite(Xn):
+            res.status, res.X = "nonfinite", X
+            return res
+        D = Xn - X
+        d = norm_fro(D, ar) / norm_fro(X, ar)
+        res.d_hist.append(d)
+        res.diff_inf_hist.append(norm_inf(D))
+        if stop == "rel_fro":
+            sval, passed = d, d < tol
+        elif stop == "abs_inf":
+            sval = res.diff_inf_hist[-1]
+            passed = sval <= tol
+        elif stop == "paper_4_1":
+            sval = norm_fro(D, ar) / (ar.num(p) ** k * alpha)
+            passed = sval < tol
+        else:
+            raise ValueError(f"unknown stop rule {stop!r}")
+        res.stop_hist.append(sval)
+        if passed:
+            res.status, res.X = "ok", Xn
+            return res
+        if converging and d >= res.d_hist[-2]:
+            res.status, res.X = "stagnated", X
+            return res
+        if not converging and d > diverge_limit:
+            res.status, res.X = "diverged", X
+            return res
+        if d < tau_switch:
+            converging = True
+            if variant == "stabilised" and not stabilising:
+                stabilising = True
+                res.switch_iter = k + 1
+        X = Xn
+    res.X = X
+    return res
+
+
+def coc(diff_inf_hist, ar: Arith = F64):
+    """Computational order of convergence (COC), Section 8, from the last three
+    infinity-norm changes e_k = ||X_k - X_{k-1}||_inf:
+    rho = ln(e_{k+1}/e_k) / ln(e_k/e_{k-1})."""
+    e0, e1, e2 = diff_inf_hist[-3:]
+    return ar.log(e2 / e1) / ar.log(e1 / e0)
+
+
+# ---------------------------------------------------------------------------
+# Residuals of the defining equations.
+# ---------------------------------------------------------------------------
+
+def penrose_residuals(A, X):
+    """Relative residuals of the four Penrose equations for X = A^dagger:
+    ||AXA - A||/||A||, ||XAX - X||/||X||, ||AX - (AX)^T||/||AX||,
+    ||XA - (XA)^T||/||XA|| (Frobenius norms)."""
+    f = np.linalg.norm
+    AX = A @ X
+    XA = X @ A
+    return (f(AX @ A - A) / f(A), f(XA @ X - X) / f(X),
+            f(AX - AX.T) / f(AX), f(XA - XA.T) / f(XA))
+
+
+def drazin_residuals(A, X, l: int):
+    """Relative residuals of the Drazin equations A^{l+1} X = A^l, XAX = X,
+    AX = XA (Frobenius norms)."""
+    f = np.linalg.norm
+    Al = np.linalg.matrix_power(A, l)
+    AX = A @ X
+    return (f(Al @ A @ X - Al) / f(Al), f(X @ A @ X - X) / f(X),
+            f(AX - X @ A) / f(AX))

@@ -1,0 +1,351 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here re-types the oracle's formulas: each test compares the oracle with
+an independent definition (the 18-term geometric sum, the paper's worked
+example, LAPACK's SVD pseudo-inverse, closed forms built from the factors of
+the input, the order-2 Newton-Schulz limit).
+"""
+
+import dataclasses
+import json
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1604_07893_amd import inputs
+
+
+# ---------------------------------------------------------------------------
+# The factored polynomial equals the 18-term geometric sum (Section 2).
+# ---------------------------------------------------------------------------
+
+def _scalar_identity_error(K, dps=60):
+    """max over 24 points of |1 - a*x1 - (1 - a*x)^18| for 1x1 matrices A=[a],
+    X=[x]: one PM loop must map the scalar residual r = 1 - a x to r^18
+    (Theorem 3.1 with F = 1 - A X), which holds iff the factored polynomial
+    equals sum_{i<18} r^i."""
+    with mpmath.workdps(dps):
+        worst = mpmath.mpf(0)
+        for t in np.linspace(0.05, 1.95, 24):
+            a = np.array([[mpmath.mpf(1)]], dtype=object)
+            x = np.array([[mpmath.mpf(float(t))]], dtype=object)
+            x1 = O.pm_step(a, x, K, O.MP)
+            r = 1 - x[0, 0]
+            worst = max(worst, abs((1 - x1[0, 0]) - r ** 18))
+        return worst
+
+
+def test_pm_polynomial_is_geometric_sum_mp():
+    with mpmath.workdps(60):
+        K = O.pm_constants(O.MP)
+        assert _scalar_identity_error(K) < mpmath.mpf("1e-50")
+
+
+def test_pm_constants_fp64_are_rounded_closed_forms():
+    with mpmath.workdps(40):
+        Kmp = O.pm_constants(O.MP)
+    K64 = O.pm_constants(O.F64)
+    for f in dataclasses.fields(K64):
+        exact = getattr(Kmp, f.name)
+        got = getattr(K64, f.name)
+        assert abs(got - float(exact)) <= 2 * np.spacing(abs(float(exact))), f.name
+
+
+def test_octic_system_and_factorisations_exact():
+    """The seven-equation system of (hyper18-33) and the splits (simplify1),
+    (simplify2), checked as polynomial identities in y = R^2 with sympy."""
+    sp = pytest.importorskip("sympy")
+    y = sp.symbols("y")
+    s93 = sp.sqrt(93)
+    a1 = sp.Rational(5, 496) * (31 + s93)
+    a2 = (3 + s93) / 8
+    a3 = sp.Rational(1, 2)
+    b1 = sp.Rational(-5, 496) * (s93 - 31)
+    b2 = (3 - s93) / 8
+    mu = sp.Rational(3, 8)
+    psi = sp.Rational(321, 1984)
+    q = sp.sqrt(27 - 2 * s93)
+    c1, c2 = (q + 1) / 4, (1 - q) / 4
+    c3 = (5 * s93 - 93) / 496
+    d1 = (-93 - 5 * s93) / 496
+    d2 = -s93 / 4
+    Ta = 1 + a1 * y + a2 * y**2 + a3 * y**3 + y**4
+    Sb = 1 + b1 * y + b2 * y**2 + a3 * y**3 + y**4
+    even = sum(y**i for i in range(9))
+    assert sp.expand(Ta * Sb + mu * y + psi * y**2 - even) == 0
+    M = (1 + c1 * y + y**2) * (1 + c2 * y + y**2)
+    assert sp.simplify(sp.expand(M + c3 * y - Ta)) == 0
+    assert sp.simplify(sp.expand(M + d1 * y + d2 * y**2 - Sb)) == 0
+    # the oracle's octic constants are these closed forms
+    oc = O.octic_constants(O.F64)
+    for name, v in dict(a1=a1, a2=a2, a3=a3, b1=b1, b2=b2, mu=mu, psi=psi).items():
+        assert abs(oc[name] - float(v)) < 1e-15
+
+
+@pytest.mark.parametrize("field,change", [
+    ("c1", "neg"), ("c3", "neg"), ("d1", "neg"), ("d2", "neg"), ("mu", "neg"),
+    ("psi", "neg"), ("c3", "zero"), ("d2", "zero"), ("psi", "zero"), ("mu", "zero"),
+])
+def test_planted_constant_mistakes_are_caught(field, change):
+    """A dropped term or a wrong sign in any constant breaks the pin above."""
+    with mpmath.workdps(60):
+        K = O.pm_constants(O.MP)
+        v = getattr(K, field)
+        Kbad = dataclasses.replace(K, **{field: -v if change == "neg" else mpmath.mpf(0)})
+        assert _scalar_identity_error(Kbad) > mpmath.mpf("1e-6")
+
+
+def test_pm_step_equals_18_term_definition_fp64():
+    rng = np.random.default_rng(7)
+    for m, n in [(9, 6), (6, 9), (8, 8)]:
+        A = rng.uniform(-1, 1, (m, n))
+        X, _ = O.x0_moore_penrose(A, "norm1inf")
+        X = X * 3.0  # move R away from I so every power of R matters
+        K = O.pm_constants()
+        x_pm = O.pm_step(A, X, K)
+        x_def = O.hyperpower_direct_step(A, X, 18)
+        assert np.linalg.norm(x_pm - x_def) <= 1e-12 * np.linalg.norm(x_def)
+
+
+def test_order_18_residual_map_mp():
+    """Theorem 3.1 for nonsingular A: R_{k+1} = R_k^18 exactly."""
+    rng = np.random.default_rng(3)
+    A64 = rng.uniform(-1, 1, (6, 6)) + 3 * np.eye(6)
+    with mpmath.workdps(80):
+        A = O.MP.asarray(A64)
+        X, _ = O.x0_moore_penrose(A, "norm1inf", ar=O.MP)
+        K = O.pm_constants(O.MP)
+        I = O.MP.eye(6)
+        for _ in range(2):
+            R = I - A @ X
+            R18 = I
+            for _ in range(18):
+                R18 = R18 @ R
+            X = O.pm_step(A, X, K, O.MP)
+            R1 = I - A @ X
+            err = max(abs(v) for v in (R1 - R18).ravel())
+            scale = max(abs(v) for v in R18.ravel()) + mpmath.mpf("1e-70")
+            assert err <= mpmath.mpf("1e-60") + mpmath.mpf("1e-40") * scale
+
+
+# ---------------------------------------------------------------------------
+# The paper's worked example: Example 8.1 / Table 1 at 150 digits.
+# ---------------------------------------------------------------------------
+
+def _example_8_1(golden_dir):
+    with open(os.path.join(golden_dir, "example_8_1.json")) as f:
+        g = json.load(f)
+
+    def ent(x):
+        if "/" in x:
+            p, q = x.split("/")
+            return mpmath.mpf(int(p)) / int(q)
+        return mpmath.mpf(int(x))
+    return g, ent
+
+
+@pytest.mark.parametrize("method", ["SM", "CM", "FM", "PM"])
+def test_table_1_example_8_1(golden_dir, method):
+    g, ent = _example_8_1(golden_dir)
+    want = g["table_1"][method]
+    with mpmath.workdps(g["dps"]):
+        A = np.array([[ent(x) for x in row] for row in g["matrix"]], dtype=object)
+        res = O.solve(A, kind="drazin", l=g["l"], method=method.lower(), stop="abs_inf",
+                      tol=mpmath.mpf(g["eps"]), ar=O.MP)
+        assert res.status == "ok"
+        assert res.iters == want["IT"]
+        rho = O.coc(res.diff_inf_hist, O.MP)
+        assert f"{float(rho):.2f}" == want["rho"]
+        # the result is the Drazin inverse: A^{l+1} X = A^l, X A X = X, A X = X A
+        Al = O.MP.eye(12)
+        for _ in range(g["l"]):
+            Al = Al @ A
+        X = res.X
+        for E in (Al @ A @ X - Al, X @ A @ X - X, A @ X - X @ A):
+            assert max(abs(v) for v in E.ravel()) < mpmath.mpf("1e-45")
+
+
+def _mant_exp(s):
+    m, e = s.split("e")
+    return float(m), int(e)
+
+
+@pytest.mark.parametrize("method", ["SM", "CM", "FM", "PM"])
+def test_table_1_final_change_digits(golden_dir, method):
+    """R_{k+1} agrees with the printed value to every printed digit."""
+    g, ent = _example_8_1(golden_dir)
+    want = g["table_1"][method]["R"]
+    mant, exp = _mant_exp(want)
+    ndig = len(want.split("e")[0].replace(".", "")) - 1
+    with mpmath.workdps(g["dps"]):
+        A = np.array([[ent(x) for x in row] for row in g["matrix"]], dtype=object)
+        res = O.solve(A, kind="drazin", l=g["l"], method=method.lower(), stop="abs_inf",
+                      tol=mpmath.mpf(g["eps"]), ar=O.MP)
+        got = res.diff_inf_hist[-1] / mpmath.mpf(10) ** exp
+    assert round(float(got), ndig) == mant
+
+
+def test_example_8_1_fp64_matches_150_digits(golden_dir):
+    """The binary64 oracle on the same matrix lands on the 150-digit Drazin
+    inverse (plain loops stop at the first change below 1e-12 relative)."""
+    g, ent = _example_8_1(golden_dir)
+    with mpmath.workdps(g["dps"]):
+        A = np.array([[ent(x) for x in row] for row in g["matrix"]], dtype=object)
+        ref = O.solve(A, kind="drazin", l=3, method="pm", stop="abs_inf",
+                      tol=mpmath.mpf("1e-50"), ar=O.MP).X
+        ref64 = np.array([[float(v) for v in row] for row in ref])
+    A64 = np.array([[float(ent(x)) for x in row] for row in g["matrix"]])
+    # plain loops lose digits on a singular matrix (Section 6); the
+    # stabilised variant keeps them (Section 7)
+    for variant, bound in (("plain", 1e-10), ("stabilised", 1e-12)):
+        r = O.solve(A64, kind="drazin", l=3, variant=variant, tol=1e-12)
+        assert r.status in ("ok", "stagnated")
+        assert np.linalg.norm(r.X - ref64) <= bound * np.linalg.norm(ref64)
+
+
+# ---------------------------------------------------------------------------
+# Moore-Penrose results against LAPACK and closed forms.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n", [(40, 25), (25, 40), (30, 30), (200, 100)])
+def test_moore_penrose_full_rank_vs_svd_pinv(m, n):
+    A = inputs.uniform(m, n, seed=11 + m + n)
+    r = O.solve(A, kind="mp", tol=1e-12)
+    assert r.status == "ok"
+    ref = np.linalg.pinv(A)
+    assert np.linalg.norm(r.X - ref) <= 1e-12 * np.linalg.norm(ref) * np.linalg.cond(A)
+    for res in O.penrose_residuals(A, r.X):
+        assert res < 1e-12
+
+
+def test_uniform_200x100_iteration_count_matches_loop_estimate():
+    """Section 5: about 2 log_18 kappa_2(A) loops to machine precision."""
+    A = inputs.uniform(200, 100, seed=1001)
+    r = O.solve(A, kind="mp", tol=1e-12)
+    kappa = np.linalg.cond(A)
+    est = 2 * math.log(kappa) / math.log(18)
+    assert r.status == "ok"
+    assert abs(r.iters - est) <= 4
+
+
+def test_rank_deficient_stabilised_vs_closed_form():
+    d = inputs.lowrank_svd(96, 48, 36, smin=1e-3, seed=5)
+    ref = (d.V / d.s) @ d.U.T
+    r = O.solve(d.A, kind="mp", alpha_rule="user", alpha=1.0, variant="stabilised",
+                tol=1e-10)
+    assert r.status == "ok"
+    assert r.switch_iter > 0
+    assert np.linalg.norm(r.X - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert np.linalg.norm(np.linalg.pinv(d.A, rcond=1e-8) - ref) <= 1e-9 * np.linalg.norm(ref)
+    res = O.penrose_residuals(d.A, r.X)
+    assert max(res) < 1e-9
+
+
+def test_rank_deficient_plain_is_caught_by_the_guard():
+    """Section 6: plain PM is not self-correcting for generalized inverses; the
+    guard stops it once the change grows, and the stabilised variant does better."""
+    d = inputs.lowrank_svd(96, 48, 36, smin=1e-3, seed=5)
+    ref = (d.V / d.s) @ d.U.T
+    r = O.solve(d.A, kind="mp", alpha_rule="user", alpha=1.0, variant="plain",
+                tol=1e-15, max_iter=60)
+    assert r.status in ("stagnated", "ok")
+    assert np.linalg.norm(r.X - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_stabilised_from_x0_misses_the_pseudo_inverse():
+    """The stabilising product applied from X0 keeps only the dominant singular
+    directions: it converges to a different {2}-inverse, not to A^dagger.  This
+    is why the stabilised variant switches in after the plain loops."""
+    d = inputs.lowrank_svd(60, 30, 20, smin=1e-3, seed=9)
+    ref = (d.V / d.s) @ d.U.T
+    r = O.solve(d.A, kind="mp", alpha_rule="user", alpha=1.0, variant="stab_always",
+                tol=1e-12)
+    assert np.linalg.norm(r.X - ref) > 0.5 * np.linalg.norm(ref)
+    X = r.X
+    assert np.linalg.norm(X @ d.A @ X - X) <= 1e-8 * max(np.linalg.norm(X), 1e-300)
+
+
+def test_newton_schulz_reaches_the_same_limit():
+    A = inputs.uniform(30, 18, seed=4)
+    x_pm = O.solve(A, kind="mp", method="pm", tol=1e-13).X
+    r_sm = O.solve(A, kind="mp", method="sm", tol=1e-13)
+    assert r_sm.status == "ok"
+    assert np.linalg.norm(x_pm - r_sm.X) <= 1e-12 * np.linalg.norm(x_pm)
+
+
+def test_theorem_6_2_and_7_1_e22_block():
+    """With X = A^dagger + V [[0,0],[0,E22]] U^T, one plain loop multiplies the
+    E22 block by 18 (Theorem 6.2) and the stabilising product removes it
+    (Theorem 7.1)."""
+    rng = np.random.default_rng(2)
+    m, n, r = 10, 8, 5
+    U = inputs.haar_columns(rng, m, m)
+    V = inputs.haar_columns(rng, n, n)
+    s = np.array([1.0, 0.8, 0.5, 0.3, 0.2])
+    A = (U[:, :r] * s) @ V[:, :r].T
+    Ad = (V[:, :r] / s) @ U[:, :r].T
+    E22 = 1e-9 * rng.standard_normal((n - r, m - r))
+    E = V[:, r:] @ E22 @ U[:, r:].T
+    K = O.pm_constants()
+    X1 = O.pm_step(A, Ad + E, K)
+    assert np.linalg.norm((X1 - Ad) - 18 * E) <= 1e-6 * np.linalg.norm(18 * E)
+    X2 = O.stabilise(A, X1)
+    assert np.linalg.norm(X2 - Ad) <= 1e-13 * np.linalg.norm(Ad)
+
+
+# ---------------------------------------------------------------------------
+# Drazin results against the Jordan-form closed form.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", ["plain", "stabilised"])
+def test_drazin_vs_jordan_closed_form(variant):
+    d = inputs.drazin_jordan(n=40, nb=31, cond_p=10.0, seed=8)
+    assert d.index == 3
+    nb = d.Q.shape[0]
+    Binv = (d.Q / d.lam) @ d.Q.T
+    J = np.zeros_like(d.A)
+    J[:nb, :nb] = Binv
+    ref = d.P @ J @ d.Pinv
+    r = O.solve(d.A, kind="drazin", l=3, variant=variant, tol=1e-10)
+    assert r.status in ("ok", "stagnated")
+    assert np.linalg.norm(r.X - ref) <= 1e-9 * np.linalg.norm(ref)
+    res = O.drazin_residuals(d.A, r.X, 3)
+    assert max(res) < 1e-8
+
+
+def test_drazin_wrong_index_is_not_the_drazin_inverse():
+    """l below ind(A) gives X0 outside the right range: the limit violates
+    A^{l+1} X = A^l for the true index (guards against an off-by-one in l)."""
+    d = inputs.drazin_jordan(n=40, nb=31, cond_p=10.0, seed=8)
+    nb = d.Q.shape[0]
+    J = np.zeros_like(d.A)
+    J[:nb, :nb] = (d.Q / d.lam) @ d.Q.T
+    ref = d.P @ J @ d.Pinv
+    r = O.solve(d.A, kind="drazin", l=1, variant="stabilised", tol=1e-10, max_iter=60)
+    assert np.linalg.norm(r.X - ref) > 1e-4 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------------------
+# Stopping rules.
+# ---------------------------------------------------------------------------
+
+def test_stop_rules_order_and_iteration_counting():
+    A = inputs.uniform(40, 25, seed=3)
+    r_fro = O.solve(A, kind="mp", stop="rel_fro", tol=1e-12)
+    r_41 = O.solve(A, kind="mp", stop="paper_4_1", tol=1e-5)
+    r_inf = O.solve(A, kind="mp", stop="abs_inf", tol=1e-10)
+    for r in (r_fro, r_41, r_inf):
+        assert r.status == "ok"
+        assert len(r.d_hist) == r.iters
+    # rule (stopreliable) divides by 18^k alpha, so it passes no later than
+    # the plain relative test at a comparable tolerance
+    assert r_41.iters <= r_fro.iters
+    assert r_41.stop_hist[-1] < 1e-5
+    k = r_41.iters - 1
+    D = np.linalg.norm(r_41.X - O.solve(A, kind="mp", stop="paper_4_1", tol=1e-5,
+                                        max_iter=k).X)
+    assert abs(D / (18.0**k * r_41.alpha) - r_41.stop_hist[-1]) <= 1e-6 * r_41.stop_hist[-1]
