@@ -1,0 +1,192 @@
+/*
+ * hyperpower.h -- C ABI of libhyperpower, an MI355X (gfx950) implementation of
+ * the 18th-order hyperpower iteration for outer generalized inverses of
+ * Pan, Soleymani and Zhao, "Highly Efficient Computation of Generalized
+ * Inverse of a Matrix" (arXiv 1604.07893).
+ *
+ * Problem (Section 1.2 and Theorem 3.1): given A (m x n) and X0 = alpha*G with
+ * R(G) and N(G) fixing the range T and null space S, iterate
+ *     R_k = I - A X_k,  X_{k+1} = X_k (I + R_k + ... + R_k^17)
+ * evaluated with the seven-product factorisation (PM) of Section 2, or with
+ * the stabilised variant (PM-modified) of Section 7, until the stopping test
+ * passes. The limit is A^(2)_{R(G),N(G)}: the Moore-Penrose inverse for
+ * G = A^T and the Drazin inverse for G = A^l, l >= ind(A) (Section 4).
+ *
+ * Conventions shared by every call:
+ *  - Matrices are real FP64, row-major, with an explicit leading dimension
+ *    (elements between the starts of consecutive rows, >= the column count).
+ *  - Every matrix and workspace pointer is DEVICE memory owned by the caller;
+ *    the library never frees or retains it. Inputs are read-only; outputs are
+ *    write-only and must not alias inputs or the workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
+ *    device work is enqueued on it; hp_solve synchronises the stream once per
+ *    loop to read the two stopping scalars.
+ *  - Return value: HP_OK (0); a positive numerical outcome (the output is
+ *    still written); or a negative error (outputs untouched).
+ *  - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef HYPERPOWER_H
+#define HYPERPOWER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HP_ABI_VERSION 1
+
+/* ---- status codes ------------------------------------------------------ */
+#define HP_OK 0
+#define HP_MAXITER 1      /* max_iter loops ran without passing the stop test */
+#define HP_STAGNATED 2    /* the change stopped decreasing after convergence set
+                             in; X is the input of the loop that saw it
+                             (Section 6: looping past convergence can diverge) */
+#define HP_DIVERGED 3     /* the relative change exceeded diverge_limit before
+                             convergence set in (alpha too large) */
+#define HP_NONFINITE 4    /* a NaN/Inf appeared; X is the last finite iterate */
+#define HP_PENDING 5      /* serving: the request has not finished yet */
+#define HP_EINVAL (-1)    /* bad argument (shape, leading dim, alignment, enum) */
+#define HP_EWORKSPACE (-2)/* workspace NULL or smaller than hp_workspace_bytes */
+#define HP_EBUDGET (-3)   /* serving: a request can never fit the HBM budget */
+#define HP_EHIP (-4)      /* a HIP runtime call failed */
+#define HP_EUNSUPPORTED (-5) /* valid but not implemented combination */
+
+/* ---- enums --------------------------------------------------------------- */
+/* which outer inverse (Section 1.2; X0 rules of Section 4) */
+#define HP_KIND_MOORE_PENROSE 0   /* G = A^T, limit A^dagger (any m, n) */
+#define HP_KIND_DRAZIN 1          /* G = A^l, limit A^D (m == n, l >= ind(A)) */
+
+/* scaling alpha of X0 = alpha*G (Section 4) */
+#define HP_ALPHA_NORM1INF 0  /* Moore-Penrose: alpha = 1/(||A||_1 ||A||_inf) */
+#define HP_ALPHA_USER 1      /* alpha = hp_params.alpha (e.g. 1/sigma_max^2 or
+                                2/(sigma_1^2 + sigma_r^2) when known) */
+#define HP_ALPHA_TRACE 2     /* Drazin: alpha = 1/Tr(A^{l+1}) */
+
+/* iteration variant */
+#define HP_VARIANT_PLAIN 0       /* (PM), Section 2: 7 products per loop */
+#define HP_VARIANT_STABILISED 1  /* (PM) loops until the relative change first
+                                    drops below tau_switch, then (PM-modified)
+                                    of Section 7 (X <- X A X after each loop):
+                                    the switch recipe that closes Section 7 */
+#define HP_VARIANT_STAB_ALWAYS 2 /* (PM-modified) from X0 (converges to a
+                                    smaller-range {2}-inverse on ill-conditioned
+                                    input; kept for completeness) */
+
+/* which side the polynomial in R is evaluated on. X(I-AX)^i = (I-XA)^i X, so
+   both give the same iterates in exact arithmetic; the left form works with
+   n x n residuals and is cheaper when m > n. */
+#define HP_SIDE_AUTO 0   /* left if m > n, else right */
+#define HP_SIDE_RIGHT 1  /* R = I - A X (m x m), X_{k+1} = X W: the paper's form */
+#define HP_SIDE_LEFT 2   /* R = I - X A (n x n), X_{k+1} = W X */
+
+/* stopping rule (Section 4, Section 8) */
+#define HP_STOP_REL_FRO 0   /* ||X_{k+1}-X_k||_F / ||X_k||_F < tol */
+#define HP_STOP_PAPER_4_1 1 /* ||X_{k+1}-X_k||_F / (18^k alpha) < tol, rule
+                               (stopreliable) with the Frobenius norm */
+#define HP_STOP_ABS_INF 2   /* ||X_{k+1}-X_k||_inf <= tol (Example 8.1) */
+
+/* arithmetic of the loops */
+#define HP_PREC_FP64 0
+
+/* hp_params.flags */
+#define HP_FLAG_TIME_KERNELS 1 /* time every GEMM launch with hipEvents on the
+                                  solve stream; sums land in hp_result.gemm_ms */
+#define HP_FLAG_INF_NORM 2     /* also compute ||X_{k+1}-X_k||_inf each loop
+                                  (implied by HP_STOP_ABS_INF); enables coc */
+
+/* GEMM element type for hp_gemm */
+#define HP_DTYPE_F64 0
+
+typedef struct hp_params {
+    int32_t kind;          /* HP_KIND_* */
+    int32_t drazin_l;      /* l >= ind(A), Drazin only (caller-supplied) */
+    int32_t alpha_rule;    /* HP_ALPHA_* */
+    int32_t variant;       /* HP_VARIANT_* */
+    double alpha;          /* used with HP_ALPHA_USER */
+    double tau_switch;     /* relative change that starts the stabilised loops
+                              and arms the stagnation guard (default 0.1) */
+    double tol;            /* stopping tolerance (default 1e-12) */
+    double diverge_limit;  /* relative change treated as divergence (1e6) */
+    int32_t max_iter;      /* loop cap (default 100, as in Section 8) */
+    int32_t stop_rule;     /* HP_STOP_* */
+    int32_t side;          /* HP_SIDE_* */
+    int32_t precision;     /* HP_PREC_* */
+    int32_t flags;         /* HP_FLAG_* */
+    int32_t reserved[7];   /* must be zero */
+} hp_params;
+
+#define HP_HIST 128
+
+typedef struct hp_result {
+    int32_t status;        /* as returned */
+    int32_t iters;         /* loops run, including the one whose test passed */
+    int32_t switch_iter;   /* first loop run stabilised; -1 if none */
+    int32_t side_used;     /* HP_SIDE_RIGHT or HP_SIDE_LEFT */
+    int32_t gemms;         /* GEMM launches, set-up included */
+    int32_t reserved0[3];
+    double alpha;          /* the alpha of X0 = alpha*G that was used */
+    double d_last;         /* last relative Frobenius change */
+    double stop_last;      /* last value of the stopping rule's quantity */
+    double coc;            /* computational order of convergence (COC) from
+                              the last three inf-norm changes; 0 if unknown */
+    double gflop;          /* executed GEMM work, 2*M*N*K per launch, GFLOP */
+    double time_ms;        /* host wall time of the call */
+    double gemm_ms;        /* summed GEMM kernel time (HP_FLAG_TIME_KERNELS) */
+    double d_hist[HP_HIST];    /* relative Frobenius change per loop */
+    double dinf_hist[HP_HIST]; /* inf-norm change per loop (HP_FLAG_INF_NORM) */
+} hp_result;
+
+typedef struct hp_handle hp_handle;
+
+/* ABI version (HP_ABI_VERSION). */
+int hp_version(void);
+
+/* Static text for a status code. Never NULL. */
+const char* hp_status_string(int status);
+
+/* Fill *p with defaults: Moore-Penrose, alpha 1/(||A||_1||A||_inf), plain
+   variant, tau_switch 0.1, tol 1e-12, max_iter 100, relative Frobenius stop,
+   side AUTO, FP64. */
+void hp_params_default(hp_params* p);
+
+/* Create a handle bound to HIP device `device` (pinned host scratch and
+   events are allocated here; no matrix memory). */
+int hp_create(hp_handle** h, int device);
+int hp_destroy(hp_handle* h);
+
+/* Bytes of device workspace hp_solve needs for this shape and these params. */
+int hp_workspace_bytes(const hp_params* p, int64_t m, int64_t n, size_t* bytes);
+
+/* Compute X (n x m, row-major, leading dimension ldx >= m) ~ A^(2)_{R(G),N(G)}
+ * for A (m x n, leading dimension lda >= n).
+ *  X0: optional device n x m start (leading dimension ldx0); NULL = the rule
+ *      in p->alpha_rule (G = A^T for Moore-Penrose, A^l for Drazin). With an
+ *      explicit X0, p->alpha (if > 0) is used only by HP_STOP_PAPER_4_1.
+ *  workspace: >= hp_workspace_bytes, 256-byte aligned device memory.
+ *  out: optional host struct filled on every return >= 0.
+ * Errors: HP_EINVAL for m or n outside [1, 65535], Drazin with m != n or l < 1, ld below the
+ * column count, a misaligned pointer, or an unknown enum; HP_EWORKSPACE;
+ * HP_EHIP. */
+int hp_solve(hp_handle* h, const hp_params* p,
+             const double* A, int64_t m, int64_t n, int64_t lda,
+             const double* X0, int64_t ldx0,
+             double* X, int64_t ldx,
+             void* workspace, size_t ws_bytes,
+             void* stream, hp_result* out);
+
+/* One matrix product on the library's MFMA GEMM kernel, exposed so that the
+ * kernel can be checked and timed on its own:
+ *     C = alpha * A B + beta_identity * I      (A M x K, B K x N, C M x N)
+ * dtype HP_DTYPE_F64. Pointers must be 16-byte aligned and lda, ldb even.
+ * Errors: HP_EINVAL (shape, ld, alignment, dtype), HP_EHIP. */
+int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
+            double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+            double beta_identity, void* C, int64_t ldc, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYPERPOWER_H */

@@ -1,0 +1,326 @@
+// MFMA GEMM with the fused hyperpower epilogue, for gfx950 (CDNA4, wave64).
+//
+// C = epilogue(A * B), A M x K, B K x N, row-major, T = double
+// (v_mfma_f64_16x16x4f64, FP64 accumulate) or T = float
+// (v_mfma_f32_16x16x4f32, FP32 accumulate).
+//
+// Block tile BM x BN, K-tile BK, each wave a WM x WN sub-tile of 16x16 MFMA
+// accumulators. A and B are read with 16-byte loads along their contiguous
+// rows into registers one K-tile ahead and written to double-buffered LDS, A
+// transposed to k-major; rows are padded by 16 elements so the four lane groups
+// of a fragment read fall on disjoint LDS banks. One barrier per K-tile.
+// The epilogue forms up to three outputs
+//     out_o = id_o * I + acc_o * (A B) + g1_o * D1 + g2_o * D2
+// (the linear combinations of one loop of iteration (PM), Section 2) and,
+// optionally, per-block FP64 partial sums of (out_0 - ref)^2 and ref^2 for the
+// stopping test of Section 4.
+#include "hp_internal.h"
+
+namespace hp {
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+    typedef dbl4 acc_t;
+    static __device__ inline acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // accumulator register r of lane l holds row (l/16) + 4r, column l%16
+    static __device__ inline int row(int g, int r) { return g + 4 * r; }
+};
+
+template <>
+struct Mfma<float> {
+    typedef flt4 acc_t;
+    static __device__ inline acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // accumulator register r of lane l holds row 4(l/16) + r, column l%16
+    static __device__ inline int row(int g, int r) { return 4 * g + r; }
+};
+
+template <typename T>
+struct Vec16;  // 16 bytes of T
+template <>
+struct Vec16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int n = 2;
+};
+template <>
+struct Vec16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int n = 4;
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Hardware hands consecutive workgroups to the 8 XCDs in turn; renumber so
+// each XCD receives one contiguous range of tile indices (its L2 then holds
+// the A and B panels those tiles share).
+__device__ inline int xcd_contiguous(int b, int nb) {
+    const int nx = 8;
+    const int q = nb / nx, r = nb % nx;
+    const int x = b % nx;
+    return x * q + min(x, r) + b / nx;
+}
+
+// Grouped tile order: GROUP tile-rows walked column by column.
+__device__ inline void tile_of(int t, int tiles_m, int tiles_n, int& tm, int& tn) {
+    constexpr int GROUP = 8;
+    const int group_size = GROUP * tiles_n;
+    const int g = t / group_size;
+    const int first = g * GROUP;
+    const int gm = min(tiles_m - first, GROUP);
+    const int in = t - g * group_size;
+    tm = first + in % gm;
+    tn = in / gm;
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+struct Cfg {
+    static constexpr int WAVES = (BM / WM) * (BN / WN);
+    static constexpr int NT = 64 * WAVES;
+    static constexpr int V = Vec16<T>::n;
+    static constexpr int PAD = 16;
+    static constexpr int LDA_S = BM + PAD;
+    static constexpr int LDB_S = BN + PAD;
+    // A tile: BM rows of BK elements, BK/V threads per row
+    static constexpr int A_TPR = BK / V;
+    static constexpr int A_RPP = NT / A_TPR;
+    static constexpr int A_PASS = BM / A_RPP;
+    // B tile: BK rows of BN elements, BN/V threads per row
+    static constexpr int B_TPR = BN / V;
+    static constexpr int B_RPP = NT / B_TPR;
+    static constexpr int B_PASS = BK / B_RPP;
+    static constexpr int TI = WM / 16, TJ = WN / 16;
+    static_assert(BM % WM == 0 && BN % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "wave tiling");
+    static_assert(BK % 4 == 0 && BK % V == 0, "K tile");
+    static_assert(NT % A_TPR == 0 && A_RPP > 0 && BM % A_RPP == 0 && A_PASS >= 1, "A loads");
+    static_assert(NT % B_TPR == 0 && B_RPP > 0 && BK % B_RPP == 0 && B_PASS >= 1, "B loads");
+    static constexpr size_t LDS_BYTES = 2 * (size_t)BK * (LDA_S + LDB_S) * sizeof(T);
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm(
+    int M, int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+    int64_t ldb, EpilogueT<T> ep, int tiles_m, int tiles_n) {
+    using C = Cfg<T, BM, BN, BK, WM, WN>;
+    using VT = typename Vec16<T>::type;
+    using ACC = typename Mfma<T>::acc_t;
+    constexpr int V = C::V;
+    __shared__ T As[2][BK][C::LDA_S];
+    __shared__ T Bs[2][BK][C::LDB_S];
+    __shared__ double red[2][C::WAVES];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int tm, tn;
+    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    const int bm = tm * BM, bn = tn * BN;
+    const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
+
+    const int a_k = V * (tid % C::A_TPR), a_r = tid / C::A_TPR;
+    const int b_n = V * (tid % C::B_TPR), b_k = tid / C::B_TPR;
+    VT ra[C::A_PASS], rb[C::B_PASS];
+
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < C::A_PASS; ++p) {
+            const int row = bm + a_r + C::A_RPP * p, k = k0 + a_k;
+            VT v = {};
+            if (row < M && k < K) {
+                v = *reinterpret_cast<const VT*>(A + (int64_t)row * lda + k);
+#pragma unroll
+                for (int e = 1; e < V; ++e)
+                    if (k + e >= K) v[e] = T(0);
+            }
+            ra[p] = v;
+        }
+#pragma unroll
+        for (int p = 0; p < C::B_PASS; ++p) {
+            const int kr = k0 + b_k + C::B_RPP * p, c = bn + b_n;
+            VT v = {};
+            if (kr < K && c < N) {
+                v = *reinterpret_cast<const VT*>(B + (int64_t)kr * ldb + c);
+#pragma unroll
+                for (int e = 1; e < V; ++e)
+                    if (c + e >= N) v[e] = T(0);
+            }
+            rb[p] = v;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < C::A_PASS; ++p)
+#pragma unroll
+            for (int e = 0; e < V; ++e) As[buf][a_k + e][a_r + C::A_RPP * p] = ra[p][e];
+#pragma unroll
+        for (int p = 0; p < C::B_PASS; ++p)
+            *reinterpret_cast<VT*>(&Bs[buf][b_k + C::B_RPP * p][b_n]) = rb[p];
+    };
+
+    ACC acc[C::TI][C::TJ];
+#pragma unroll
+    for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TJ; ++j) acc[i][j] = ACC{};
+
+    const int nk = (K + BK - 1) / BK;
+    load(0);
+    store(0);
+    __syncthreads();
+    const int fr = lane & 15, fg = lane >> 4;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            T a[C::TI], b[C::TJ];
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i) a[i] = As[cur][ks + fg][wm + i * 16 + fr];
+#pragma unroll
+            for (int j = 0; j < C::TJ; ++j) b[j] = Bs[cur][ks + fg][wn + j * 16 + fr];
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < C::TJ; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) store(cur ^ 1);
+        __syncthreads();
+    }
+
+    // ---- epilogue ----
+    double s_diff = 0.0, s_ref = 0.0;
+#pragma unroll
+    for (int i = 0; i < C::TI; ++i) {
+#pragma unroll
+        for (int j = 0; j < C::TJ; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = bm + wm + i * 16 + Mfma<T>::row(fg, r);
+                const int col = bn + wn + j * 16 + fr;
+                if (row < M && col < N) {
+                    const T a = acc[i][j][r];
+                    const T d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : T(0);
+                    const T d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : T(0);
+                    const T idv = (row == col) ? T(1) : T(0);
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) {
+                        if (ep.out[o]) {
+                            T v = T(ep.acc_c[o]) * a;
+                            if (ep.id[o] != 0.0) v += T(ep.id[o]) * idv;
+                            if (ep.g1[o] != 0.0) v += T(ep.g1[o]) * d1;
+                            if (ep.g2[o] != 0.0) v += T(ep.g2[o]) * d2;
+                            ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
+                            if (o == 0 && ep.ref) {
+                                const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];
+                                const double df = (double)v - x0;
+                                s_diff += df * df;
+                                s_ref += x0 * x0;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (ep.ref) {
+        const double sd = wave_sum(s_diff), sr = wave_sum(s_ref);
+        if (lane == 0) {
+            red[0][wave] = sd;
+            red[1][wave] = sr;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < C::WAVES; ++w) {
+                a += red[0][w];
+                b += red[1][w];
+            }
+            ep.partials[2 * blockIdx.x] = a;
+            ep.partials[2 * blockIdx.x + 1] = b;
+        }
+    }
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+hipError_t launch(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
+                  int64_t ldb, const EpilogueT<T>& ep, hipStream_t s) {
+    using C = Cfg<T, BM, BN, BK, WM, WN>;
+    const int tm = (int)cdiv(M, BM), tn = (int)cdiv(N, BN);
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN>), dim3(tm * tn), dim3(C::NT), 0, s, (int)M,
+                       (int)N, (int)K, A, lda, B, ldb, ep, tm, tn);
+    return hipGetLastError();
+}
+
+// Tile configurations, indexed by GemmTile.
+struct TileShape {
+    int bm, bn;
+};
+constexpr TileShape kShapes[] = {
+    {128, 128},  // TILE_128x128_W4: 4 waves of 64x64
+    {128, 128},  // TILE_128x128_W8: 8 waves of 64x32
+    {128, 64},   // TILE_128x64_W4: 4 waves of 64x32
+    {64, 64},    // TILE_64x64_W4: 4 waves of 32x32
+    {256, 128},  // TILE_256x128_W8: 8 waves of 64x64
+};
+
+template <typename T>
+hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
+                    const T* B, int64_t ldb, const EpilogueT<T>& ep, hipStream_t s) {
+    constexpr int BKF = 16 * sizeof(double) / sizeof(T);  // 128-byte K-tile rows
+    switch (t) {
+        case TILE_128x128_W4: return launch<T, 128, 128, BKF, 64, 64>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W8: return launch<T, 128, 128, BKF, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x64_W4: return launch<T, 128, 64, BKF, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_64x64_W4: return launch<T, 64, 64, BKF, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_256x128_W8: return launch<T, 256, 128, BKF, 64, 64>(M, N, K, A, lda, B, ldb, ep, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int gemm_blocks(GemmTile t, int64_t M, int64_t N) {
+    const TileShape sh = kShapes[(int)t];
+    return (int)(cdiv(M, sh.bm) * cdiv(N, sh.bn));
+}
+
+int gemm_max_blocks(int64_t M, int64_t N) {
+    int b = 0;
+    for (int t = 0; t < TILE_COUNT; ++t) b = std::max(b, gemm_blocks((GemmTile)t, M, N));
+    return b;
+}
+
+GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K) {
+    (void)K;
+    const int64_t big = cdiv(M, 128) * cdiv(N, 128);
+    if (big >= 256) return TILE_128x128_W8;
+    if (cdiv(M, 128) * cdiv(N, 64) >= 256) return TILE_128x64_W4;
+    return TILE_64x64_W4;
+}
+
+hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                const double* B, int64_t ldb, const EpilogueT<double>& ep, hipStream_t s) {
+    return dispatch<double>(t, M, N, K, A, lda, B, ldb, ep, s);
+}
+
+hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                const float* B, int64_t ldb, const EpilogueT<float>& ep, hipStream_t s) {
+    return dispatch<float>(t, M, N, K, A, lda, B, ldb, ep, s);
+}
+
+}  // namespace hp

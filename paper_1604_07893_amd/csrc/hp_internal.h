@@ -1,0 +1,109 @@
+// Internal interface between the host driver (hp_driver.cpp) and the device
+// kernels (hp_kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace hp {
+
+// Device scalar slots (doubles) in the workspace's scalar area.
+enum ScalarSlot : int {
+    SLOT_ALPHA = 0,      // alpha of X0
+    SLOT_DIFF2 = 1,      // sum (X_{k+1} - X_k)^2
+    SLOT_REF2 = 2,       // sum X_k^2
+    SLOT_DINF = 3,       // ||X_{k+1} - X_k||_inf
+    SLOT_TRACE = 4,      // Tr(A^{l+1})
+    SLOT_NORM1 = 5,      // ||A||_1
+    SLOT_NORMINF = 6,    // ||A||_inf
+    SLOT_COUNT = 8
+};
+
+// Fused GEMM epilogue. For output o (0..2) with out[o] != nullptr:
+//   out[o][i][j] = id[o]*[i==j] + acc_c[o]*acc + g1[o]*D1[i][j] + g2[o]*D2[i][j]
+// If ref != nullptr, each block also writes FP64 partial sums
+//   partials[2*b] = sum (out0 - ref)^2, partials[2*b+1] = sum ref^2
+// over the elements it owns (b = linear block index).
+template <typename T>
+struct EpilogueT {
+    T* out[3];
+    int64_t ldo[3];
+    double id[3];
+    double acc_c[3];
+    double g1[3];
+    double g2[3];
+    const T* D1;
+    int64_t ld1;
+    const T* D2;
+    int64_t ld2;
+    const T* ref;
+    int64_t ldref;
+    double* partials;
+};
+using Epilogue = EpilogueT<double>;
+
+template <typename T>
+inline EpilogueT<T> epilogue_plain(T* C, int64_t ldc, double acc_c = 1.0, double id = 0.0) {
+    EpilogueT<T> e{};
+    e.out[0] = C;
+    e.ldo[0] = ldc;
+    e.acc_c[0] = acc_c;
+    e.id[0] = id;
+    return e;
+}
+
+// Block-tile configurations of the MFMA GEMM (hp_gemm.hip).
+enum GemmTile : int {
+    TILE_128x128_W4 = 0,  // 4 waves, 64x64 each
+    TILE_128x128_W8 = 1,  // 8 waves, 64x32 each
+    TILE_128x64_W4 = 2,   // 4 waves, 64x32 each
+    TILE_64x64_W4 = 3,    // 4 waves, 32x32 each
+    TILE_256x128_W8 = 4,  // 8 waves, 64x64 each
+    TILE_COUNT = 5
+};
+
+// Blocks (and partial-sum pairs) a launch with this tile uses for M x N.
+int gemm_blocks(GemmTile t, int64_t M, int64_t N);
+// The largest of gemm_blocks over every tile (sizes the partials buffer).
+int gemm_max_blocks(int64_t M, int64_t N);
+// Tile choice for an M x N x K product.
+GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K);
+
+// C = epilogue(A[M x K] * B[K x N]); all row-major, lda/ldb multiples of 16
+// bytes, pointers 16-byte aligned.
+hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                const double* B, int64_t ldb, const EpilogueT<double>& ep, hipStream_t s);
+hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                const float* B, int64_t ldb, const EpilogueT<float>& ep, hipStream_t s);
+
+// ||A||_1 and ||A||_inf of an M x N matrix, then scal[SLOT_ALPHA] =
+// 1/(||A||_1 ||A||_inf). `tmp` needs (ceil(M/256)+1)*N + M doubles.
+hipError_t alpha_norm1inf(const double* A, int64_t lda, int64_t M, int64_t N, double* tmp,
+                          double* scal, hipStream_t s);
+
+// scal[SLOT_TRACE] = sum_ij P[i][j] * A[j][i] = Tr(P A), scal[SLOT_ALPHA] =
+// 1/that (n x n). `tmp` needs ceil(n/32)^2 doubles.
+hipError_t alpha_trace(const double* P, int64_t ldp, const double* A, int64_t lda, int64_t n,
+                       double* tmp, double* scal, hipStream_t s);
+
+// Y[j][i] = (*alpha_dev) * A[i][j]; A is M x N, Y is N x M.
+hipError_t transpose_scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y,
+                           int64_t ldy, const double* alpha_dev, hipStream_t s);
+
+// Y = (*alpha_dev) * A elementwise (M x N).
+hipError_t scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y, int64_t ldy,
+                 const double* alpha_dev, hipStream_t s);
+
+// Y = I (M x N identity).
+hipError_t set_identity(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s);
+
+// scal[SLOT_DIFF2], scal[SLOT_REF2] = fixed-order sums of the pair partials.
+hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipStream_t s);
+
+// scal[SLOT_DINF] = max_i sum_j |X1[i][j] - X0[i][j]|. `tmp` needs M doubles.
+hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_t ld0,
+                         int64_t M, int64_t N, double* tmp, double* scal, hipStream_t s);
+
+}  // namespace hp

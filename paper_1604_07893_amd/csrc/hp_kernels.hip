@@ -1,0 +1,271 @@
+// Small device kernels of libhyperpower for gfx950 (CDNA4, wave64): the X0
+// rules of Section 4 (norms, trace, transpose-scale), the fixed-order
+// reductions of the stopping test and precision conversions. The hot kernel,
+// the MFMA GEMM with the fused loop epilogue, is in hp_gemm.hip.
+#include "hp_internal.h"
+
+namespace hp {
+namespace {
+
+constexpr int kThreads = 256;  // 4 waves of 64
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum over a 256-thread block in a fixed order; the result is valid in thread 0.
+__device__ double block_sum(double v) {
+    __shared__ double red[kThreads / 64];
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_max(double v) {
+    __shared__ double red[kThreads / 64];
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers.
+// ---------------------------------------------------------------------------
+
+// Column sums of |A| over 256-row chunks: part[chunk][col].
+__global__ __launch_bounds__(kThreads) void k_abs_colsum_part(const double* __restrict__ A, int64_t lda,
+                                                              int M, int N, double* __restrict__ part) {
+    const int col = blockIdx.x * kThreads + threadIdx.x;
+    const int chunk = blockIdx.y;
+    if (col >= N) return;
+    const int r0 = chunk * 256, r1 = min(M, r0 + 256);
+    double s = 0.0;
+    for (int r = r0; r < r1; ++r) s += fabs(A[(int64_t)r * lda + col]);
+    part[(int64_t)chunk * N + col] = s;
+}
+
+// Row sums of |A|: one block per row.
+__global__ __launch_bounds__(kThreads) void k_abs_rowsum(const double* __restrict__ A, int64_t lda, int N,
+                                                         double* __restrict__ rows) {
+    const int r = blockIdx.x;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < N; c += kThreads) s += fabs(A[(int64_t)r * lda + c]);
+    s = block_sum(s);
+    if (threadIdx.x == 0) rows[r] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_alpha_norm1inf(const double* __restrict__ part, int nchunk,
+                                                             int N, const double* __restrict__ rows,
+                                                             int M, double* __restrict__ scal) {
+    double m1 = 0.0;
+    for (int c = threadIdx.x; c < N; c += kThreads) {
+        double s = 0.0;
+        for (int ch = 0; ch < nchunk; ++ch) s += part[(int64_t)ch * N + c];
+        m1 = fmax(m1, s);
+    }
+    double mi = 0.0;
+    for (int r = threadIdx.x; r < M; r += kThreads) mi = fmax(mi, rows[r]);
+    m1 = block_max(m1);
+    mi = block_max(mi);
+    if (threadIdx.x == 0) {
+        scal[SLOT_NORM1] = m1;
+        scal[SLOT_NORMINF] = mi;
+        scal[SLOT_ALPHA] = 1.0 / (m1 * mi);
+    }
+}
+
+// Partial sums of P[i][j] * A[j][i] over 32x32 tiles (A read through LDS so
+// that both operands are read along rows).
+__global__ __launch_bounds__(kThreads) void k_trace_part(const double* __restrict__ P, int64_t ldp,
+                                                         const double* __restrict__ A, int64_t lda,
+                                                         int n, double* __restrict__ part) {
+    __shared__ double t[32][33];
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int y = ty; y < 32; y += 8) {
+        const int j = bj + y, i = bi + tx;
+        t[y][tx] = (j < n && i < n) ? A[(int64_t)j * lda + i] : 0.0;
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int y = ty; y < 32; y += 8) {
+        const int i = bi + y, j = bj + tx;
+        if (i < n && j < n) s += P[(int64_t)i * ldp + j] * t[tx][y];
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_trace_final(const double* __restrict__ part, int np,
+                                                          double* __restrict__ scal) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += kThreads) s += part[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) {
+        scal[SLOT_TRACE] = s;
+        scal[SLOT_ALPHA] = 1.0 / s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_transpose_scale(const double* __restrict__ A, int64_t lda,
+                                                              int M, int N, double* __restrict__ Y,
+                                                              int64_t ldy,
+                                                              const double* __restrict__ alpha) {
+    __shared__ double t[32][33];
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const double al = *alpha;
+    for (int y = ty; y < 32; y += 8) {
+        const int i = bi + y, j = bj + tx;
+        if (i < M && j < N) t[y][tx] = A[(int64_t)i * lda + j];
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int j = bj + y, i = bi + tx;
+        if (j < N && i < M) Y[(int64_t)j * ldy + i] = al * t[tx][y];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale(const double* __restrict__ A, int64_t lda, int M,
+                                                    int N, double* __restrict__ Y, int64_t ldy,
+                                                    const double* __restrict__ alpha) {
+    const double al = *alpha;
+    const int r = blockIdx.y;
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < N; c += gridDim.x * kThreads)
+        Y[(int64_t)r * ldy + c] = al * A[(int64_t)r * lda + c];
+}
+
+__global__ __launch_bounds__(kThreads) void k_identity(double* __restrict__ Y, int64_t ldy, int M, int N) {
+    const int r = blockIdx.y;
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < N; c += gridDim.x * kThreads)
+        Y[(int64_t)r * ldy + c] = (r == c) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_pairs(const double* __restrict__ part, int nb,
+                                                           double* __restrict__ scal) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) {
+        s0 += part[2 * b];
+        s1 += part[2 * b + 1];
+    }
+    s0 = block_sum(s0);
+    s1 = block_sum(s1);
+    if (threadIdx.x == 0) {
+        scal[SLOT_DIFF2] = s0;
+        scal[SLOT_REF2] = s1;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_diff_rowsum(const double* __restrict__ X1, int64_t ld1,
+                                                          const double* __restrict__ X0, int64_t ld0,
+                                                          int N, double* __restrict__ rows) {
+    const int r = blockIdx.x;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < N; c += kThreads)
+        s += fabs(X1[(int64_t)r * ld1 + c] - X0[(int64_t)r * ld0 + c]);
+    s = block_sum(s);
+    if (threadIdx.x == 0) rows[r] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_max_to_slot(const double* __restrict__ v, int n,
+                                                          double* __restrict__ scal, int slot) {
+    double m = 0.0;
+    bool nan = false;
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+        const double x = v[i];
+        if (x != x) nan = true;
+        m = fmax(m, x);
+    }
+    if (nan) m = __builtin_nan("");
+    // NaN-propagating block max
+    __shared__ int any_nan;
+    if (threadIdx.x == 0) any_nan = 0;
+    __syncthreads();
+    if (nan) any_nan = 1;
+    __syncthreads();
+    const double r = block_max(nan ? 0.0 : m);
+    if (threadIdx.x == 0) scal[slot] = any_nan ? __builtin_nan("") : r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+
+hipError_t alpha_norm1inf(const double* A, int64_t lda, int64_t M, int64_t N, double* tmp,
+                          double* scal, hipStream_t s) {
+    const int nchunk = (int)cdiv(M, 256);
+    double* part = tmp;
+    double* rows = tmp + (int64_t)nchunk * N;
+    hipLaunchKernelGGL(k_abs_colsum_part, dim3((unsigned)cdiv(N, kThreads), nchunk), dim3(kThreads),
+                       0, s, A, lda, (int)M, (int)N, part);
+    hipLaunchKernelGGL(k_abs_rowsum, dim3((unsigned)M), dim3(kThreads), 0, s, A, lda, (int)N, rows);
+    hipLaunchKernelGGL(k_alpha_norm1inf, dim3(1), dim3(kThreads), 0, s, part, nchunk, (int)N, rows,
+                       (int)M, scal);
+    return hipGetLastError();
+}
+
+hipError_t alpha_trace(const double* P, int64_t ldp, const double* A, int64_t lda, int64_t n,
+                       double* tmp, double* scal, hipStream_t s) {
+    const int nt = (int)cdiv(n, 32);
+    hipLaunchKernelGGL(k_trace_part, dim3(nt, nt), dim3(kThreads), 0, s, P, ldp, A, lda, (int)n, tmp);
+    hipLaunchKernelGGL(k_trace_final, dim3(1), dim3(kThreads), 0, s, tmp, nt * nt, scal);
+    return hipGetLastError();
+}
+
+hipError_t transpose_scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y,
+                           int64_t ldy, const double* alpha_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose_scale, dim3((unsigned)cdiv(N, 32), (unsigned)cdiv(M, 32)),
+                       dim3(kThreads), 0, s, A, lda, (int)M, (int)N, Y, ldy, alpha_dev);
+    return hipGetLastError();
+}
+
+hipError_t scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y, int64_t ldy,
+                 const double* alpha_dev, hipStream_t s) {
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N, kThreads), 16);
+    hipLaunchKernelGGL(k_scale, dim3(gx, (unsigned)M), dim3(kThreads), 0, s, A, lda, (int)M, (int)N,
+                       Y, ldy, alpha_dev);
+    return hipGetLastError();
+}
+
+hipError_t set_identity(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s) {
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N, kThreads), 16);
+    hipLaunchKernelGGL(k_identity, dim3(gx, (unsigned)M), dim3(kThreads), 0, s, Y, ldy, (int)M, (int)N);
+    return hipGetLastError();
+}
+
+hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kThreads), 0, s, partials, nblocks, scal);
+    return hipGetLastError();
+}
+
+hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_t ld0, int64_t M,
+                         int64_t N, double* tmp, double* scal, hipStream_t s) {
+    hipLaunchKernelGGL(k_diff_rowsum, dim3((unsigned)M), dim3(kThreads), 0, s, X1, ld1, X0, ld0,
+                       (int)N, tmp);
+    hipLaunchKernelGGL(k_max_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal, (int)SLOT_DINF);
+    return hipGetLastError();
+}
+
+}  // namespace hp

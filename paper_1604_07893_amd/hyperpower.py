@@ -1,0 +1,250 @@
+"""ctypes binding of libhyperpower (the C ABI in include/hyperpower.h).
+
+Argument marshalling only: every step of the iteration runs in the library's
+HIP kernels. PyTorch provides device memory (tensors) and the stream; nothing
+here computes on the matrices. If the library is missing the calls raise; there
+is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhyperpower.so")
+
+# ---- constants mirrored from include/hyperpower.h ---------------------------
+HP_ABI_VERSION = 1
+HP_OK, HP_MAXITER, HP_STAGNATED, HP_DIVERGED, HP_NONFINITE, HP_PENDING = 0, 1, 2, 3, 4, 5
+HP_EINVAL, HP_EWORKSPACE, HP_EBUDGET, HP_EHIP, HP_EUNSUPPORTED = -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "stagnated", 3: "diverged", 4: "nonfinite", 5: "pending"}
+
+KIND = {"mp": 0, "moore_penrose": 0, "drazin": 1}
+ALPHA = {"norm1inf": 0, "user": 1, "trace": 2}
+VARIANT = {"plain": 0, "stabilised": 1, "stabilized": 1, "stab_always": 2}
+SIDE = {"auto": 0, "right": 1, "left": 2}
+STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2}
+PREC = {"fp64": 0}
+FLAG_TIME_KERNELS, FLAG_INF_NORM = 1, 2
+DTYPE = {torch.float64: 0}
+HP_HIST = 128
+
+
+class HpParams(ctypes.Structure):
+    _fields_ = [
+        ("kind", c_int32), ("drazin_l", c_int32), ("alpha_rule", c_int32), ("variant", c_int32),
+        ("alpha", c_double), ("tau_switch", c_double), ("tol", c_double), ("diverge_limit", c_double),
+        ("max_iter", c_int32), ("stop_rule", c_int32), ("side", c_int32), ("precision", c_int32),
+        ("flags", c_int32), ("reserved", c_int32 * 7),
+    ]
+
+
+class HpResult(ctypes.Structure):
+    _fields_ = [
+        ("status", c_int32), ("iters", c_int32), ("switch_iter", c_int32), ("side_used", c_int32),
+        ("gemms", c_int32), ("reserved0", c_int32 * 3),
+        ("alpha", c_double), ("d_last", c_double), ("stop_last", c_double), ("coc", c_double),
+        ("gflop", c_double), ("time_ms", c_double), ("gemm_ms", c_double),
+        ("d_hist", c_double * HP_HIST), ("dinf_hist", c_double * HP_HIST),
+    ]
+
+
+# Every symbol the header declares, with its ctypes signature.
+SIGNATURES = {
+    "hp_version": (c_int, []),
+    "hp_status_string": (ctypes.c_char_p, [c_int]),
+    "hp_params_default": (None, [POINTER(HpParams)]),
+    "hp_create": (c_int, [POINTER(c_void_p), c_int]),
+    "hp_destroy": (c_int, [c_void_p]),
+    "hp_workspace_bytes": (c_int, [POINTER(HpParams), c_int64, c_int64, POINTER(c_size_t)]),
+    "hp_solve": (c_int, [c_void_p, POINTER(HpParams), c_void_p, c_int64, c_int64, c_int64,
+                         c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t, c_void_p,
+                         POINTER(HpResult)]),
+    "hp_gemm": (c_int, [c_void_p, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
+                        c_void_p, c_int64, c_double, c_void_p, c_int64, c_void_p]),
+}
+
+_lib = None
+_lock = threading.Lock()
+_handles: dict[int, "Handle"] = {}
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    """Load libhyperpower.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise RuntimeError(
+                f"libhyperpower.so not found at {p}; build it first "
+                "(python -c 'import __graft_entry__ as g; g.build()')")
+        lib = ctypes.CDLL(p)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        if lib.hp_version() != HP_ABI_VERSION:
+            raise RuntimeError("libhyperpower ABI version mismatch")
+        if path is None:
+            _lib = lib
+        return lib
+
+
+class HyperpowerError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = load_library()
+        super().__init__(f"{where}: {lib.hp_status_string(code).decode()} ({code})")
+        self.code = code
+
+
+class Handle:
+    def __init__(self, device: int):
+        lib = load_library()
+        h = c_void_p()
+        rc = lib.hp_create(ctypes.byref(h), device)
+        if rc != HP_OK:
+            raise HyperpowerError(rc, "hp_create")
+        self.ptr = h
+        self.device = device
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                load_library().hp_destroy(self.ptr)
+        except Exception:
+            pass
+
+
+def handle(device: int | None = None) -> Handle:
+    dev = torch.cuda.current_device() if device is None else device
+    if dev not in _handles:
+        _handles[dev] = Handle(dev)
+    return _handles[dev]
+
+
+def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", tau_switch=0.1,
+                tol=1e-12, max_iter=100, stop="rel_fro", side="auto", precision="fp64",
+                diverge_limit=1e6, time_kernels=False, inf_norm=False) -> HpParams:
+    p = HpParams()
+    load_library().hp_params_default(ctypes.byref(p))
+    p.kind = KIND[kind]
+    p.drazin_l = int(l)
+    if alpha_rule is None:
+        alpha_rule = "trace" if p.kind == 1 else "norm1inf"
+    p.alpha_rule = ALPHA[alpha_rule]
+    p.alpha = float(alpha)
+    p.variant = VARIANT[variant]
+    p.tau_switch = float(tau_switch)
+    p.tol = float(tol)
+    p.max_iter = int(max_iter)
+    p.stop_rule = STOP[stop]
+    p.side = SIDE[side]
+    p.precision = PREC[precision]
+    p.diverge_limit = float(diverge_limit)
+    p.flags = (FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
+    return p
+
+
+def _check_matrix(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a row-major 2-D tensor (stride(1) == 1)")
+
+
+def workspace_bytes(params: HpParams, m: int, n: int) -> int:
+    nb = c_size_t()
+    rc = load_library().hp_workspace_bytes(ctypes.byref(params), m, n, ctypes.byref(nb))
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_workspace_bytes")
+    return nb.value
+
+
+def result_dict(r: HpResult) -> dict:
+    it = min(r.iters, HP_HIST)
+    return {
+        "status": STATUS_NAMES.get(r.status, str(r.status)), "status_code": r.status,
+        "iters": r.iters, "switch_iter": r.switch_iter,
+        "side": {1: "right", 2: "left"}.get(r.side_used, "?"), "gemms": r.gemms,
+        "alpha": r.alpha, "d_last": r.d_last, "stop_last": r.stop_last, "coc": r.coc,
+        "gflop": r.gflop, "time_ms": r.time_ms, "gemm_ms": r.gemm_ms,
+        "d_hist": list(r.d_hist[:it]), "dinf_hist": list(r.dinf_hist[:it]),
+    }
+
+
+def solve(A: torch.Tensor, *, X0: torch.Tensor | None = None, out: torch.Tensor | None = None,
+          workspace: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
+          **kw) -> tuple[torch.Tensor, dict]:
+    """Generalized inverse of A (m x n, float64, on the GPU) by the hyperpower
+    iteration; returns (X n x m, info). Keyword arguments are those of
+    make_params (kind, l, alpha_rule, alpha, variant, tau_switch, tol, max_iter,
+    stop, side, ...). Raises HyperpowerError on a negative status; a positive
+    status (maxiter/stagnated/diverged/nonfinite) is reported in info."""
+    _check_matrix(A, "A")
+    m, n = A.shape
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    params = make_params(**kw)
+    nbytes = workspace_bytes(params, m, n)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    if workspace.data_ptr() % 256:
+        raise ValueError("workspace must be 256-byte aligned")
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.float64, device=A.device)
+    _check_matrix(out, "out")
+    x0p, ldx0 = None, 0
+    if X0 is not None:
+        _check_matrix(X0, "X0")
+        x0p, ldx0 = X0.data_ptr(), X0.stride(0)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    res = HpResult()
+    rc = load_library().hp_solve(
+        handle(dev).ptr, ctypes.byref(params), A.data_ptr(), m, n, A.stride(0), x0p, ldx0,
+        out.data_ptr(), out.stride(0), workspace.data_ptr(), workspace.numel(), s.cuda_stream,
+        ctypes.byref(res))
+    if rc < 0:
+        raise HyperpowerError(rc, "hp_solve")
+    return out, result_dict(res)
+
+
+def pinv(A: torch.Tensor, **kw) -> tuple[torch.Tensor, dict]:
+    """Moore-Penrose inverse (X0 = alpha A^T, Section 4)."""
+    return solve(A, kind="mp", **kw)
+
+
+def drazin(A: torch.Tensor, l: int, **kw) -> tuple[torch.Tensor, dict]:
+    """Drazin inverse with l >= ind(A) (X0 = A^l / Tr(A^{l+1}), Section 4)."""
+    return solve(A, kind="drazin", l=l, **kw)
+
+
+def gemm(A: torch.Tensor, B: torch.Tensor, *, alpha: float = 1.0, beta_identity: float = 0.0,
+         out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """C = alpha A B + beta_identity I on the library's MFMA GEMM kernel."""
+    if A.dtype != B.dtype or A.dtype not in DTYPE:
+        raise ValueError("unsupported dtype")
+    for t, nm in ((A, "A"), (B, "B")):
+        if not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError(f"{nm} must be a row-major device matrix")
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    if out is None:
+        out = torch.empty((M, N), dtype=A.dtype, device=A.device)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    rc = load_library().hp_gemm(handle(dev).ptr, DTYPE[A.dtype], M, N, K, alpha, A.data_ptr(),
+                                A.stride(0), B.data_ptr(), B.stride(0), beta_identity,
+                                out.data_ptr(), out.stride(0), s.cuda_stream)
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_gemm")
+    return out

@@ -1,0 +1,76 @@
+"""The FP64 MFMA GEMM kernel against numpy's FP64 product, elementwise within
+the standard error bound |C - C_hat| <= c K u (|A| |B|)."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import need_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0**-53
+
+
+def even_ld(a):
+    """Device copy whose leading dimension is rounded up to an even count (the
+    kernel reads 16-byte pairs along rows)."""
+    r, c = a.shape
+    buf = torch.zeros((r, c + (c & 1)), dtype=torch.float64, device="cuda:0")
+    buf[:, :c] = to_dev(a)
+    return buf[:, :c]
+
+SHAPES = [
+    (1, 1, 1), (16, 16, 4), (128, 128, 16), (127, 129, 17), (200, 200, 100),
+    (257, 129, 33), (130, 7, 300), (5, 300, 2), (333, 444, 555), (1024, 1024, 1024),
+    (64, 2048, 96),
+]
+
+
+@pytest.mark.parametrize("M,N,K", SHAPES)
+def test_gemm_f64_matches_numpy(M, N, K):
+    hpw = need_gpu()
+    say(f"gemm f64 M={M} N={N} K={K}")
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    C = hpw.gemm(even_ld(A), even_ld(B))
+    torch.cuda.synchronize()
+    ref = A @ B
+    bound = (np.abs(A) @ np.abs(B)) * (2 * K + 4) * U64
+    err = np.abs(C.cpu().numpy() - ref)
+    assert np.all(err <= bound + 1e-300), float((err / (bound + 1e-300)).max())
+
+
+def test_gemm_epilogue_identity_and_scale_with_padded_ld():
+    hpw = need_gpu()
+    rng = np.random.default_rng(5)
+    M, K, N = 150, 70, 150
+    big = rng.standard_normal((M, K + 10))
+    A = to_dev(big)[:, :K]                      # lda = K + 10 (even)
+    B = to_dev(rng.standard_normal((K, N)))
+    out = torch.full((M, N + 6), 7.0, dtype=torch.float64, device="cuda:0")
+    C = hpw.gemm(A, B, alpha=-1.0, beta_identity=1.0, out=out[:, :N])
+    torch.cuda.synchronize()
+    ref = np.eye(M, N) - big[:, :K] @ B.cpu().numpy()
+    assert np.max(np.abs(C.cpu().numpy() - ref)) < 1e-12
+    # the padding columns of the output were not touched
+    assert torch.all(out[:, N:] == 7.0)
+
+
+def test_gemm_is_deterministic():
+    hpw = need_gpu()
+    rng = np.random.default_rng(9)
+    A = to_dev(rng.standard_normal((300, 260)))
+    B = to_dev(rng.standard_normal((260, 280)))
+    c1 = hpw.gemm(A, B).cpu()
+    c2 = hpw.gemm(A, B).cpu()
+    assert torch.equal(c1, c2)
+
+
+def test_gemm_rejects_bad_arguments():
+    hpw = need_gpu()
+    A = torch.zeros((8, 9), dtype=torch.float64, device="cuda:0")   # odd lda
+    B = torch.zeros((9, 8), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(hpw.HyperpowerError):
+        hpw.gemm(A, B)
