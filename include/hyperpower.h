@@ -88,7 +88,21 @@ extern "C" {
 #define HP_STOP_ABS_INF 2   /* ||X_{k+1}-X_k||_inf <= tol (Example 8.1) */
 
 /* arithmetic of the loops */
-#define HP_PREC_FP64 0
+#define HP_PREC_FP64 0  /* every loop in FP64 (FP64 MFMA, FP64 accumulate) */
+#define HP_PREC_FP32 1  /* every loop in FP32 storage and FP32 MFMA; the stop
+                           sums in FP64; X returned in FP64. Reaches about
+                           kappa(A) * 6e-8, not an FP64 tolerance. */
+#define HP_PREC_MIXED 2 /* stage 0: 16-bit MFMA products (hp_params.low_dtype)
+                           on FP32 storage with FP32 accumulation; stage 1:
+                           FP32; stage 2: FP64 loops until the stop test
+                           passes. A stage ends when its relative change stops
+                           halving (below 1) or falls under 10x its unit
+                           roundoff; the FP64 stage alone applies the stop test
+                           and the stagnation guard. */
+
+/* hp_params.low_dtype: operand type of the first mixed stage */
+#define HP_LOWP_BF16 0
+#define HP_LOWP_F16 1
 
 /* hp_params.flags */
 #define HP_FLAG_TIME_KERNELS 1 /* time every GEMM launch with hipEvents on the
@@ -97,7 +111,11 @@ extern "C" {
                                   (implied by HP_STOP_ABS_INF); enables coc */
 
 /* GEMM element type for hp_gemm */
-#define HP_DTYPE_F64 0
+#define HP_DTYPE_F64 0 /* FP64 operands, v_mfma_f64_16x16x4f64, FP64 accumulate */
+#define HP_DTYPE_F32 1 /* FP32 operands, v_mfma_f32_16x16x4f32, FP32 accumulate */
+#define HP_DTYPE_BF16_F32 2 /* FP32 in memory, operands rounded to bf16,
+                               v_mfma_f32_16x16x32_bf16, FP32 accumulate and C */
+#define HP_DTYPE_F16_F32 3  /* as above with fp16 operands (f16 MFMA) */
 
 typedef struct hp_params {
     int32_t kind;          /* HP_KIND_* */
@@ -114,7 +132,8 @@ typedef struct hp_params {
     int32_t side;          /* HP_SIDE_* */
     int32_t precision;     /* HP_PREC_* */
     int32_t flags;         /* HP_FLAG_* */
-    int32_t reserved[7];   /* must be zero */
+    int32_t low_dtype;     /* HP_LOWP_*, HP_PREC_MIXED only */
+    int32_t reserved[6];   /* must be zero */
 } hp_params;
 
 #define HP_HIST 128
@@ -125,7 +144,7 @@ typedef struct hp_result {
     int32_t switch_iter;   /* first loop run stabilised; -1 if none */
     int32_t side_used;     /* HP_SIDE_RIGHT or HP_SIDE_LEFT */
     int32_t gemms;         /* GEMM launches, set-up included */
-    int32_t reserved0[3];
+    int32_t iters_stage[3];/* loops run in the 16-bit, FP32 and FP64 stages */
     double alpha;          /* the alpha of X0 = alpha*G that was used */
     double d_last;         /* last relative Frobenius change */
     double stop_last;      /* last value of the stopping rule's quantity */
@@ -134,6 +153,8 @@ typedef struct hp_result {
     double gflop;          /* executed GEMM work, 2*M*N*K per launch, GFLOP */
     double time_ms;        /* host wall time of the call */
     double gemm_ms;        /* summed GEMM kernel time (HP_FLAG_TIME_KERNELS) */
+    double d_stage[3];     /* last relative change in each stage */
+    double gflop_stage[3]; /* executed GEMM work per stage (set-up in stage 2) */
     double d_hist[HP_HIST];    /* relative Frobenius change per loop */
     double dinf_hist[HP_HIST]; /* inf-norm change per loop (HP_FLAG_INF_NORM) */
 } hp_result;
@@ -179,7 +200,10 @@ int hp_solve(hp_handle* h, const hp_params* p,
 /* One matrix product on the library's MFMA GEMM kernel, exposed so that the
  * kernel can be checked and timed on its own:
  *     C = alpha * A B + beta_identity * I      (A M x K, B K x N, C M x N)
- * dtype HP_DTYPE_F64. Pointers must be 16-byte aligned and lda, ldb even.
+ * dtype HP_DTYPE_F64 (A, B, C double) or HP_DTYPE_F32 / HP_DTYPE_BF16_F32 /
+ * HP_DTYPE_F16_F32 (A, B, C float). Pointers
+ * must be 16-byte aligned and the rows of A and B must start on 16-byte
+ * boundaries (lda, ldb multiples of 16 bytes).
  * Errors: HP_EINVAL (shape, ld, alignment, dtype), HP_EHIP. */
 int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
             double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "hp_internal.h"
 #include "hyperpower.h"
@@ -68,12 +69,20 @@ inline int64_t pad_ld(int64_t cols) {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Workspace layout. FP64 set: A, three n x m iterates (X_k, X_{k+1}, X_{k+1/2})
+// and seven s x s loop matrices. FP32 set (FP32 and mixed precision): the same
+// in single precision. FP32-only solves keep just A and one iterate in FP64
+// (X0 is formed there).
 struct Plan {
     int64_t m = 0, n = 0;
     bool left = false;
     int64_t s = 0;          // side of the residual R (n for left, m for right)
-    int64_t ldA = 0, ldX = 0, ldS = 0;
-    size_t offA = 0, offX[3] = {0, 0, 0}, offS[7] = {0, 0, 0, 0, 0, 0, 0};
+    int64_t ldA = 0, ldX = 0, ldS = 0;  // FP64 leading dimensions (elements)
+    int64_t ldA32 = 0, ldX32 = 0, ldS32 = 0;
+    int nX64 = 0, nS64 = 0, nX32 = 0, nS32 = 0;
+    bool has32 = false;
+    size_t offA = 0, offX[3] = {}, offS[7] = {};
+    size_t offA32 = 0, offX32[3] = {}, offS32[7] = {};
     size_t offSmall = 0, nSmall = 0, offScal = 0, total = 0;
 };
 
@@ -92,16 +101,39 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n) {
     pl.ldA = pad_ld(n);
     pl.ldX = pad_ld(m);
     pl.ldS = pad_ld(pl.s);
+    pl.ldA32 = pad_ld(n);
+    pl.ldX32 = pad_ld(m);
+    pl.ldS32 = pad_ld(pl.s);
+    const bool fp32only = p->precision == HP_PREC_FP32;
+    pl.has32 = p->precision != HP_PREC_FP64;
+    pl.nX64 = fp32only ? 1 : 3;
+    pl.nS64 = fp32only ? 0 : 7;
+    pl.nX32 = pl.has32 ? 3 : 0;
+    pl.nS32 = pl.has32 ? 7 : 0;
+    // Drazin set-up forms A^l in two s x s buffers of the FP64 set
+    if (fp32only && p->kind == HP_KIND_DRAZIN) pl.nS64 = 2;
     size_t off = 0;
     pl.offA = off;
     off = align_up(off + sizeof(double) * (size_t)(m * pl.ldA));
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < pl.nX64; ++i) {
         pl.offX[i] = off;
         off = align_up(off + sizeof(double) * (size_t)(n * pl.ldX));
     }
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < pl.nS64; ++i) {
         pl.offS[i] = off;
         off = align_up(off + sizeof(double) * (size_t)(pl.s * pl.ldS));
+    }
+    if (pl.has32) {
+        pl.offA32 = off;
+        off = align_up(off + sizeof(float) * (size_t)(m * pl.ldA32));
+        for (int i = 0; i < pl.nX32; ++i) {
+            pl.offX32[i] = off;
+            off = align_up(off + sizeof(float) * (size_t)(n * pl.ldX32));
+        }
+        for (int i = 0; i < pl.nS32; ++i) {
+            pl.offS32[i] = off;
+            off = align_up(off + sizeof(float) * (size_t)(pl.s * pl.ldS32));
+        }
     }
     // small area: GEMM partial pairs, norm sums, trace partials, row sums
     const int64_t big = std::max(m, n);
@@ -133,10 +165,11 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
     if (p->variant < HP_VARIANT_PLAIN || p->variant > HP_VARIANT_STAB_ALWAYS) return HP_EINVAL;
     if (p->side < HP_SIDE_AUTO || p->side > HP_SIDE_LEFT) return HP_EINVAL;
     if (p->stop_rule < HP_STOP_REL_FRO || p->stop_rule > HP_STOP_ABS_INF) return HP_EINVAL;
-    if (p->precision != HP_PREC_FP64) return HP_EUNSUPPORTED;
+    if (p->precision < HP_PREC_FP64 || p->precision > HP_PREC_MIXED) return HP_EINVAL;
+    if (p->low_dtype != HP_LOWP_BF16 && p->low_dtype != HP_LOWP_F16) return HP_EINVAL;
     if (p->max_iter < 1 || p->max_iter > 100000) return HP_EINVAL;
     if (!(p->tol >= 0.0) || !(p->tau_switch > 0.0) || !(p->diverge_limit > 0.0)) return HP_EINVAL;
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < 6; ++i)
         if (p->reserved[i] != 0) return HP_EINVAL;
     return HP_OK;
 }
@@ -166,6 +199,18 @@ struct GemmTimer {
     }
 };
 
+// Which MFMA path a product runs on.
+enum Engine { ENG_F64, ENG_F32, ENG_BF16, ENG_F16 };
+
+// The buffers of one precision.
+template <typename T>
+struct Set {
+    T* A = nullptr;
+    T* X[3] = {};
+    T* S[7] = {};
+    int64_t ldA = 0, ldX = 0, ldS = 0;
+};
+
 struct Solver {
     hp_handle* h;
     const hp_params* p;
@@ -177,19 +222,31 @@ struct Solver {
     double gflop = 0.0;
     int gemms = 0;
     int last_blocks = 0;  // blocks (partial pairs) of the latest product
+    int stage = 2;        // 0 16-bit, 1 FP32, 2 FP64 (for per-stage accounting)
 
-    double* ptr(size_t off) { return reinterpret_cast<double*>(ws + off); }
+    template <typename T>
+    T* ptr(size_t off) { return reinterpret_cast<T*>(ws + off); }
 
-    int gemm(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
-             int64_t ldb, const Epilogue& ep) {
+    template <typename T>
+    int gemm(Engine eng, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
+             int64_t ldb, const hp::EpilogueT<T>& ep) {
         const hp::GemmTile t = h->forced_tile >= 0 ? (hp::GemmTile)h->forced_tile
                                                    : hp::gemm_pick_tile(M, N, K);
         timer.before();
-        hipError_t e = hp::gemm(t, M, N, K, A, lda, B, ldb, ep, s);
+        hipError_t e;
+        if constexpr (std::is_same<T, double>::value) {
+            e = hp::gemm(t, M, N, K, A, lda, B, ldb, ep, s);
+        } else {
+            if (eng == ENG_F32) e = hp::gemm(t, M, N, K, A, lda, B, ldb, ep, s);
+            else e = hp::gemm_lowp(t, eng == ENG_BF16 ? hp::LOWP_BF16 : hp::LOWP_F16, M, N, K, A,
+                                   lda, B, ldb, ep, s);
+        }
         timer.after();
         last_blocks = hp::gemm_blocks(t, M, N);
         if (e != hipSuccess) return HP_EHIP;
-        gflop += 2.0 * (double)M * (double)N * (double)K * 1e-9;
+        const double g = 2.0 * (double)M * (double)N * (double)K * 1e-9;
+        gflop += g;
+        res->gflop_stage[stage] += g;
         ++gemms;
         return HP_OK;
     }
@@ -201,35 +258,121 @@ struct Solver {
         if (rc_ != HP_OK) return rc_; \
     } while (0)
 
+// One loop of (PM), Section 2, in the association printed there, on buffers
+// of one precision: R, R^2, R^4 (epilogue: F1, F2), F1 F2 (epilogue: T, S),
+// T S (+ mu R^2 + psi R^4), R V (+ V), and the update; if `stab`, the
+// stabilising product X A X of (PM-modified), Section 7, follows. The update
+// (or the stabilising product) writes the partial sums of the stopping test
+// against X_k into `partials`.
+template <typename T>
+int pm_loop(Solver& S, Engine eng, const Set<T>& b, T* Xk, T* Xn, T* Xh, bool stab,
+            double* partials) {
+    const PMConst K = pm_const();
+    const int64_t m = S.pl.m, n = S.pl.n, sd = S.pl.s;
+    const int64_t ldS = b.ldS, ldX = b.ldX, ldA = b.ldA;
+    T* R = b.S[0];
+    T* R2 = b.S[1];
+    T* R4 = b.S[2];
+    T* F1 = b.S[3];
+    T* F2 = b.S[4];
+    T* Tm = b.S[5];
+    T* Sm = b.S[6];
+    T* V = F1;  // F1, F2 are dead once T and S exist
+    T* W = F2;
+    {   // R = I - A X (right, m x m) or I - X A (left, n x n)
+        hp::EpilogueT<T> e = hp::epilogue_plain(R, ldS, -1.0, 1.0);
+        if (S.pl.left) CHK(S.gemm<T>(eng, n, n, m, Xk, ldX, b.A, ldA, e));
+        else CHK(S.gemm<T>(eng, m, m, n, b.A, ldA, Xk, ldX, e));
+    }
+    CHK(S.gemm<T>(eng, sd, sd, sd, R, ldS, R, ldS, hp::epilogue_plain(R2, ldS)));
+    {   // R4 = R2 R2; F1 = I + c1 R2 + R4; F2 = I + c2 R2 + R4
+        hp::EpilogueT<T> e{};
+        e.out[0] = R4; e.ldo[0] = ldS; e.acc_c[0] = 1.0;
+        e.out[1] = F1; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.id[1] = 1.0; e.g1[1] = K.c1;
+        e.out[2] = F2; e.ldo[2] = ldS; e.acc_c[2] = 1.0; e.id[2] = 1.0; e.g1[2] = K.c2;
+        e.D1 = R2; e.ld1 = ldS;
+        CHK(S.gemm<T>(eng, sd, sd, sd, R2, ldS, R2, ldS, e));
+    }
+    {   // M = F1 F2; T = M + c3 R2; S = M + d1 R2 + d2 R4
+        hp::EpilogueT<T> e{};
+        e.out[0] = Tm; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.c3;
+        e.out[1] = Sm; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.g1[1] = K.d1; e.g2[1] = K.d2;
+        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
+        CHK(S.gemm<T>(eng, sd, sd, sd, F1, ldS, F2, ldS, e));
+    }
+    {   // V = T S + mu R2 + psi R4
+        hp::EpilogueT<T> e{};
+        e.out[0] = V; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.mu; e.g2[0] = K.psi;
+        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
+        CHK(S.gemm<T>(eng, sd, sd, sd, Tm, ldS, Sm, ldS, e));
+    }
+    {   // W = (I + R) V = V + R V
+        hp::EpilogueT<T> e{};
+        e.out[0] = W; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = 1.0;
+        e.D1 = V; e.ld1 = ldS;
+        CHK(S.gemm<T>(eng, sd, sd, sd, R, ldS, V, ldS, e));
+    }
+    {   // update: X W (right) or W X (left)
+        hp::EpilogueT<T> e = hp::epilogue_plain(stab ? Xh : Xn, ldX);
+        if (!stab) {
+            e.ref = Xk; e.ldref = ldX; e.partials = partials;
+        }
+        if (S.pl.left) CHK(S.gemm<T>(eng, n, m, n, W, ldS, Xk, ldX, e));
+        else CHK(S.gemm<T>(eng, n, m, m, Xk, ldX, W, ldS, e));
+    }
+    if (stab) {
+        // X_{k+1} = X_{k+1/2} A X_{k+1/2}, associated so that the middle
+        // product is the smaller square
+        hp::EpilogueT<T> e = hp::epilogue_plain(Xn, ldX);
+        e.ref = Xk; e.ldref = ldX; e.partials = partials;
+        if (m >= n) {
+            CHK(S.gemm<T>(eng, n, n, m, Xh, ldX, b.A, ldA, hp::epilogue_plain(R, ldS)));
+            CHK(S.gemm<T>(eng, n, m, n, R, ldS, Xh, ldX, e));
+        } else {
+            CHK(S.gemm<T>(eng, m, m, n, b.A, ldA, Xh, ldX, hp::epilogue_plain(R, ldS)));
+            CHK(S.gemm<T>(eng, n, m, m, Xh, ldX, R, ldS, e));
+        }
+    }
+    return HP_OK;
+}
+
+constexpr double kUnitRoundoff[3] = {0.0, 5.960464477539063e-08, 1.1102230246251565e-16};
+
 int run_solve(Solver& S, const double* A, int64_t lda, const double* X0, int64_t ldx0, double* X,
               int64_t ldx) {
     const hp_params* p = S.p;
     const Plan& pl = S.pl;
     hipStream_t s = S.s;
     hp_result* res = S.res;
-    const int64_t m = pl.m, n = pl.n, sd = pl.s;
-    const PMConst K = pm_const();
+    const int64_t m = pl.m, n = pl.n;
 
-    double* Aw = S.ptr(pl.offA);
-    double* Xb[3] = {S.ptr(pl.offX[0]), S.ptr(pl.offX[1]), S.ptr(pl.offX[2])};
-    double* Sb[7];
-    for (int i = 0; i < 7; ++i) Sb[i] = S.ptr(pl.offS[i]);
-    double* small = S.ptr(pl.offSmall);
-    double* scal = S.ptr(pl.offScal);
+    Set<double> b64;
+    b64.A = S.ptr<double>(pl.offA);
+    for (int i = 0; i < pl.nX64; ++i) b64.X[i] = S.ptr<double>(pl.offX[i]);
+    for (int i = 0; i < pl.nS64; ++i) b64.S[i] = S.ptr<double>(pl.offS[i]);
+    b64.ldA = pl.ldA; b64.ldX = pl.ldX; b64.ldS = pl.ldS;
+    Set<float> b32;
+    if (pl.has32) {
+        b32.A = S.ptr<float>(pl.offA32);
+        for (int i = 0; i < pl.nX32; ++i) b32.X[i] = S.ptr<float>(pl.offX32[i]);
+        for (int i = 0; i < pl.nS32; ++i) b32.S[i] = S.ptr<float>(pl.offS32[i]);
+        b32.ldA = pl.ldA32; b32.ldX = pl.ldX32; b32.ldS = pl.ldS32;
+    }
+    double* small = S.ptr<double>(pl.offSmall);
+    double* scal = S.ptr<double>(pl.offScal);
     double* hs = S.h->host_scal;
     const int64_t ldA = pl.ldA, ldX = pl.ldX, ldS = pl.ldS;
 
     // A -> padded internal copy
-    HIPCHK(hipMemcpy2DAsync(Aw, ldA * sizeof(double), A, lda * sizeof(double), n * sizeof(double),
-                            m, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpy2DAsync(b64.A, ldA * sizeof(double), A, lda * sizeof(double),
+                            n * sizeof(double), m, hipMemcpyDeviceToDevice, s));
 
-    // ---- X0 (Section 4) ----
-    double* Xk = Xb[0];
-    double* Xn = Xb[1];
-    double* Xh = Xb[2];
+    // ---- X0 (Section 4), formed in FP64 ----
+    double* X0w = b64.X[0];
     double alpha = 0.0;
+    S.stage = 2;
     if (X0) {
-        HIPCHK(hipMemcpy2DAsync(Xk, ldX * sizeof(double), X0, ldx0 * sizeof(double),
+        HIPCHK(hipMemcpy2DAsync(X0w, ldX * sizeof(double), X0, ldx0 * sizeof(double),
                                 m * sizeof(double), n, hipMemcpyDeviceToDevice, s));
         alpha = p->alpha > 0.0 ? p->alpha : 1.0;
     } else {
@@ -240,22 +383,23 @@ int run_solve(Solver& S, const double* A, int64_t lda, const double* X0, int64_t
         }
         if (p->kind == HP_KIND_MOORE_PENROSE) {
             if (p->alpha_rule == HP_ALPHA_NORM1INF)
-                HIPCHK(hp::alpha_norm1inf(Aw, ldA, m, n, small, scal, s));
-            HIPCHK(hp::transpose_scale(Aw, ldA, m, n, Xk, ldX, scal + hp::SLOT_ALPHA, s));
+                HIPCHK(hp::alpha_norm1inf(b64.A, ldA, m, n, small, scal, s));
+            HIPCHK(hp::transpose_scale(b64.A, ldA, m, n, X0w, ldX, scal + hp::SLOT_ALPHA, s));
         } else {
             // G = A^l by repeated products, alpha = 1/Tr(A^{l+1}) = 1/Tr(A^l A)
-            const double* P = Aw;
+            const double* P = b64.A;
             int64_t ldp = ldA;
-            double* pp[2] = {Sb[0], Sb[1]};
+            double* pp[2] = {b64.S[0], b64.S[1]};
             for (int i = 1; i < p->drazin_l; ++i) {
                 double* dst = pp[i & 1];
-                CHK(S.gemm(n, n, n, P, ldp, Aw, ldA, hp::epilogue_plain(dst, ldS)));
+                CHK(S.gemm<double>(ENG_F64, n, n, n, P, ldp, b64.A, ldA,
+                                   hp::epilogue_plain(dst, ldS)));
                 P = dst;
                 ldp = ldS;
             }
             if (p->alpha_rule == HP_ALPHA_TRACE)
-                HIPCHK(hp::alpha_trace(P, ldp, Aw, ldA, n, small, scal, s));
-            HIPCHK(hp::scale(P, ldp, n, n, Xk, ldX, scal + hp::SLOT_ALPHA, s));
+                HIPCHK(hp::alpha_trace(P, ldp, b64.A, ldA, n, small, scal, s));
+            HIPCHK(hp::scale(P, ldp, n, n, X0w, ldX, scal + hp::SLOT_ALPHA, s));
         }
         HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * hp::SLOT_COUNT, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -264,102 +408,96 @@ int run_solve(Solver& S, const double* A, int64_t lda, const double* X0, int64_t
     }
     res->alpha = alpha;
 
-    // ---- the loop ----
+    // ---- stages ----
+    int stage = p->precision == HP_PREC_MIXED ? 0 : (p->precision == HP_PREC_FP32 ? 1 : 2);
+    const int final_stage = p->precision == HP_PREC_FP32 ? 1 : 2;
+    const Engine low_eng = p->low_dtype == HP_LOWP_F16 ? ENG_F16 : ENG_BF16;
+    // current iterate indices into the X sets
+    int ik = 0, in_ = 1;
+    if (stage < 2) {
+        HIPCHK(hp::convert(b64.A, ldA, m, n, b32.A, b32.ldA, s));
+        HIPCHK(hp::convert(X0w, ldX, n, m, b32.X[0], b32.ldX, s));
+    }
+
     const bool want_inf = (p->flags & HP_FLAG_INF_NORM) || p->stop_rule == HP_STOP_ABS_INF;
     bool stabilising = p->variant == HP_VARIANT_STAB_ALWAYS;
     res->switch_iter = stabilising ? 0 : -1;
     bool converging = false;
+    bool stage_first = true;  // no stagnation test on a stage's first loop
     double d_prev = 0.0;
     int status = HP_MAXITER;
-    double* result = nullptr;
-    double* R = Sb[0];
-    double* R2 = Sb[1];
-    double* R4 = Sb[2];
-    double* F1 = Sb[3];
-    double* F2 = Sb[4];
-    double* T = Sb[5];
-    double* Sm = Sb[6];
-    double* V = F1;  // F1, F2 are dead once T and S exist
-    double* W = F2;
+    int result_idx = -1;      // index into the final set's X buffers
 
     for (int k = 0; k < p->max_iter; ++k) {
-        // R = I - A X (right, m x m) or I - X A (left, n x n)
-        {
-            Epilogue e = hp::epilogue_plain(R, ldS, -1.0, 1.0);
-            if (pl.left) CHK(S.gemm(n, n, m, Xk, ldX, Aw, ldA, e));
-            else CHK(S.gemm(m, m, n, Aw, ldA, Xk, ldX, e));
-        }
-        CHK(S.gemm(sd, sd, sd, R, ldS, R, ldS, hp::epilogue_plain(R2, ldS)));
-        {   // R4 = R2 R2; F1 = I + c1 R2 + R4; F2 = I + c2 R2 + R4
-            Epilogue e{};
-            e.out[0] = R4; e.ldo[0] = ldS; e.acc_c[0] = 1.0;
-            e.out[1] = F1; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.id[1] = 1.0; e.g1[1] = K.c1;
-            e.out[2] = F2; e.ldo[2] = ldS; e.acc_c[2] = 1.0; e.id[2] = 1.0; e.g1[2] = K.c2;
-            e.D1 = R2; e.ld1 = ldS;
-            CHK(S.gemm(sd, sd, sd, R2, ldS, R2, ldS, e));
-        }
-        {   // M = F1 F2; T = M + c3 R2; S = M + d1 R2 + d2 R4
-            Epilogue e{};
-            e.out[0] = T; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.c3;
-            e.out[1] = Sm; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.g1[1] = K.d1; e.g2[1] = K.d2;
-            e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
-            CHK(S.gemm(sd, sd, sd, F1, ldS, F2, ldS, e));
-        }
-        {   // V = T S + mu R2 + psi R4
-            Epilogue e{};
-            e.out[0] = V; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.mu; e.g2[0] = K.psi;
-            e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
-            CHK(S.gemm(sd, sd, sd, T, ldS, Sm, ldS, e));
-        }
-        {   // W = (I + R) V = V + R V
-            Epilogue e{};
-            e.out[0] = W; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = 1.0;
-            e.D1 = V; e.ld1 = ldS;
-            CHK(S.gemm(sd, sd, sd, R, ldS, V, ldS, e));
-        }
-        // update: X W (right) or W X (left); partials of the stop test on the
-        // last product of the loop
-        double* upd = stabilising ? Xh : Xn;
-        {
-            Epilogue e = hp::epilogue_plain(upd, ldX);
-            if (!stabilising) {
-                e.ref = Xk; e.ldref = ldX; e.partials = small;
-            }
-            if (pl.left) CHK(S.gemm(n, m, n, W, ldS, Xk, ldX, e));
-            else CHK(S.gemm(n, m, m, Xk, ldX, W, ldS, e));
-        }
-        if (stabilising) {
-            // X_{k+1} = X_{k+1/2} A X_{k+1/2}, associated so that the middle
-            // product is the smaller square
-            Epilogue e = hp::epilogue_plain(Xn, ldX);
-            e.ref = Xk; e.ldref = ldX; e.partials = small;
-            if (m >= n) {
-                CHK(S.gemm(n, n, m, Xh, ldX, Aw, ldA, hp::epilogue_plain(R, ldS)));
-                CHK(S.gemm(n, m, n, R, ldS, Xh, ldX, e));
-            } else {
-                CHK(S.gemm(m, m, n, Aw, ldA, Xh, ldX, hp::epilogue_plain(R, ldS)));
-                CHK(S.gemm(n, m, m, Xh, ldX, R, ldS, e));
-            }
+        S.stage = stage;
+        if (stage == 2) {
+            CHK(pm_loop<double>(S, ENG_F64, b64, b64.X[ik], b64.X[in_], b64.X[2], stabilising, small));
+        } else {
+            CHK(pm_loop<float>(S, stage == 0 ? low_eng : ENG_F32, b32, b32.X[ik], b32.X[in_],
+                               b32.X[2], stabilising, small));
         }
         HIPCHK(hp::reduce_pairs(small, S.last_blocks, scal, s));
-        if (want_inf) HIPCHK(hp::diff_norm_inf(Xn, ldX, Xk, ldX, n, m, small, scal, s));
+        if (want_inf && stage == 2)
+            HIPCHK(hp::diff_norm_inf(b64.X[in_], ldX, b64.X[ik], ldX, n, m, small, scal, s));
         HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * hp::SLOT_COUNT, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         S.timer.harvest();
 
         res->iters = k + 1;
+        res->iters_stage[stage] += 1;
         const double diff2 = hs[hp::SLOT_DIFF2], ref2 = hs[hp::SLOT_REF2];
         const double d = std::sqrt(diff2) / std::sqrt(ref2);
         if (k < HP_HIST) res->d_hist[k] = d;
+        res->d_stage[stage] = d;
         double dinf = 0.0;
-        if (want_inf) {
+        if (want_inf && stage == 2) {
             dinf = hs[hp::SLOT_DINF];
             if (k < HP_HIST) res->dinf_hist[k] = dinf;
         }
         res->d_last = d;
-        if (!std::isfinite(d) || !std::isfinite(diff2) || (want_inf && !std::isfinite(dinf))) {
+        const bool finite = std::isfinite(d) && std::isfinite(diff2) && (!want_inf || std::isfinite(dinf));
+
+        if (stage != final_stage) {
+            // a lower stage ends when its change stops halving, reaches its
+            // rounding floor, or goes non-finite (16-bit overflow); the next
+            // stage continues from the better of the last two iterates
+            const double u = stage == 0 ? (p->low_dtype == HP_LOWP_F16 ? 4.8828125e-4 : 3.90625e-3)
+                                        : kUnitRoundoff[1];
+            const bool stalled = !stage_first && d < 1.0 && d >= 0.5 * d_prev;
+            const bool floor = d < 10.0 * u || d < p->tol;
+            if (d < p->tau_switch) {
+                converging = true;
+                if (p->variant == HP_VARIANT_STABILISED && !stabilising) {
+                    stabilising = true;
+                    res->switch_iter = k + 1;
+                }
+            }
+            if (!finite || stalled || floor) {
+                const bool keep_new = finite && !(stalled && d >= d_prev);
+                const int from = keep_new ? in_ : ik;
+                const int next = stage + 1;
+                if (next == 2) {
+                    HIPCHK(hp::convert(b32.X[from], b32.ldX, n, m, b64.X[0], ldX, s));
+                    ik = 0;
+                    in_ = 1;
+                } else {
+                    ik = from;
+                    in_ = from == 0 ? 1 : 0;
+                }
+                stage = next;
+                stage_first = true;
+                d_prev = d;
+                continue;
+            }
+            stage_first = false;
+            d_prev = d;
+            std::swap(ik, in_);
+            continue;
+        }
+
+        if (!finite) {
             status = HP_NONFINITE;
-            result = Xk;
+            result_idx = ik;
             break;
         }
         double sval;
@@ -377,17 +515,17 @@ int run_solve(Solver& S, const double* A, int64_t lda, const double* X0, int64_t
         res->stop_last = sval;
         if (passed) {
             status = HP_OK;
-            result = Xn;
+            result_idx = in_;
             break;
         }
-        if (converging && d >= d_prev) {
+        if (converging && !stage_first && d >= d_prev) {
             status = HP_STAGNATED;
-            result = Xk;
+            result_idx = ik;
             break;
         }
         if (!converging && d > p->diverge_limit) {
             status = HP_DIVERGED;
-            result = Xk;
+            result_idx = ik;
             break;
         }
         if (d < p->tau_switch) {
@@ -397,18 +535,23 @@ int run_solve(Solver& S, const double* A, int64_t lda, const double* X0, int64_t
                 res->switch_iter = k + 1;
             }
         }
+        stage_first = false;
         d_prev = d;
-        std::swap(Xk, Xn);
+        std::swap(ik, in_);
     }
-    if (!result) result = Xk;  // HP_MAXITER: the last iterate
+    if (result_idx < 0) result_idx = ik;  // HP_MAXITER: the last iterate
 
     const int it = std::min(res->iters, HP_HIST);
     if (want_inf && it >= 3) {
         const double e0 = res->dinf_hist[it - 3], e1 = res->dinf_hist[it - 2], e2 = res->dinf_hist[it - 1];
-        res->coc = std::log(e2 / e1) / std::log(e1 / e0);
+        if (e0 > 0 && e1 > 0 && e2 > 0) res->coc = std::log(e2 / e1) / std::log(e1 / e0);
     }
-    HIPCHK(hipMemcpy2DAsync(X, ldx * sizeof(double), result, ldX * sizeof(double),
-                            m * sizeof(double), n, hipMemcpyDeviceToDevice, s));
+    if (stage == 2) {
+        HIPCHK(hipMemcpy2DAsync(X, ldx * sizeof(double), b64.X[result_idx], ldX * sizeof(double),
+                                m * sizeof(double), n, hipMemcpyDeviceToDevice, s));
+    } else {
+        HIPCHK(hp::convert(b32.X[result_idx], b32.ldX, n, m, X, ldx, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
     return status;
 }
@@ -530,20 +673,31 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alp
             int64_t lda, const void* B, int64_t ldb, double beta_identity, void* C, int64_t ldc,
             void* stream) {
     if (!h || !A || !B || !C) return HP_EINVAL;
-    if (dtype != HP_DTYPE_F64) return HP_EINVAL;
+    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16_F32) return HP_EINVAL;
     if (M < 1 || N < 1 || K < 1 || M > (1 << 24) || N > (1 << 24) || K > (1 << 24)) return HP_EINVAL;
     if (lda < K || ldb < N || ldc < N) return HP_EINVAL;
-    if ((lda | ldb) & 1) return HP_EINVAL;
+    const int64_t vec = dtype == HP_DTYPE_F64 ? 2 : 4;  // elements per 16 bytes
+    if (lda % vec || ldb % vec) return HP_EINVAL;
     if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
          reinterpret_cast<uintptr_t>(C)) & 15)
         return HP_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
-    hp::Epilogue e = hp::epilogue_plain(static_cast<double*>(C), ldc, alpha, beta_identity);
     const hp::GemmTile t =
         h->forced_tile >= 0 ? (hp::GemmTile)h->forced_tile : hp::gemm_pick_tile(M, N, K);
-    if (hp::gemm(t, M, N, K, static_cast<const double*>(A), lda, static_cast<const double*>(B), ldb,
-                 e, reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
-        return HP_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (dtype == HP_DTYPE_F64) {
+        e = hp::gemm(t, M, N, K, static_cast<const double*>(A), lda, static_cast<const double*>(B),
+                     ldb, hp::epilogue_plain(static_cast<double*>(C), ldc, alpha, beta_identity), s);
+    } else if (dtype == HP_DTYPE_F32) {
+        e = hp::gemm(t, M, N, K, static_cast<const float*>(A), lda, static_cast<const float*>(B),
+                     ldb, hp::epilogue_plain(static_cast<float*>(C), ldc, alpha, beta_identity), s);
+    } else {
+        e = hp::gemm_lowp(t, dtype == HP_DTYPE_BF16_F32 ? hp::LOWP_BF16 : hp::LOWP_F16, M, N, K,
+                          static_cast<const float*>(A), lda, static_cast<const float*>(B), ldb,
+                          hp::epilogue_plain(static_cast<float*>(C), ldc, alpha, beta_identity), s);
+    }
+    if (e != hipSuccess) return HP_EHIP;
     return HP_OK;
 }
 

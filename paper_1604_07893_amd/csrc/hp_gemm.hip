@@ -254,6 +254,228 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm(
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// 16-bit MFMA GEMM on FP32 storage: C = epilogue(A * B) with A, B, C FP32 in
+// memory, the operands rounded to bf16 or fp16 (round to nearest even) while
+// they are staged into LDS, v_mfma_f32_16x16x32_{bf16,f16} with FP32
+// accumulation. Each lane's fragment is 8 consecutive k of one row (A) or one
+// column (B), so both operands are kept k-contiguous in LDS: A is written as
+// read; each thread transposes a 4x4 block of B in registers.
+// ---------------------------------------------------------------------------
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef float flt4v __attribute__((ext_vector_type(4)));
+
+template <typename L>
+struct Mfma16;
+template <>
+struct Mfma16<__bf16> {
+    typedef bf16x8 frag_t;
+    typedef bf16x4 quad_t;
+    static __device__ inline flt4 mma(frag_t a, frag_t b, flt4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma16<_Float16> {
+    typedef f16x8 frag_t;
+    typedef f16x4 quad_t;
+    static __device__ inline flt4 mma(frag_t a, frag_t b, flt4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <int BM, int BN, int BK, int WM, int WN>
+struct CfgLP {
+    static constexpr int WAVES = (BM / WM) * (BN / WN);
+    static constexpr int NT = 64 * WAVES;
+    static constexpr int KP = BK + 8;  // LDS row pitch (16-bit elements): 16 lanes at one k hit distinct banks
+    static constexpr int A_TPR = BK / 4;            // float4 loads per A row
+    static constexpr int A_RPP = NT / A_TPR;
+    static constexpr int A_PASS = BM / A_RPP;
+    static constexpr int B_POS = (BK / 4) * (BN / 4);  // 4x4 blocks of B
+    static constexpr int B_PASS = B_POS / NT;
+    static constexpr int TI = WM / 16, TJ = WN / 16;
+    static_assert(BK % 32 == 0, "K tile");
+    static_assert((BN / 4) % 8 == 0, "B blocks");
+    // 4x4 block `pos` of the B tile -> (column quad nq, k quad kq): runs of 8
+    // lanes read 128 contiguous bytes of one row; the next lanes step in k so
+    // the transposed 8-byte LDS writes spread over the banks.
+    static __device__ inline void b_pos(int pos, int& nq, int& kq) {
+        const int lo = pos % 8, rest = pos / 8;
+        kq = rest % (BK / 4);
+        nq = (rest / (BK / 4)) * 8 + lo;
+    }
+    static_assert(NT % A_TPR == 0 && BM % A_RPP == 0 && A_PASS >= 1, "A loads");
+    static_assert(B_POS % NT == 0 && B_PASS >= 1, "B loads");
+};
+
+template <typename L, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_lp(
+    int M, int N, int K, const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+    int64_t ldb, EpilogueT<float> ep, int tiles_m, int tiles_n) {
+    using C = CfgLP<BM, BN, BK, WM, WN>;
+    using FR = typename Mfma16<L>::frag_t;
+    using QD = typename Mfma16<L>::quad_t;
+    __shared__ __attribute__((aligned(16))) L As[2][BM][C::KP];
+    __shared__ __attribute__((aligned(16))) L Bs[2][BN][C::KP];
+    __shared__ double red[2][C::WAVES];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int tm, tn;
+    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    const int bm = tm * BM, bn = tn * BN;
+    const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
+
+    const int a_k = 4 * (tid % C::A_TPR), a_r = tid / C::A_TPR;
+    flt4v ra[C::A_PASS];
+    flt4v rb[C::B_PASS][4];
+
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < C::A_PASS; ++p) {
+            const int row = bm + a_r + C::A_RPP * p, k = k0 + a_k;
+            flt4v v = {0.f, 0.f, 0.f, 0.f};
+            if (row < M && k < K) {
+                v = *reinterpret_cast<const flt4v*>(A + (int64_t)row * lda + k);
+#pragma unroll
+                for (int e = 1; e < 4; ++e)
+                    if (k + e >= K) v[e] = 0.f;
+            }
+            ra[p] = v;
+        }
+#pragma unroll
+        for (int p = 0; p < C::B_PASS; ++p) {
+            int nq, kq;
+            C::b_pos(tid + C::NT * p, nq, kq);
+            const int c = bn + 4 * nq;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int kr = k0 + 4 * kq + r;
+                flt4v v = {0.f, 0.f, 0.f, 0.f};
+                if (kr < K && c < N) {
+                    v = *reinterpret_cast<const flt4v*>(B + (int64_t)kr * ldb + c);
+#pragma unroll
+                    for (int e = 1; e < 4; ++e)
+                        if (c + e >= N) v[e] = 0.f;
+                }
+                rb[p][r] = v;
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < C::A_PASS; ++p) {
+            QD q;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) q[e] = (L)ra[p][e];
+            *reinterpret_cast<QD*>(&As[buf][a_r + C::A_RPP * p][a_k]) = q;
+        }
+#pragma unroll
+        for (int p = 0; p < C::B_PASS; ++p) {
+            int nq, kq;
+            C::b_pos(tid + C::NT * p, nq, kq);
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                QD q;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) q[r] = (L)rb[p][r][cc];
+                *reinterpret_cast<QD*>(&Bs[buf][4 * nq + cc][4 * kq]) = q;
+            }
+        }
+    };
+
+    flt4 acc[C::TI][C::TJ];
+#pragma unroll
+    for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TJ; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    const int nk = (K + BK - 1) / BK;
+    load(0);
+    store(0);
+    __syncthreads();
+    const int fr = lane & 15, fg = lane >> 4;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 32) {
+            FR a[C::TI], b[C::TJ];
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i)
+                a[i] = *reinterpret_cast<const FR*>(&As[cur][wm + i * 16 + fr][ks + 8 * fg]);
+#pragma unroll
+            for (int j = 0; j < C::TJ; ++j)
+                b[j] = *reinterpret_cast<const FR*>(&Bs[cur][wn + j * 16 + fr][ks + 8 * fg]);
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < C::TJ; ++j) acc[i][j] = Mfma16<L>::mma(a[i], b[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) store(cur ^ 1);
+        __syncthreads();
+    }
+
+    double s_diff = 0.0, s_ref = 0.0;
+#pragma unroll
+    for (int i = 0; i < C::TI; ++i) {
+#pragma unroll
+        for (int j = 0; j < C::TJ; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = bm + wm + i * 16 + 4 * fg + r;
+                const int col = bn + wn + j * 16 + fr;
+                if (row < M && col < N) {
+                    const float a = acc[i][j][r];
+                    const float d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : 0.f;
+                    const float d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : 0.f;
+                    const float idv = (row == col) ? 1.f : 0.f;
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) {
+                        if (ep.out[o]) {
+                            float v = (float)ep.acc_c[o] * a;
+                            if (ep.id[o] != 0.0) v += (float)ep.id[o] * idv;
+                            if (ep.g1[o] != 0.0) v += (float)ep.g1[o] * d1;
+                            if (ep.g2[o] != 0.0) v += (float)ep.g2[o] * d2;
+                            ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
+                            if (o == 0 && ep.ref) {
+                                const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];
+                                const double df = (double)v - x0;
+                                s_diff += df * df;
+                                s_ref += x0 * x0;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (ep.ref) {
+        const double sd = wave_sum(s_diff), sr = wave_sum(s_ref);
+        if (lane == 0) {
+            red[0][wave] = sd;
+            red[1][wave] = sr;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < C::WAVES; ++w) {
+                a += red[0][w];
+                b += red[1][w];
+            }
+            ep.partials[2 * blockIdx.x] = a;
+            ep.partials[2 * blockIdx.x + 1] = b;
+        }
+    }
+}
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN>
@@ -292,7 +514,37 @@ hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int
     }
 }
 
+template <typename L, int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_lp(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                     int64_t ldb, const EpilogueT<float>& ep, hipStream_t s) {
+    using C = CfgLP<BM, BN, BK, WM, WN>;
+    const int tm = (int)cdiv(M, BM), tn = (int)cdiv(N, BN);
+    hipLaunchKernelGGL((k_gemm_lp<L, BM, BN, BK, WM, WN>), dim3(tm * tn), dim3(C::NT), 0, s,
+                       (int)M, (int)N, (int)K, A, lda, B, ldb, ep, tm, tn);
+    return hipGetLastError();
+}
+
+template <typename L>
+hipError_t dispatch_lp(GemmTile t, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, const EpilogueT<float>& ep, hipStream_t s) {
+    switch (t) {
+        case TILE_128x128_W4: return launch_lp<L, 128, 128, 64, 64, 64>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W8: return launch_lp<L, 128, 128, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x64_W4: return launch_lp<L, 128, 64, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_64x64_W4: return launch_lp<L, 64, 64, 64, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_256x128_W8: return launch_lp<L, 256, 128, 64, 64, 64>(M, N, K, A, lda, B, ldb, ep, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+hipError_t gemm_lowp(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, const float* A,
+                     int64_t lda, const float* B, int64_t ldb, const EpilogueT<float>& ep,
+                     hipStream_t s) {
+    if (lp == LOWP_BF16) return dispatch_lp<__bf16>(t, M, N, K, A, lda, B, ldb, ep, s);
+    return dispatch_lp<_Float16>(t, M, N, K, A, lda, B, ldb, ep, s);
+}
 
 int gemm_blocks(GemmTile t, int64_t M, int64_t N) {
     const TileShape sh = kShapes[(int)t];

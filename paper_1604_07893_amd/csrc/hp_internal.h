@@ -78,6 +78,13 @@ hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const double* A, in
 hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                 const float* B, int64_t ldb, const EpilogueT<float>& ep, hipStream_t s);
 
+// 16-bit MFMA product of FP32 matrices (operands rounded to nearest even while
+// staged, FP32 accumulation); lda/ldb multiples of 4 floats.
+enum LowPrec : int { LOWP_BF16 = 0, LOWP_F16 = 1 };
+hipError_t gemm_lowp(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, const float* A,
+                     int64_t lda, const float* B, int64_t ldb, const EpilogueT<float>& ep,
+                     hipStream_t s);
+
 // ||A||_1 and ||A||_inf of an M x N matrix, then scal[SLOT_ALPHA] =
 // 1/(||A||_1 ||A||_inf). `tmp` needs (ceil(M/256)+1)*N + M doubles.
 hipError_t alpha_norm1inf(const double* A, int64_t lda, int64_t M, int64_t N, double* tmp,
@@ -105,5 +112,12 @@ hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipSt
 // scal[SLOT_DINF] = max_i sum_j |X1[i][j] - X0[i][j]|. `tmp` needs M doubles.
 hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_t ld0,
                          int64_t M, int64_t N, double* tmp, double* scal, hipStream_t s);
+
+// Y = X elementwise with a change of precision (M x N; narrowing rounds to
+// nearest even).
+hipError_t convert(const double* X, int64_t ldx, int64_t M, int64_t N, float* Y, int64_t ldy,
+                   hipStream_t s);
+hipError_t convert(const float* X, int64_t ldx, int64_t M, int64_t N, double* Y, int64_t ldy,
+                   hipStream_t s);
 
 }  // namespace hp

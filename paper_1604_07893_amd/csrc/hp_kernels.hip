@@ -207,6 +207,16 @@ __global__ __launch_bounds__(kThreads) void k_max_to_slot(const double* __restri
     if (threadIdx.x == 0) scal[slot] = any_nan ? __builtin_nan("") : r;
 }
 
+// Elementwise precision conversion of an M x N matrix (round to nearest even
+// when narrowing).
+template <typename S, typename D>
+__global__ __launch_bounds__(kThreads) void k_convert(const S* __restrict__ X, int64_t ldx, int M,
+                                                      int N, D* __restrict__ Y, int64_t ldy) {
+    const int r = blockIdx.y;
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < N; c += gridDim.x * kThreads)
+        Y[(int64_t)r * ldy + c] = (D)X[(int64_t)r * ldx + c];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -266,6 +276,29 @@ hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_
                        (int)N, tmp);
     hipLaunchKernelGGL(k_max_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal, (int)SLOT_DINF);
     return hipGetLastError();
+}
+
+}  // namespace hp
+
+namespace hp {
+
+template <typename S, typename D>
+static hipError_t convert_impl(const S* X, int64_t ldx, int64_t M, int64_t N, D* Y, int64_t ldy,
+                               hipStream_t s) {
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N, kThreads), 16);
+    hipLaunchKernelGGL((k_convert<S, D>), dim3(gx, (unsigned)M), dim3(kThreads), 0, s, X, ldx,
+                       (int)M, (int)N, Y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t convert(const double* X, int64_t ldx, int64_t M, int64_t N, float* Y, int64_t ldy,
+                   hipStream_t s) {
+    return convert_impl(X, ldx, M, N, Y, ldy, s);
+}
+
+hipError_t convert(const float* X, int64_t ldx, int64_t M, int64_t N, double* Y, int64_t ldy,
+                   hipStream_t s) {
+    return convert_impl(X, ldx, M, N, Y, ldy, s);
 }
 
 }  // namespace hp

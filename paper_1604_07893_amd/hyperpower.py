@@ -29,9 +29,10 @@ ALPHA = {"norm1inf": 0, "user": 1, "trace": 2}
 VARIANT = {"plain": 0, "stabilised": 1, "stabilized": 1, "stab_always": 2}
 SIDE = {"auto": 0, "right": 1, "left": 2}
 STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2}
-PREC = {"fp64": 0}
+PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
+LOWP = {"bf16": 0, "f16": 1, "fp16": 1}
 FLAG_TIME_KERNELS, FLAG_INF_NORM = 1, 2
-DTYPE = {torch.float64: 0}
+DTYPE = {torch.float64: 0, torch.float32: 1}
 HP_HIST = 128
 
 
@@ -40,16 +41,17 @@ class HpParams(ctypes.Structure):
         ("kind", c_int32), ("drazin_l", c_int32), ("alpha_rule", c_int32), ("variant", c_int32),
         ("alpha", c_double), ("tau_switch", c_double), ("tol", c_double), ("diverge_limit", c_double),
         ("max_iter", c_int32), ("stop_rule", c_int32), ("side", c_int32), ("precision", c_int32),
-        ("flags", c_int32), ("reserved", c_int32 * 7),
+        ("flags", c_int32), ("low_dtype", c_int32), ("reserved", c_int32 * 6),
     ]
 
 
 class HpResult(ctypes.Structure):
     _fields_ = [
         ("status", c_int32), ("iters", c_int32), ("switch_iter", c_int32), ("side_used", c_int32),
-        ("gemms", c_int32), ("reserved0", c_int32 * 3),
+        ("gemms", c_int32), ("iters_stage", c_int32 * 3),
         ("alpha", c_double), ("d_last", c_double), ("stop_last", c_double), ("coc", c_double),
         ("gflop", c_double), ("time_ms", c_double), ("gemm_ms", c_double),
+        ("d_stage", c_double * 3), ("gflop_stage", c_double * 3),
         ("d_hist", c_double * HP_HIST), ("dinf_hist", c_double * HP_HIST),
     ]
 
@@ -131,7 +133,8 @@ def handle(device: int | None = None) -> Handle:
 
 def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", tau_switch=0.1,
                 tol=1e-12, max_iter=100, stop="rel_fro", side="auto", precision="fp64",
-                diverge_limit=1e6, time_kernels=False, inf_norm=False) -> HpParams:
+                diverge_limit=1e6, time_kernels=False, inf_norm=False,
+                low_dtype="bf16") -> HpParams:
     p = HpParams()
     load_library().hp_params_default(ctypes.byref(p))
     p.kind = KIND[kind]
@@ -147,6 +150,7 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
     p.stop_rule = STOP[stop]
     p.side = SIDE[side]
     p.precision = PREC[precision]
+    p.low_dtype = LOWP[low_dtype]
     p.diverge_limit = float(diverge_limit)
     p.flags = (FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
     return p
@@ -177,6 +181,8 @@ def result_dict(r: HpResult) -> dict:
         "side": {1: "right", 2: "left"}.get(r.side_used, "?"), "gemms": r.gemms,
         "alpha": r.alpha, "d_last": r.d_last, "stop_last": r.stop_last, "coc": r.coc,
         "gflop": r.gflop, "time_ms": r.time_ms, "gemm_ms": r.gemm_ms,
+        "iters_stage": list(r.iters_stage), "d_stage": list(r.d_stage),
+        "gflop_stage": list(r.gflop_stage),
         "d_hist": list(r.d_hist[:it]), "dinf_hist": list(r.dinf_hist[:it]),
     }
 
@@ -227,10 +233,18 @@ def drazin(A: torch.Tensor, l: int, **kw) -> tuple[torch.Tensor, dict]:
 
 
 def gemm(A: torch.Tensor, B: torch.Tensor, *, alpha: float = 1.0, beta_identity: float = 0.0,
-         out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None) -> torch.Tensor:
-    """C = alpha A B + beta_identity I on the library's MFMA GEMM kernel."""
+         out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
+         operands: str | None = None) -> torch.Tensor:
+    """C = alpha A B + beta_identity I on the library's MFMA GEMM kernel.
+    operands: None (the tensors' type), or "bf16" / "f16" for float32 tensors
+    whose products run on 16-bit MFMA with FP32 accumulation."""
     if A.dtype != B.dtype or A.dtype not in DTYPE:
         raise ValueError("unsupported dtype")
+    code = DTYPE[A.dtype]
+    if operands is not None:
+        if A.dtype != torch.float32:
+            raise ValueError("16-bit operands need float32 tensors")
+        code = {"bf16": 2, "f16": 3}[operands]
     for t, nm in ((A, "A"), (B, "B")):
         if not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
             raise ValueError(f"{nm} must be a row-major device matrix")
@@ -242,7 +256,7 @@ def gemm(A: torch.Tensor, B: torch.Tensor, *, alpha: float = 1.0, beta_identity:
         out = torch.empty((M, N), dtype=A.dtype, device=A.device)
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
     dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
-    rc = load_library().hp_gemm(handle(dev).ptr, DTYPE[A.dtype], M, N, K, alpha, A.data_ptr(),
+    rc = load_library().hp_gemm(handle(dev).ptr, code, M, N, K, alpha, A.data_ptr(),
                                 A.stride(0), B.data_ptr(), B.stride(0), beta_identity,
                                 out.data_ptr(), out.stride(0), s.cuda_stream)
     if rc != HP_OK:

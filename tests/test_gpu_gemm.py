@@ -74,3 +74,49 @@ def test_gemm_rejects_bad_arguments():
     B = torch.zeros((9, 8), dtype=torch.float64, device="cuda:0")
     with pytest.raises(hpw.HyperpowerError):
         hpw.gemm(A, B)
+
+
+@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (127, 129, 17), (333, 444, 555), (64, 2048, 96)])
+def test_gemm_f32_matches_numpy(M, N, K):
+    hpw = need_gpu()
+    say(f"gemm f32 M={M} N={N} K={K}")
+    rng = np.random.default_rng(M + 5 * N + 11 * K)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    pad = lambda c: (c + 3) // 4 * 4
+    Ad = torch.zeros((M, pad(K)), dtype=torch.float32, device="cuda:0")
+    Bd = torch.zeros((K, pad(N)), dtype=torch.float32, device="cuda:0")
+    Ad[:, :K] = torch.from_numpy(A).cuda()
+    Bd[:, :N] = torch.from_numpy(B).cuda()
+    C = hpw.gemm(Ad[:, :K], Bd[:, :N])
+    torch.cuda.synchronize()
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    bound = (np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64)) * (2 * K + 4) * 2.0**-24
+    err = np.abs(C.cpu().numpy().astype(np.float64) - ref)
+    assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
+
+
+@pytest.mark.parametrize("operands", ["bf16", "f16"])
+@pytest.mark.parametrize("M,N,K", [(16, 16, 32), (127, 129, 17), (333, 444, 555), (256, 256, 1024)])
+def test_gemm_16bit_operands_match_rounded_product(operands, M, N, K):
+    """FP32 storage, operands rounded to bf16/fp16 (nearest even), FP32
+    accumulation: compare with the FP64 product of the rounded operands."""
+    hpw = need_gpu()
+    say(f"gemm {operands} M={M} N={N} K={K}")
+    rng = np.random.default_rng(M + 3 * N + 7 * K)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    pad = lambda c: (c + 3) // 4 * 4
+    Ad = torch.zeros((M, pad(K)), dtype=torch.float32, device="cuda:0")
+    Bd = torch.zeros((K, pad(N)), dtype=torch.float32, device="cuda:0")
+    Ad[:, :K] = torch.from_numpy(A).cuda()
+    Bd[:, :N] = torch.from_numpy(B).cuda()
+    C = hpw.gemm(Ad[:, :K], Bd[:, :N], operands=operands)
+    torch.cuda.synchronize()
+    tdt = torch.bfloat16 if operands == "bf16" else torch.float16
+    Ar = torch.from_numpy(A).to(tdt).double().numpy()
+    Br = torch.from_numpy(B).to(tdt).double().numpy()
+    ref = Ar @ Br
+    bound = (np.abs(Ar) @ np.abs(Br)) * (2 * K + 4) * 2.0**-24
+    err = np.abs(C.cpu().numpy().astype(np.float64) - ref)
+    assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())

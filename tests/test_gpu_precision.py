@@ -1,0 +1,89 @@
+"""Precision modes: FP32 loops, and mixed 16-bit -> FP32 -> FP64 stages, against
+the FP64 oracle (the result the FP64 iteration converges to) and closed forms."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_common import need_gpu, rel, say, to_dev
+from paper_1604_07893_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def run(A, **kw):
+    hpw = need_gpu()
+    X, info = hpw.solve(to_dev(A), **kw)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), info
+
+
+def test_fp32_mode_reaches_single_precision_accuracy():
+    say("fp32 mode 200x100")
+    A = inputs.uniform(200, 100, seed=1001)
+    ref = O.solve(A, kind="mp", tol=1e-12)
+    X, info = run(A, precision="fp32", tol=1e-6)
+    kappa = np.linalg.cond(A)
+    assert info["status"] in ("ok", "stagnated")
+    assert info["iters_stage"] == [0, info["iters"], 0]
+    assert rel(X, ref.X) <= 50 * kappa * 6e-8
+
+
+@pytest.mark.parametrize("low", ["bf16", "f16"])
+def test_mixed_square_matches_fp64_oracle(low):
+    """Square nonsingular 384x384, s log-uniform in [1e-3, 1]: 16-bit loops,
+    FP32 loops, FP64 loops; the result matches the FP64 oracle to 1e-10."""
+    say(f"mixed {low} 384")
+    d = inputs.square_svd(384, smin=1e-3, seed=31)
+    ref = O.solve(d.A, kind="mp", alpha_rule="user", alpha=1.0, tol=1e-12)
+    closed = (d.V / d.s) @ d.U.T
+    X, info = run(d.A, precision="mixed", low_dtype=low, alpha_rule="user", alpha=1.0, tol=1e-12)
+    say(f"  stages {info['iters_stage']} d_stage {info['d_stage']}")
+    assert info["status"] == "ok"
+    assert all(c >= 1 for c in info["iters_stage"])
+    assert rel(X, ref.X) <= 1e-10
+    assert rel(X, closed) <= 1e-10
+    # the 16-bit and FP32 stages did most of the loops
+    assert info["iters_stage"][2] <= 3
+
+
+def test_mixed_error_per_stage_decreases():
+    """Stopping after each stage (max_iter at the stage boundary) gives the
+    per-stage error against the FP64 oracle; it falls stage by stage."""
+    d = inputs.square_svd(256, smin=1e-3, seed=32)
+    ref = O.solve(d.A, kind="mp", alpha_rule="user", alpha=1.0, tol=1e-12)
+    kw = dict(precision="mixed", alpha_rule="user", alpha=1.0, tol=1e-12)
+    _, full = run(d.A, **kw)
+    s0, s1, s2 = full["iters_stage"]
+    errs = []
+    for cap in (s0, s0 + s1, s0 + s1 + s2):
+        X, info = run(d.A, max_iter=cap, **kw)
+        errs.append(rel(X, ref.X))
+    say(f"  per-stage error {errs}")
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] <= 1e-4 and errs[2] <= 1e-10
+
+
+def test_mixed_drazin():
+    d = inputs.drazin_jordan(n=160, nb=140, cond_p=10.0, seed=33)
+    nb = d.Q.shape[0]
+    J = np.zeros_like(d.A)
+    J[:nb, :nb] = (d.Q / d.lam) @ d.Q.T
+    closed = d.P @ J @ d.Pinv
+    X, info = run(d.A, kind="drazin", l=3, variant="stabilised", precision="mixed", tol=1e-10)
+    say(f"  drazin mixed stages {info['iters_stage']} status {info['status']}")
+    assert info["status"] in ("ok", "stagnated")
+    assert rel(X, closed) <= 1e-9
+
+
+def test_fp32_rank_deficient_stabilised_stagnates_at_its_floor():
+    """FP32 cannot reach 1e-10 on a kappa=1e4 rank-deficient input; the
+    stabilised FP32 run ends at its floor without blowing up."""
+    d = inputs.lowrank_svd(320, 160, 120, smin=1e-4, seed=12)
+    closed = (d.V / d.s) @ d.U.T
+    X, info = run(d.A, alpha_rule="user", alpha=1.0, variant="stabilised", precision="fp32",
+                  tol=1e-10)
+    assert info["status"] in ("stagnated", "ok")
+    assert np.all(np.isfinite(X))
+    assert rel(X, closed) <= 1e-1
