@@ -92,6 +92,8 @@ extern "C" {
 #define HP_PREC_FP32 1  /* every loop in FP32 storage and FP32 MFMA; the stop
                            sums in FP64; X returned in FP64. Reaches about
                            kappa(A) * 6e-8, not an FP64 tolerance. */
+#define HP_PREC_FP32_FP64 3 /* stage 1 (FP32) then stage 2 (FP64): HP_PREC_MIXED
+                               without the 16-bit stage */
 #define HP_PREC_MIXED 2 /* stage 0: 16-bit MFMA products (hp_params.low_dtype)
                            on FP32 storage with FP32 accumulation; stage 1:
                            FP32; stage 2: FP64 loops until the stop test
@@ -155,6 +157,8 @@ typedef struct hp_result {
     double gemm_ms;        /* summed GEMM kernel time (HP_FLAG_TIME_KERNELS) */
     double d_stage[3];     /* last relative change in each stage */
     double gflop_stage[3]; /* executed GEMM work per stage (set-up in stage 2) */
+    double queue_ms;       /* served requests: submit -> admission */
+    double run_ms;         /* served requests: admission -> result written */
     double d_hist[HP_HIST];    /* relative Frobenius change per loop */
     double dinf_hist[HP_HIST]; /* inf-norm change per loop (HP_FLAG_INF_NORM) */
 } hp_result;
@@ -208,6 +212,55 @@ int hp_solve(hp_handle* h, const hp_params* p,
 int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
             double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
             double beta_identity, void* C, int64_t ldc, void* stream);
+
+/* ---- many problems: batched and served forms --------------------------- */
+
+/* One matrix of a batch or one served request. A (m x n, lda) and the
+ * optional X0 (n x m, ldx0) are read-only device memory; X (n x m, ldx) is
+ * written when the problem finishes. All three stay owned by the caller and
+ * must stay valid until then. */
+typedef struct hp_problem {
+    const double* A;
+    int64_t m, n, lda;
+    const double* X0;
+    int64_t ldx0;
+    double* X;
+    int64_t ldx;
+} hp_problem;
+
+/* Workspace for hp_solve_batched over these problems. */
+int hp_batched_workspace_bytes(const hp_params* p, int count, const hp_problem* probs,
+                               size_t* bytes);
+
+/* Solve `count` problems of uneven shapes with the same params. Every loop
+ * runs each product of all unfinished problems in one persistent grouped MFMA
+ * launch (64x64 tiles walked from a device-side table); each problem stops on
+ * its own test. A problem's result is bitwise the same whatever else is in
+ * the batch. Precision HP_PREC_FP64, HP_PREC_FP32 or HP_PREC_FP32_FP64;
+ * stop rules REL_FRO and PAPER_4_1. outs: `count` results (may be NULL).
+ * Returns HP_OK if the call ran (see each outs[i].status), else an error. */
+int hp_solve_batched(hp_handle* h, const hp_params* p, int count, const hp_problem* probs,
+                     void* workspace, size_t ws_bytes, void* stream, hp_result* outs);
+
+/* Continuous-batching server. Requests are queued by hp_serve_submit and
+ * admitted in arrival order while a slot is free and their workspace fits in
+ * the server's HBM budget (allocated once here); each hp_serve_step admits
+ * what fits, runs one loop of every admitted request (grouped launches as in
+ * hp_solve_batched, so a request's result does not depend on its neighbours),
+ * and retires the requests that finished, writing their X and freeing their
+ * memory. Not thread-safe. */
+typedef struct hp_server hp_server;
+int hp_serve_create(hp_handle* h, const hp_params* p, size_t hbm_budget, int max_slots,
+                    void* stream, hp_server** out);
+/* HP_EBUDGET if the request alone exceeds the budget, HP_EINVAL for a bad
+ * shape; otherwise queues it and returns a ticket. */
+int hp_serve_submit(hp_server* sv, const hp_problem* prob, uint64_t* ticket);
+/* One scheduling step; reports the requests running and waiting after it. */
+int hp_serve_step(hp_server* sv, int* active, int* waiting);
+/* HP_PENDING while the request is queued or running; afterwards its final
+ * status (out filled, ticket released). HP_EINVAL for an unknown ticket. */
+int hp_serve_poll(hp_server* sv, uint64_t ticket, hp_result* out);
+int hp_serve_destroy(hp_server* sv);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,503 @@
+// Batched and served forms of the hyperpower iteration.
+//
+// A group holds problems of uneven shapes, each with its own workspace and
+// its own host-side loop state. One group loop runs, for every product of the
+// loop of (PM) (Section 2) -- and of (PM-modified) (Section 7) for problems
+// past the switch -- a single persistent grouped MFMA launch over all
+// unfinished problems, then one fixed-order reduction per problem, one copy of
+// all stopping sums to the host and each problem's own stop/switch/stage
+// decision. Per-tile arithmetic never depends on the other entries of a
+// table, so a problem's result is the same alone or in any mix.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <vector>
+
+#include "hp_host.h"
+
+namespace hp {
+
+// fixed-order per-problem sum of partial pairs (hp_kernels.hip)
+struct ReduceEntry {
+    const double* partials;
+    int npairs;
+    int pad;
+};
+hipError_t reduce_pairs_grouped(const ReduceEntry* ents, int count, double* out, hipStream_t s);
+
+}  // namespace hp
+
+namespace {
+
+using namespace hp;
+using Clock = std::chrono::steady_clock;
+
+inline double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+constexpr int kSlots = 9;  // products per loop at most (7 plain + 2 stabilising)
+
+struct Problem {
+    hp_problem pr{};
+    Plan pl;
+    Buffers bf;
+    char* ws = nullptr;
+    size_t ws_off = 0, ws_bytes = 0;  // arena placement (server)
+    LoopState st;
+    hp_result res{};
+    int last_tiles = 0;
+    bool finished = false;
+    Clock::time_point t_submit, t_admit, t_finish;
+};
+
+// Device tables of a group: for every product slot and precision a header
+// and up to `cap` entries, then the reduction table and its output; mirrored
+// by a pinned host staging area that is copied over once per loop.
+struct Tables {
+    int cap = 0;
+    size_t bytes = 0;
+    size_t off_hdr[2][kSlots] = {};
+    size_t off_ent[2][kSlots] = {};
+    size_t off_red = 0, off_out = 0;
+    char* dev = nullptr;
+    char* host = nullptr;
+
+    static size_t layout(int cap, Tables* t) {
+        size_t off = 0;
+        for (int prec = 0; prec < 2; ++prec) {
+            const size_t esz = prec == 0 ? sizeof(GroupEntry<double>) : sizeof(GroupEntry<float>);
+            for (int j = 0; j < kSlots; ++j) {
+                if (t) t->off_hdr[prec][j] = off;
+                off = align_up(off + sizeof(GroupHeader));
+                if (t) t->off_ent[prec][j] = off;
+                off = align_up(off + esz * (size_t)cap);
+            }
+        }
+        if (t) t->off_red = off;
+        off = align_up(off + sizeof(ReduceEntry) * (size_t)cap);
+        if (t) t->off_out = off;
+        off = align_up(off + 2 * sizeof(double) * (size_t)cap);
+        return off;
+    }
+};
+
+struct Group {
+    hp_handle* h = nullptr;
+    hp_params prm{};
+    hipStream_t s = nullptr;
+    Tables tb;
+    int grid = 1024;  // persistent grid of the grouped launches
+};
+
+// Products outside the loop (Drazin set-up, projection) run as single
+// launches on the problem's own shapes.
+auto single_gemm(Group& g, Problem& P) {
+    return [&g, &P](const GemmCall<double>& c) {
+        const GemmTile t = gemm_pick_tile(c.M, c.N, c.K);
+        if (hp::gemm(t, c.M, c.N, c.K, c.A, c.lda, c.B, c.ldb, c.ep, g.s) != hipSuccess) return HP_EHIP;
+        const double gf = 2.0 * (double)c.M * (double)c.N * (double)c.K * 1e-9;
+        P.res.gflop += gf;
+        P.res.gflop_stage[2] += gf;
+        P.res.gemms += 1;
+        return HP_OK;
+    };
+}
+
+int admit(Group& g, Problem& P) {
+    P.bf = carve(P.pl, P.ws);
+    std::memset(&P.res, 0, sizeof(P.res));
+    P.res.switch_iter = -1;
+    P.res.side_used = P.pl.left ? HP_SIDE_LEFT : HP_SIDE_RIGHT;
+    double alpha = 0.0;
+    CHK(setup_x0(&g.prm, P.pl, P.bf, P.pr.A, P.pr.lda, P.pr.X0, P.pr.ldx0, g.h->host_scal, g.s,
+                 single_gemm(g, P), &alpha));
+    P.res.alpha = alpha;
+    P.st.init(&g.prm, &P.res, alpha);
+    if (P.st.stage < 2) {
+        HIPCHK(convert(P.bf.b64.A, P.bf.b64.ldA, P.pl.m, P.pl.n, P.bf.b32.A, P.bf.b32.ldA, g.s));
+        HIPCHK(convert(P.bf.b64.X[0], P.bf.b64.ldX, P.pl.n, P.pl.m, P.bf.b32.X[0], P.bf.b32.ldX, g.s));
+    }
+    P.finished = false;
+    return HP_OK;
+}
+
+template <typename T>
+void append(Tables& tb, int prec, int slot, const GemmCall<T>& c, int* tiles_out) {
+    GroupHeader* hdr = reinterpret_cast<GroupHeader*>(tb.host + tb.off_hdr[prec][slot]);
+    GroupEntry<T>* ents = reinterpret_cast<GroupEntry<T>*>(tb.host + tb.off_ent[prec][slot]);
+    const int tn = (int)cdiv(c.N, grouped_tile_n()), tm = (int)cdiv(c.M, grouped_tile_m());
+    GroupEntry<T>& e = ents[hdr->count];
+    e.M = (int)c.M;
+    e.N = (int)c.N;
+    e.K = (int)c.K;
+    e.tiles_n = tn;
+    e.tile_start = hdr->total_tiles;
+    e.pad = 0;
+    e.A = c.A;
+    e.lda = c.lda;
+    e.B = c.B;
+    e.ldb = c.ldb;
+    e.ep = c.ep;
+    hdr->count += 1;
+    hdr->total_tiles += tm * tn;
+    *tiles_out = tm * tn;
+}
+
+// Retire a finished problem: write X (FP64) and stamp it.
+int retire(Group& g, Problem& P) {
+    LoopState& st = P.st;
+    st.finish_maxiter();
+    const int64_t m = P.pl.m, n = P.pl.n;
+    if (st.stage == 2) {
+        HIPCHK(hipMemcpy2DAsync(P.pr.X, P.pr.ldx * sizeof(double), P.bf.b64.X[st.result_idx],
+                                P.bf.b64.ldX * sizeof(double), m * sizeof(double), n,
+                                hipMemcpyDeviceToDevice, g.s));
+    } else {
+        HIPCHK(convert(P.bf.b32.X[st.result_idx], P.bf.b32.ldX, n, m, P.pr.X, P.pr.ldx, g.s));
+    }
+    P.res.status = st.status;
+    P.finished = true;
+    return HP_OK;
+}
+
+// One loop of every problem in `act` (all admitted, none finished). Problems
+// that finish are retired (X written, stream synchronised before return).
+int group_loop(Group& g, std::vector<Problem*>& act) {
+    Tables& tb = g.tb;
+    std::memset(tb.host, 0, tb.off_red);
+    const int np = (int)act.size();
+    ReduceEntry* red = reinterpret_cast<ReduceEntry*>(tb.host + tb.off_red);
+    for (int i = 0; i < np; ++i) {
+        Problem& P = *act[i];
+        LoopState& st = P.st;
+        int tiles = 0;
+        if (st.stage == 2) {
+            GemmCall<double> calls[kSlots];
+            const int nc = describe_pm_loop<double>(P.pl, P.bf.b64, P.bf.b64.X[st.ik],
+                                                    P.bf.b64.X[st.in_], P.bf.b64.X[2],
+                                                    st.stabilising, P.bf.small, calls);
+            for (int j = 0; j < nc; ++j) {
+                append(tb, 0, j, calls[j], &tiles);
+                const double gf = 2.0 * (double)calls[j].M * calls[j].N * calls[j].K * 1e-9;
+                P.res.gflop += gf;
+                P.res.gflop_stage[2] += gf;
+            }
+            P.res.gemms += nc;
+        } else {
+            if (st.engine() != ENG_F32) return HP_EUNSUPPORTED;
+            GemmCall<float> calls[kSlots];
+            const int nc = describe_pm_loop<float>(P.pl, P.bf.b32, P.bf.b32.X[st.ik],
+                                                   P.bf.b32.X[st.in_], P.bf.b32.X[2],
+                                                   st.stabilising, P.bf.small, calls);
+            for (int j = 0; j < nc; ++j) {
+                append(tb, 1, j, calls[j], &tiles);
+                const double gf = 2.0 * (double)calls[j].M * calls[j].N * calls[j].K * 1e-9;
+                P.res.gflop += gf;
+                P.res.gflop_stage[st.stage] += gf;
+            }
+            P.res.gemms += nc;
+        }
+        P.last_tiles = tiles;
+        red[i] = ReduceEntry{P.bf.small, tiles, 0};
+    }
+    HIPCHK(hipMemcpyAsync(tb.dev, tb.host, tb.off_out, hipMemcpyHostToDevice, g.s));
+    for (int j = 0; j < kSlots; ++j) {
+        for (int prec = 0; prec < 2; ++prec) {
+            const GroupHeader* hh = reinterpret_cast<const GroupHeader*>(tb.host + tb.off_hdr[prec][j]);
+            if (hh->count == 0) continue;
+            const GroupHeader* hdr = reinterpret_cast<const GroupHeader*>(tb.dev + tb.off_hdr[prec][j]);
+            const int grid = std::min(g.grid, hh->total_tiles);
+            if (prec == 0)
+                HIPCHK(gemm_grouped(hdr, reinterpret_cast<const GroupEntry<double>*>(tb.dev + tb.off_ent[0][j]),
+                                    grid, g.s));
+            else
+                HIPCHK(gemm_grouped(hdr, reinterpret_cast<const GroupEntry<float>*>(tb.dev + tb.off_ent[1][j]),
+                                    grid, g.s));
+        }
+    }
+    double* dout = reinterpret_cast<double*>(tb.dev + tb.off_out);
+    double* hout = reinterpret_cast<double*>(tb.host + tb.off_out);
+    HIPCHK(reduce_pairs_grouped(reinterpret_cast<const ReduceEntry*>(tb.dev + tb.off_red), np, dout, g.s));
+    HIPCHK(hipMemcpyAsync(hout, dout, 2 * sizeof(double) * (size_t)np, hipMemcpyDeviceToHost, g.s));
+    HIPCHK(hipStreamSynchronize(g.s));
+
+    bool any_done = false;
+    for (int i = 0; i < np; ++i) {
+        Problem& P = *act[i];
+        LoopState& st = P.st;
+        const LoopState::Action a = st.step(hout[2 * i], hout[2 * i + 1], 0.0, false);
+        if (a == LoopState::NEXT_STAGE) {
+            const int next = st.stage + 1;
+            if (next == 2) {
+                HIPCHK(convert(P.bf.b32.X[st.from_idx], P.bf.b32.ldX, P.pl.n, P.pl.m,
+                               P.bf.b64.X[0], P.bf.b64.ldX, g.s));
+                if (P.pl.has_proj) CHK(project_mp(P.pl, P.bf, g.s, single_gemm(g, P)));
+            }
+            st.enter_stage(next);
+        }
+        if (a == LoopState::DONE || st.k >= g.prm.max_iter) {
+            CHK(retire(g, P));
+            any_done = true;
+        }
+    }
+    if (any_done) HIPCHK(hipStreamSynchronize(g.s));
+    const Clock::time_point now = Clock::now();
+    for (Problem* P : act)
+        if (P->finished) P->t_finish = now;
+    return HP_OK;
+}
+
+int validate_group_params(const hp_params* p) {
+    if (p->precision != HP_PREC_FP64 && p->precision != HP_PREC_FP32 &&
+        p->precision != HP_PREC_FP32_FP64)
+        return HP_EUNSUPPORTED;
+    if (p->stop_rule == HP_STOP_ABS_INF || (p->flags & HP_FLAG_INF_NORM)) return HP_EUNSUPPORTED;
+    return HP_OK;
+}
+
+int validate_problem(const hp_params* p, const hp_problem& pr) {
+    CHK(validate(p, pr.m, pr.n));
+    if (!pr.A || !pr.X) return HP_EINVAL;
+    if (pr.lda < pr.n || pr.ldx < pr.m || (pr.X0 && pr.ldx0 < pr.m)) return HP_EINVAL;
+    return HP_OK;
+}
+
+int tables_alloc(Tables& tb, int cap) {
+    tb.cap = cap;
+    tb.bytes = Tables::layout(cap, &tb);
+    if (hipMalloc(reinterpret_cast<void**>(&tb.dev), tb.bytes) != hipSuccess) return HP_EHIP;
+    if (hipHostMalloc(reinterpret_cast<void**>(&tb.host), tb.bytes, hipHostMallocDefault) != hipSuccess)
+        return HP_EHIP;
+    return HP_OK;
+}
+
+void tables_free(Tables& tb) {
+    if (tb.dev) (void)hipFree(tb.dev);
+    if (tb.host) (void)hipHostFree(tb.host);
+    tb.dev = tb.host = nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Server
+// ---------------------------------------------------------------------------
+
+struct hp_server {
+    Group g;
+    char* arena = nullptr;
+    size_t budget = 0;
+    int max_slots = 0;
+    std::map<size_t, size_t> free_list;  // offset -> bytes
+    uint64_t next_ticket = 1;
+    std::map<uint64_t, Problem> reqs;
+    std::deque<uint64_t> waiting;
+    std::vector<uint64_t> active;
+
+    bool alloc(size_t bytes, size_t* off) {
+        for (auto it = free_list.begin(); it != free_list.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t roff = it->first + bytes;
+                free_list.erase(it);
+                if (rest) free_list[roff] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto it = free_list.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_list.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_list.erase(nx);
+        }
+        if (it != free_list.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_list.erase(it);
+            }
+        }
+    }
+};
+
+extern "C" {
+
+int hp_batched_workspace_bytes(const hp_params* p, int count, const hp_problem* probs, size_t* bytes) {
+    if (!p || !bytes || count < 1 || !probs) return HP_EINVAL;
+    CHK(validate_group_params(p));
+    size_t total = Tables::layout(count, nullptr);
+    for (int i = 0; i < count; ++i) {
+        CHK(validate(p, probs[i].m, probs[i].n));
+        total += align_up(make_plan(p, probs[i].m, probs[i].n).total);
+    }
+    *bytes = total;
+    return HP_OK;
+}
+
+int hp_solve_batched(hp_handle* h, const hp_params* p, int count, const hp_problem* probs,
+                     void* workspace, size_t ws_bytes, void* stream, hp_result* outs) {
+    const Clock::time_point t0 = Clock::now();
+    if (!h || !p || count < 1 || !probs) return HP_EINVAL;
+    CHK(validate_group_params(p));
+    for (int i = 0; i < count; ++i) CHK(validate_problem(p, probs[i]));
+    size_t need = 0;
+    CHK(hp_batched_workspace_bytes(p, count, probs, &need));
+    if (!workspace || ws_bytes < need) return HP_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return HP_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
+
+    Group g;
+    g.h = h;
+    g.prm = *p;
+    g.s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    // the tables live at the start of the workspace; staging is pinned host memory
+    g.tb.cap = count;
+    g.tb.bytes = Tables::layout(count, &g.tb);
+    g.tb.dev = ws;
+    if (hipHostMalloc(reinterpret_cast<void**>(&g.tb.host), g.tb.bytes, hipHostMallocDefault) != hipSuccess)
+        return HP_EHIP;
+    std::vector<Problem> P(count);
+    size_t off = align_up(g.tb.bytes);
+    int rc = HP_OK;
+    for (int i = 0; i < count && rc == HP_OK; ++i) {
+        P[i].pr = probs[i];
+        P[i].pl = make_plan(p, probs[i].m, probs[i].n);
+        P[i].ws = ws + off;
+        off += align_up(P[i].pl.total);
+        rc = admit(g, P[i]);
+    }
+    std::vector<Problem*> act;
+    for (auto& q : P) act.push_back(&q);
+    while (rc == HP_OK && !act.empty()) {
+        rc = group_loop(g, act);
+        act.erase(std::remove_if(act.begin(), act.end(), [](Problem* q) { return q->finished; }),
+                  act.end());
+    }
+    (void)hipHostFree(g.tb.host);
+    if (rc != HP_OK) return rc;
+    const double wall = ms_between(t0, Clock::now());
+    if (outs) {
+        for (int i = 0; i < count; ++i) {
+            P[i].res.time_ms = wall;
+            outs[i] = P[i].res;
+        }
+    }
+    return HP_OK;
+}
+
+int hp_serve_create(hp_handle* h, const hp_params* p, size_t hbm_budget, int max_slots,
+                    void* stream, hp_server** out) {
+    if (!h || !p || !out || max_slots < 1 || hbm_budget < kAlign) return HP_EINVAL;
+    *out = nullptr;
+    CHK(validate_group_params(p));
+    CHK(validate(p, 1, 1));
+    if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
+    hp_server* sv = new hp_server();
+    sv->g.h = h;
+    sv->g.prm = *p;
+    sv->g.s = reinterpret_cast<hipStream_t>(stream);
+    sv->budget = hbm_budget / kAlign * kAlign;
+    sv->max_slots = max_slots;
+    if (hipMalloc(reinterpret_cast<void**>(&sv->arena), sv->budget) != hipSuccess) {
+        delete sv;
+        return HP_EHIP;
+    }
+    sv->free_list[0] = sv->budget;
+    if (tables_alloc(sv->g.tb, max_slots) != HP_OK) {
+        (void)hipFree(sv->arena);
+        tables_free(sv->g.tb);
+        delete sv;
+        return HP_EHIP;
+    }
+    *out = sv;
+    return HP_OK;
+}
+
+int hp_serve_submit(hp_server* sv, const hp_problem* prob, uint64_t* ticket) {
+    if (!sv || !prob || !ticket) return HP_EINVAL;
+    CHK(validate_problem(&sv->g.prm, *prob));
+    const Plan pl = make_plan(&sv->g.prm, prob->m, prob->n);
+    if (align_up(pl.total) > sv->budget) return HP_EBUDGET;
+    const uint64_t t = sv->next_ticket++;
+    Problem& P = sv->reqs[t];
+    P.pr = *prob;
+    P.pl = pl;
+    P.ws_bytes = align_up(pl.total);
+    P.t_submit = Clock::now();
+    sv->waiting.push_back(t);
+    *ticket = t;
+    return HP_OK;
+}
+
+int hp_serve_step(hp_server* sv, int* active, int* waiting) {
+    if (!sv) return HP_EINVAL;
+    if (hipSetDevice(sv->g.h->device) != hipSuccess) return HP_EHIP;
+    // admit in arrival order while a slot and memory are free
+    while (!sv->waiting.empty() && (int)sv->active.size() < sv->max_slots) {
+        Problem& P = sv->reqs[sv->waiting.front()];
+        size_t off = 0;
+        if (!sv->alloc(P.ws_bytes, &off)) break;
+        P.ws_off = off;
+        P.ws = sv->arena + off;
+        CHK(admit(sv->g, P));
+        P.t_admit = Clock::now();
+        sv->active.push_back(sv->waiting.front());
+        sv->waiting.pop_front();
+    }
+    if (!sv->active.empty()) {
+        std::vector<Problem*> act;
+        for (uint64_t t : sv->active) act.push_back(&sv->reqs[t]);
+        CHK(group_loop(sv->g, act));
+        std::vector<uint64_t> still;
+        for (uint64_t t : sv->active) {
+            Problem& P = sv->reqs[t];
+            if (P.finished) {
+                P.res.queue_ms = ms_between(P.t_submit, P.t_admit);
+                P.res.run_ms = ms_between(P.t_admit, P.t_finish);
+                P.res.time_ms = ms_between(P.t_submit, P.t_finish);
+                sv->release(P.ws_off, P.ws_bytes);
+                P.ws = nullptr;
+            } else {
+                still.push_back(t);
+            }
+        }
+        sv->active.swap(still);
+    }
+    if (active) *active = (int)sv->active.size();
+    if (waiting) *waiting = (int)sv->waiting.size();
+    return HP_OK;
+}
+
+int hp_serve_poll(hp_server* sv, uint64_t ticket, hp_result* out) {
+    if (!sv) return HP_EINVAL;
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return HP_EINVAL;
+    if (!it->second.finished) return HP_PENDING;
+    const int st = it->second.res.status;
+    if (out) *out = it->second.res;
+    sv->reqs.erase(it);
+    return st;
+}
+
+int hp_serve_destroy(hp_server* sv) {
+    if (!sv) return HP_EINVAL;
+    (void)hipSetDevice(sv->g.h->device);
+    (void)hipStreamSynchronize(sv->g.s);
+    if (sv->arena) (void)hipFree(sv->arena);
+    tables_free(sv->g.tb);
+    delete sv;
+    return HP_OK;
+}
+
+}  // extern "C"

@@ -1,8 +1,8 @@
-// Host driver and C ABI of libhyperpower.
+// Host driver and C ABI of libhyperpower: single solves.
 //
 // One hp_solve call runs the loop of Section 2, iteration (PM), optionally
 // switching to (PM-modified) of Section 7, on the caller's stream: every
-// product is one k_gemm_f64 launch whose epilogue forms the next linear
+// product is one MFMA GEMM launch whose epilogue forms the next linear
 // combination, and the two stopping sums come back to the host once per loop.
 #include <hip/hip_runtime.h>
 
@@ -14,26 +14,9 @@
 #include <cstring>
 #include <type_traits>
 
-#include "hp_internal.h"
-#include "hyperpower.h"
+#include "hp_host.h"
 
-struct hp_handle {
-    int device = 0;
-    int forced_tile = -1;         // HP_GEMM_TILE: one tile configuration for every product
-    double* host_scal = nullptr;  // pinned, hp::SLOT_COUNT doubles
-    static constexpr int kEvents = 64;
-    hipEvent_t ev[kEvents] = {};
-};
-
-namespace {
-
-using hp::Epilogue;
-
-// Constants of the factored polynomial: the closed forms printed in Section 2
-// (c1, c2, c3 of (simplify1); d1, d2 of (simplify2); mu, psi of (hyper18-33)).
-struct PMConst {
-    double c1, c2, c3, d1, d2, mu, psi;
-};
+namespace hp {
 
 PMConst pm_const() {
     const double r93 = std::sqrt(93.0);
@@ -49,44 +32,19 @@ PMConst pm_const() {
     return k;
 }
 
-#define HIPCHK(x)                           \
-    do {                                    \
-        if ((x) != hipSuccess) return HP_EHIP; \
-    } while (0)
-
-inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+static inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 // Leading dimension of the library's internal matrices: a multiple of 8
-// doubles (64 bytes) so every row start is aligned for 16-byte loads, nudged
-// off multiples of 1 KiB so that the rows of a tile do not all start on the
-// same memory channel.
-inline int64_t pad_ld(int64_t cols) {
+// elements so every row start is aligned for 16-byte loads, nudged off
+// multiples of 128 elements so that the rows of a tile do not all start on
+// the same memory channel.
+int64_t pad_ld(int64_t cols) {
     int64_t ld = round_up(cols, 8);
     if (ld % 128 == 0) ld += 8;
     return ld;
 }
 
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// Workspace layout. FP64 set: A, three n x m iterates (X_k, X_{k+1}, X_{k+1/2})
-// and seven s x s loop matrices. FP32 set (FP32 and mixed precision): the same
-// in single precision. FP32-only solves keep just A and one iterate in FP64
-// (X0 is formed there).
-struct Plan {
-    int64_t m = 0, n = 0;
-    bool left = false;
-    int64_t s = 0;          // side of the residual R (n for left, m for right)
-    int64_t ldA = 0, ldX = 0, ldS = 0;  // FP64 leading dimensions (elements)
-    int64_t ldA32 = 0, ldX32 = 0, ldS32 = 0;
-    int nX64 = 0, nS64 = 0, nX32 = 0, nS32 = 0;
-    bool has32 = false;
-    size_t offA = 0, offX[3] = {}, offS[7] = {};
-    size_t offA32 = 0, offX32[3] = {}, offS32[7] = {};
-    size_t offSmall = 0, nSmall = 0, offScal = 0, total = 0;
-};
-
-bool choose_left(const hp_params* p, int64_t m, int64_t n) {
+static bool choose_left(const hp_params* p, int64_t m, int64_t n) {
     if (p->side == HP_SIDE_LEFT) return true;
     if (p->side == HP_SIDE_RIGHT) return false;
     return m > n;
@@ -122,6 +80,13 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n) {
     for (int i = 0; i < pl.nS64; ++i) {
         pl.offS[i] = off;
         off = align_up(off + sizeof(double) * (size_t)(pl.s * pl.ldS));
+    }
+    pl.has_proj = pl.has32 && p->kind == HP_KIND_MOORE_PENROSE && p->precision != HP_PREC_FP32;
+    if (pl.has_proj) {
+        pl.offAt = off;
+        off = align_up(off + sizeof(double) * (size_t)(n * pl.ldX));
+        pl.offXt = off;
+        off = align_up(off + sizeof(double) * (size_t)(m * pl.ldA));
     }
     if (pl.has32) {
         pl.offA32 = off;
@@ -165,7 +130,7 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
     if (p->variant < HP_VARIANT_PLAIN || p->variant > HP_VARIANT_STAB_ALWAYS) return HP_EINVAL;
     if (p->side < HP_SIDE_AUTO || p->side > HP_SIDE_LEFT) return HP_EINVAL;
     if (p->stop_rule < HP_STOP_REL_FRO || p->stop_rule > HP_STOP_ABS_INF) return HP_EINVAL;
-    if (p->precision < HP_PREC_FP64 || p->precision > HP_PREC_MIXED) return HP_EINVAL;
+    if (p->precision < HP_PREC_FP64 || p->precision > HP_PREC_FP32_FP64) return HP_EINVAL;
     if (p->low_dtype != HP_LOWP_BF16 && p->low_dtype != HP_LOWP_F16) return HP_EINVAL;
     if (p->max_iter < 1 || p->max_iter > 100000) return HP_EINVAL;
     if (!(p->tol >= 0.0) || !(p->tau_switch > 0.0) || !(p->diverge_limit > 0.0)) return HP_EINVAL;
@@ -173,6 +138,166 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
         if (p->reserved[i] != 0) return HP_EINVAL;
     return HP_OK;
 }
+
+Buffers carve(const Plan& pl, char* ws) {
+    Buffers bf;
+    auto d = [&](size_t off) { return reinterpret_cast<double*>(ws + off); };
+    auto f = [&](size_t off) { return reinterpret_cast<float*>(ws + off); };
+    bf.b64.A = d(pl.offA);
+    for (int i = 0; i < pl.nX64; ++i) bf.b64.X[i] = d(pl.offX[i]);
+    for (int i = 0; i < pl.nS64; ++i) bf.b64.S[i] = d(pl.offS[i]);
+    bf.b64.ldA = pl.ldA;
+    bf.b64.ldX = pl.ldX;
+    bf.b64.ldS = pl.ldS;
+    if (pl.has32) {
+        bf.b32.A = f(pl.offA32);
+        for (int i = 0; i < pl.nX32; ++i) bf.b32.X[i] = f(pl.offX32[i]);
+        for (int i = 0; i < pl.nS32; ++i) bf.b32.S[i] = f(pl.offS32[i]);
+        bf.b32.ldA = pl.ldA32;
+        bf.b32.ldX = pl.ldX32;
+        bf.b32.ldS = pl.ldS32;
+    }
+    if (pl.has_proj) {
+        bf.At = d(pl.offAt);
+        bf.Xt = d(pl.offXt);
+    }
+    bf.small = d(pl.offSmall);
+    bf.scal = d(pl.offScal);
+    return bf;
+}
+
+// ---------------------------------------------------------------------------
+// LoopState
+// ---------------------------------------------------------------------------
+
+static constexpr double kUnitRoundoffF32 = 5.960464477539063e-08;
+
+void LoopState::init(const hp_params* prm, hp_result* r, double a) {
+    p = prm;
+    res = r;
+    alpha = a;
+    stage = p->precision == HP_PREC_MIXED ? 0
+            : (p->precision == HP_PREC_FP32 || p->precision == HP_PREC_FP32_FP64) ? 1
+                                                                                  : 2;
+    final_stage = p->precision == HP_PREC_FP32 ? 1 : 2;
+    stabilising = p->variant == HP_VARIANT_STAB_ALWAYS;
+    res->switch_iter = stabilising ? 0 : -1;
+    converging = false;
+    stage_first = true;
+    d_prev = 0.0;
+    ik = 0;
+    in_ = 1;
+    k = 0;
+    status = HP_MAXITER;
+    result_idx = -1;
+}
+
+Engine LoopState::engine() const {
+    if (stage == 2) return ENG_F64;
+    if (stage == 1) return ENG_F32;
+    return p->low_dtype == HP_LOWP_F16 ? ENG_F16 : ENG_BF16;
+}
+
+void LoopState::enter_stage(int next) {
+    stage = next;
+    stage_first = true;
+    if (next == 2) {
+        ik = 0;
+        in_ = 1;
+    } else {
+        ik = from_idx;
+        in_ = from_idx == 0 ? 1 : 0;
+    }
+}
+
+LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool have_dinf) {
+    res->iters = k + 1;
+    res->iters_stage[stage] += 1;
+    const double d = std::sqrt(diff2) / std::sqrt(ref2);
+    if (k < HP_HIST) {
+        res->d_hist[k] = d;
+        if (have_dinf) res->dinf_hist[k] = dinf;
+    }
+    res->d_stage[stage] = d;
+    res->d_last = d;
+    ++k;
+    const bool finite = std::isfinite(d) && std::isfinite(diff2) && (!have_dinf || std::isfinite(dinf));
+    auto note_switch = [&]() {
+        if (d < p->tau_switch) {
+            converging = true;
+            if (p->variant == HP_VARIANT_STABILISED && !stabilising) {
+                stabilising = true;
+                res->switch_iter = k;
+            }
+        }
+    };
+
+    if (stage != final_stage) {
+        // a lower stage ends when its change stops halving, reaches its
+        // rounding floor, or goes non-finite (16-bit overflow); the next stage
+        // continues from the better of the last two iterates
+        const double u = stage == 0 ? (p->low_dtype == HP_LOWP_F16 ? 4.8828125e-4 : 3.90625e-3)
+                                    : kUnitRoundoffF32;
+        const bool stalled = !stage_first && d < 1.0 && d >= 0.5 * d_prev;
+        const bool floor = d < 10.0 * u || d < p->tol;
+        if (finite) note_switch();
+        if (!finite || stalled || floor) {
+            const bool keep_new = finite && !(stalled && d >= d_prev);
+            from_idx = keep_new ? in_ : ik;
+            d_prev = d;
+            return NEXT_STAGE;
+        }
+        stage_first = false;
+        d_prev = d;
+        std::swap(ik, in_);
+        return CONTINUE;
+    }
+
+    if (!finite) {
+        status = HP_NONFINITE;
+        result_idx = ik;
+        return DONE;
+    }
+    double sval;
+    bool passed;
+    if (p->stop_rule == HP_STOP_REL_FRO) {
+        sval = d;
+        passed = d < p->tol;
+    } else if (p->stop_rule == HP_STOP_ABS_INF) {
+        sval = dinf;
+        passed = dinf <= p->tol;
+    } else {
+        sval = std::sqrt(diff2) / (std::pow(18.0, (double)(k - 1)) * alpha);
+        passed = sval < p->tol;
+    }
+    res->stop_last = sval;
+    if (passed) {
+        status = HP_OK;
+        result_idx = in_;
+        return DONE;
+    }
+    if (converging && !stage_first && d >= d_prev) {
+        status = HP_STAGNATED;
+        result_idx = ik;
+        return DONE;
+    }
+    if (!converging && d > p->diverge_limit) {
+        status = HP_DIVERGED;
+        result_idx = ik;
+        return DONE;
+    }
+    note_switch();
+    stage_first = false;
+    d_prev = d;
+    std::swap(ik, in_);
+    return CONTINUE;
+}
+
+}  // namespace hp
+
+namespace {
+
+using namespace hp;
 
 // Pairs of hipEvents around GEMM launches, harvested after each stream sync.
 struct GemmTimer {
@@ -199,361 +324,122 @@ struct GemmTimer {
     }
 };
 
-// Which MFMA path a product runs on.
-enum Engine { ENG_F64, ENG_F32, ENG_BF16, ENG_F16 };
-
-// The buffers of one precision.
-template <typename T>
-struct Set {
-    T* A = nullptr;
-    T* X[3] = {};
-    T* S[7] = {};
-    int64_t ldA = 0, ldX = 0, ldS = 0;
-};
-
 struct Solver {
     hp_handle* h;
     const hp_params* p;
     hipStream_t s;
     Plan pl;
-    char* ws;
     hp_result* res;
     GemmTimer timer;
     double gflop = 0.0;
     int gemms = 0;
     int last_blocks = 0;  // blocks (partial pairs) of the latest product
-    int stage = 2;        // 0 16-bit, 1 FP32, 2 FP64 (for per-stage accounting)
+    int stage = 2;        // for per-stage accounting
 
     template <typename T>
-    T* ptr(size_t off) { return reinterpret_cast<T*>(ws + off); }
-
-    template <typename T>
-    int gemm(Engine eng, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
-             int64_t ldb, const hp::EpilogueT<T>& ep) {
-        const hp::GemmTile t = h->forced_tile >= 0 ? (hp::GemmTile)h->forced_tile
-                                                   : hp::gemm_pick_tile(M, N, K);
+    int gemm(Engine eng, const GemmCall<T>& g) {
+        const GemmTile t = h->forced_tile >= 0 ? (GemmTile)h->forced_tile
+                                                : gemm_pick_tile(g.M, g.N, g.K);
         timer.before();
         hipError_t e;
         if constexpr (std::is_same<T, double>::value) {
-            e = hp::gemm(t, M, N, K, A, lda, B, ldb, ep, s);
+            (void)eng;
+            e = hp::gemm(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.ep, s);
         } else {
-            if (eng == ENG_F32) e = hp::gemm(t, M, N, K, A, lda, B, ldb, ep, s);
-            else e = hp::gemm_lowp(t, eng == ENG_BF16 ? hp::LOWP_BF16 : hp::LOWP_F16, M, N, K, A,
-                                   lda, B, ldb, ep, s);
+            if (eng == ENG_F32) e = hp::gemm(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.ep, s);
+            else e = gemm_lowp(t, eng == ENG_BF16 ? LOWP_BF16 : LOWP_F16, g.M, g.N, g.K, g.A, g.lda,
+                               g.B, g.ldb, g.ep, s);
         }
         timer.after();
-        last_blocks = hp::gemm_blocks(t, M, N);
+        last_blocks = gemm_blocks(t, g.M, g.N);
         if (e != hipSuccess) return HP_EHIP;
-        const double g = 2.0 * (double)M * (double)N * (double)K * 1e-9;
-        gflop += g;
-        res->gflop_stage[stage] += g;
+        const double gf = 2.0 * (double)g.M * (double)g.N * (double)g.K * 1e-9;
+        gflop += gf;
+        res->gflop_stage[stage] += gf;
         ++gemms;
         return HP_OK;
     }
 };
 
-#define CHK(x)                      \
-    do {                            \
-        int rc_ = (x);              \
-        if (rc_ != HP_OK) return rc_; \
-    } while (0)
-
-// One loop of (PM), Section 2, in the association printed there, on buffers
-// of one precision: R, R^2, R^4 (epilogue: F1, F2), F1 F2 (epilogue: T, S),
-// T S (+ mu R^2 + psi R^4), R V (+ V), and the update; if `stab`, the
-// stabilising product X A X of (PM-modified), Section 7, follows. The update
-// (or the stabilising product) writes the partial sums of the stopping test
-// against X_k into `partials`.
-template <typename T>
-int pm_loop(Solver& S, Engine eng, const Set<T>& b, T* Xk, T* Xn, T* Xh, bool stab,
-            double* partials) {
-    const PMConst K = pm_const();
-    const int64_t m = S.pl.m, n = S.pl.n, sd = S.pl.s;
-    const int64_t ldS = b.ldS, ldX = b.ldX, ldA = b.ldA;
-    T* R = b.S[0];
-    T* R2 = b.S[1];
-    T* R4 = b.S[2];
-    T* F1 = b.S[3];
-    T* F2 = b.S[4];
-    T* Tm = b.S[5];
-    T* Sm = b.S[6];
-    T* V = F1;  // F1, F2 are dead once T and S exist
-    T* W = F2;
-    {   // R = I - A X (right, m x m) or I - X A (left, n x n)
-        hp::EpilogueT<T> e = hp::epilogue_plain(R, ldS, -1.0, 1.0);
-        if (S.pl.left) CHK(S.gemm<T>(eng, n, n, m, Xk, ldX, b.A, ldA, e));
-        else CHK(S.gemm<T>(eng, m, m, n, b.A, ldA, Xk, ldX, e));
-    }
-    CHK(S.gemm<T>(eng, sd, sd, sd, R, ldS, R, ldS, hp::epilogue_plain(R2, ldS)));
-    {   // R4 = R2 R2; F1 = I + c1 R2 + R4; F2 = I + c2 R2 + R4
-        hp::EpilogueT<T> e{};
-        e.out[0] = R4; e.ldo[0] = ldS; e.acc_c[0] = 1.0;
-        e.out[1] = F1; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.id[1] = 1.0; e.g1[1] = K.c1;
-        e.out[2] = F2; e.ldo[2] = ldS; e.acc_c[2] = 1.0; e.id[2] = 1.0; e.g1[2] = K.c2;
-        e.D1 = R2; e.ld1 = ldS;
-        CHK(S.gemm<T>(eng, sd, sd, sd, R2, ldS, R2, ldS, e));
-    }
-    {   // M = F1 F2; T = M + c3 R2; S = M + d1 R2 + d2 R4
-        hp::EpilogueT<T> e{};
-        e.out[0] = Tm; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.c3;
-        e.out[1] = Sm; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.g1[1] = K.d1; e.g2[1] = K.d2;
-        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
-        CHK(S.gemm<T>(eng, sd, sd, sd, F1, ldS, F2, ldS, e));
-    }
-    {   // V = T S + mu R2 + psi R4
-        hp::EpilogueT<T> e{};
-        e.out[0] = V; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.mu; e.g2[0] = K.psi;
-        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
-        CHK(S.gemm<T>(eng, sd, sd, sd, Tm, ldS, Sm, ldS, e));
-    }
-    {   // W = (I + R) V = V + R V
-        hp::EpilogueT<T> e{};
-        e.out[0] = W; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = 1.0;
-        e.D1 = V; e.ld1 = ldS;
-        CHK(S.gemm<T>(eng, sd, sd, sd, R, ldS, V, ldS, e));
-    }
-    {   // update: X W (right) or W X (left)
-        hp::EpilogueT<T> e = hp::epilogue_plain(stab ? Xh : Xn, ldX);
-        if (!stab) {
-            e.ref = Xk; e.ldref = ldX; e.partials = partials;
-        }
-        if (S.pl.left) CHK(S.gemm<T>(eng, n, m, n, W, ldS, Xk, ldX, e));
-        else CHK(S.gemm<T>(eng, n, m, m, Xk, ldX, W, ldS, e));
-    }
-    if (stab) {
-        // X_{k+1} = X_{k+1/2} A X_{k+1/2}, associated so that the middle
-        // product is the smaller square
-        hp::EpilogueT<T> e = hp::epilogue_plain(Xn, ldX);
-        e.ref = Xk; e.ldref = ldX; e.partials = partials;
-        if (m >= n) {
-            CHK(S.gemm<T>(eng, n, n, m, Xh, ldX, b.A, ldA, hp::epilogue_plain(R, ldS)));
-            CHK(S.gemm<T>(eng, n, m, n, R, ldS, Xh, ldX, e));
-        } else {
-            CHK(S.gemm<T>(eng, m, m, n, b.A, ldA, Xh, ldX, hp::epilogue_plain(R, ldS)));
-            CHK(S.gemm<T>(eng, n, m, m, Xh, ldX, R, ldS, e));
-        }
-    }
-    return HP_OK;
-}
-
-constexpr double kUnitRoundoff[3] = {0.0, 5.960464477539063e-08, 1.1102230246251565e-16};
-
-int run_solve(Solver& S, const double* A, int64_t lda, const double* X0, int64_t ldx0, double* X,
-              int64_t ldx) {
+int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X0, int64_t ldx0,
+              double* X, int64_t ldx) {
     const hp_params* p = S.p;
     const Plan& pl = S.pl;
     hipStream_t s = S.s;
     hp_result* res = S.res;
     const int64_t m = pl.m, n = pl.n;
-
-    Set<double> b64;
-    b64.A = S.ptr<double>(pl.offA);
-    for (int i = 0; i < pl.nX64; ++i) b64.X[i] = S.ptr<double>(pl.offX[i]);
-    for (int i = 0; i < pl.nS64; ++i) b64.S[i] = S.ptr<double>(pl.offS[i]);
-    b64.ldA = pl.ldA; b64.ldX = pl.ldX; b64.ldS = pl.ldS;
-    Set<float> b32;
-    if (pl.has32) {
-        b32.A = S.ptr<float>(pl.offA32);
-        for (int i = 0; i < pl.nX32; ++i) b32.X[i] = S.ptr<float>(pl.offX32[i]);
-        for (int i = 0; i < pl.nS32; ++i) b32.S[i] = S.ptr<float>(pl.offS32[i]);
-        b32.ldA = pl.ldA32; b32.ldX = pl.ldX32; b32.ldS = pl.ldS32;
-    }
-    double* small = S.ptr<double>(pl.offSmall);
-    double* scal = S.ptr<double>(pl.offScal);
+    const Buffers bf = carve(pl, ws);
     double* hs = S.h->host_scal;
-    const int64_t ldA = pl.ldA, ldX = pl.ldX, ldS = pl.ldS;
 
-    // A -> padded internal copy
-    HIPCHK(hipMemcpy2DAsync(b64.A, ldA * sizeof(double), A, lda * sizeof(double),
-                            n * sizeof(double), m, hipMemcpyDeviceToDevice, s));
-
-    // ---- X0 (Section 4), formed in FP64 ----
-    double* X0w = b64.X[0];
     double alpha = 0.0;
     S.stage = 2;
-    if (X0) {
-        HIPCHK(hipMemcpy2DAsync(X0w, ldX * sizeof(double), X0, ldx0 * sizeof(double),
-                                m * sizeof(double), n, hipMemcpyDeviceToDevice, s));
-        alpha = p->alpha > 0.0 ? p->alpha : 1.0;
-    } else {
-        if (p->alpha_rule == HP_ALPHA_USER) {
-            hs[hp::SLOT_ALPHA] = p->alpha;
-            HIPCHK(hipMemcpyAsync(scal + hp::SLOT_ALPHA, hs + hp::SLOT_ALPHA, sizeof(double),
-                                  hipMemcpyHostToDevice, s));
-        }
-        if (p->kind == HP_KIND_MOORE_PENROSE) {
-            if (p->alpha_rule == HP_ALPHA_NORM1INF)
-                HIPCHK(hp::alpha_norm1inf(b64.A, ldA, m, n, small, scal, s));
-            HIPCHK(hp::transpose_scale(b64.A, ldA, m, n, X0w, ldX, scal + hp::SLOT_ALPHA, s));
-        } else {
-            // G = A^l by repeated products, alpha = 1/Tr(A^{l+1}) = 1/Tr(A^l A)
-            const double* P = b64.A;
-            int64_t ldp = ldA;
-            double* pp[2] = {b64.S[0], b64.S[1]};
-            for (int i = 1; i < p->drazin_l; ++i) {
-                double* dst = pp[i & 1];
-                CHK(S.gemm<double>(ENG_F64, n, n, n, P, ldp, b64.A, ldA,
-                                   hp::epilogue_plain(dst, ldS)));
-                P = dst;
-                ldp = ldS;
-            }
-            if (p->alpha_rule == HP_ALPHA_TRACE)
-                HIPCHK(hp::alpha_trace(P, ldp, b64.A, ldA, n, small, scal, s));
-            HIPCHK(hp::scale(P, ldp, n, n, X0w, ldX, scal + hp::SLOT_ALPHA, s));
-        }
-        HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * hp::SLOT_COUNT, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        S.timer.harvest();
-        alpha = hs[hp::SLOT_ALPHA];
-    }
+    CHK(setup_x0(p, pl, bf, A, lda, X0, ldx0, hs, s,
+                 [&](const GemmCall<double>& g) { return S.gemm<double>(ENG_F64, g); }, &alpha));
+    S.timer.harvest();
     res->alpha = alpha;
 
-    // ---- stages ----
-    int stage = p->precision == HP_PREC_MIXED ? 0 : (p->precision == HP_PREC_FP32 ? 1 : 2);
-    const int final_stage = p->precision == HP_PREC_FP32 ? 1 : 2;
-    const Engine low_eng = p->low_dtype == HP_LOWP_F16 ? ENG_F16 : ENG_BF16;
-    // current iterate indices into the X sets
-    int ik = 0, in_ = 1;
-    if (stage < 2) {
-        HIPCHK(hp::convert(b64.A, ldA, m, n, b32.A, b32.ldA, s));
-        HIPCHK(hp::convert(X0w, ldX, n, m, b32.X[0], b32.ldX, s));
+    LoopState st;
+    st.init(p, res, alpha);
+    if (st.stage < 2) {
+        HIPCHK(convert(bf.b64.A, bf.b64.ldA, m, n, bf.b32.A, bf.b32.ldA, s));
+        HIPCHK(convert(bf.b64.X[0], bf.b64.ldX, n, m, bf.b32.X[0], bf.b32.ldX, s));
     }
-
     const bool want_inf = (p->flags & HP_FLAG_INF_NORM) || p->stop_rule == HP_STOP_ABS_INF;
-    bool stabilising = p->variant == HP_VARIANT_STAB_ALWAYS;
-    res->switch_iter = stabilising ? 0 : -1;
-    bool converging = false;
-    bool stage_first = true;  // no stagnation test on a stage's first loop
-    double d_prev = 0.0;
-    int status = HP_MAXITER;
-    int result_idx = -1;      // index into the final set's X buffers
 
-    for (int k = 0; k < p->max_iter; ++k) {
-        S.stage = stage;
-        if (stage == 2) {
-            CHK(pm_loop<double>(S, ENG_F64, b64, b64.X[ik], b64.X[in_], b64.X[2], stabilising, small));
+    while (st.k < p->max_iter) {
+        S.stage = st.stage;
+        if (st.stage == 2) {
+            GemmCall<double> calls[9];
+            const int nc = describe_pm_loop<double>(pl, bf.b64, bf.b64.X[st.ik], bf.b64.X[st.in_],
+                                                    bf.b64.X[2], st.stabilising, bf.small, calls);
+            for (int i = 0; i < nc; ++i) CHK(S.gemm<double>(ENG_F64, calls[i]));
         } else {
-            CHK(pm_loop<float>(S, stage == 0 ? low_eng : ENG_F32, b32, b32.X[ik], b32.X[in_],
-                               b32.X[2], stabilising, small));
+            GemmCall<float> calls[9];
+            const int nc = describe_pm_loop<float>(pl, bf.b32, bf.b32.X[st.ik], bf.b32.X[st.in_],
+                                                   bf.b32.X[2], st.stabilising, bf.small, calls);
+            for (int i = 0; i < nc; ++i) CHK(S.gemm<float>(st.engine(), calls[i]));
         }
-        HIPCHK(hp::reduce_pairs(small, S.last_blocks, scal, s));
-        if (want_inf && stage == 2)
-            HIPCHK(hp::diff_norm_inf(b64.X[in_], ldX, b64.X[ik], ldX, n, m, small, scal, s));
-        HIPCHK(hipMemcpyAsync(hs, scal, sizeof(double) * hp::SLOT_COUNT, hipMemcpyDeviceToHost, s));
+        HIPCHK(reduce_pairs(bf.small, S.last_blocks, bf.scal, s));
+        const bool inf_now = want_inf && st.stage == 2;
+        if (inf_now)
+            HIPCHK(diff_norm_inf(bf.b64.X[st.in_], bf.b64.ldX, bf.b64.X[st.ik], bf.b64.ldX, n, m,
+                                 bf.small, bf.scal, s));
+        HIPCHK(hipMemcpyAsync(hs, bf.scal, sizeof(double) * SLOT_COUNT, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         S.timer.harvest();
 
-        res->iters = k + 1;
-        res->iters_stage[stage] += 1;
-        const double diff2 = hs[hp::SLOT_DIFF2], ref2 = hs[hp::SLOT_REF2];
-        const double d = std::sqrt(diff2) / std::sqrt(ref2);
-        if (k < HP_HIST) res->d_hist[k] = d;
-        res->d_stage[stage] = d;
-        double dinf = 0.0;
-        if (want_inf && stage == 2) {
-            dinf = hs[hp::SLOT_DINF];
-            if (k < HP_HIST) res->dinf_hist[k] = dinf;
-        }
-        res->d_last = d;
-        const bool finite = std::isfinite(d) && std::isfinite(diff2) && (!want_inf || std::isfinite(dinf));
-
-        if (stage != final_stage) {
-            // a lower stage ends when its change stops halving, reaches its
-            // rounding floor, or goes non-finite (16-bit overflow); the next
-            // stage continues from the better of the last two iterates
-            const double u = stage == 0 ? (p->low_dtype == HP_LOWP_F16 ? 4.8828125e-4 : 3.90625e-3)
-                                        : kUnitRoundoff[1];
-            const bool stalled = !stage_first && d < 1.0 && d >= 0.5 * d_prev;
-            const bool floor = d < 10.0 * u || d < p->tol;
-            if (d < p->tau_switch) {
-                converging = true;
-                if (p->variant == HP_VARIANT_STABILISED && !stabilising) {
-                    stabilising = true;
-                    res->switch_iter = k + 1;
+        const LoopState::Action a = st.step(hs[SLOT_DIFF2], hs[SLOT_REF2], hs[SLOT_DINF], inf_now);
+        if (a == LoopState::DONE) break;
+        if (a == LoopState::NEXT_STAGE) {
+            const int next = st.stage + 1;
+            if (next == 2) {
+                HIPCHK(convert(bf.b32.X[st.from_idx], bf.b32.ldX, n, m, bf.b64.X[0], bf.b64.ldX, s));
+                if (pl.has_proj) {
+                    S.stage = 2;
+                    CHK(project_mp(pl, bf, s, [&](const GemmCall<double>& g) {
+                        return S.gemm<double>(ENG_F64, g);
+                    }));
                 }
             }
-            if (!finite || stalled || floor) {
-                const bool keep_new = finite && !(stalled && d >= d_prev);
-                const int from = keep_new ? in_ : ik;
-                const int next = stage + 1;
-                if (next == 2) {
-                    HIPCHK(hp::convert(b32.X[from], b32.ldX, n, m, b64.X[0], ldX, s));
-                    ik = 0;
-                    in_ = 1;
-                } else {
-                    ik = from;
-                    in_ = from == 0 ? 1 : 0;
-                }
-                stage = next;
-                stage_first = true;
-                d_prev = d;
-                continue;
-            }
-            stage_first = false;
-            d_prev = d;
-            std::swap(ik, in_);
-            continue;
+            st.enter_stage(next);
         }
-
-        if (!finite) {
-            status = HP_NONFINITE;
-            result_idx = ik;
-            break;
-        }
-        double sval;
-        bool passed;
-        if (p->stop_rule == HP_STOP_REL_FRO) {
-            sval = d;
-            passed = d < p->tol;
-        } else if (p->stop_rule == HP_STOP_ABS_INF) {
-            sval = dinf;
-            passed = dinf <= p->tol;
-        } else {
-            sval = std::sqrt(diff2) / (std::pow(18.0, (double)k) * alpha);
-            passed = sval < p->tol;
-        }
-        res->stop_last = sval;
-        if (passed) {
-            status = HP_OK;
-            result_idx = in_;
-            break;
-        }
-        if (converging && !stage_first && d >= d_prev) {
-            status = HP_STAGNATED;
-            result_idx = ik;
-            break;
-        }
-        if (!converging && d > p->diverge_limit) {
-            status = HP_DIVERGED;
-            result_idx = ik;
-            break;
-        }
-        if (d < p->tau_switch) {
-            converging = true;
-            if (p->variant == HP_VARIANT_STABILISED && !stabilising) {
-                stabilising = true;
-                res->switch_iter = k + 1;
-            }
-        }
-        stage_first = false;
-        d_prev = d;
-        std::swap(ik, in_);
     }
-    if (result_idx < 0) result_idx = ik;  // HP_MAXITER: the last iterate
+    st.finish_maxiter();
 
     const int it = std::min(res->iters, HP_HIST);
     if (want_inf && it >= 3) {
         const double e0 = res->dinf_hist[it - 3], e1 = res->dinf_hist[it - 2], e2 = res->dinf_hist[it - 1];
         if (e0 > 0 && e1 > 0 && e2 > 0) res->coc = std::log(e2 / e1) / std::log(e1 / e0);
     }
-    if (stage == 2) {
-        HIPCHK(hipMemcpy2DAsync(X, ldx * sizeof(double), b64.X[result_idx], ldX * sizeof(double),
-                                m * sizeof(double), n, hipMemcpyDeviceToDevice, s));
+    if (st.stage == 2) {
+        HIPCHK(hipMemcpy2DAsync(X, ldx * sizeof(double), bf.b64.X[st.result_idx],
+                                bf.b64.ldX * sizeof(double), m * sizeof(double), n,
+                                hipMemcpyDeviceToDevice, s));
     } else {
-        HIPCHK(hp::convert(b32.X[result_idx], b32.ldX, n, m, X, ldx, s));
+        HIPCHK(convert(bf.b32.X[st.result_idx], bf.b32.ldX, n, m, X, ldx, s));
     }
     HIPCHK(hipStreamSynchronize(s));
-    return status;
+    return st.status;
 }
 
 const char* const kStatusText[] = {"ok", "max_iter reached", "stagnated", "diverged",
@@ -656,10 +542,10 @@ int hp_solve(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64
     res->switch_iter = -1;
     res->side_used = pl.left ? HP_SIDE_LEFT : HP_SIDE_RIGHT;
 
-    Solver S{h, p, reinterpret_cast<hipStream_t>(stream), pl, static_cast<char*>(workspace), res,
+    Solver S{h, p, reinterpret_cast<hipStream_t>(stream), pl, res,
              GemmTimer{h, (p->flags & HP_FLAG_TIME_KERNELS) != 0, 0, 0.0,
                        reinterpret_cast<hipStream_t>(stream)}};
-    rc = run_solve(S, A, lda, X0, ldx0, X, ldx);
+    rc = run_solve(S, static_cast<char*>(workspace), A, lda, X0, ldx0, X, ldx);
     res->status = rc;
     res->gflop = S.gflop;
     res->gemms = S.gemms;

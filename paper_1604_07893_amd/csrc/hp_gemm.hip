@@ -110,10 +110,12 @@ struct Cfg {
     static constexpr size_t LDS_BYTES = 2 * (size_t)BK * (LDA_S + LDB_S) * sizeof(T);
 };
 
+// One BM x BN output tile (tm, tn) of C = epilogue(A * B); the block's
+// partial sums (if any) go to pair `part` of ep.partials.
 template <typename T, int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm(
-    int M, int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
-    int64_t ldb, EpilogueT<T> ep, int tiles_m, int tiles_n) {
+__device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, int64_t lda,
+                                 const T* __restrict__ B, int64_t ldb, const EpilogueT<T>& ep,
+                                 int tm, int tn, int part) {
     using C = Cfg<T, BM, BN, BK, WM, WN>;
     using VT = typename Vec16<T>::type;
     using ACC = typename Mfma<T>::acc_t;
@@ -125,8 +127,6 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm(
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    int tm, tn;
-    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
     const int bm = tm * BM, bn = tn * BN;
     const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
 
@@ -248,9 +248,41 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm(
                 a += red[0][w];
                 b += red[1][w];
             }
-            ep.partials[2 * blockIdx.x] = a;
-            ep.partials[2 * blockIdx.x + 1] = b;
+            ep.partials[2 * part] = a;
+            ep.partials[2 * part + 1] = b;
         }
+    }
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm(
+    int M, int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+    int64_t ldb, EpilogueT<T> ep, int tiles_m, int tiles_n) {
+    int tm, tn;
+    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    gemm_tile<T, BM, BN, BK, WM, WN>(M, N, K, A, lda, B, ldb, ep, tm, tn, blockIdx.x);
+}
+
+// Persistent grouped launch: the grid walks the tiles of every product in
+// the table (entries in order, tiles of an entry row-major); each tile is
+// computed exactly as a single launch of that product would compute it, so an
+// entry's result does not depend on the other entries.
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_grouped(
+    const GroupHeader* __restrict__ hdr, const GroupEntry<T>* __restrict__ ents) {
+    const int count = hdr->count;
+    const int total = hdr->total_tiles;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ents[mid].tile_start <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const GroupEntry<T> g = ents[lo];
+        const int local = t - g.tile_start;
+        gemm_tile<T, BM, BN, BK, WM, WN>(g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.ep,
+                                         local / g.tiles_n, local % g.tiles_n, local);
     }
 }
 
@@ -538,6 +570,23 @@ hipError_t dispatch_lp(GemmTile t, int64_t M, int64_t N, int64_t K, const float*
 }
 
 }  // namespace
+
+int grouped_tile_m() { return 64; }
+int grouped_tile_n() { return 64; }
+
+hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<double>* ents, int grid,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm_grouped<double, 64, 64, 16, 32, 32>), dim3(grid), dim3(256), 0, s,
+                       hdr, ents);
+    return hipGetLastError();
+}
+
+hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<float>* ents, int grid,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm_grouped<float, 64, 64, 32, 32, 32>), dim3(grid), dim3(256), 0, s,
+                       hdr, ents);
+    return hipGetLastError();
+}
 
 hipError_t gemm_lowp(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, const float* A,
                      int64_t lda, const float* B, int64_t ldb, const EpilogueT<float>& ep,

@@ -1,0 +1,293 @@
+// Host-side pieces shared by the single, batched and served solvers.
+// Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "hp_internal.h"
+#include "hyperpower.h"
+
+struct hp_handle {
+    int device = 0;
+    int forced_tile = -1;         // HP_GEMM_TILE: one tile configuration for every product
+    double* host_scal = nullptr;  // pinned, hp::SLOT_COUNT doubles
+    static constexpr int kEvents = 64;
+    hipEvent_t ev[kEvents] = {};
+};
+
+#define HIPCHK(x)                              \
+    do {                                       \
+        if ((x) != hipSuccess) return HP_EHIP; \
+    } while (0)
+
+#define CHK(x)                        \
+    do {                              \
+        int rc_ = (x);                \
+        if (rc_ != HP_OK) return rc_; \
+    } while (0)
+
+namespace hp {
+
+// Constants of the factored polynomial: the closed forms printed in Section 2
+// (c1, c2, c3 of (simplify1); d1, d2 of (simplify2); mu, psi of (hyper18-33)).
+struct PMConst {
+    double c1, c2, c3, d1, d2, mu, psi;
+};
+PMConst pm_const();
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t pad_ld(int64_t cols);
+
+// Workspace layout of one problem. FP64 set: A, three n x m iterates (X_k,
+// X_{k+1}, X_{k+1/2}) and seven s x s loop matrices. FP32 set (FP32 and mixed
+// precision): the same in single precision. FP32-only solves keep just A and
+// one iterate in FP64 (X0 is formed there).
+struct Plan {
+    int64_t m = 0, n = 0;
+    bool left = false;
+    int64_t s = 0;  // side of the residual R (n for left, m for right)
+    int64_t ldA = 0, ldX = 0, ldS = 0;
+    int64_t ldA32 = 0, ldX32 = 0, ldS32 = 0;
+    int nX64 = 0, nS64 = 0, nX32 = 0, nS32 = 0;
+    bool has32 = false;
+    size_t offA = 0, offX[3] = {}, offS[7] = {};
+    size_t offA32 = 0, offX32[3] = {}, offS32[7] = {};
+    bool has_proj = false;      // A^T (n x m) and X^T (m x n) for the projection
+    size_t offAt = 0, offXt = 0;
+    size_t offSmall = 0, nSmall = 0, offScal = 0, total = 0;
+};
+Plan make_plan(const hp_params* p, int64_t m, int64_t n);
+int validate(const hp_params* p, int64_t m, int64_t n);
+
+// Which MFMA path a product runs on.
+enum Engine { ENG_F64, ENG_F32, ENG_BF16, ENG_F16 };
+
+// The buffers of one precision.
+template <typename T>
+struct Set {
+    T* A = nullptr;
+    T* X[3] = {};
+    T* S[7] = {};
+    int64_t ldA = 0, ldX = 0, ldS = 0;
+};
+
+struct Buffers {
+    Set<double> b64;
+    Set<float> b32;
+    double* At = nullptr;  // n x m, ld b64.ldX
+    double* Xt = nullptr;  // m x n, ld b64.ldA
+    double* small = nullptr;
+    double* scal = nullptr;
+};
+Buffers carve(const Plan& pl, char* ws);
+
+// One product of a loop: C = epilogue(A B), A M x K, B K x N.
+template <typename T>
+struct GemmCall {
+    int64_t M, N, K;
+    const T* A;
+    int64_t lda;
+    const T* B;
+    int64_t ldb;
+    EpilogueT<T> ep;
+};
+
+// The products of one loop of (PM), Section 2, in the association printed
+// there: R = I - A X (right form) or I - X A (left form); R^2; R^4 with
+// F1 = I + c1 R^2 + R^4 and F2 = I + c2 R^2 + R^4 in its epilogue; F1 F2 with
+// T = M + c3 R^2 and S = M + d1 R^2 + d2 R^4; T S + mu R^2 + psi R^4 = V;
+// V + R V = W; the update X W (right) or W X (left). With `stab`, the update
+// writes X_{k+1/2} and the stabilising product X_{k+1/2} A X_{k+1/2} of
+// (PM-modified), Section 7, follows, associated so that the middle product is
+// the smaller square. The last product writes the partial sums of the
+// stopping test against X_k into `partials`. Returns the number of calls.
+template <typename T>
+int describe_pm_loop(const Plan& pl, const Set<T>& b, T* Xk, T* Xn, T* Xh, bool stab,
+                     double* partials, GemmCall<T> out[9]) {
+    const PMConst K = pm_const();
+    const int64_t m = pl.m, n = pl.n, sd = pl.s;
+    const int64_t ldS = b.ldS, ldX = b.ldX, ldA = b.ldA;
+    T* R = b.S[0];
+    T* R2 = b.S[1];
+    T* R4 = b.S[2];
+    T* F1 = b.S[3];
+    T* F2 = b.S[4];
+    T* Tm = b.S[5];
+    T* Sm = b.S[6];
+    T* V = F1;  // F1, F2 are dead once T and S exist
+    T* W = F2;
+    int c = 0;
+    {
+        EpilogueT<T> e = epilogue_plain(R, ldS, -1.0, 1.0);
+        if (pl.left) out[c++] = {n, n, m, Xk, ldX, b.A, ldA, e};
+        else out[c++] = {m, m, n, b.A, ldA, Xk, ldX, e};
+    }
+    out[c++] = {sd, sd, sd, R, ldS, R, ldS, epilogue_plain(R2, ldS)};
+    {
+        EpilogueT<T> e{};
+        e.out[0] = R4; e.ldo[0] = ldS; e.acc_c[0] = 1.0;
+        e.out[1] = F1; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.id[1] = 1.0; e.g1[1] = K.c1;
+        e.out[2] = F2; e.ldo[2] = ldS; e.acc_c[2] = 1.0; e.id[2] = 1.0; e.g1[2] = K.c2;
+        e.D1 = R2; e.ld1 = ldS;
+        out[c++] = {sd, sd, sd, R2, ldS, R2, ldS, e};
+    }
+    {
+        EpilogueT<T> e{};
+        e.out[0] = Tm; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.c3;
+        e.out[1] = Sm; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.g1[1] = K.d1; e.g2[1] = K.d2;
+        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
+        out[c++] = {sd, sd, sd, F1, ldS, F2, ldS, e};
+    }
+    {
+        EpilogueT<T> e{};
+        e.out[0] = V; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.mu; e.g2[0] = K.psi;
+        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
+        out[c++] = {sd, sd, sd, Tm, ldS, Sm, ldS, e};
+    }
+    {
+        EpilogueT<T> e{};
+        e.out[0] = W; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = 1.0;
+        e.D1 = V; e.ld1 = ldS;
+        out[c++] = {sd, sd, sd, R, ldS, V, ldS, e};
+    }
+    {
+        EpilogueT<T> e = epilogue_plain(stab ? Xh : Xn, ldX);
+        if (!stab) {
+            e.ref = Xk; e.ldref = ldX; e.partials = partials;
+        }
+        if (pl.left) out[c++] = {n, m, n, W, ldS, Xk, ldX, e};
+        else out[c++] = {n, m, m, Xk, ldX, W, ldS, e};
+    }
+    if (stab) {
+        EpilogueT<T> e = epilogue_plain(Xn, ldX);
+        e.ref = Xk; e.ldref = ldX; e.partials = partials;
+        if (m >= n) {
+            out[c++] = {n, n, m, Xh, ldX, b.A, ldA, epilogue_plain(R, ldS)};
+            out[c++] = {n, m, n, R, ldS, Xh, ldX, e};
+        } else {
+            out[c++] = {m, m, n, b.A, ldA, Xh, ldX, epilogue_plain(R, ldS)};
+            out[c++] = {n, m, m, Xh, ldX, R, ldS, e};
+        }
+    }
+    return c;
+}
+
+// Forms X0 = alpha G (Section 4) in the FP64 iterate b64.X[0] on stream s
+// (products go through `gemm`), synchronises, and returns alpha.
+template <typename GemmFn>
+int setup_x0(const hp_params* p, const Plan& pl, const Buffers& bf, const double* A, int64_t lda,
+             const double* X0, int64_t ldx0, double* host_scal, hipStream_t s, GemmFn&& gemm,
+             double* alpha_out) {
+    const int64_t m = pl.m, n = pl.n;
+    const Set<double>& b = bf.b64;
+    HIPCHK(hipMemcpy2DAsync(b.A, b.ldA * sizeof(double), A, lda * sizeof(double),
+                            n * sizeof(double), m, hipMemcpyDeviceToDevice, s));
+    double* X0w = b.X[0];
+    if (X0) {
+        HIPCHK(hipMemcpy2DAsync(X0w, b.ldX * sizeof(double), X0, ldx0 * sizeof(double),
+                                m * sizeof(double), n, hipMemcpyDeviceToDevice, s));
+        *alpha_out = p->alpha > 0.0 ? p->alpha : 1.0;
+        return HP_OK;
+    }
+    if (p->alpha_rule == HP_ALPHA_USER) {
+        host_scal[SLOT_ALPHA] = p->alpha;
+        HIPCHK(hipMemcpyAsync(bf.scal + SLOT_ALPHA, host_scal + SLOT_ALPHA, sizeof(double),
+                              hipMemcpyHostToDevice, s));
+    }
+    if (p->kind == HP_KIND_MOORE_PENROSE) {
+        if (p->alpha_rule == HP_ALPHA_NORM1INF)
+            HIPCHK(alpha_norm1inf(b.A, b.ldA, m, n, bf.small, bf.scal, s));
+        HIPCHK(transpose_scale(b.A, b.ldA, m, n, X0w, b.ldX, bf.scal + SLOT_ALPHA, s));
+    } else {
+        // G = A^l by repeated products, alpha = 1/Tr(A^{l+1}) = 1/Tr(A^l A)
+        const double* P = b.A;
+        int64_t ldp = b.ldA;
+        double* pp[2] = {b.S[0], b.S[1]};
+        for (int i = 1; i < p->drazin_l; ++i) {
+            double* dst = pp[i & 1];
+            GemmCall<double> g{n, n, n, P, ldp, b.A, b.ldA, epilogue_plain(dst, b.ldS)};
+            CHK(gemm(g));
+            P = dst;
+            ldp = b.ldS;
+        }
+        if (p->alpha_rule == HP_ALPHA_TRACE)
+            HIPCHK(alpha_trace(P, ldp, b.A, b.ldA, n, bf.small, bf.scal, s));
+        HIPCHK(scale(P, ldp, n, n, X0w, b.ldX, bf.scal + SLOT_ALPHA, s));
+    }
+    HIPCHK(hipMemcpyAsync(host_scal, bf.scal, sizeof(double) * SLOT_COUNT, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *alpha_out = host_scal[SLOT_ALPHA];
+    return HP_OK;
+}
+
+// Moore-Penrose only, on entering the FP64 stage from a lower one:
+//     X <- (X A)^T X (A X)^T = A^T X^T X X^T A^T
+// in FP64, which removes the components of X outside R(A^T) x R(A) that
+// rounding in the lower stages left behind and that the loops of (PM) do not
+// correct (first-order analysis in the proof of Theorem 6.2: the off-diagonal
+// error blocks are carried unchanged). This step is not part of the paper: it
+// applies the third and fourth Penrose equations ((AX)^T = AX, (XA)^T = XA),
+// which the Moore-Penrose inverse satisfies. Associated so that every
+// intermediate is min(m, n) square; X is b64.X[0] in and out.
+template <typename GemmFn>
+int project_mp(const Plan& pl, const Buffers& bf, hipStream_t s, GemmFn&& gemm) {
+    const int64_t m = pl.m, n = pl.n;
+    const Set<double>& b = bf.b64;
+    double* X = b.X[0];
+    HIPCHK(transpose_scale(b.A, b.ldA, m, n, bf.At, b.ldX, nullptr, s));  // A^T: n x m
+    HIPCHK(transpose_scale(X, b.ldX, n, m, bf.Xt, b.ldA, nullptr, s));    // X^T: m x n
+    if (m > n) {
+        // (A^T X^T)(X X^T) A^T with n x n intermediates
+        CHK(gemm(GemmCall<double>{n, n, m, bf.At, b.ldX, bf.Xt, b.ldA, epilogue_plain(b.S[0], b.ldS)}));
+        CHK(gemm(GemmCall<double>{n, n, m, X, b.ldX, bf.Xt, b.ldA, epilogue_plain(b.S[1], b.ldS)}));
+        CHK(gemm(GemmCall<double>{n, n, n, b.S[0], b.ldS, b.S[1], b.ldS, epilogue_plain(b.S[2], b.ldS)}));
+        CHK(gemm(GemmCall<double>{n, m, n, b.S[2], b.ldS, bf.At, b.ldX, epilogue_plain(X, b.ldX)}));
+    } else {
+        // A^T (X^T X)(X^T A^T) with m x m intermediates
+        CHK(gemm(GemmCall<double>{m, m, n, bf.Xt, b.ldA, X, b.ldX, epilogue_plain(b.S[0], b.ldS)}));
+        CHK(gemm(GemmCall<double>{m, m, n, bf.Xt, b.ldA, bf.At, b.ldX, epilogue_plain(b.S[1], b.ldS)}));
+        CHK(gemm(GemmCall<double>{m, m, m, b.S[0], b.ldS, b.S[1], b.ldS, epilogue_plain(b.S[2], b.ldS)}));
+        CHK(gemm(GemmCall<double>{n, m, m, bf.At, b.ldX, b.S[2], b.ldS, epilogue_plain(X, b.ldX)}));
+    }
+    return HP_OK;
+}
+
+// Host-side state of one problem's iteration: the stopping rule, the switch
+// to the stabilised variant, the precision stages and the guards.
+struct LoopState {
+    enum Action { CONTINUE, NEXT_STAGE, DONE };
+    const hp_params* p = nullptr;
+    hp_result* res = nullptr;
+    double alpha = 0.0;
+    int stage = 2;        // 0 16-bit, 1 FP32, 2 FP64
+    int final_stage = 2;
+    bool stabilising = false;
+    bool converging = false;
+    bool stage_first = true;  // no stagnation test on a stage's first loop
+    double d_prev = 0.0;
+    int ik = 0, in_ = 1;  // current and next iterate (index into the stage's set)
+    int k = 0;            // loops run
+    int status = HP_MAXITER;
+    int result_idx = -1;  // iterate to return (index into the final stage's set)
+    int from_idx = 0;     // NEXT_STAGE: iterate the next stage starts from
+
+    void init(const hp_params* prm, hp_result* r, double a);
+    Engine engine() const;
+    // Digest one loop's sums; `dinf` is used if have_dinf.
+    Action step(double diff2, double ref2, double dinf, bool have_dinf);
+    // After NEXT_STAGE the caller moves the iterate `from_idx` into the next
+    // stage's set; this resets the indices (FP64 stage: X[0]).
+    void enter_stage(int next);
+    bool done() const { return result_idx >= 0; }
+    void finish_maxiter() {
+        if (result_idx < 0) result_idx = ik;
+    }
+};
+
+}  // namespace hp

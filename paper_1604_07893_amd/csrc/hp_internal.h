@@ -78,6 +78,31 @@ hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const double* A, in
 hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                 const float* B, int64_t ldb, const EpilogueT<float>& ep, hipStream_t s);
 
+// Grouped products: one persistent launch computes every entry of a device
+// table. Tiles are grouped_tile_m() x grouped_tile_n(); entry e covers tiles
+// [tile_start, tile_start + tiles_m * tiles_n) and writes its partial sums
+// (if ep.ref) to ep.partials[2*local_tile ...].
+struct GroupHeader {
+    int count;        // entries in the table
+    int total_tiles;  // sum of the entries' tile counts
+};
+template <typename T>
+struct GroupEntry {
+    int M, N, K, tiles_n;
+    int tile_start, pad;
+    const T* A;
+    int64_t lda;
+    const T* B;
+    int64_t ldb;
+    EpilogueT<T> ep;
+};
+int grouped_tile_m();
+int grouped_tile_n();
+hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<double>* ents, int grid,
+                        hipStream_t s);
+hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<float>* ents, int grid,
+                        hipStream_t s);
+
 // 16-bit MFMA product of FP32 matrices (operands rounded to nearest even while
 // staged, FP32 accumulation); lda/ldb multiples of 4 floats.
 enum LowPrec : int { LOWP_BF16 = 0, LOWP_F16 = 1 };
@@ -95,7 +120,7 @@ hipError_t alpha_norm1inf(const double* A, int64_t lda, int64_t M, int64_t N, do
 hipError_t alpha_trace(const double* P, int64_t ldp, const double* A, int64_t lda, int64_t n,
                        double* tmp, double* scal, hipStream_t s);
 
-// Y[j][i] = (*alpha_dev) * A[i][j]; A is M x N, Y is N x M.
+// Y[j][i] = (*alpha_dev) * A[i][j] (alpha_dev NULL: 1); A is M x N, Y is N x M.
 hipError_t transpose_scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y,
                            int64_t ldy, const double* alpha_dev, hipStream_t s);
 

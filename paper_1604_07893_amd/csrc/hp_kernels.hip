@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_transpose_scale(const double* __re
     __shared__ double t[32][33];
     const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const double al = *alpha;
+    const double al = alpha ? *alpha : 1.0;
     for (int y = ty; y < 32; y += 8) {
         const int i = bi + y, j = bj + tx;
         if (i < M && j < N) t[y][tx] = A[(int64_t)i * lda + j];
@@ -205,6 +205,29 @@ __global__ __launch_bounds__(kThreads) void k_max_to_slot(const double* __restri
     __syncthreads();
     const double r = block_max(nan ? 0.0 : m);
     if (threadIdx.x == 0) scal[slot] = any_nan ? __builtin_nan("") : r;
+}
+
+// One block per problem: fixed-order sums of that problem's partial pairs.
+struct ReduceEntryDev {
+    const double* partials;
+    int npairs;
+    int pad;
+};
+
+__global__ __launch_bounds__(kThreads) void k_reduce_pairs_grouped(const ReduceEntryDev* __restrict__ ents,
+                                                                   double* __restrict__ out) {
+    const ReduceEntryDev e = ents[blockIdx.x];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < e.npairs; b += kThreads) {
+        s0 += e.partials[2 * b];
+        s1 += e.partials[2 * b + 1];
+    }
+    s0 = block_sum(s0);
+    s1 = block_sum(s1);
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = s0;
+        out[2 * blockIdx.x + 1] = s1;
+    }
 }
 
 // Elementwise precision conversion of an M x N matrix (round to nearest even
@@ -299,6 +322,23 @@ hipError_t convert(const double* X, int64_t ldx, int64_t M, int64_t N, float* Y,
 hipError_t convert(const float* X, int64_t ldx, int64_t M, int64_t N, double* Y, int64_t ldy,
                    hipStream_t s) {
     return convert_impl(X, ldx, M, N, Y, ldy, s);
+}
+
+}  // namespace hp
+
+namespace hp {
+
+struct ReduceEntry {
+    const double* partials;
+    int npairs;
+    int pad;
+};
+static_assert(sizeof(ReduceEntry) == sizeof(ReduceEntryDev), "reduce table layout");
+
+hipError_t reduce_pairs_grouped(const ReduceEntry* ents, int count, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_pairs_grouped, dim3((unsigned)count), dim3(kThreads), 0, s,
+                       reinterpret_cast<const ReduceEntryDev*>(ents), out);
+    return hipGetLastError();
 }
 
 }  // namespace hp

@@ -29,7 +29,7 @@ ALPHA = {"norm1inf": 0, "user": 1, "trace": 2}
 VARIANT = {"plain": 0, "stabilised": 1, "stabilized": 1, "stab_always": 2}
 SIDE = {"auto": 0, "right": 1, "left": 2}
 STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2}
-PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
+PREC = {"fp64": 0, "fp32": 1, "mixed": 2, "fp32_fp64": 3}
 LOWP = {"bf16": 0, "f16": 1, "fp16": 1}
 FLAG_TIME_KERNELS, FLAG_INF_NORM = 1, 2
 DTYPE = {torch.float64: 0, torch.float32: 1}
@@ -52,7 +52,15 @@ class HpResult(ctypes.Structure):
         ("alpha", c_double), ("d_last", c_double), ("stop_last", c_double), ("coc", c_double),
         ("gflop", c_double), ("time_ms", c_double), ("gemm_ms", c_double),
         ("d_stage", c_double * 3), ("gflop_stage", c_double * 3),
+        ("queue_ms", c_double), ("run_ms", c_double),
         ("d_hist", c_double * HP_HIST), ("dinf_hist", c_double * HP_HIST),
+    ]
+
+
+class HpProblem(ctypes.Structure):
+    _fields_ = [
+        ("A", c_void_p), ("m", c_int64), ("n", c_int64), ("lda", c_int64),
+        ("X0", c_void_p), ("ldx0", c_int64), ("X", c_void_p), ("ldx", c_int64),
     ]
 
 
@@ -69,6 +77,16 @@ SIGNATURES = {
                          POINTER(HpResult)]),
     "hp_gemm": (c_int, [c_void_p, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
                         c_void_p, c_int64, c_double, c_void_p, c_int64, c_void_p]),
+    "hp_batched_workspace_bytes": (c_int, [POINTER(HpParams), c_int, POINTER(HpProblem),
+                                           POINTER(c_size_t)]),
+    "hp_solve_batched": (c_int, [c_void_p, POINTER(HpParams), c_int, POINTER(HpProblem), c_void_p,
+                                 c_size_t, c_void_p, POINTER(HpResult)]),
+    "hp_serve_create": (c_int, [c_void_p, POINTER(HpParams), c_size_t, c_int, c_void_p,
+                                POINTER(c_void_p)]),
+    "hp_serve_submit": (c_int, [c_void_p, POINTER(HpProblem), POINTER(ctypes.c_uint64)]),
+    "hp_serve_step": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int)]),
+    "hp_serve_poll": (c_int, [c_void_p, ctypes.c_uint64, POINTER(HpResult)]),
+    "hp_serve_destroy": (c_int, [c_void_p]),
 }
 
 _lib = None
@@ -182,7 +200,7 @@ def result_dict(r: HpResult) -> dict:
         "alpha": r.alpha, "d_last": r.d_last, "stop_last": r.stop_last, "coc": r.coc,
         "gflop": r.gflop, "time_ms": r.time_ms, "gemm_ms": r.gemm_ms,
         "iters_stage": list(r.iters_stage), "d_stage": list(r.d_stage),
-        "gflop_stage": list(r.gflop_stage),
+        "gflop_stage": list(r.gflop_stage), "queue_ms": r.queue_ms, "run_ms": r.run_ms,
         "d_hist": list(r.d_hist[:it]), "dinf_hist": list(r.dinf_hist[:it]),
     }
 
@@ -262,3 +280,105 @@ def gemm(A: torch.Tensor, B: torch.Tensor, *, alpha: float = 1.0, beta_identity:
     if rc != HP_OK:
         raise HyperpowerError(rc, "hp_gemm")
     return out
+
+
+def _problem(A: torch.Tensor, X: torch.Tensor, X0: torch.Tensor | None = None) -> HpProblem:
+    _check_matrix(A, "A")
+    _check_matrix(X, "X")
+    m, n = A.shape
+    if tuple(X.shape) != (n, m):
+        raise ValueError("X must be n x m")
+    pr = HpProblem()
+    pr.A, pr.m, pr.n, pr.lda = A.data_ptr(), m, n, A.stride(0)
+    pr.X, pr.ldx = X.data_ptr(), X.stride(0)
+    if X0 is not None:
+        _check_matrix(X0, "X0")
+        pr.X0, pr.ldx0 = X0.data_ptr(), X0.stride(0)
+    return pr
+
+
+def solve_batched(As: list, *, stream: torch.cuda.Stream | None = None,
+                  **kw) -> tuple[list, list]:
+    """Generalized inverses of several matrices (uneven shapes) in grouped
+    launches; returns ([X_i], [info_i])."""
+    if not As:
+        return [], []
+    dev = As[0].device
+    params = make_params(**kw)
+    Xs = [torch.empty((a.shape[1], a.shape[0]), dtype=torch.float64, device=dev) for a in As]
+    probs = (HpProblem * len(As))(*[_problem(a, x) for a, x in zip(As, Xs)])
+    lib = load_library()
+    nb = c_size_t()
+    rc = lib.hp_batched_workspace_bytes(ctypes.byref(params), len(As), probs, ctypes.byref(nb))
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_batched_workspace_bytes")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    outs = (HpResult * len(As))()
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    rc = lib.hp_solve_batched(handle(idx).ptr, ctypes.byref(params), len(As), probs, ws.data_ptr(),
+                              ws.numel(), s.cuda_stream, outs)
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_solve_batched")
+    return Xs, [result_dict(o) for o in outs]
+
+
+class Server:
+    """Continuous-batching request server (hp_serve_*): submit() queues a
+    request, step() admits what fits the HBM budget and the slot count and runs
+    one loop of every admitted request, poll() returns finished results."""
+
+    def __init__(self, *, hbm_budget: int = 1 << 30, max_slots: int = 64,
+                 device: int | None = None, stream: torch.cuda.Stream | None = None, **kw):
+        self.lib = load_library()
+        self.dev = torch.cuda.current_device() if device is None else device
+        self.params = make_params(**kw)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        ptr = c_void_p()
+        rc = self.lib.hp_serve_create(handle(self.dev).ptr, ctypes.byref(self.params),
+                                      int(hbm_budget), int(max_slots), self.stream.cuda_stream,
+                                      ctypes.byref(ptr))
+        if rc != HP_OK:
+            raise HyperpowerError(rc, "hp_serve_create")
+        self.ptr = ptr
+        self._keep: dict[int, tuple] = {}
+
+    def submit(self, A: torch.Tensor, X: torch.Tensor | None = None) -> int:
+        if X is None:
+            X = torch.empty((A.shape[1], A.shape[0]), dtype=torch.float64, device=A.device)
+        pr = _problem(A, X)
+        t = ctypes.c_uint64()
+        rc = self.lib.hp_serve_submit(self.ptr, ctypes.byref(pr), ctypes.byref(t))
+        if rc != HP_OK:
+            raise HyperpowerError(rc, "hp_serve_submit")
+        self._keep[t.value] = (A, X)  # the library reads A and writes X until done
+        return t.value
+
+    def step(self) -> tuple[int, int]:
+        a, w = c_int(), c_int()
+        rc = self.lib.hp_serve_step(self.ptr, ctypes.byref(a), ctypes.byref(w))
+        if rc != HP_OK:
+            raise HyperpowerError(rc, "hp_serve_step")
+        return a.value, w.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (X, info)."""
+        r = HpResult()
+        rc = self.lib.hp_serve_poll(self.ptr, ticket, ctypes.byref(r))
+        if rc == HP_PENDING:
+            return None
+        if rc < 0:
+            raise HyperpowerError(rc, "hp_serve_poll")
+        _, X = self._keep.pop(ticket)
+        return X, result_dict(r)
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            self.lib.hp_serve_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

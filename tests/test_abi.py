@@ -23,7 +23,9 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("hp_version", "hp_status_string", "hp_params_default", "hp_create",
-                     "hp_destroy", "hp_workspace_bytes", "hp_solve", "hp_gemm"):
+                     "hp_destroy", "hp_workspace_bytes", "hp_solve", "hp_gemm",
+                     "hp_batched_workspace_bytes", "hp_solve_batched", "hp_serve_create",
+                     "hp_serve_submit", "hp_serve_step", "hp_serve_poll", "hp_serve_destroy"):
         assert required in names
 
 
@@ -46,7 +48,8 @@ def test_host_only_calls():
     assert p.tol == 1e-12 and p.max_iter == 100 and abs(p.tau_switch - 0.1) < 1e-15
     # struct layouts mirror the header
     assert ctypes.sizeof(hpw.HpParams) == 96
-    assert ctypes.sizeof(hpw.HpResult) == 32 + 7 * 8 + 6 * 8 + 2 * 128 * 8
+    assert ctypes.sizeof(hpw.HpResult) == 32 + 7 * 8 + 8 * 8 + 2 * 128 * 8
+    assert ctypes.sizeof(hpw.HpProblem) == 8 * 8
     # workspace sizes grow with the problem and reject bad arguments
     small = hpw.workspace_bytes(p, 200, 100)
     big = hpw.workspace_bytes(p, 4096, 2048)

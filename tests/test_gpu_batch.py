@@ -1,0 +1,120 @@
+"""Batched (grouped launches) and served (continuous batching) forms against
+the oracle, plus the alone-vs-in-mix identity of each result."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_common import need_gpu, rel, say, to_dev
+from paper_1604_07893_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_problems(seed=40):
+    rng = np.random.default_rng(seed)
+    shapes = [(64, 64, False), (130, 65, False), (65, 130, False), (257, 129, False),
+              (300, 75, False), (96, 96, True), (200, 100, True), (128, 128, False)]
+    return [inputs.request_matrix(rng, m, n, d) for m, n, d in shapes]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_fp64"])
+def test_batched_matches_oracle(precision):
+    hpw = need_gpu()
+    say(f"batched {precision}")
+    As = mixed_problems()
+    Xs, infos = hpw.solve_batched([to_dev(a) for a in As], variant="stabilised", tol=1e-12,
+                                  precision=precision)
+    torch.cuda.synchronize()
+    for A, X, info in zip(As, Xs, infos):
+        ref = O.solve(A, kind="mp", variant="stabilised", tol=1e-12)
+        ref_p = np.linalg.pinv(A, rcond=1e-10)
+        err = rel(X.cpu().numpy(), ref.X)
+        say(f"  {A.shape} {info['status']} iters {info['iters']} stages {info['iters_stage']} "
+            f"err {err:.2e} vs pinv {rel(X.cpu().numpy(), ref_p):.2e}")
+        assert info["status"] in ("ok", "stagnated")
+        assert err <= 1e-10
+        assert rel(X.cpu().numpy(), ref_p) <= 1e-9
+
+
+def test_batched_alone_equals_in_mix_bitwise():
+    hpw = need_gpu()
+    As = mixed_problems(41)
+    dev = [to_dev(a) for a in As]
+    Xs, _ = hpw.solve_batched(dev, variant="stabilised", tol=1e-12, precision="fp32_fp64")
+    for i in (0, 3, 6):
+        Xa, _ = hpw.solve_batched([dev[i]], variant="stabilised", tol=1e-12, precision="fp32_fp64")
+        assert torch.equal(Xa[0], Xs[i]), i
+
+
+def test_server_continuous_batching_and_budget():
+    """Requests submitted while others run are admitted as memory frees up;
+    every result equals the same request served alone (bitwise) and matches
+    the oracle."""
+    hpw = need_gpu()
+    rng = np.random.default_rng(42)
+    shapes = [(256, 128), (512, 512), (64, 64), (384, 96), (128, 256), (200, 200), (96, 48)]
+    As = [rng.standard_normal(s) for s in shapes]
+    kw = dict(variant="stabilised", tol=1e-12, precision="fp32_fp64")
+    budget = 24 << 20  # too small for all at once: forces waiting and reuse
+    srv = hpw.Server(hbm_budget=budget, max_slots=4, **kw)
+    tickets = []
+    done = {}
+    max_active, saw_waiting = 0, False
+    for i, A in enumerate(As):
+        tickets.append(srv.submit(to_dev(A)))
+        if i % 2 == 1:  # interleave arrivals with steps
+            a, w = srv.step()
+            max_active, saw_waiting = max(max_active, a), saw_waiting or w > 0
+    steps = 0
+    while len(done) < len(As) and steps < 500:
+        a, w = srv.step()
+        max_active, saw_waiting = max(max_active, a), saw_waiting or w > 0
+        steps += 1
+        for i, t in enumerate(tickets):
+            if i not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[i] = r
+    srv.close()
+    assert len(done) == len(As)
+    assert 1 < max_active <= 4 and saw_waiting
+    for i, A in enumerate(As):
+        X, info = done[i]
+        assert info["status"] in ("ok", "stagnated")
+        ref = O.solve(A, kind="mp", variant="stabilised", tol=1e-12)
+        assert rel(X.cpu().numpy(), ref.X) <= 1e-10
+        assert info["queue_ms"] >= 0 and info["run_ms"] > 0
+        alone = hpw.Server(hbm_budget=budget, max_slots=4, **kw)
+        t = alone.submit(to_dev(A))
+        r = None
+        while r is None:
+            alone.step()
+            r = alone.poll(t)
+        alone.close()
+        assert torch.equal(r[0], X), i
+
+
+def test_server_rejects_request_over_budget():
+    hpw = need_gpu()
+    srv = hpw.Server(hbm_budget=1 << 20, max_slots=2, precision="fp64")
+    with pytest.raises(hpw.HyperpowerError) as e:
+        srv.submit(torch.zeros((1024, 1024), dtype=torch.float64, device="cuda:0"))
+    assert e.value.code == hpw.HP_EBUDGET
+    srv.close()
+
+
+def test_single_fp32_fp64_rectangular_uses_projection():
+    """FP32 loops then FP64 loops on a rectangular input reach FP64 accuracy
+    (the projection onto the Penrose conditions removes the FP32 error left in
+    the blocks the iteration does not correct)."""
+    hpw = need_gpu()
+    rng = np.random.default_rng(43)
+    for (m, n, d) in [(512, 256, False), (300, 150, True), (150, 300, False)]:
+        A = inputs.request_matrix(rng, m, n, d)
+        ref = np.linalg.pinv(A, rcond=1e-10)
+        X, info = hpw.solve(to_dev(A), variant="stabilised", precision="fp32_fp64", tol=1e-12)
+        err = rel(X.cpu().numpy(), ref)
+        say(f"  {m}x{n} deficient={d} stages {info['iters_stage']} err {err:.2e}")
+        assert err <= 1e-10
