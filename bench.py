@@ -1,18 +1,21 @@
 """Benchmark: Moore-Penrose inverses per second of the 18th-order hyperpower
 iteration on one MI355X.
 
-Workload (one step = one complete inverse, inputs resident in HBM):
+Headline workload (one step = one complete inverse, inputs resident in HBM):
 rectangular rank-deficient A = U diag(s) V^T, 4096 x 2048, rank 1536, U and V
 Haar-orthogonal (seeded), nonzero s log-spaced in [1e-4, 1]; X0 = A^T /
 sigma_max^2 (sigma_max = 1 by construction); the stabilised variant (plain
 seven-product loops, then X <- X A X loops once the relative change drops below
 0.1); FP64; stop at relative Frobenius change < 1e-10.
 
-Prints one JSON line with the throughput, the roofline of the dominant kernel
-(the FP64 MFMA GEMM: executed 2MNK flops over its summed hipEvent time on the
-solve stream) and a CPU baseline (the oracle timed on this host).
+The same JSON line carries the roofline of the dominant kernel (the FP64 MFMA
+GEMM: executed 2MNK flops over its hipEvent-timed launches on the solve
+stream), a CPU baseline (the oracle on this host, bounded sample), and under
+"extras" the other workloads: the same input in FP32; a square 8192 x 8192
+(s log-uniform in [1e-3, 1]) in mixed precision against FP64; a 2048 x 2048
+Drazin input (index 3); and a served Poisson stream with p50/p99 latency.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline] [--no-extras]
 """
 
 from __future__ import annotations
@@ -29,11 +32,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "inverses/s + GEMM TFLOP/s at rel. residual 1e-10, mixed vs FP64; p99 latency"
-PEAK_FP64_TFLOPS = 78.6
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 M, N, RANK, SMIN, SEED, TOL = 4096, 2048, 1536, 1e-4, 1002, 1e-10
 WORKLOAD = (f"moore-penrose {M}x{N} rank {RANK}, s log-spaced [{SMIN:g},1], Haar U/V seed {SEED}; "
             f"X0=A^T/sigma_max^2; stabilised (switch at rel. change < 0.1); fp64; "
             f"stop rel. Frobenius change < {TOL:g}")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def timed_solves(hpw, torch, A, steps, warmup, **params):
+    """Run warmup + steps solves on resident inputs; returns (seconds per
+    inverse, infos, X)."""
+    dev = A.device
+    m, n = A.shape
+    nbytes = hpw.workspace_bytes(hpw.make_params(**params), m, n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    X = torch.empty((n, m), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(warmup):
+        hpw.solve(A, out=X, workspace=ws, stream=stream, **params)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = hpw.solve(A, out=X, workspace=ws, stream=stream, **params)
+        infos.append(info)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, infos, X
 
 
 def cpu_baseline(d, n_plain: int, n_stab: int) -> dict:
@@ -64,12 +96,135 @@ def cpu_baseline(d, n_plain: int, n_stab: int) -> dict:
                        f"{n_stab} stabilised loops per inverse")}
 
 
+def extra_fp32(hpw, torch, A, closed, steps):
+    sec, infos, X = timed_solves(hpw, torch, A, steps, 1, alpha_rule="user", alpha=1.0,
+                                 variant="stabilised", tol=TOL, precision="fp32")
+    return {"workload": "same 4096x2048 input, FP32 loops", "inverses_per_s": 1 / sec,
+            "status": infos[-1]["status"], "iters": infos[-1]["iters"],
+            "rel_err_vs_closed_form": rel(X.cpu().numpy(), closed),
+            "note": "FP32 cannot reach 1e-10 at kappa = 1e4; the run ends at its floor"}
+
+
+def extra_mixed(hpw, torch, steps):
+    from paper_1604_07893_amd import inputs
+    n = 8192
+    A, U, s, V = inputs.square_svd_device(n, smin=1e-3, seed=1003)
+    torch.cuda.synchronize()
+    out = {"workload": f"square {n}x{n}, s log-uniform [1e-3,1], Haar U/V (seed 1003, built on "
+                       "the GPU); X0=A^T; plain; tol 1e-10"}
+    ref = None
+    for prec in ("fp64", "mixed"):
+        sec, infos, X = timed_solves(hpw, torch, A, steps, 1, alpha_rule="user", alpha=1.0,
+                                     tol=TOL, precision=prec, time_kernels=True)
+        inf = infos[-1]
+        if ref is None:
+            # closed form V diag(1/s) U^T, on the GPU in FP64 (a reference, not the method)
+            ref = (V / s) @ U.T.contiguous()
+        err = float(torch.linalg.norm(X - ref) / torch.linalg.norm(ref))
+        gf = sum(i["gflop"] for i in infos) / len(infos)
+        out[prec] = {"inverses_per_s": 1 / sec, "ms_per_inverse": sec * 1e3, "status": inf["status"],
+                     "iters": inf["iters"], "iters_stage": inf["iters_stage"],
+                     "gflop_stage": inf["gflop_stage"], "gflop_per_inverse": gf,
+                     "gemm_tflops": gf / (sum(i["gemm_ms"] for i in infos) / len(infos)),
+                     "rel_err_vs_closed_form": err}
+        if prec == "mixed":
+            caps = np.cumsum(inf["iters_stage"])
+            per_stage = []
+            for cap in caps[:2]:
+                Xs, _ = hpw.solve(A, alpha_rule="user", alpha=1.0, tol=TOL, precision=prec,
+                                  max_iter=int(cap))
+                per_stage.append(float(torch.linalg.norm(Xs - ref) / torch.linalg.norm(ref)))
+            per_stage.append(err)
+            out[prec]["rel_err_after_stage"] = per_stage
+        log(f"mixed-vs-fp64 {prec}: {out[prec]}")
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["inverses_per_s"] / out["fp64"]["inverses_per_s"]
+    del A, U, s, V, ref
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_drazin(hpw, torch, steps):
+    from paper_1604_07893_amd import inputs
+    d = inputs.drazin_jordan(n=2048, nb=1792, cond_p=10.0, seed=1004)
+    nb = d.Q.shape[0]
+    J = np.zeros_like(d.A)
+    J[:nb, :nb] = (d.Q / d.lam) @ d.Q.T
+    closed = d.P @ J @ d.Pinv
+    A = torch.from_numpy(d.A).cuda()
+    out = {"workload": "drazin 2048x2048, B 1792 (eig U[0.5,2]), nilpotent 256 (index 3), "
+                       "cond(P)=10; X0=A^3/Tr(A^4); tol 1e-10"}
+    for variant in ("plain", "stabilised"):
+        sec, infos, X = timed_solves(hpw, torch, A, steps, 1, kind="drazin", l=3, variant=variant,
+                                     tol=TOL)
+        out[variant] = {"inverses_per_s": 1 / sec, "status": infos[-1]["status"],
+                        "iters": infos[-1]["iters"], "rel_err_vs_closed_form": rel(X.cpu().numpy(), closed)}
+    return out
+
+
+def extra_served(hpw, torch, n_req: int, warm: int):
+    """Poisson stream of Moore-Penrose requests (m log-uniform in [64, 2048],
+    n = m/r, r in {1,2,4}, N(0,1), 10% rank-deficient at half rank) through the
+    continuous-batching server, FP32 loops then FP64 (with the Penrose
+    projection), at 80% of the measured saturation rate."""
+    from paper_1604_07893_amd import inputs
+    kw = dict(variant="stabilised", tol=1e-10, precision="fp32_fp64")
+    budget = 32 << 30
+    reqs = inputs.request_stream(n_req + warm, qps=1.0, seed=1005)
+    mats = [torch.from_numpy(r.A).cuda() for r in reqs]
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        srv = hpw.Server(hbm_budget=budget, max_slots=64, **kw)
+        t0 = time.perf_counter()
+        pending = {}
+        lat, nxt, done = [], 0, 0
+        res = []
+        while done < len(mats):
+            now = time.perf_counter() - t0
+            while nxt < len(mats) and arrivals[nxt] <= now:
+                pending[srv.submit(mats[nxt])] = (nxt, arrivals[nxt])
+                nxt += 1
+            if not pending:
+                time.sleep(max(0.0, min(arrivals[nxt] - now, 0.001)))
+                continue
+            srv.step()
+            t_now = time.perf_counter() - t0
+            for tk in list(pending):
+                r = srv.poll(tk)
+                if r is not None:
+                    i, arr = pending.pop(tk)
+                    lat.append((i, t_now - arr))
+                    res.append((i, r[1]))
+                    done += 1
+        wall = time.perf_counter() - t0
+        srv.close()
+        return wall, lat, res
+
+    # saturation: everything arrives at t = 0
+    wall0, _, _ = run([0.0] * len(mats))
+    sat = len(mats) / wall0
+    qps = 0.8 * sat
+    rng = np.random.default_rng(1005)
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(mats))).tolist()
+    wall, lat, res = run(arrivals)
+    lat_ms = np.array([l for i, l in sorted(lat) if i >= warm]) * 1e3
+    statuses = [r["status"] for i, r in res]
+    return {"workload": (f"{n_req} Poisson requests (+{warm} warm-up), m log-uniform [64,2048], "
+                         "n=m/r r in {1,2,4}, N(0,1), 10% rank-deficient; FP32 loops + FP64 "
+                         "final loops in grouped launches; budget 32 GiB, 64 slots"),
+            "saturation_req_per_s": sat, "offered_qps": qps,
+            "inverses_per_s": len(mats) / wall, "p50_ms": float(np.percentile(lat_ms, 50)),
+            "p99_ms": float(np.percentile(lat_ms, 99)),
+            "ok_fraction": statuses.count("ok") / len(statuses)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hyperpower "
@@ -84,27 +239,11 @@ def main() -> int:
     dev = torch.device("cuda:0")
     d = inputs.lowrank_svd(M, N, RANK, smin=SMIN, seed=SEED)
     A = torch.from_numpy(d.A).to(dev)
-    params = dict(alpha_rule="user", alpha=1.0, variant="stabilised", tol=TOL)
-    nbytes = hpw.workspace_bytes(hpw.make_params(**params), M, N)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    X = torch.empty((N, M), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream(dev)
-
-    for _ in range(args.warmup):
-        hpw.solve(A, out=X, workspace=ws, stream=stream, **params)
-    torch.cuda.synchronize()
-
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, info = hpw.solve(A, out=X, workspace=ws, stream=stream, time_kernels=True, **params)
-        infos.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
     closed = (d.V / d.s) @ d.U.T
-    Xh = X.cpu().numpy()
-    err = float(np.linalg.norm(Xh - closed) / np.linalg.norm(closed))
+    params = dict(alpha_rule="user", alpha=1.0, variant="stabilised", tol=TOL)
+    sec, infos, X = timed_solves(hpw, torch, A, args.steps, args.warmup, time_kernels=True,
+                                 **params)
+    err = rel(X.cpu().numpy(), closed)
 
     gflop = sum(i["gflop"] for i in infos)
     gemm_ms = sum(i["gemm_ms"] for i in infos)
@@ -116,12 +255,12 @@ def main() -> int:
 
     line = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": 1.0 / sec,
         "unit": "inverses/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": sec * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -131,22 +270,36 @@ def main() -> int:
                    "side": last["side"], "precision": "fp64", "tol": TOL},
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_gemm_f64",
+            "kernel": "k_gemm (FP64 MFMA GEMM with the fused loop epilogue)",
             "achieved": achieved,
-            "peak": PEAK_FP64_TFLOPS,
+            "peak": PEAK_TFLOPS["f64"],
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS,
+            "frac": achieved / PEAK_TFLOPS["f64"],
             "traffic": None,
             "gflop_per_launch": gflop / max(launches, 1),
             "avg_launch_ms": gemm_ms / max(launches, 1),
         },
-        "gemm_tflops_executed": gflop / (elapsed * 1e3),
+        "gemm_tflops_executed": gflop / (sec * args.steps * 1e3),
         "iters": last["iters"],
         "plain_loops": n_plain,
         "stabilised_loops": n_stab,
         "status": last["status"],
         "rel_err_vs_closed_form": err,
     }
+    log(f"headline: {1 / sec:.2f} inverses/s, GEMM {achieved:.1f} TFLOP/s, err {err:.2e}")
+    if not args.no_extras:
+        extras = {}
+        for name, fn in (("fp32_4096x2048", lambda: extra_fp32(hpw, torch, A, closed, 5)),
+                         ("mixed_vs_fp64_8192", lambda: extra_mixed(hpw, torch, 2)),
+                         ("drazin_2048", lambda: extra_drazin(hpw, torch, 3)),
+                         ("served_stream", lambda: extra_served(hpw, torch, 300, 30))):
+            t0 = time.perf_counter()
+            try:
+                extras[name] = fn()
+            except Exception as e:  # a failing extra must not hide the headline
+                extras[name] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"extra {name} done in {time.perf_counter() - t0:.1f} s")
+        line["extras"] = extras
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(d, n_plain, n_stab)
     print(json.dumps(line), flush=True)

@@ -56,7 +56,8 @@ extern "C" {
 /* ---- enums --------------------------------------------------------------- */
 /* which outer inverse (Section 1.2; X0 rules of Section 4) */
 #define HP_KIND_MOORE_PENROSE 0   /* G = A^T, limit A^dagger (any m, n) */
-#define HP_KIND_DRAZIN 1          /* G = A^l, limit A^D (m == n, l >= ind(A)) */
+#define HP_KIND_DRAZIN 1          /* G = A^l, limit A^D (m == n, l >= ind(A));
+                                     HP_PREC_FP64 only (HP_EUNSUPPORTED otherwise) */
 
 /* scaling alpha of X0 = alpha*G (Section 4) */
 #define HP_ALPHA_NORM1INF 0  /* Moore-Penrose: alpha = 1/(||A||_1 ||A||_inf) */
@@ -100,7 +101,13 @@ extern "C" {
                            passes. A stage ends when its relative change stops
                            halving (below 1) or falls under 10x its unit
                            roundoff; the FP64 stage alone applies the stop test
-                           and the stagnation guard. */
+                           and the stagnation guard. For Moore-Penrose input
+                           that is not square, or whose lower stage stalled
+                           above its rounding floor, the FP64 stage starts with
+                           X <- (XA)^T X (AX)^T: FP32 error in the parts of X
+                           outside R(A^T) x R(A) is not corrected by the loops
+                           (an addition to the paper's method, from its third
+                           and fourth Penrose equations). */
 
 /* hp_params.low_dtype: operand type of the first mixed stage */
 #define HP_LOWP_BF16 0

@@ -122,6 +122,8 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
     if (p->kind != HP_KIND_MOORE_PENROSE && p->kind != HP_KIND_DRAZIN) return HP_EINVAL;
     if (p->kind == HP_KIND_DRAZIN) {
         if (m != n || p->drazin_l < 1 || p->drazin_l > 64) return HP_EINVAL;
+        // lower-precision stages are not stable on the nilpotent part
+        if (p->precision != HP_PREC_FP64) return HP_EUNSUPPORTED;
         if (p->alpha_rule != HP_ALPHA_TRACE && p->alpha_rule != HP_ALPHA_USER) return HP_EINVAL;
     } else if (p->alpha_rule != HP_ALPHA_NORM1INF && p->alpha_rule != HP_ALPHA_USER) {
         return HP_EINVAL;
@@ -244,6 +246,7 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         if (!finite || stalled || floor) {
             const bool keep_new = finite && !(stalled && d >= d_prev);
             from_idx = keep_new ? in_ : ik;
+            exit_floor = finite && floor && !stalled;
             d_prev = d;
             return NEXT_STAGE;
         }
@@ -414,7 +417,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
             const int next = st.stage + 1;
             if (next == 2) {
                 HIPCHK(convert(bf.b32.X[st.from_idx], bf.b32.ldX, n, m, bf.b64.X[0], bf.b64.ldX, s));
-                if (pl.has_proj) {
+                if (needs_projection(pl, st.exit_floor)) {
                     S.stage = 2;
                     CHK(project_mp(pl, bf, s, [&](const GemmCall<double>& g) {
                         return S.gemm<double>(ENG_F64, g);

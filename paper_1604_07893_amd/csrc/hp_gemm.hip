@@ -130,44 +130,57 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
     const int bm = tm * BM, bn = tn * BN;
     const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
 
+    // Global -> register staging. Every load is issued unconditionally from an
+    // address that is always inside the operand (out-of-range rows/columns are
+    // redirected to element 0) so the loads of a K-tile go out back to back;
+    // out-of-range elements are zeroed when the registers are written to LDS.
     const int a_k = V * (tid % C::A_TPR), a_r = tid / C::A_TPR;
     const int b_n = V * (tid % C::B_TPR), b_k = tid / C::B_TPR;
     VT ra[C::A_PASS], rb[C::B_PASS];
+    const T* a_ptr[C::A_PASS];
+    bool a_row_ok[C::A_PASS];
+#pragma unroll
+    for (int p = 0; p < C::A_PASS; ++p) {
+        const int row = bm + a_r + C::A_RPP * p;
+        a_row_ok[p] = row < M;
+        a_ptr[p] = A + (int64_t)(a_row_ok[p] ? row : 0) * lda + a_k;
+    }
+    const int b_col = bn + b_n;
+    const bool b_col_ok = b_col < N;
+    const T* b_ptr = B + (b_col_ok ? b_col : 0) + (int64_t)b_k * ldb;
 
     auto load = [&](int k0) {
+        const bool ka = k0 + a_k < K;
 #pragma unroll
         for (int p = 0; p < C::A_PASS; ++p) {
-            const int row = bm + a_r + C::A_RPP * p, k = k0 + a_k;
-            VT v = {};
-            if (row < M && k < K) {
-                v = *reinterpret_cast<const VT*>(A + (int64_t)row * lda + k);
-#pragma unroll
-                for (int e = 1; e < V; ++e)
-                    if (k + e >= K) v[e] = T(0);
-            }
-            ra[p] = v;
+            const T* src = (a_row_ok[p] && ka) ? a_ptr[p] + k0 : A;
+            ra[p] = *reinterpret_cast<const VT*>(src);
         }
 #pragma unroll
         for (int p = 0; p < C::B_PASS; ++p) {
-            const int kr = k0 + b_k + C::B_RPP * p, c = bn + b_n;
-            VT v = {};
-            if (kr < K && c < N) {
-                v = *reinterpret_cast<const VT*>(B + (int64_t)kr * ldb + c);
-#pragma unroll
-                for (int e = 1; e < V; ++e)
-                    if (c + e >= N) v[e] = T(0);
-            }
-            rb[p] = v;
+            const int kr = k0 + b_k + C::B_RPP * p;
+            const T* src = (b_col_ok && kr < K) ? b_ptr + (int64_t)(k0 + C::B_RPP * p) * ldb : B;
+            rb[p] = *reinterpret_cast<const VT*>(src);
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, int k0) {
 #pragma unroll
-        for (int p = 0; p < C::A_PASS; ++p)
+        for (int p = 0; p < C::A_PASS; ++p) {
 #pragma unroll
-            for (int e = 0; e < V; ++e) As[buf][a_k + e][a_r + C::A_RPP * p] = ra[p][e];
+            for (int e = 0; e < V; ++e) {
+                const bool ok = a_row_ok[p] && (k0 + a_k + e < K);
+                As[buf][a_k + e][a_r + C::A_RPP * p] = ok ? ra[p][e] : T(0);
+            }
+        }
 #pragma unroll
-        for (int p = 0; p < C::B_PASS; ++p)
-            *reinterpret_cast<VT*>(&Bs[buf][b_k + C::B_RPP * p][b_n]) = rb[p];
+        for (int p = 0; p < C::B_PASS; ++p) {
+            const bool krow = k0 + b_k + C::B_RPP * p < K;
+            VT v = rb[p];
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (!(krow && b_col + e < N)) v[e] = T(0);
+            *reinterpret_cast<VT*>(&Bs[buf][b_k + C::B_RPP * p][b_n]) = v;
+        }
     };
 
     ACC acc[C::TI][C::TJ];
@@ -178,7 +191,7 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
 
     const int nk = (K + BK - 1) / BK;
     load(0);
-    store(0);
+    store(0, 0);
     __syncthreads();
     const int fr = lane & 15, fg = lane >> 4;
     for (int kt = 0; kt < nk; ++kt) {
@@ -196,7 +209,7 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
 #pragma unroll
                 for (int j = 0; j < C::TJ; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
         }
-        if (kt + 1 < nk) store(cur ^ 1);
+        if (kt + 1 < nk) store(cur ^ 1, (kt + 1) * BK);
         __syncthreads();
     }
 
@@ -365,23 +378,25 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_lp(
     const int bm = tm * BM, bn = tn * BN;
     const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
 
+    // Branch-free staging as in gemm_tile: loads from always-valid addresses,
+    // masking when the registers are rounded and written to LDS.
     const int a_k = 4 * (tid % C::A_TPR), a_r = tid / C::A_TPR;
     flt4v ra[C::A_PASS];
     flt4v rb[C::B_PASS][4];
+    bool a_row_ok[C::A_PASS];
+    const float* a_ptr[C::A_PASS];
+#pragma unroll
+    for (int p = 0; p < C::A_PASS; ++p) {
+        const int row = bm + a_r + C::A_RPP * p;
+        a_row_ok[p] = row < M;
+        a_ptr[p] = A + (int64_t)(a_row_ok[p] ? row : 0) * lda + a_k;
+    }
 
     auto load = [&](int k0) {
+        const bool ka = k0 + a_k < K;
 #pragma unroll
-        for (int p = 0; p < C::A_PASS; ++p) {
-            const int row = bm + a_r + C::A_RPP * p, k = k0 + a_k;
-            flt4v v = {0.f, 0.f, 0.f, 0.f};
-            if (row < M && k < K) {
-                v = *reinterpret_cast<const flt4v*>(A + (int64_t)row * lda + k);
-#pragma unroll
-                for (int e = 1; e < 4; ++e)
-                    if (k + e >= K) v[e] = 0.f;
-            }
-            ra[p] = v;
-        }
+        for (int p = 0; p < C::A_PASS; ++p)
+            ra[p] = *reinterpret_cast<const flt4v*>((a_row_ok[p] && ka) ? a_ptr[p] + k0 : A);
 #pragma unroll
         for (int p = 0; p < C::B_PASS; ++p) {
             int nq, kq;
@@ -390,34 +405,33 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_lp(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int kr = k0 + 4 * kq + r;
-                flt4v v = {0.f, 0.f, 0.f, 0.f};
-                if (kr < K && c < N) {
-                    v = *reinterpret_cast<const flt4v*>(B + (int64_t)kr * ldb + c);
-#pragma unroll
-                    for (int e = 1; e < 4; ++e)
-                        if (c + e >= N) v[e] = 0.f;
-                }
-                rb[p][r] = v;
+                const float* src = (kr < K && c < N) ? B + (int64_t)kr * ldb + c : B;
+                rb[p][r] = *reinterpret_cast<const flt4v*>(src);
             }
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, int k0) {
 #pragma unroll
         for (int p = 0; p < C::A_PASS; ++p) {
             QD q;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) q[e] = (L)ra[p][e];
+            for (int e = 0; e < 4; ++e)
+                q[e] = (a_row_ok[p] && k0 + a_k + e < K) ? (L)ra[p][e] : (L)0.f;
             *reinterpret_cast<QD*>(&As[buf][a_r + C::A_RPP * p][a_k]) = q;
         }
 #pragma unroll
         for (int p = 0; p < C::B_PASS; ++p) {
             int nq, kq;
             C::b_pos(tid + C::NT * p, nq, kq);
+            const int c = bn + 4 * nq;
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) {
                 QD q;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) q[r] = (L)rb[p][r][cc];
+                for (int r = 0; r < 4; ++r) {
+                    const bool ok = (k0 + 4 * kq + r < K) && (c + cc < N);
+                    q[r] = ok ? (L)rb[p][r][cc] : (L)0.f;
+                }
                 *reinterpret_cast<QD*>(&Bs[buf][4 * nq + cc][4 * kq]) = q;
             }
         }
@@ -431,7 +445,7 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_lp(
 
     const int nk = (K + BK - 1) / BK;
     load(0);
-    store(0);
+    store(0, 0);
     __syncthreads();
     const int fr = lane & 15, fg = lane >> 4;
     for (int kt = 0; kt < nk; ++kt) {
@@ -451,7 +465,7 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_lp(
 #pragma unroll
                 for (int j = 0; j < C::TJ; ++j) acc[i][j] = Mfma16<L>::mma(a[i], b[j], acc[i][j]);
         }
-        if (kt + 1 < nk) store(cur ^ 1);
+        if (kt + 1 < nk) store(cur ^ 1, (kt + 1) * BK);
         __syncthreads();
     }
 
@@ -530,7 +544,12 @@ constexpr TileShape kShapes[] = {
     {128, 64},   // TILE_128x64_W4: 4 waves of 64x32
     {64, 64},    // TILE_64x64_W4: 4 waves of 32x32
     {256, 128},  // TILE_256x128_W8: 8 waves of 64x64
+    {128, 64},   // TILE_128x64_W8: 8 waves of 32x32
+    {64, 128},   // TILE_64x128_W8: 8 waves of 32x32
+    {128, 128},  // TILE_128x128_W8_K2: 8 waves of 64x32, double K-tile
+    {128, 128},  // TILE_128x128_W16: 16 waves of 32x32
 };
+static_assert(sizeof(kShapes) / sizeof(kShapes[0]) == TILE_COUNT, "tile table");
 
 template <typename T>
 hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
@@ -542,6 +561,10 @@ hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int
         case TILE_128x64_W4: return launch<T, 128, 64, BKF, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_64x64_W4: return launch<T, 64, 64, BKF, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_256x128_W8: return launch<T, 256, 128, BKF, 64, 64>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x64_W8: return launch<T, 128, 64, BKF, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_64x128_W8: return launch<T, 64, 128, BKF, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W8_K2: return launch<T, 128, 128, 2 * BKF, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W16: return launch<T, 128, 128, BKF, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -565,6 +588,12 @@ hipError_t dispatch_lp(GemmTile t, int64_t M, int64_t N, int64_t K, const float*
         case TILE_128x64_W4: return launch_lp<L, 128, 64, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_64x64_W4: return launch_lp<L, 64, 64, 64, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_256x128_W8: return launch_lp<L, 256, 128, 64, 64, 64>(M, N, K, A, lda, B, ldb, ep, s);
+        // the 16-bit kernel stages B in 4x4 blocks: fewer blocks than threads
+        // would leave lanes idle, so the smaller tiles keep 4 waves here
+        case TILE_128x64_W8: return launch_lp<L, 128, 64, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_64x128_W8: return launch_lp<L, 64, 128, 64, 32, 64>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W8_K2: return launch_lp<L, 128, 128, 128, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W16: return launch_lp<L, 128, 128, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -608,9 +637,11 @@ int gemm_max_blocks(int64_t M, int64_t N) {
 
 GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K) {
     (void)K;
+    // two or more 128x128 tiles per CU: 8 waves of 64x32; fewer: halve the
+    // tile so that two blocks share each CU
     const int64_t big = cdiv(M, 128) * cdiv(N, 128);
-    if (big >= 256) return TILE_128x128_W8;
-    if (cdiv(M, 128) * cdiv(N, 64) >= 256) return TILE_128x64_W4;
+    if (big >= 512) return TILE_128x128_W8;
+    if (cdiv(M, 128) * cdiv(N, 64) >= 256) return TILE_128x64_W8;
     return TILE_64x64_W4;
 }
 

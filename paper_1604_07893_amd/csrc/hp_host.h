@@ -234,7 +234,9 @@ int setup_x0(const hp_params* p, const Plan& pl, const Buffers& bf, const double
 // error blocks are carried unchanged). This step is not part of the paper: it
 // applies the third and fourth Penrose equations ((AX)^T = AX, (XA)^T = XA),
 // which the Moore-Penrose inverse satisfies. Associated so that every
-// intermediate is min(m, n) square; X is b64.X[0] in and out.
+// intermediate is min(m, n) square; X is b64.X[0] in and out. A square input
+// whose lower stage converged to its rounding floor has no such blocks and
+// skips it (see needs_projection).
 template <typename GemmFn>
 int project_mp(const Plan& pl, const Buffers& bf, hipStream_t s, GemmFn&& gemm) {
     const int64_t m = pl.m, n = pl.n;
@@ -258,6 +260,10 @@ int project_mp(const Plan& pl, const Buffers& bf, hipStream_t s, GemmFn&& gemm) 
     return HP_OK;
 }
 
+inline bool needs_projection(const Plan& pl, bool lower_stage_hit_floor) {
+    return pl.has_proj && (pl.m != pl.n || !lower_stage_hit_floor);
+}
+
 // Host-side state of one problem's iteration: the stopping rule, the switch
 // to the stabilised variant, the precision stages and the guards.
 struct LoopState {
@@ -276,6 +282,7 @@ struct LoopState {
     int status = HP_MAXITER;
     int result_idx = -1;  // iterate to return (index into the final stage's set)
     int from_idx = 0;     // NEXT_STAGE: iterate the next stage starts from
+    bool exit_floor = false;  // NEXT_STAGE: the stage ended at its rounding floor
 
     void init(const hp_params* prm, hp_result* r, double a);
     Engine engine() const;

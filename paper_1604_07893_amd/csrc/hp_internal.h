@@ -61,7 +61,11 @@ enum GemmTile : int {
     TILE_128x64_W4 = 2,   // 4 waves, 64x32 each
     TILE_64x64_W4 = 3,    // 4 waves, 32x32 each
     TILE_256x128_W8 = 4,  // 8 waves, 64x64 each
-    TILE_COUNT = 5
+    TILE_128x64_W8 = 5,   // 8 waves, 32x32 each
+    TILE_64x128_W8 = 6,   // 8 waves, 32x32 each
+    TILE_128x128_W8_K2 = 7,  // as TILE_128x128_W8 with a K-tile twice as deep
+    TILE_128x128_W16 = 8, // 16 waves, 32x32 each
+    TILE_COUNT = 9
 };
 
 // Blocks (and partial-sum pairs) a launch with this tile uses for M x N.

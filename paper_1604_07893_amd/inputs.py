@@ -67,6 +67,31 @@ def lowrank_svd(m: int = 4096, n: int = 2048, r: int = 1536, smin: float = 1e-4,
     return SVDInput(np.ascontiguousarray(A), U, s, V)
 
 
+def square_svd_device(n: int = 8192, smin: float = 1e-3, seed: int = 1003, device="cuda"):
+    """The square_svd recipe built on the GPU with torch (FP64): Haar factors
+    from torch.linalg.qr of seeded Gaussians (sign-fixed), s log-uniform in
+    [smin, 1] with the end points pinned. Returns torch tensors (A, U, s, V).
+    Used where the host QR of two n x n matrices would dominate (n = 8192)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def haar(k):
+        q, r = torch.linalg.qr(torch.randn(k, k, dtype=torch.float64, device=device, generator=g))
+        d = torch.sign(torch.diagonal(r))
+        d[d == 0] = 1.0
+        return q * d
+
+    U = haar(n)
+    V = haar(n)
+    s = torch.exp(torch.empty(n, dtype=torch.float64, device=device).uniform_(
+        float(np.log(smin)), 0.0, generator=g))
+    s[0], s[-1] = 1.0, smin
+    s = torch.sort(s, descending=True).values
+    A = (U * s) @ V.T.contiguous()
+    return A.contiguous(), U, s, V
+
+
 def square_svd(n: int = 8192, smin: float = 1e-3, seed: int = 1003) -> SVDInput:
     rng = np.random.default_rng(seed)
     U = haar_columns(rng, n, n)
