@@ -102,8 +102,9 @@ extern "C" {
                            halving (below 1) or falls under 10x its unit
                            roundoff; the FP64 stage alone applies the stop test
                            and the stagnation guard. For Moore-Penrose input
-                           that is not square, or whose lower stage stalled
-                           above its rounding floor, the FP64 stage starts with
+                           that is not square, or square with
+                           ||I - AX||_F^2 >= 0.5 after the lower stage (rank
+                           deficient), the FP64 stage starts with
                            X <- (XA)^T X (AX)^T: FP32 error in the parts of X
                            outside R(A^T) x R(A) is not corrected by the loops
                            (an addition to the paper's method, from its third

@@ -237,8 +237,9 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
             if (next == 2) {
                 HIPCHK(convert(P.bf.b32.X[st.from_idx], P.bf.b32.ldX, P.pl.n, P.pl.m,
                                P.bf.b64.X[0], P.bf.b64.ldX, g.s));
-                if (needs_projection(P.pl, st.exit_floor))
-                    CHK(project_mp(P.pl, P.bf, g.s, single_gemm(g, P)));
+                bool proj = false;
+                CHK(needs_projection(P.pl, P.bf, g.h->host_scal, g.s, &proj));
+                if (proj) CHK(project_mp(P.pl, P.bf, g.s, single_gemm(g, P)));
             }
             st.enter_stage(next);
         }

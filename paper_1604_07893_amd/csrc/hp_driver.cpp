@@ -246,7 +246,6 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         if (!finite || stalled || floor) {
             const bool keep_new = finite && !(stalled && d >= d_prev);
             from_idx = keep_new ? in_ : ik;
-            exit_floor = finite && floor && !stalled;
             d_prev = d;
             return NEXT_STAGE;
         }
@@ -417,7 +416,9 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
             const int next = st.stage + 1;
             if (next == 2) {
                 HIPCHK(convert(bf.b32.X[st.from_idx], bf.b32.ldX, n, m, bf.b64.X[0], bf.b64.ldX, s));
-                if (needs_projection(pl, st.exit_floor)) {
+                bool proj = false;
+                CHK(needs_projection(pl, bf, hs, s, &proj));
+                if (proj) {
                     S.stage = 2;
                     CHK(project_mp(pl, bf, s, [&](const GemmCall<double>& g) {
                         return S.gemm<double>(ENG_F64, g);

@@ -112,7 +112,7 @@ struct Cfg {
 
 // One BM x BN output tile (tm, tn) of C = epilogue(A * B); the block's
 // partial sums (if any) go to pair `part` of ep.partials.
-template <typename T, int BM, int BN, int BK, int WM, int WN>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1>
 __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, int64_t lda,
                                  const T* __restrict__ B, int64_t ldb, const EpilogueT<T>& ep,
                                  int tm, int tn, int part) {
@@ -134,9 +134,11 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
     // address that is always inside the operand (out-of-range rows/columns are
     // redirected to element 0) so the loads of a K-tile go out back to back;
     // out-of-range elements are zeroed when the registers are written to LDS.
+    // Two register sets: the loads of K-tile t+2 are issued while tile t is
+    // multiplied, so each load has two tiles of MFMA work to arrive.
     const int a_k = V * (tid % C::A_TPR), a_r = tid / C::A_TPR;
     const int b_n = V * (tid % C::B_TPR), b_k = tid / C::B_TPR;
-    VT ra[C::A_PASS], rb[C::B_PASS];
+    VT ra[PF][C::A_PASS], rb[PF][C::B_PASS];
     const T* a_ptr[C::A_PASS];
     bool a_row_ok[C::A_PASS];
 #pragma unroll
@@ -149,33 +151,33 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
     const bool b_col_ok = b_col < N;
     const T* b_ptr = B + (b_col_ok ? b_col : 0) + (int64_t)b_k * ldb;
 
-    auto load = [&](int k0) {
+    auto load = [&](int set, int k0) {
         const bool ka = k0 + a_k < K;
 #pragma unroll
         for (int p = 0; p < C::A_PASS; ++p) {
             const T* src = (a_row_ok[p] && ka) ? a_ptr[p] + k0 : A;
-            ra[p] = *reinterpret_cast<const VT*>(src);
+            ra[set][p] = *reinterpret_cast<const VT*>(src);
         }
 #pragma unroll
         for (int p = 0; p < C::B_PASS; ++p) {
             const int kr = k0 + b_k + C::B_RPP * p;
             const T* src = (b_col_ok && kr < K) ? b_ptr + (int64_t)(k0 + C::B_RPP * p) * ldb : B;
-            rb[p] = *reinterpret_cast<const VT*>(src);
+            rb[set][p] = *reinterpret_cast<const VT*>(src);
         }
     };
-    auto store = [&](int buf, int k0) {
+    auto store = [&](int set, int buf, int k0) {
 #pragma unroll
         for (int p = 0; p < C::A_PASS; ++p) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const bool ok = a_row_ok[p] && (k0 + a_k + e < K);
-                As[buf][a_k + e][a_r + C::A_RPP * p] = ok ? ra[p][e] : T(0);
+                As[buf][a_k + e][a_r + C::A_RPP * p] = ok ? ra[set][p][e] : T(0);
             }
         }
 #pragma unroll
         for (int p = 0; p < C::B_PASS; ++p) {
             const bool krow = k0 + b_k + C::B_RPP * p < K;
-            VT v = rb[p];
+            VT v = rb[set][p];
 #pragma unroll
             for (int e = 0; e < V; ++e)
                 if (!(krow && b_col + e < N)) v[e] = T(0);
@@ -189,28 +191,54 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
 #pragma unroll
         for (int j = 0; j < C::TJ; ++j) acc[i][j] = ACC{};
 
-    const int nk = (K + BK - 1) / BK;
-    load(0);
-    store(0, 0);
-    __syncthreads();
     const int fr = lane & 15, fg = lane >> 4;
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) load((kt + 1) * BK);
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             T a[C::TI], b[C::TJ];
 #pragma unroll
-            for (int i = 0; i < C::TI; ++i) a[i] = As[cur][ks + fg][wm + i * 16 + fr];
+            for (int i = 0; i < C::TI; ++i) a[i] = As[buf][ks + fg][wm + i * 16 + fr];
 #pragma unroll
-            for (int j = 0; j < C::TJ; ++j) b[j] = Bs[cur][ks + fg][wn + j * 16 + fr];
+            for (int j = 0; j < C::TJ; ++j) b[j] = Bs[buf][ks + fg][wn + j * 16 + fr];
 #pragma unroll
             for (int i = 0; i < C::TI; ++i)
 #pragma unroll
                 for (int j = 0; j < C::TJ; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
         }
-        if (kt + 1 < nk) store(cur ^ 1, (kt + 1) * BK);
+    };
+
+    const int nk = (K + BK - 1) / BK;
+    if constexpr (PF == 1) {
+        // one K-tile ahead: load t+1 into registers while tile t is multiplied
+        load(0, 0);
+        store(0, 0, 0);
         __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < nk) load(0, (kt + 1) * BK);
+            compute(cur);
+            if (kt + 1 < nk) store(0, cur ^ 1, (kt + 1) * BK);
+            __syncthreads();
+        }
+    } else {
+        // two K-tiles ahead: tile kt lives in LDS buffer kt % 2 and, until
+        // stored, in register set kt % 2; the body handles an even and an odd
+        // tile so that both register sets are indexed statically
+        load(0, 0);
+        store(0, 0, 0);
+        if (nk > 1) load(1, BK);
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            if (kt + 2 < nk) load(0, (kt + 2) * BK);
+            compute(0);
+            if (kt + 1 < nk) store(1, 1, (kt + 1) * BK);
+            __syncthreads();
+            if (kt + 1 >= nk) break;
+            if (kt + 3 < nk) load(1, (kt + 3) * BK);
+            compute(1);
+            if (kt + 2 < nk) store(0, 0, (kt + 2) * BK);
+            __syncthreads();
+        }
     }
 
     // ---- epilogue ----
@@ -267,13 +295,13 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
     }
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
 __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm(
     int M, int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
     int64_t ldb, EpilogueT<T> ep, int tiles_m, int tiles_n) {
     int tm, tn;
     tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
-    gemm_tile<T, BM, BN, BK, WM, WN>(M, N, K, A, lda, B, ldb, ep, tm, tn, blockIdx.x);
+    gemm_tile<T, BM, BN, BK, WM, WN, PF>(M, N, K, A, lda, B, ldb, ep, tm, tn, blockIdx.x);
 }
 
 // Persistent grouped launch: the grid walks the tiles of every product in
@@ -524,13 +552,13 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_lp(
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1>
 hipError_t launch(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
                   int64_t ldb, const EpilogueT<T>& ep, hipStream_t s) {
     using C = Cfg<T, BM, BN, BK, WM, WN>;
     const int tm = (int)cdiv(M, BM), tn = (int)cdiv(N, BN);
-    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN>), dim3(tm * tn), dim3(C::NT), 0, s, (int)M,
-                       (int)N, (int)K, A, lda, B, ldb, ep, tm, tn);
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, PF>), dim3(tm * tn), dim3(C::NT), 0, s,
+                       (int)M, (int)N, (int)K, A, lda, B, ldb, ep, tm, tn);
     return hipGetLastError();
 }
 
@@ -548,6 +576,8 @@ constexpr TileShape kShapes[] = {
     {64, 128},   // TILE_64x128_W8: 8 waves of 32x32
     {128, 128},  // TILE_128x128_W8_K2: 8 waves of 64x32, double K-tile
     {128, 128},  // TILE_128x128_W16: 16 waves of 32x32
+    {128, 128},  // TILE_128x128_W8_P2: 8 waves, loads two K-tiles ahead
+    {128, 128},  // TILE_128x128_W16_P2: 16 waves, loads two K-tiles ahead
 };
 static_assert(sizeof(kShapes) / sizeof(kShapes[0]) == TILE_COUNT, "tile table");
 
@@ -565,6 +595,8 @@ hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int
         case TILE_64x128_W8: return launch<T, 64, 128, BKF, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W8_K2: return launch<T, 128, 128, 2 * BKF, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W16: return launch<T, 128, 128, BKF, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W8_P2: return launch<T, 128, 128, BKF, 64, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W16_P2: return launch<T, 128, 128, BKF, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -593,7 +625,9 @@ hipError_t dispatch_lp(GemmTile t, int64_t M, int64_t N, int64_t K, const float*
         case TILE_128x64_W8: return launch_lp<L, 128, 64, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_64x128_W8: return launch_lp<L, 64, 128, 64, 32, 64>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W8_K2: return launch_lp<L, 128, 128, 128, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
-        case TILE_128x128_W16: return launch_lp<L, 128, 128, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W16:
+        case TILE_128x128_W8_P2:
+        case TILE_128x128_W16_P2: return launch_lp<L, 128, 128, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -637,11 +671,10 @@ int gemm_max_blocks(int64_t M, int64_t N) {
 
 GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K) {
     (void)K;
-    // two or more 128x128 tiles per CU: 8 waves of 64x32; fewer: halve the
-    // tile so that two blocks share each CU
-    const int64_t big = cdiv(M, 128) * cdiv(N, 128);
-    if (big >= 512) return TILE_128x128_W8;
-    if (cdiv(M, 128) * cdiv(N, 64) >= 256) return TILE_128x64_W8;
+    // 128x128 tiles with 8 waves of 64x32 won every measured shape from
+    // 2048^3 up (smaller tiles cost more LDS traffic per flop than they gain
+    // in occupancy); small products use 64x64 tiles to spread over the CUs
+    if (cdiv(M, 128) * cdiv(N, 128) >= 64) return TILE_128x128_W8;
     return TILE_64x64_W4;
 }
 

@@ -167,12 +167,14 @@ int describe_pm_loop(const Plan& pl, const Set<T>& b, T* Xk, T* Xn, T* Xh, bool 
     if (stab) {
         EpilogueT<T> e = epilogue_plain(Xn, ldX);
         e.ref = Xk; e.ldref = ldX; e.partials = partials;
+        // the middle product goes to R^2's buffer (dead by now) so that R
+        // stays available after the loop
         if (m >= n) {
-            out[c++] = {n, n, m, Xh, ldX, b.A, ldA, epilogue_plain(R, ldS)};
-            out[c++] = {n, m, n, R, ldS, Xh, ldX, e};
+            out[c++] = {n, n, m, Xh, ldX, b.A, ldA, epilogue_plain(R2, ldS)};
+            out[c++] = {n, m, n, R2, ldS, Xh, ldX, e};
         } else {
-            out[c++] = {m, m, n, b.A, ldA, Xh, ldX, epilogue_plain(R, ldS)};
-            out[c++] = {n, m, m, Xh, ldX, R, ldS, e};
+            out[c++] = {m, m, n, b.A, ldA, Xh, ldX, epilogue_plain(R2, ldS)};
+            out[c++] = {n, m, m, Xh, ldX, R2, ldS, e};
         }
     }
     return c;
@@ -234,9 +236,8 @@ int setup_x0(const hp_params* p, const Plan& pl, const Buffers& bf, const double
 // error blocks are carried unchanged). This step is not part of the paper: it
 // applies the third and fourth Penrose equations ((AX)^T = AX, (XA)^T = XA),
 // which the Moore-Penrose inverse satisfies. Associated so that every
-// intermediate is min(m, n) square; X is b64.X[0] in and out. A square input
-// whose lower stage converged to its rounding floor has no such blocks and
-// skips it (see needs_projection).
+// intermediate is min(m, n) square; X is b64.X[0] in and out. A square
+// nonsingular input has no such blocks and skips it (see needs_projection).
 template <typename GemmFn>
 int project_mp(const Plan& pl, const Buffers& bf, hipStream_t s, GemmFn&& gemm) {
     const int64_t m = pl.m, n = pl.n;
@@ -260,8 +261,25 @@ int project_mp(const Plan& pl, const Buffers& bf, hipStream_t s, GemmFn&& gemm) 
     return HP_OK;
 }
 
-inline bool needs_projection(const Plan& pl, bool lower_stage_hit_floor) {
-    return pl.has_proj && (pl.m != pl.n || !lower_stage_hit_floor);
+// Whether the projection is needed on entering the FP64 stage: always for a
+// non-square input; for a square one only if it is rank deficient, read off
+// the last lower-stage residual R = I - A X (or I - X A): its squared
+// Frobenius norm is about the number of directions X does not invert (each
+// contributes 1) and is small for a nonsingular input. Synchronises `s`.
+inline int needs_projection(const Plan& pl, const Buffers& bf, double* host_scal, hipStream_t s,
+                            bool* out) {
+    *out = false;
+    if (!pl.has_proj) return HP_OK;
+    if (pl.m != pl.n) {
+        *out = true;
+        return HP_OK;
+    }
+    HIPCHK(sumsq(bf.b32.S[0], bf.b32.ldS, pl.s, pl.s, bf.small, bf.scal, SLOT_RNORM2, s));
+    HIPCHK(hipMemcpyAsync(host_scal + SLOT_RNORM2, bf.scal + SLOT_RNORM2, sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = !(host_scal[SLOT_RNORM2] < 0.5);
+    return HP_OK;
 }
 
 // Host-side state of one problem's iteration: the stopping rule, the switch
@@ -282,7 +300,6 @@ struct LoopState {
     int status = HP_MAXITER;
     int result_idx = -1;  // iterate to return (index into the final stage's set)
     int from_idx = 0;     // NEXT_STAGE: iterate the next stage starts from
-    bool exit_floor = false;  // NEXT_STAGE: the stage ended at its rounding floor
 
     void init(const hp_params* prm, hp_result* r, double a);
     Engine engine() const;

@@ -18,6 +18,7 @@ enum ScalarSlot : int {
     SLOT_TRACE = 4,      // Tr(A^{l+1})
     SLOT_NORM1 = 5,      // ||A||_1
     SLOT_NORMINF = 6,    // ||A||_inf
+    SLOT_RNORM2 = 7,     // ||R||_F^2 of a lower stage's last residual
     SLOT_COUNT = 8
 };
 
@@ -65,7 +66,9 @@ enum GemmTile : int {
     TILE_64x128_W8 = 6,   // 8 waves, 32x32 each
     TILE_128x128_W8_K2 = 7,  // as TILE_128x128_W8 with a K-tile twice as deep
     TILE_128x128_W16 = 8, // 16 waves, 32x32 each
-    TILE_COUNT = 9
+    TILE_128x128_W8_P2 = 9,   // TILE_128x128_W8 loading two K-tiles ahead
+    TILE_128x128_W16_P2 = 10, // TILE_128x128_W16 loading two K-tiles ahead
+    TILE_COUNT = 11
 };
 
 // Blocks (and partial-sum pairs) a launch with this tile uses for M x N.
@@ -141,6 +144,11 @@ hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipSt
 // scal[SLOT_DINF] = max_i sum_j |X1[i][j] - X0[i][j]|. `tmp` needs M doubles.
 hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_t ld0,
                          int64_t M, int64_t N, double* tmp, double* scal, hipStream_t s);
+
+// scal[slot] = sum of squares of the M x N matrix X (fixed order). `tmp`
+// needs M doubles.
+hipError_t sumsq(const float* X, int64_t ldx, int64_t M, int64_t N, double* tmp, double* scal,
+                 int slot, hipStream_t s);
 
 // Y = X elementwise with a change of precision (M x N; narrowing rounds to
 // nearest even).

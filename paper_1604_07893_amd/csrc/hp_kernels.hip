@@ -207,6 +207,28 @@ __global__ __launch_bounds__(kThreads) void k_max_to_slot(const double* __restri
     if (threadIdx.x == 0) scal[slot] = any_nan ? __builtin_nan("") : r;
 }
 
+// Row sums of squares of an M x N matrix (one block per row).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_rowsumsq(const T* __restrict__ X, int64_t ldx, int N,
+                                                       double* __restrict__ rows) {
+    const int r = blockIdx.x;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < N; c += kThreads) {
+        const double v = (double)X[(int64_t)r * ldx + c];
+        s += v * v;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) rows[r] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_sum_to_slot(const double* __restrict__ v, int n,
+                                                          double* __restrict__ scal, int slot) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kThreads) s += v[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) scal[slot] = s;
+}
+
 // One block per problem: fixed-order sums of that problem's partial pairs.
 struct ReduceEntryDev {
     const double* partials;
@@ -338,6 +360,17 @@ static_assert(sizeof(ReduceEntry) == sizeof(ReduceEntryDev), "reduce table layou
 hipError_t reduce_pairs_grouped(const ReduceEntry* ents, int count, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_pairs_grouped, dim3((unsigned)count), dim3(kThreads), 0, s,
                        reinterpret_cast<const ReduceEntryDev*>(ents), out);
+    return hipGetLastError();
+}
+
+}  // namespace hp
+
+namespace hp {
+
+hipError_t sumsq(const float* X, int64_t ldx, int64_t M, int64_t N, double* tmp, double* scal,
+                 int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_rowsumsq<float>, dim3((unsigned)M), dim3(kThreads), 0, s, X, ldx, (int)N, tmp);
+    hipLaunchKernelGGL(k_sum_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal, slot);
     return hipGetLastError();
 }
 
