@@ -68,6 +68,20 @@ def timed_solves(hpw, torch, A, steps, warmup, **params):
     return (time.perf_counter() - t0) / steps, infos, X
 
 
+def measured_traffic():
+    """HBM bytes per FP64 GEMM launch from the committed rocprofv3 counter
+    summary, if it was taken on the current GEMM source (else None)."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "k_gemm_f64_lowrank4096x2048_traffic.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, "paper_1604_07893_amd", "csrc", "hp_gemm.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("hp_gemm_hip_sha256") == sha else None
+
+
 def cpu_baseline(d, n_plain: int, n_stab: int) -> dict:
     """The oracle (numpy FP64, OpenBLAS) timed on a bounded sample: one plain
     and one stabilised loop on the full-size input, scaled by the loop counts
@@ -277,7 +291,8 @@ def main() -> int:
             "peak": PEAK_TFLOPS["f64"],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS["f64"],
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "gflop_per_launch": gflop / max(launches, 1),
             "avg_launch_ms": gemm_ms / max(launches, 1),
         },

@@ -99,8 +99,9 @@ extern "C" {
                            on FP32 storage with FP32 accumulation; stage 1:
                            FP32; stage 2: FP64 loops until the stop test
                            passes. A stage ends when its relative change stops
-                           halving (below 1) or falls under 10x its unit
-                           roundoff; the FP64 stage alone applies the stop test
+                           halving (below 1), falls under 10x its unit
+                           roundoff, or one loop after it first fell below 0.2;
+                           the FP64 stage alone applies the stop test
                            and the stagnation guard. For Moore-Penrose input
                            that is not square, or square with
                            ||I - AX||_F^2 >= 0.5 after the lower stage (rank
@@ -119,6 +120,9 @@ extern "C" {
                                   solve stream; sums land in hp_result.gemm_ms */
 #define HP_FLAG_INF_NORM 2     /* also compute ||X_{k+1}-X_k||_inf each loop
                                   (implied by HP_STOP_ABS_INF); enables coc */
+#define HP_FLAG_NO_GRAPH 4     /* batched/served: launch each loop's kernels one
+                                  by one instead of replaying the captured
+                                  hipGraph of the loop */
 
 /* GEMM element type for hp_gemm */
 #define HP_DTYPE_F64 0 /* FP64 operands, v_mfma_f64_16x16x4f64, FP64 accumulate */
@@ -220,6 +224,23 @@ int hp_solve(hp_handle* h, const hp_params* p,
 int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
             double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
             double beta_identity, void* C, int64_t ldc, void* stream);
+
+/* ---- tile autotuning ------------------------------------------------------ */
+
+/* Time every tile configuration of the GEMM kernel for dtype on an M x N x K
+ * product (operands filled by the library in `scratch`, which needs
+ * (M*K + K*N + M*N) elements of the dtype's storage type, 16-byte aligned),
+ * `reps` timed launches each after one warm-up, and record the fastest in the
+ * handle: later products of exactly this (dtype, M, N, K) use it. Returns the
+ * chosen tile index and its mean launch time. The environment variable
+ * HP_GEMM_TILE, if set, still overrides every choice. */
+int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* scratch,
+                size_t scratch_bytes, int reps, void* stream, int* tile, double* ms);
+
+/* The handle's table as rows of 5 int64 (dtype, M, N, K, tile): export
+ * copies up to `cap` rows and reports the count; import adds rows. */
+int hp_tune_export(hp_handle* h, int64_t* rows, int cap, int* count);
+int hp_tune_import(hp_handle* h, const int64_t* rows, int count);
 
 /* ---- many problems: batched and served forms --------------------------- */
 

@@ -26,7 +26,9 @@ struct ReduceEntry {
     int npairs;
     int pad;
 };
-hipError_t reduce_pairs_grouped(const ReduceEntry* ents, int count, double* out, hipStream_t s);
+// grid >= *count blocks; blocks past *count exit at once
+hipError_t reduce_pairs_grouped(const int* count, const ReduceEntry* ents, int grid, double* out,
+                                hipStream_t s);
 
 }  // namespace hp
 
@@ -64,7 +66,7 @@ struct Tables {
     size_t bytes = 0;
     size_t off_hdr[2][kSlots] = {};
     size_t off_ent[2][kSlots] = {};
-    size_t off_red = 0, off_out = 0;
+    size_t off_cnt = 0, off_red = 0, off_out = 0;
     char* dev = nullptr;
     char* host = nullptr;
 
@@ -79,6 +81,8 @@ struct Tables {
                 off = align_up(off + esz * (size_t)cap);
             }
         }
+        if (t) t->off_cnt = off;
+        off = align_up(off + sizeof(int));
         if (t) t->off_red = off;
         off = align_up(off + sizeof(ReduceEntry) * (size_t)cap);
         if (t) t->off_out = off;
@@ -93,13 +97,79 @@ struct Group {
     hipStream_t s = nullptr;
     Tables tb;
     int grid = 1024;  // persistent grid of the grouped launches
+    // One loop's device work -- table upload, the 2 x 9 grouped launches, the
+    // per-problem reduction and the download of the sums -- captured once as
+    // a hipGraph and replayed every loop (every launch has a fixed grid and
+    // reads its sizes from the uploaded tables). No memset nodes.
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;  // capture needs a stream other than the null stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;  // order the replay against stream s
 };
+
+// Enqueue one loop's device work on stream s (used eagerly or under capture).
+int enqueue_loop(Group& g, hipStream_t s) {
+    Tables& tb = g.tb;
+    HIPCHK(hipMemcpyAsync(tb.dev, tb.host, tb.off_out, hipMemcpyHostToDevice, s));
+    for (int j = 0; j < kSlots; ++j) {
+        HIPCHK(gemm_grouped(reinterpret_cast<const GroupHeader*>(tb.dev + tb.off_hdr[0][j]),
+                            reinterpret_cast<const GroupEntry<double>*>(tb.dev + tb.off_ent[0][j]),
+                            g.grid, s));
+        HIPCHK(gemm_grouped(reinterpret_cast<const GroupHeader*>(tb.dev + tb.off_hdr[1][j]),
+                            reinterpret_cast<const GroupEntry<float>*>(tb.dev + tb.off_ent[1][j]),
+                            g.grid, s));
+    }
+    HIPCHK(reduce_pairs_grouped(reinterpret_cast<const int*>(tb.dev + tb.off_cnt),
+                                reinterpret_cast<const ReduceEntry*>(tb.dev + tb.off_red), tb.cap,
+                                reinterpret_cast<double*>(tb.dev + tb.off_out), s));
+    HIPCHK(hipMemcpyAsync(tb.host + tb.off_out, tb.dev + tb.off_out, 2 * sizeof(double) * (size_t)tb.cap,
+                          hipMemcpyDeviceToHost, s));
+    return HP_OK;
+}
+
+int run_loop_device(Group& g) {
+    if (!g.use_graph) return enqueue_loop(g, g.s);
+    if (!g.exec) {
+        if (!g.cap_stream) HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming));
+        HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_loop(g, g.cap_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(g.cap_stream, &graph);
+        if (rc != HP_OK) return rc;
+        if (e != hipSuccess) return HP_EHIP;
+        g.graph = graph;
+        HIPCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    }
+    // the graph runs on the capture stream, ordered after the group stream's work
+    HIPCHK(hipEventRecord(g.ev_in, g.s));
+    HIPCHK(hipStreamWaitEvent(g.cap_stream, g.ev_in, 0));
+    HIPCHK(hipGraphLaunch(g.exec, g.cap_stream));
+    HIPCHK(hipEventRecord(g.ev_out, g.cap_stream));
+    HIPCHK(hipStreamWaitEvent(g.s, g.ev_out, 0));
+    return HP_OK;
+}
+
+void group_release(Group& g) {
+    if (g.cap_stream) (void)hipStreamSynchronize(g.cap_stream);
+    if (g.ev_in) (void)hipEventDestroy(g.ev_in);
+    if (g.ev_out) (void)hipEventDestroy(g.ev_out);
+    g.ev_in = g.ev_out = nullptr;
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.cap_stream) (void)hipStreamDestroy(g.cap_stream);
+    g.exec = nullptr;
+    g.graph = nullptr;
+    g.cap_stream = nullptr;
+}
 
 // Products outside the loop (Drazin set-up, projection) run as single
 // launches on the problem's own shapes.
 auto single_gemm(Group& g, Problem& P) {
     return [&g, &P](const GemmCall<double>& c) {
-        const GemmTile t = gemm_pick_tile(c.M, c.N, c.K);
+        const GemmTile t = choose_tile(g.h, HP_DTYPE_F64, c.M, c.N, c.K);
         if (hp::gemm(t, c.M, c.N, c.K, c.A, c.lda, c.B, c.ldb, c.ep, g.s) != hipSuccess) return HP_EHIP;
         const double gf = 2.0 * (double)c.M * (double)c.N * (double)c.K * 1e-9;
         P.res.gflop += gf;
@@ -172,6 +242,7 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
     Tables& tb = g.tb;
     std::memset(tb.host, 0, tb.off_red);
     const int np = (int)act.size();
+    *reinterpret_cast<int*>(tb.host + tb.off_cnt) = np;
     ReduceEntry* red = reinterpret_cast<ReduceEntry*>(tb.host + tb.off_red);
     for (int i = 0; i < np; ++i) {
         Problem& P = *act[i];
@@ -206,26 +277,9 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
         P.last_tiles = tiles;
         red[i] = ReduceEntry{P.bf.small, tiles, 0};
     }
-    HIPCHK(hipMemcpyAsync(tb.dev, tb.host, tb.off_out, hipMemcpyHostToDevice, g.s));
-    for (int j = 0; j < kSlots; ++j) {
-        for (int prec = 0; prec < 2; ++prec) {
-            const GroupHeader* hh = reinterpret_cast<const GroupHeader*>(tb.host + tb.off_hdr[prec][j]);
-            if (hh->count == 0) continue;
-            const GroupHeader* hdr = reinterpret_cast<const GroupHeader*>(tb.dev + tb.off_hdr[prec][j]);
-            const int grid = std::min(g.grid, hh->total_tiles);
-            if (prec == 0)
-                HIPCHK(gemm_grouped(hdr, reinterpret_cast<const GroupEntry<double>*>(tb.dev + tb.off_ent[0][j]),
-                                    grid, g.s));
-            else
-                HIPCHK(gemm_grouped(hdr, reinterpret_cast<const GroupEntry<float>*>(tb.dev + tb.off_ent[1][j]),
-                                    grid, g.s));
-        }
-    }
-    double* dout = reinterpret_cast<double*>(tb.dev + tb.off_out);
-    double* hout = reinterpret_cast<double*>(tb.host + tb.off_out);
-    HIPCHK(reduce_pairs_grouped(reinterpret_cast<const ReduceEntry*>(tb.dev + tb.off_red), np, dout, g.s));
-    HIPCHK(hipMemcpyAsync(hout, dout, 2 * sizeof(double) * (size_t)np, hipMemcpyDeviceToHost, g.s));
+    CHK(run_loop_device(g));
     HIPCHK(hipStreamSynchronize(g.s));
+    const double* hout = reinterpret_cast<const double*>(tb.host + tb.off_out);
 
     bool any_done = false;
     for (int i = 0; i < np; ++i) {
@@ -362,6 +416,7 @@ int hp_solve_batched(hp_handle* h, const hp_params* p, int count, const hp_probl
     g.h = h;
     g.prm = *p;
     g.s = reinterpret_cast<hipStream_t>(stream);
+    g.use_graph = (p->flags & HP_FLAG_NO_GRAPH) == 0;
     char* ws = static_cast<char*>(workspace);
     // the tables live at the start of the workspace; staging is pinned host memory
     g.tb.cap = count;
@@ -386,6 +441,7 @@ int hp_solve_batched(hp_handle* h, const hp_params* p, int count, const hp_probl
         act.erase(std::remove_if(act.begin(), act.end(), [](Problem* q) { return q->finished; }),
                   act.end());
     }
+    group_release(g);
     (void)hipHostFree(g.tb.host);
     if (rc != HP_OK) return rc;
     const double wall = ms_between(t0, Clock::now());
@@ -409,6 +465,7 @@ int hp_serve_create(hp_handle* h, const hp_params* p, size_t hbm_budget, int max
     sv->g.h = h;
     sv->g.prm = *p;
     sv->g.s = reinterpret_cast<hipStream_t>(stream);
+    sv->g.use_graph = (p->flags & HP_FLAG_NO_GRAPH) == 0;
     sv->budget = hbm_budget / kAlign * kAlign;
     sv->max_slots = max_slots;
     if (hipMalloc(reinterpret_cast<void**>(&sv->arena), sv->budget) != hipSuccess) {
@@ -496,6 +553,7 @@ int hp_serve_destroy(hp_server* sv) {
     if (!sv) return HP_EINVAL;
     (void)hipSetDevice(sv->g.h->device);
     (void)hipStreamSynchronize(sv->g.s);
+    group_release(sv->g);
     if (sv->arena) (void)hipFree(sv->arena);
     tables_free(sv->g.tb);
     delete sv;

@@ -173,6 +173,10 @@ Buffers carve(const Plan& pl, char* ws) {
 // ---------------------------------------------------------------------------
 
 static constexpr double kUnitRoundoffF32 = 5.960464477539063e-08;
+// A lower stage ends one loop after its relative change first falls below
+// this: the order-18 contraction then takes the next iterate to the stage's
+// rounding floor, so a further loop would only confirm it.
+static constexpr double kPredict = 0.2;
 
 void LoopState::init(const hp_params* prm, hp_result* r, double a) {
     p = prm;
@@ -186,6 +190,7 @@ void LoopState::init(const hp_params* prm, hp_result* r, double a) {
     res->switch_iter = stabilising ? 0 : -1;
     converging = false;
     stage_first = true;
+    armed = false;
     d_prev = 0.0;
     ik = 0;
     in_ = 1;
@@ -203,6 +208,7 @@ Engine LoopState::engine() const {
 void LoopState::enter_stage(int next) {
     stage = next;
     stage_first = true;
+    armed = false;
     if (next == 2) {
         ik = 0;
         in_ = 1;
@@ -243,12 +249,13 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         const bool stalled = !stage_first && d < 1.0 && d >= 0.5 * d_prev;
         const bool floor = d < 10.0 * u || d < p->tol;
         if (finite) note_switch();
-        if (!finite || stalled || floor) {
+        if (!finite || stalled || floor || armed) {
             const bool keep_new = finite && !(stalled && d >= d_prev);
             from_idx = keep_new ? in_ : ik;
             d_prev = d;
             return NEXT_STAGE;
         }
+        armed = d < kPredict;
         stage_first = false;
         d_prev = d;
         std::swap(ik, in_);
@@ -340,8 +347,10 @@ struct Solver {
 
     template <typename T>
     int gemm(Engine eng, const GemmCall<T>& g) {
-        const GemmTile t = h->forced_tile >= 0 ? (GemmTile)h->forced_tile
-                                                : gemm_pick_tile(g.M, g.N, g.K);
+        int dt = HP_DTYPE_F64;
+        if constexpr (!std::is_same<T, double>::value)
+            dt = eng == ENG_F32 ? HP_DTYPE_F32 : (eng == ENG_BF16 ? HP_DTYPE_BF16_F32 : HP_DTYPE_F16_F32);
+        const GemmTile t = choose_tile(h, dt, g.M, g.N, g.K);
         timer.before();
         hipError_t e;
         if constexpr (std::is_same<T, double>::value) {
@@ -572,8 +581,7 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alp
          reinterpret_cast<uintptr_t>(C)) & 15)
         return HP_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
-    const hp::GemmTile t =
-        h->forced_tile >= 0 ? (hp::GemmTile)h->forced_tile : hp::gemm_pick_tile(M, N, K);
+    const hp::GemmTile t = hp::choose_tile(h, dtype, M, N, K);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
     if (dtype == HP_DTYPE_F64) {
@@ -588,6 +596,98 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alp
                           hp::epilogue_plain(static_cast<float*>(C), ldc, alpha, beta_identity), s);
     }
     if (e != hipSuccess) return HP_EHIP;
+    return HP_OK;
+}
+
+int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* scratch,
+                size_t scratch_bytes, int reps, void* stream, int* tile, double* ms) {
+    if (!h || !scratch || !tile || !ms || reps < 1) return HP_EINVAL;
+    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16_F32) return HP_EINVAL;
+    if (M < 1 || N < 1 || K < 1 || M > 65535 || N > 65535 || K > 65535) return HP_EINVAL;
+    const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;
+    const int64_t vec = 16 / (int64_t)esz;
+    const int64_t lda = (K + vec - 1) / vec * vec, ldb = (N + vec - 1) / vec * vec, ldc = N;
+    const size_t need = esz * (size_t)(M * lda + K * ldb + M * ldc) + 64;
+    if (scratch_bytes < need) return HP_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(scratch) % 16) return HP_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(scratch);
+    void* A = base;
+    void* B = base + esz * (size_t)(M * lda);
+    void* C = base + esz * (size_t)(M * lda + K * ldb);
+    // operands: identity-like fills are enough for timing (no data dependence)
+    if (dtype == HP_DTYPE_F64) {
+        HIPCHK(hp::set_identity(static_cast<double*>(A), lda, M, K, s));
+        HIPCHK(hp::set_identity(static_cast<double*>(B), ldb, K, N, s));
+    } else {
+        HIPCHK(hipMemsetAsync(A, 0, esz * (size_t)(M * lda), s));
+        HIPCHK(hipMemsetAsync(B, 0, esz * (size_t)(K * ldb), s));
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = -1;
+    double best_ms = 0.0;
+    for (int t = 0; t < hp::TILE_COUNT; ++t) {
+        auto launch = [&]() -> hipError_t {
+            if (dtype == HP_DTYPE_F64)
+                return hp::gemm((hp::GemmTile)t, M, N, K, static_cast<const double*>(A), lda,
+                                static_cast<const double*>(B), ldb,
+                                hp::epilogue_plain(static_cast<double*>(C), ldc), s);
+            if (dtype == HP_DTYPE_F32)
+                return hp::gemm((hp::GemmTile)t, M, N, K, static_cast<const float*>(A), lda,
+                                static_cast<const float*>(B), ldb,
+                                hp::epilogue_plain(static_cast<float*>(C), ldc), s);
+            return hp::gemm_lowp((hp::GemmTile)t, dtype == HP_DTYPE_BF16_F32 ? hp::LOWP_BF16 : hp::LOWP_F16,
+                                 M, N, K, static_cast<const float*>(A), lda,
+                                 static_cast<const float*>(B), ldb,
+                                 hp::epilogue_plain(static_cast<float*>(C), ldc), s);
+        };
+        if (launch() != hipSuccess) continue;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) (void)launch();
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float el = 0.f;
+        (void)hipEventElapsedTime(&el, e0, e1);
+        const double avg = el / reps;
+        if (best < 0 || avg < best_ms) {
+            best = t;
+            best_ms = avg;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best < 0) return HP_EHIP;
+    h->tuned[{dtype, M, N, K}] = best;
+    *tile = best;
+    *ms = best_ms;
+    return HP_OK;
+}
+
+int hp_tune_export(hp_handle* h, int64_t* rows, int cap, int* count) {
+    if (!h || !count || (cap > 0 && !rows)) return HP_EINVAL;
+    int i = 0;
+    for (const auto& kv : h->tuned) {
+        if (i < cap) {
+            for (int j = 0; j < 4; ++j) rows[5 * i + j] = kv.first[j];
+            rows[5 * i + 4] = kv.second;
+        }
+        ++i;
+    }
+    *count = i;
+    return HP_OK;
+}
+
+int hp_tune_import(hp_handle* h, const int64_t* rows, int count) {
+    if (!h || count < 0 || (count > 0 && !rows)) return HP_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        const int64_t* r = rows + 5 * i;
+        if (r[0] < HP_DTYPE_F64 || r[0] > HP_DTYPE_F16_F32 || r[4] < 0 || r[4] >= hp::TILE_COUNT)
+            return HP_EINVAL;
+        h->tuned[{r[0], r[1], r[2], r[3]}] = (int)r[4];
+    }
     return HP_OK;
 }
 

@@ -671,10 +671,15 @@ int gemm_max_blocks(int64_t M, int64_t N) {
 
 GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K) {
     (void)K;
-    // 128x128 tiles with 8 waves of 64x32 won every measured shape from
-    // 2048^3 up (smaller tiles cost more LDS traffic per flop than they gain
-    // in occupancy); small products use 64x64 tiles to spread over the CUs
-    if (cdiv(M, 128) * cdiv(N, 128) >= 64) return TILE_128x128_W8;
+    // From the MI355X sweep: with two or more 128x128 tiles per CU (256 CUs)
+    // the 8-wave tile with one K-tile of prefetch is fastest (58 TFLOP/s FP64
+    // at 8192^3); with fewer, a single block per CU must hide its own load
+    // latency and the 16-wave tile loading two K-tiles ahead wins (47.7 vs
+    // 44.9 at 2048^3). Smaller tiles lose more to LDS traffic than they gain
+    // in occupancy; tiny products use 64x64 tiles to spread over the CUs.
+    const int64_t tiles = cdiv(M, 128) * cdiv(N, 128);
+    if (tiles >= 512) return TILE_128x128_W8;
+    if (tiles >= 64) return TILE_128x128_W16_P2;
     return TILE_64x64_W4;
 }
 

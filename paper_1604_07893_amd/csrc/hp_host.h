@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <cstdint>
 #include <type_traits>
 
@@ -15,6 +17,8 @@
 struct hp_handle {
     int device = 0;
     int forced_tile = -1;         // HP_GEMM_TILE: one tile configuration for every product
+    // autotuned tiles: (dtype, M, N, K) -> tile index
+    std::map<std::array<int64_t, 4>, int> tuned;
     double* host_scal = nullptr;  // pinned, hp::SLOT_COUNT doubles
     static constexpr int kEvents = 64;
     hipEvent_t ev[kEvents] = {};
@@ -32,6 +36,15 @@ struct hp_handle {
     } while (0)
 
 namespace hp {
+
+// The tile a product of this dtype (HP_DTYPE_*) and shape runs on: the
+// environment override, else the handle's autotuned entry, else the default.
+inline GemmTile choose_tile(const hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K) {
+    if (h->forced_tile >= 0) return (GemmTile)h->forced_tile;
+    auto it = h->tuned.find({dtype, M, N, K});
+    if (it != h->tuned.end()) return (GemmTile)it->second;
+    return gemm_pick_tile(M, N, K);
+}
 
 // Constants of the factored polynomial: the closed forms printed in Section 2
 // (c1, c2, c3 of (simplify1); d1, d2 of (simplify2); mu, psi of (hyper18-33)).
@@ -294,6 +307,7 @@ struct LoopState {
     bool stabilising = false;
     bool converging = false;
     bool stage_first = true;  // no stagnation test on a stage's first loop
+    bool armed = false;       // lower stage: the previous change was below kPredict
     double d_prev = 0.0;
     int ik = 0, in_ = 1;  // current and next iterate (index into the stage's set)
     int k = 0;            // loops run

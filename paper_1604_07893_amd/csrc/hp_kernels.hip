@@ -236,8 +236,10 @@ struct ReduceEntryDev {
     int pad;
 };
 
-__global__ __launch_bounds__(kThreads) void k_reduce_pairs_grouped(const ReduceEntryDev* __restrict__ ents,
+__global__ __launch_bounds__(kThreads) void k_reduce_pairs_grouped(const int* __restrict__ count,
+                                                                   const ReduceEntryDev* __restrict__ ents,
                                                                    double* __restrict__ out) {
+    if ((int)blockIdx.x >= *count) return;  // uniform per block
     const ReduceEntryDev e = ents[blockIdx.x];
     double s0 = 0.0, s1 = 0.0;
     for (int b = threadIdx.x; b < e.npairs; b += kThreads) {
@@ -357,8 +359,9 @@ struct ReduceEntry {
 };
 static_assert(sizeof(ReduceEntry) == sizeof(ReduceEntryDev), "reduce table layout");
 
-hipError_t reduce_pairs_grouped(const ReduceEntry* ents, int count, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_pairs_grouped, dim3((unsigned)count), dim3(kThreads), 0, s,
+hipError_t reduce_pairs_grouped(const int* count, const ReduceEntry* ents, int grid, double* out,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_pairs_grouped, dim3((unsigned)grid), dim3(kThreads), 0, s, count,
                        reinterpret_cast<const ReduceEntryDev*>(ents), out);
     return hipGetLastError();
 }

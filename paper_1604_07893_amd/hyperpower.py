@@ -31,7 +31,7 @@ SIDE = {"auto": 0, "right": 1, "left": 2}
 STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2, "fp32_fp64": 3}
 LOWP = {"bf16": 0, "f16": 1, "fp16": 1}
-FLAG_TIME_KERNELS, FLAG_INF_NORM = 1, 2
+FLAG_TIME_KERNELS, FLAG_INF_NORM, FLAG_NO_GRAPH = 1, 2, 4
 DTYPE = {torch.float64: 0, torch.float32: 1}
 HP_HIST = 128
 
@@ -77,6 +77,10 @@ SIGNATURES = {
                          POINTER(HpResult)]),
     "hp_gemm": (c_int, [c_void_p, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
                         c_void_p, c_int64, c_double, c_void_p, c_int64, c_void_p]),
+    "hp_autotune": (c_int, [c_void_p, c_int, c_int64, c_int64, c_int64, c_void_p, c_size_t, c_int,
+                            c_void_p, POINTER(c_int), POINTER(c_double)]),
+    "hp_tune_export": (c_int, [c_void_p, POINTER(c_int64), c_int, POINTER(c_int)]),
+    "hp_tune_import": (c_int, [c_void_p, POINTER(c_int64), c_int]),
     "hp_batched_workspace_bytes": (c_int, [POINTER(HpParams), c_int, POINTER(HpProblem),
                                            POINTER(c_size_t)]),
     "hp_solve_batched": (c_int, [c_void_p, POINTER(HpParams), c_int, POINTER(HpProblem), c_void_p,
@@ -152,7 +156,7 @@ def handle(device: int | None = None) -> Handle:
 def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", tau_switch=0.1,
                 tol=1e-12, max_iter=100, stop="rel_fro", side="auto", precision="fp64",
                 diverge_limit=1e6, time_kernels=False, inf_norm=False,
-                low_dtype="bf16") -> HpParams:
+                low_dtype="bf16", graph=True) -> HpParams:
     p = HpParams()
     load_library().hp_params_default(ctypes.byref(p))
     p.kind = KIND[kind]
@@ -170,7 +174,8 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
     p.precision = PREC[precision]
     p.low_dtype = LOWP[low_dtype]
     p.diverge_limit = float(diverge_limit)
-    p.flags = (FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
+    p.flags = ((FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
+               | (0 if graph else FLAG_NO_GRAPH))
     return p
 
 
@@ -382,3 +387,56 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+GEMM_DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+
+
+def autotune(shapes, dtype: str = "f64", reps: int = 3, device: int | None = None) -> list:
+    """Time every tile configuration on each (M, N, K) and keep the fastest in
+    the device's handle; returns [(M, N, K, tile, ms)]."""
+    dev = torch.cuda.current_device() if device is None else device
+    h = handle(dev)
+    code = GEMM_DTYPES[dtype]
+    esz = 8 if code == 0 else 4
+    out = []
+    for (M, N, K) in shapes:
+        v = 16 // esz
+        lda, ldb = (K + v - 1) // v * v, (N + v - 1) // v * v
+        nbytes = esz * (M * lda + K * ldb + M * N) + 64
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{dev}")
+        t, ms = c_int(), c_double()
+        rc = load_library().hp_autotune(h.ptr, code, M, N, K, scratch.data_ptr(), nbytes, reps,
+                                        torch.cuda.current_stream(dev).cuda_stream,
+                                        ctypes.byref(t), ctypes.byref(ms))
+        if rc != HP_OK:
+            raise HyperpowerError(rc, "hp_autotune")
+        out.append((M, N, K, t.value, ms.value))
+    return out
+
+
+def tuning_table(device: int | None = None) -> list:
+    """The handle's autotuned entries as [(dtype_code, M, N, K, tile)]."""
+    dev = torch.cuda.current_device() if device is None else device
+    lib, h = load_library(), handle(dev)
+    n = c_int()
+    lib.hp_tune_export(h.ptr, None, 0, ctypes.byref(n))
+    rows = (c_int64 * (5 * max(n.value, 1)))()
+    lib.hp_tune_export(h.ptr, rows, n.value, ctypes.byref(n))
+    return [tuple(rows[5 * i:5 * i + 5]) for i in range(n.value)]
+
+
+def save_tuning(path: str, device: int | None = None):
+    import json
+    with open(path, "w") as f:
+        json.dump({"rows": tuning_table(device)}, f)
+
+
+def load_tuning(path: str, device: int | None = None):
+    import json
+    dev = torch.cuda.current_device() if device is None else device
+    rows = json.load(open(path))["rows"]
+    flat = (c_int64 * (5 * max(len(rows), 1)))(*[int(x) for r in rows for x in r])
+    rc = load_library().hp_tune_import(handle(dev).ptr, flat, len(rows))
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_tune_import")

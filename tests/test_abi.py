@@ -25,7 +25,8 @@ def test_header_declares_the_boundary():
     for required in ("hp_version", "hp_status_string", "hp_params_default", "hp_create",
                      "hp_destroy", "hp_workspace_bytes", "hp_solve", "hp_gemm",
                      "hp_batched_workspace_bytes", "hp_solve_batched", "hp_serve_create",
-                     "hp_serve_submit", "hp_serve_step", "hp_serve_poll", "hp_serve_destroy"):
+                     "hp_serve_submit", "hp_serve_step", "hp_serve_poll", "hp_serve_destroy",
+                     "hp_autotune", "hp_tune_export", "hp_tune_import"):
         assert required in names
 
 

@@ -120,3 +120,18 @@ def test_gemm_16bit_operands_match_rounded_product(operands, M, N, K):
     bound = (np.abs(Ar) @ np.abs(Br)) * (2 * K + 4) * 2.0**-24
     err = np.abs(C.cpu().numpy().astype(np.float64) - ref)
     assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
+
+
+def test_autotune_picks_a_tile_and_keeps_results_correct():
+    hpw = need_gpu()
+    res = hpw.autotune([(512, 512, 512), (300, 200, 100)], dtype="f64", reps=2)
+    assert len(res) == 2 and all(r[4] > 0 for r in res)
+    table = hpw.tuning_table()
+    assert {(r[1], r[2], r[3]) for r in table} >= {(512, 512, 512), (300, 200, 100)}
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((300, 100))
+    B = rng.standard_normal((100, 200))
+    C = hpw.gemm(even_ld(A), even_ld(B))
+    ref = A @ B
+    bound = (np.abs(A) @ np.abs(B)) * 204 * U64
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
