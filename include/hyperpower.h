@@ -225,6 +225,26 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
             double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
             double beta_identity, void* C, int64_t ldc, void* stream);
 
+/* ---- residuals of the defining equations ---------------------------------- */
+
+/* Workspace for hp_residuals. */
+int hp_residuals_workspace_bytes(int kind, int l, int64_t m, int64_t n, size_t* bytes);
+
+/* Relative residuals, in FP64 on the GPU, of the equations that define the
+ * inverse X (n x m) of A (m x n), Frobenius norms:
+ *  HP_KIND_MOORE_PENROSE (the four Penrose equations):
+ *    out[0] = ||AXA - A||/||A||, out[1] = ||XAX - X||/||X||,
+ *    out[2] = ||AX - (AX)^T||/||AX||, out[3] = ||XA - (XA)^T||/||XA||;
+ *  HP_KIND_DRAZIN (m == n, l >= ind(A); Section 1.2):
+ *    out[0] = ||A^{l+1} X - A^l||/||A^l||, out[1] = ||XAX - X||/||X||,
+ *    out[2] = ||AX - XA||/||AX||, out[3] = 0.
+ * A, X: device, row-major, lda >= n, ldx >= m, 16-byte aligned with lda and
+ * ldx even. out: host array of 4. Synchronises the stream. Errors: HP_EINVAL,
+ * HP_EWORKSPACE, HP_EHIP. */
+int hp_residuals(hp_handle* h, int kind, int l, const double* A, int64_t m, int64_t n, int64_t lda,
+                 const double* X, int64_t ldx, void* workspace, size_t ws_bytes, void* stream,
+                 double out[4]);
+
 /* ---- tile autotuning ------------------------------------------------------ */
 
 /* Time every tile configuration of the GEMM kernel for dtype on an M x N x K

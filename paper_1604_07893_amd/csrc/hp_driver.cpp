@@ -599,6 +599,105 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alp
     return HP_OK;
 }
 
+static void residual_layout(int kind, int l, int64_t m, int64_t n, size_t off[8], size_t* total) {
+    // AX (m x m), XA (n x n), AXA (m x n), XAX (n x m), then for Drazin two
+    // n x n power buffers; then the small area and the scalar slots
+    const int64_t ldm = hp::pad_ld(m), ldn = hp::pad_ld(n);
+    size_t o = 0;
+    off[0] = o; o = hp::align_up(o + 8 * (size_t)(m * ldm));
+    off[1] = o; o = hp::align_up(o + 8 * (size_t)(n * ldn));
+    off[2] = o; o = hp::align_up(o + 8 * (size_t)(m * ldn));
+    off[3] = o; o = hp::align_up(o + 8 * (size_t)(n * ldm));
+    off[4] = o; o = hp::align_up(o + (kind == HP_KIND_DRAZIN ? 8 * (size_t)(n * ldn) : 0));
+    off[5] = o; o = hp::align_up(o + (kind == HP_KIND_DRAZIN ? 8 * (size_t)(n * ldn) : 0));
+    const int64_t big = std::max(m, n);
+    off[6] = o; o = hp::align_up(o + 8 * (size_t)std::max<int64_t>(big, ((big + 31) / 32) * ((big + 31) / 32)));
+    off[7] = o; o = hp::align_up(o + 8 * 16);
+    (void)l;
+    *total = o;
+}
+
+int hp_residuals_workspace_bytes(int kind, int l, int64_t m, int64_t n, size_t* bytes) {
+    if (!bytes || m < 1 || n < 1 || m > 65535 || n > 65535) return HP_EINVAL;
+    if (kind != HP_KIND_MOORE_PENROSE && kind != HP_KIND_DRAZIN) return HP_EINVAL;
+    if (kind == HP_KIND_DRAZIN && (m != n || l < 1 || l > 64)) return HP_EINVAL;
+    size_t off[8];
+    residual_layout(kind, l, m, n, off, bytes);
+    return HP_OK;
+}
+
+int hp_residuals(hp_handle* h, int kind, int l, const double* A, int64_t m, int64_t n, int64_t lda,
+                 const double* X, int64_t ldx, void* workspace, size_t ws_bytes, void* stream,
+                 double out[4]) {
+    if (!h || !A || !X || !out) return HP_EINVAL;
+    size_t need = 0;
+    CHK(hp_residuals_workspace_bytes(kind, l, m, n, &need));
+    if (lda < n || ldx < m || (lda & 1) || (ldx & 1)) return HP_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(X)) & 15) return HP_EINVAL;
+    if (!workspace || ws_bytes < need) return HP_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) % hp::kAlign) return HP_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    size_t off[8], total;
+    residual_layout(kind, l, m, n, off, &total);
+    char* w = static_cast<char*>(workspace);
+    auto dp = [&](int i) { return reinterpret_cast<double*>(w + off[i]); };
+    const int64_t ldm = hp::pad_ld(m), ldn = hp::pad_ld(n);
+    double *AX = dp(0), *XA = dp(1), *AXA = dp(2), *XAX = dp(3), *tmp = dp(6), *scal = dp(7);
+    auto mm = [&](int64_t M, int64_t N, int64_t K, const double* P, int64_t ldp, const double* Q,
+                  int64_t ldq, double* C, int64_t ldc) -> int {
+        const hp::GemmTile t = hp::choose_tile(h, HP_DTYPE_F64, M, N, K);
+        return hp::gemm(t, M, N, K, P, ldp, Q, ldq, hp::epilogue_plain(C, ldc), s) == hipSuccess
+                   ? HP_OK : HP_EHIP;
+    };
+    CHK(mm(m, m, n, A, lda, X, ldx, AX, ldm));     // AX
+    CHK(mm(n, n, m, X, ldx, A, lda, XA, ldn));     // XA
+    CHK(mm(n, m, n, XA, ldn, X, ldx, XAX, ldm));   // XAX
+    double* hs = h->host_scal;
+    if (kind == HP_KIND_MOORE_PENROSE) {
+        CHK(mm(m, n, m, AX, ldm, A, lda, AXA, ldn));   // AXA
+        HIPCHK(hp::diffsq(AXA, ldn, A, lda, 1.0, m, n, tmp, scal, 0, s));
+        HIPCHK(hp::diffsq(A, lda, nullptr, 0, 0.0, m, n, tmp, scal, 1, s));
+        HIPCHK(hp::diffsq(XAX, ldm, X, ldx, 1.0, n, m, tmp, scal, 2, s));
+        HIPCHK(hp::diffsq(X, ldx, nullptr, 0, 0.0, n, m, tmp, scal, 3, s));
+        HIPCHK(hp::asymsq(AX, ldm, m, tmp, scal, 4, s));
+        HIPCHK(hp::diffsq(AX, ldm, nullptr, 0, 0.0, m, m, tmp, scal, 5, s));
+        HIPCHK(hp::asymsq(XA, ldn, n, tmp, scal, 6, s));
+        HIPCHK(hp::diffsq(XA, ldn, nullptr, 0, 0.0, n, n, tmp, scal, 7, s));
+        HIPCHK(hipMemcpyAsync(hs, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double v[8];
+        std::memcpy(v, hs, sizeof(v));
+        for (int i = 0; i < 4; ++i) out[i] = std::sqrt(v[2 * i]) / std::sqrt(v[2 * i + 1]);
+        return HP_OK;
+    }
+    // Drazin: A^l by repeated products (A^1 = A), then A^{l+1} X = A^l (A X)
+    double* pw[2] = {dp(4), dp(5)};
+    const double* Al = A;
+    int64_t ldl = lda;
+    for (int i = 1; i < l; ++i) {
+        double* dst = pw[i & 1];
+        CHK(mm(n, n, n, Al, ldl, A, lda, dst, ldn));
+        Al = dst;
+        ldl = ldn;
+    }
+    double* other = (Al == pw[0]) ? pw[1] : pw[0];
+    CHK(mm(n, n, n, Al, ldl, AX, ldm, other, ldn));  // A^l (A X) = A^{l+1} X
+    HIPCHK(hp::diffsq(other, ldn, Al, ldl, 1.0, n, n, tmp, scal, 0, s));
+    HIPCHK(hp::diffsq(Al, ldl, nullptr, 0, 0.0, n, n, tmp, scal, 1, s));
+    HIPCHK(hp::diffsq(XAX, ldm, X, ldx, 1.0, n, n, tmp, scal, 2, s));
+    HIPCHK(hp::diffsq(X, ldx, nullptr, 0, 0.0, n, n, tmp, scal, 3, s));
+    HIPCHK(hp::diffsq(AX, ldm, XA, ldn, 1.0, n, n, tmp, scal, 4, s));
+    HIPCHK(hp::diffsq(AX, ldm, nullptr, 0, 0.0, n, n, tmp, scal, 5, s));
+    HIPCHK(hipMemcpyAsync(hs, scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double v[6];
+    std::memcpy(v, hs, sizeof(v));
+    for (int i = 0; i < 3; ++i) out[i] = std::sqrt(v[2 * i]) / std::sqrt(v[2 * i + 1]);
+    out[3] = 0.0;
+    return HP_OK;
+}
+
 int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* scratch,
                 size_t scratch_bytes, int reps, void* stream, int* tile, double* ms) {
     if (!h || !scratch || !tile || !ms || reps < 1) return HP_EINVAL;

@@ -150,6 +150,15 @@ hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_
 hipError_t sumsq(const float* X, int64_t ldx, int64_t M, int64_t N, double* tmp, double* scal,
                  int slot, hipStream_t s);
 
+// scal[slot] = sum over the M x N entries of (P - c Q)^2 (Q may be NULL).
+// `tmp` needs M doubles.
+hipError_t diffsq(const double* P, int64_t ldp, const double* Q, int64_t ldq, double c, int64_t M,
+                  int64_t N, double* tmp, double* scal, int slot, hipStream_t s);
+// scal[slot] = sum over the n x n entries of (P - P^T)^2. `tmp` needs
+// ceil(n/32)^2 doubles.
+hipError_t asymsq(const double* P, int64_t ldp, int64_t n, double* tmp, double* scal, int slot,
+                  hipStream_t s);
+
 // Y = X elementwise with a change of precision (M x N; narrowing rounds to
 // nearest even).
 hipError_t convert(const double* X, int64_t ldx, int64_t M, int64_t N, float* Y, int64_t ldy,

@@ -229,6 +229,45 @@ __global__ __launch_bounds__(kThreads) void k_sum_to_slot(const double* __restri
     if (threadIdx.x == 0) scal[slot] = s;
 }
 
+// Row sums of (P - c Q)^2, or of (P - c Q^T)^2 when `transposed` (P, Q are
+// M x N; for the transposed form M == N and Q^T is read through LDS tiles).
+__global__ __launch_bounds__(kThreads) void k_rowdiffsq(const double* __restrict__ P, int64_t ldp,
+                                                        const double* __restrict__ Q, int64_t ldq,
+                                                        int M, int N, double c,
+                                                        double* __restrict__ rows) {
+    const int r = blockIdx.x;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < N; j += kThreads) {
+        const double v = P[(int64_t)r * ldp + j] - (Q ? c * Q[(int64_t)r * ldq + j] : 0.0);
+        s += v * v;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) rows[r] = s;
+}
+
+// Partial sums of (P[i][j] - P[j][i])^2 over 32x32 tiles (n x n).
+__global__ __launch_bounds__(kThreads) void k_asym_part(const double* __restrict__ P, int64_t ldp,
+                                                        int n, double* __restrict__ part) {
+    __shared__ double t[32][33];
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int y = ty; y < 32; y += 8) {
+        const int j = bj + y, i = bi + tx;
+        t[y][tx] = (j < n && i < n) ? P[(int64_t)j * ldp + i] : 0.0;
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int y = ty; y < 32; y += 8) {
+        const int i = bi + y, j = bj + tx;
+        if (i < n && j < n) {
+            const double v = P[(int64_t)i * ldp + j] - t[tx][y];
+            s += v * v;
+        }
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
 // One block per problem: fixed-order sums of that problem's partial pairs.
 struct ReduceEntryDev {
     const double* partials;
@@ -374,6 +413,26 @@ hipError_t sumsq(const float* X, int64_t ldx, int64_t M, int64_t N, double* tmp,
                  int slot, hipStream_t s) {
     hipLaunchKernelGGL(k_rowsumsq<float>, dim3((unsigned)M), dim3(kThreads), 0, s, X, ldx, (int)N, tmp);
     hipLaunchKernelGGL(k_sum_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal, slot);
+    return hipGetLastError();
+}
+
+}  // namespace hp
+
+namespace hp {
+
+hipError_t diffsq(const double* P, int64_t ldp, const double* Q, int64_t ldq, double c, int64_t M,
+                  int64_t N, double* tmp, double* scal, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_rowdiffsq, dim3((unsigned)M), dim3(kThreads), 0, s, P, ldp, Q, ldq, (int)M,
+                       (int)N, c, tmp);
+    hipLaunchKernelGGL(k_sum_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal, slot);
+    return hipGetLastError();
+}
+
+hipError_t asymsq(const double* P, int64_t ldp, int64_t n, double* tmp, double* scal, int slot,
+                  hipStream_t s) {
+    const int nt = (int)cdiv(n, 32);
+    hipLaunchKernelGGL(k_asym_part, dim3(nt, nt), dim3(kThreads), 0, s, P, ldp, (int)n, tmp);
+    hipLaunchKernelGGL(k_sum_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, nt * nt, scal, slot);
     return hipGetLastError();
 }
 

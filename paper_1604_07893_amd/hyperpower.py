@@ -81,6 +81,9 @@ SIGNATURES = {
                             c_void_p, POINTER(c_int), POINTER(c_double)]),
     "hp_tune_export": (c_int, [c_void_p, POINTER(c_int64), c_int, POINTER(c_int)]),
     "hp_tune_import": (c_int, [c_void_p, POINTER(c_int64), c_int]),
+    "hp_residuals_workspace_bytes": (c_int, [c_int, c_int, c_int64, c_int64, POINTER(c_size_t)]),
+    "hp_residuals": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int64, c_int64, c_int64, c_void_p,
+                             c_int64, c_void_p, c_size_t, c_void_p, POINTER(c_double)]),
     "hp_batched_workspace_bytes": (c_int, [POINTER(HpParams), c_int, POINTER(HpProblem),
                                            POINTER(c_size_t)]),
     "hp_solve_batched": (c_int, [c_void_p, POINTER(HpParams), c_int, POINTER(HpProblem), c_void_p,
@@ -440,3 +443,25 @@ def load_tuning(path: str, device: int | None = None):
     rc = load_library().hp_tune_import(handle(dev).ptr, flat, len(rows))
     if rc != HP_OK:
         raise HyperpowerError(rc, "hp_tune_import")
+
+
+def residuals(A: torch.Tensor, X: torch.Tensor, kind: str = "mp", l: int = 0) -> list:
+    """Relative residuals of the defining equations of X = A^(2), computed on
+    the GPU in FP64 (four Penrose equations, or the three Drazin equations)."""
+    _check_matrix(A, "A")
+    _check_matrix(X, "X")
+    m, n = A.shape
+    lib = load_library()
+    nb = c_size_t()
+    rc = lib.hp_residuals_workspace_bytes(KIND[kind], int(l), m, n, ctypes.byref(nb))
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_residuals_workspace_bytes")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=A.device)
+    out = (c_double * 4)()
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    rc = lib.hp_residuals(handle(dev).ptr, KIND[kind], int(l), A.data_ptr(), m, n, A.stride(0),
+                          X.data_ptr(), X.stride(0), ws.data_ptr(), ws.numel(),
+                          torch.cuda.current_stream(A.device).cuda_stream, out)
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_residuals")
+    return list(out)

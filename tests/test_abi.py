@@ -26,7 +26,8 @@ def test_header_declares_the_boundary():
                      "hp_destroy", "hp_workspace_bytes", "hp_solve", "hp_gemm",
                      "hp_batched_workspace_bytes", "hp_solve_batched", "hp_serve_create",
                      "hp_serve_submit", "hp_serve_step", "hp_serve_poll", "hp_serve_destroy",
-                     "hp_autotune", "hp_tune_export", "hp_tune_import"):
+                     "hp_autotune", "hp_tune_export", "hp_tune_import",
+                     "hp_residuals_workspace_bytes", "hp_residuals"):
         assert required in names
 
 

@@ -209,3 +209,19 @@ def test_drazin_2048_full_size():
         say(f"  {variant}: status={info['status']} iters={info['iters']} err={rel(X, closed):.2e}")
         assert info["status"] in ("ok", "stagnated")
         assert rel(X, closed) <= (1e-10 if variant == "stabilised" else 1e-9)
+
+
+def test_gpu_residuals_match_oracle_residuals():
+    """hp_residuals against the oracle's residual definitions on the same X."""
+    hpw = need_gpu()
+    d = inputs.lowrank_svd(300, 160, 120, smin=1e-3, seed=50)
+    X = (d.V / d.s) @ d.U.T + 1e-7 * np.random.default_rng(1).standard_normal((160, 300))
+    got = hpw.residuals(to_dev(d.A), to_dev(np.ascontiguousarray(X)))
+    want = O.penrose_residuals(d.A, X)
+    np.testing.assert_allclose(got, want, rtol=1e-6)
+    dz = inputs.drazin_jordan(n=96, nb=84, cond_p=10.0, seed=51)
+    Xd = np.linalg.pinv(dz.A)  # any X: both sides evaluate the same equations
+    got = hpw.residuals(to_dev(dz.A), to_dev(Xd), kind="drazin", l=3)
+    want = O.drazin_residuals(dz.A, Xd, 3)
+    np.testing.assert_allclose(got[:3], want, rtol=1e-6)
+    assert got[3] == 0.0
