@@ -225,6 +225,23 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
             double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
             double beta_identity, void* C, int64_t ldc, void* stream);
 
+/* Workspace that lets hp_gemm_ws split K over several blocks per output tile
+ * (the split-K tiles, chosen for products with too few 128 x 128 output tiles
+ * to occupy every compute unit); 0 when the product would not split. */
+int hp_gemm_workspace_bytes(int dtype, int64_t M, int64_t N, int64_t K, size_t* bytes);
+
+/* hp_gemm with a workspace (device memory, 256-byte aligned). With at least
+ * hp_gemm_workspace_bytes for the tile the handle chooses, a split tile stores
+ * its partial tiles there and the last block of each output tile adds them in
+ * a fixed order, so the result is the same from run to run; with less (or
+ * NULL and 0) the product runs unsplit. The workspace's counters are cleared
+ * on the stream by every call; calls that share a workspace must not overlap.
+ * Errors: as hp_gemm (a misaligned workspace is HP_EINVAL). */
+int hp_gemm_ws(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
+               double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+               double beta_identity, void* C, int64_t ldc, void* workspace, size_t ws_bytes,
+               void* stream);
+
 /* ---- residuals of the defining equations ---------------------------------- */
 
 /* Workspace for hp_residuals. */
@@ -247,13 +264,18 @@ int hp_residuals(hp_handle* h, int kind, int l, const double* A, int64_t m, int6
 
 /* ---- tile autotuning ------------------------------------------------------ */
 
+/* Scratch hp_autotune needs for this product: the operands and result
+ * (rows padded to 16 bytes) and the split-K scratch of the split tiles. */
+int hp_autotune_scratch_bytes(int dtype, int64_t M, int64_t N, int64_t K, size_t* bytes);
+
 /* Time every tile configuration of the GEMM kernel for dtype on an M x N x K
- * product (operands filled by the library in `scratch`, which needs
- * (M*K + K*N + M*N) elements of the dtype's storage type, 16-byte aligned),
- * `reps` timed launches each after one warm-up, and record the fastest in the
- * handle: later products of exactly this (dtype, M, N, K) use it. Returns the
- * chosen tile index and its mean launch time. The environment variable
- * HP_GEMM_TILE, if set, still overrides every choice. */
+ * product (operands filled by the library in `scratch`, device memory of at
+ * least hp_autotune_scratch_bytes, 16-byte aligned), `reps` timed launches
+ * each after one warm-up, and record the fastest in the handle: later
+ * products of exactly this (dtype, M, N, K) use it. Returns the chosen tile
+ * index and its mean launch time. The environment variable HP_GEMM_TILE, if
+ * set, still overrides every choice. Errors: HP_EINVAL, HP_EWORKSPACE (scratch
+ * too small), HP_EHIP. */
 int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* scratch,
                 size_t scratch_bytes, int reps, void* stream, int* tile, double* ms);
 

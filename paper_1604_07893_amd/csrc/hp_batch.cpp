@@ -394,7 +394,7 @@ int hp_batched_workspace_bytes(const hp_params* p, int count, const hp_problem* 
     size_t total = Tables::layout(count, nullptr);
     for (int i = 0; i < count; ++i) {
         CHK(validate(p, probs[i].m, probs[i].n));
-        total += align_up(make_plan(p, probs[i].m, probs[i].n).total);
+        total += align_up(make_plan(p, probs[i].m, probs[i].n, false).total);
     }
     *bytes = total;
     return HP_OK;
@@ -429,7 +429,7 @@ int hp_solve_batched(hp_handle* h, const hp_params* p, int count, const hp_probl
     int rc = HP_OK;
     for (int i = 0; i < count && rc == HP_OK; ++i) {
         P[i].pr = probs[i];
-        P[i].pl = make_plan(p, probs[i].m, probs[i].n);
+        P[i].pl = make_plan(p, probs[i].m, probs[i].n, false);
         P[i].ws = ws + off;
         off += align_up(P[i].pl.total);
         rc = admit(g, P[i]);
@@ -486,7 +486,7 @@ int hp_serve_create(hp_handle* h, const hp_params* p, size_t hbm_budget, int max
 int hp_serve_submit(hp_server* sv, const hp_problem* prob, uint64_t* ticket) {
     if (!sv || !prob || !ticket) return HP_EINVAL;
     CHK(validate_problem(&sv->g.prm, *prob));
-    const Plan pl = make_plan(&sv->g.prm, prob->m, prob->n);
+    const Plan pl = make_plan(&sv->g.prm, prob->m, prob->n, false);
     if (align_up(pl.total) > sv->budget) return HP_EBUDGET;
     const uint64_t t = sv->next_ticket++;
     Problem& P = sv->reqs[t];

@@ -50,7 +50,7 @@ static bool choose_left(const hp_params* p, int64_t m, int64_t n) {
     return m > n;
 }
 
-Plan make_plan(const hp_params* p, int64_t m, int64_t n) {
+Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area) {
     Plan pl;
     pl.m = m;
     pl.n = n;
@@ -98,6 +98,24 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n) {
         for (int i = 0; i < pl.nS32; ++i) {
             pl.offS32[i] = off;
             off = align_up(off + sizeof(float) * (size_t)(pl.s * pl.ldS32));
+        }
+    }
+    if (split_area) {
+        // every product of a solve is (m or n) x (m or n) x (m or n)
+        const int64_t dims[2] = {m, n};
+        const hp::GemmType types[2] = {hp::GT_F64, hp::GT_F32};
+        for (hp::GemmType gt : types)
+            for (int64_t M : dims)
+                for (int64_t N : dims)
+                    for (int64_t K : dims)
+                        pl.splitSlots = std::max(
+                            pl.splitSlots,
+                            hp::gemm_split_slots(hp::gemm_pick_tile(M, N, K, gt), M, N, K));
+        if (pl.splitSlots > 0) {
+            pl.offSplit = off;
+            off = align_up(off + sizeof(double) * 128 * 128 * (size_t)pl.splitSlots);
+            pl.offSplitCnt = off;
+            off = align_up(off + sizeof(unsigned) * (size_t)pl.splitSlots);
         }
     }
     // small area: GEMM partial pairs, norm sums, trace partials, row sums
@@ -165,6 +183,10 @@ Buffers carve(const Plan& pl, char* ws) {
     }
     bf.small = d(pl.offSmall);
     bf.scal = d(pl.offScal);
+    if (pl.splitSlots > 0) {
+        bf.split_part = d(pl.offSplit);
+        bf.split_cnt = reinterpret_cast<unsigned*>(ws + pl.offSplitCnt);
+    }
     return bf;
 }
 
@@ -344,22 +366,30 @@ struct Solver {
     int gemms = 0;
     int last_blocks = 0;  // blocks (partial pairs) of the latest product
     int stage = 2;        // for per-stage accounting
+    double* split_part = nullptr;  // split-K scratch of the workspace (Plan)
+    unsigned* split_cnt = nullptr;
 
     template <typename T>
     int gemm(Engine eng, const GemmCall<T>& g) {
         int dt = HP_DTYPE_F64;
         if constexpr (!std::is_same<T, double>::value)
             dt = eng == ENG_F32 ? HP_DTYPE_F32 : (eng == ENG_BF16 ? HP_DTYPE_BF16_F32 : HP_DTYPE_F16_F32);
-        const GemmTile t = choose_tile(h, dt, g.M, g.N, g.K);
+        EpilogueT<T> ep = g.ep;
+        if (split_part) {
+            ep.split_part = reinterpret_cast<T*>(split_part);
+            ep.split_cnt = split_cnt;
+            ep.split_slots = pl.splitSlots * (int64_t)(sizeof(double) / sizeof(T));
+        }
+        const GemmTile t = choose_tile(h, dt, g.M, g.N, g.K, ep.split_slots);
         timer.before();
         hipError_t e;
         if constexpr (std::is_same<T, double>::value) {
             (void)eng;
-            e = hp::gemm(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.ep, s);
+            e = hp::gemm(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, ep, s);
         } else {
-            if (eng == ENG_F32) e = hp::gemm(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.ep, s);
+            if (eng == ENG_F32) e = hp::gemm(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, ep, s);
             else e = gemm_lowp(t, eng == ENG_BF16 ? LOWP_BF16 : LOWP_F16, g.M, g.N, g.K, g.A, g.lda,
-                               g.B, g.ldb, g.ep, s);
+                               g.B, g.ldb, ep, s);
         }
         timer.after();
         last_blocks = gemm_blocks(t, g.M, g.N);
@@ -381,6 +411,11 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
     const int64_t m = pl.m, n = pl.n;
     const Buffers bf = carve(pl, ws);
     double* hs = S.h->host_scal;
+    if (bf.split_cnt) {
+        HIPCHK(zero_u32(bf.split_cnt, pl.splitSlots, s));
+        S.split_part = bf.split_part;
+        S.split_cnt = bf.split_cnt;
+    }
 
     double alpha = 0.0;
     S.stage = 2;
@@ -568,10 +603,22 @@ int hp_solve(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64
     return rc;
 }
 
-int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alpha, const void* A,
-            int64_t lda, const void* B, int64_t ldb, double beta_identity, void* C, int64_t ldc,
-            void* stream) {
-    if (!h || !A || !B || !C) return HP_EINVAL;
+// Split-K workspace of hp_gemm_ws: `slots` partial tiles of 128 x 128
+// elements of the dtype's storage type, then `slots` counters.
+static int64_t gemm_ws_slots(const hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K) {
+    const hp::GemmTile t = h ? hp::choose_tile(h, dtype, M, N, K, INT64_MAX)
+                             : hp::gemm_pick_tile(M, N, K, hp::gemm_type(dtype));
+    return hp::gemm_split_slots(t, M, N, K);
+}
+static size_t gemm_ws_bytes(int dtype, int64_t slots) {
+    if (slots <= 0) return 0;
+    const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;
+    return hp::align_up(esz * 128 * 128 * (size_t)slots) + sizeof(unsigned) * (size_t)slots;
+}
+
+static int gemm_args(int dtype, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+                     const void* B, int64_t ldb, const void* C, int64_t ldc) {
+    if (!A || !B || !C) return HP_EINVAL;
     if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16_F32) return HP_EINVAL;
     if (M < 1 || N < 1 || K < 1 || M > (1 << 24) || N > (1 << 24) || K > (1 << 24)) return HP_EINVAL;
     if (lda < K || ldb < N || ldc < N) return HP_EINVAL;
@@ -580,16 +627,38 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alp
     if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
          reinterpret_cast<uintptr_t>(C)) & 15)
         return HP_EINVAL;
+    return HP_OK;
+}
+
+static int gemm_run(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alpha,
+                    const void* A, int64_t lda, const void* B, int64_t ldb, double beta_identity,
+                    void* C, int64_t ldc, void* workspace, int64_t slots, void* stream) {
     if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
-    const hp::GemmTile t = hp::choose_tile(h, dtype, M, N, K);
+    const hp::GemmTile t = hp::choose_tile(h, dtype, M, N, K, workspace ? slots : 0);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned* cnt = nullptr;
+    if (workspace && slots > 0) {
+        const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;
+        cnt = reinterpret_cast<unsigned*>(static_cast<char*>(workspace) +
+                                          hp::align_up(esz * 128 * 128 * (size_t)slots));
+        HIPCHK(hp::zero_u32(cnt, slots, s));
+    }
+    auto split = [&](auto ep) {
+        using E = std::remove_pointer_t<decltype(ep.split_part)>;
+        if (cnt) {
+            ep.split_part = static_cast<E*>(workspace);
+            ep.split_cnt = cnt;
+            ep.split_slots = slots;
+        }
+        return ep;
+    };
     hipError_t e;
     if (dtype == HP_DTYPE_F64) {
         e = hp::gemm(t, M, N, K, static_cast<const double*>(A), lda, static_cast<const double*>(B),
-                     ldb, hp::epilogue_plain(static_cast<double*>(C), ldc, alpha, beta_identity), s);
+                     ldb, split(hp::epilogue_plain(static_cast<double*>(C), ldc, alpha, beta_identity)), s);
     } else if (dtype == HP_DTYPE_F32) {
         e = hp::gemm(t, M, N, K, static_cast<const float*>(A), lda, static_cast<const float*>(B),
-                     ldb, hp::epilogue_plain(static_cast<float*>(C), ldc, alpha, beta_identity), s);
+                     ldb, split(hp::epilogue_plain(static_cast<float*>(C), ldc, alpha, beta_identity)), s);
     } else {
         e = hp::gemm_lowp(t, dtype == HP_DTYPE_BF16_F32 ? hp::LOWP_BF16 : hp::LOWP_F16, M, N, K,
                           static_cast<const float*>(A), lda, static_cast<const float*>(B), ldb,
@@ -597,6 +666,39 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alp
     }
     if (e != hipSuccess) return HP_EHIP;
     return HP_OK;
+}
+
+int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alpha, const void* A,
+            int64_t lda, const void* B, int64_t ldb, double beta_identity, void* C, int64_t ldc,
+            void* stream) {
+    if (!h) return HP_EINVAL;
+    CHK(gemm_args(dtype, M, N, K, A, lda, B, ldb, C, ldc));
+    return gemm_run(h, dtype, M, N, K, alpha, A, lda, B, ldb, beta_identity, C, ldc, nullptr, 0,
+                    stream);
+}
+
+int hp_gemm_workspace_bytes(int dtype, int64_t M, int64_t N, int64_t K, size_t* bytes) {
+    if (!bytes) return HP_EINVAL;
+    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16_F32) return HP_EINVAL;
+    if (M < 1 || N < 1 || K < 1 || M > (1 << 24) || N > (1 << 24) || K > (1 << 24)) return HP_EINVAL;
+    *bytes = gemm_ws_bytes(dtype, gemm_ws_slots(nullptr, dtype, M, N, K));
+    return HP_OK;
+}
+
+int hp_gemm_ws(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alpha,
+               const void* A, int64_t lda, const void* B, int64_t ldb, double beta_identity,
+               void* C, int64_t ldc, void* workspace, size_t ws_bytes, void* stream) {
+    if (!h) return HP_EINVAL;
+    CHK(gemm_args(dtype, M, N, K, A, lda, B, ldb, C, ldc));
+    if (!workspace && ws_bytes) return HP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % hp::kAlign) return HP_EINVAL;
+    // the tile the handle chooses (environment override, autotuned entry or
+    // default) decides how much of the workspace is used; with less than that
+    // the product runs unsplit
+    int64_t slots = gemm_ws_slots(h, dtype, M, N, K);
+    if (!workspace || ws_bytes < gemm_ws_bytes(dtype, slots)) slots = 0;
+    return gemm_run(h, dtype, M, N, K, alpha, A, lda, B, ldb, beta_identity, C, ldc, workspace,
+                    slots, stream);
 }
 
 static void residual_layout(int kind, int l, int64_t m, int64_t n, size_t off[8], size_t* total) {
@@ -698,16 +800,44 @@ int hp_residuals(hp_handle* h, int kind, int l, const double* A, int64_t m, int6
     return HP_OK;
 }
 
-int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* scratch,
-                size_t scratch_bytes, int reps, void* stream, int* tile, double* ms) {
-    if (!h || !scratch || !tile || !ms || reps < 1) return HP_EINVAL;
+// Scratch of hp_autotune: operands and result, then split-K scratch for 4
+// partial tiles per output tile and as many counters.
+struct TuneLayout {
+    int64_t lda, ldb, ldc, slots;
+    size_t ops, part, total;
+};
+static int tune_layout(int dtype, int64_t M, int64_t N, int64_t K, TuneLayout* L) {
     if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16_F32) return HP_EINVAL;
     if (M < 1 || N < 1 || K < 1 || M > 65535 || N > 65535 || K > 65535) return HP_EINVAL;
     const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;
     const int64_t vec = 16 / (int64_t)esz;
-    const int64_t lda = (K + vec - 1) / vec * vec, ldb = (N + vec - 1) / vec * vec, ldc = N;
-    const size_t need = esz * (size_t)(M * lda + K * ldb + M * ldc) + 64;
-    if (scratch_bytes < need) return HP_EWORKSPACE;
+    L->lda = (K + vec - 1) / vec * vec;
+    L->ldb = (N + vec - 1) / vec * vec;
+    L->ldc = N;
+    L->slots = 4 * ((M + 127) / 128) * ((N + 127) / 128);
+    L->ops = hp::align_up(esz * (size_t)(M * L->lda + K * L->ldb + M * L->ldc));
+    L->part = hp::align_up(esz * 128 * 128 * (size_t)L->slots);
+    L->total = L->ops + L->part + sizeof(unsigned) * (size_t)L->slots;
+    return HP_OK;
+}
+
+int hp_autotune_scratch_bytes(int dtype, int64_t M, int64_t N, int64_t K, size_t* bytes) {
+    if (!bytes) return HP_EINVAL;
+    TuneLayout L;
+    CHK(tune_layout(dtype, M, N, K, &L));
+    *bytes = L.total;
+    return HP_OK;
+}
+
+int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* scratch,
+                size_t scratch_bytes, int reps, void* stream, int* tile, double* ms) {
+    if (!h || !scratch || !tile || !ms || reps < 1) return HP_EINVAL;
+    TuneLayout L;
+    CHK(tune_layout(dtype, M, N, K, &L));
+    const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;
+    const int64_t lda = L.lda, ldb = L.ldb, ldc = L.ldc, slots = L.slots;
+    const size_t ops = L.ops;
+    if (scratch_bytes < L.total) return HP_EWORKSPACE;
     if (reinterpret_cast<uintptr_t>(scratch) % 16) return HP_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -715,6 +845,16 @@ int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* 
     void* A = base;
     void* B = base + esz * (size_t)(M * lda);
     void* C = base + esz * (size_t)(M * lda + K * ldb);
+    void* split_part = base + ops;
+    unsigned* split_cnt = reinterpret_cast<unsigned*>(base + ops + L.part);
+    HIPCHK(hp::zero_u32(split_cnt, slots, s));
+    auto with_split = [&](auto ep) {
+        using E = std::remove_pointer_t<decltype(ep.split_part)>;
+        ep.split_part = static_cast<E*>(split_part);
+        ep.split_cnt = split_cnt;
+        ep.split_slots = slots;
+        return ep;
+    };
     // operands: identity-like fills are enough for timing (no data dependence)
     if (dtype == HP_DTYPE_F64) {
         HIPCHK(hp::set_identity(static_cast<double*>(A), lda, M, K, s));
@@ -733,11 +873,11 @@ int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* 
             if (dtype == HP_DTYPE_F64)
                 return hp::gemm((hp::GemmTile)t, M, N, K, static_cast<const double*>(A), lda,
                                 static_cast<const double*>(B), ldb,
-                                hp::epilogue_plain(static_cast<double*>(C), ldc), s);
+                                with_split(hp::epilogue_plain(static_cast<double*>(C), ldc)), s);
             if (dtype == HP_DTYPE_F32)
                 return hp::gemm((hp::GemmTile)t, M, N, K, static_cast<const float*>(A), lda,
                                 static_cast<const float*>(B), ldb,
-                                hp::epilogue_plain(static_cast<float*>(C), ldc), s);
+                                with_split(hp::epilogue_plain(static_cast<float*>(C), ldc)), s);
             return hp::gemm_lowp((hp::GemmTile)t, dtype == HP_DTYPE_BF16_F32 ? hp::LOWP_BF16 : hp::LOWP_F16,
                                  M, N, K, static_cast<const float*>(A), lda,
                                  static_cast<const float*>(B), ldb,

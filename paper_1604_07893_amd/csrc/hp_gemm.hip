@@ -6,15 +6,21 @@
 //
 // Block tile BM x BN, K-tile BK, each wave a WM x WN sub-tile of 16x16 MFMA
 // accumulators. A and B are read with 16-byte loads along their contiguous
-// rows into registers one K-tile ahead and written to double-buffered LDS, A
-// transposed to k-major; rows are padded by 16 elements so the four lane groups
-// of a fragment read fall on disjoint LDS banks. One barrier per K-tile.
+// rows into registers one K-tile ahead and written, as 16-byte vectors, to
+// double-buffered LDS in the layout they were read in (A m-major, B k-major),
+// rows padded so that a fragment read spreads over the banks. One barrier per
+// K-tile. Products with too few output tiles to occupy the chip can split K
+// over 2 or 4 blocks per tile; the last block of a tile to finish adds the
+// partial tiles in a fixed order, so the result does not depend on which
+// block finishes last.
 // The epilogue forms up to three outputs
 //     out_o = id_o * I + acc_o * (A B) + g1_o * D1 + g2_o * D2
 // (the linear combinations of one loop of iteration (PM), Section 2) and,
 // optionally, per-block FP64 partial sums of (out_0 - ref)^2 and ref^2 for the
 // stopping test of Section 4.
 #include "hp_internal.h"
+
+#include <type_traits>
 
 namespace hp {
 namespace {
@@ -92,7 +98,10 @@ struct Cfg {
     static constexpr int NT = 64 * WAVES;
     static constexpr int V = Vec16<T>::n;
     static constexpr int PAD = 16;
-    static constexpr int LDA_S = BM + PAD;
+    // A is kept as read, As[m][k], rows padded by one 16-byte vector: the 16
+    // lanes of a fragment read (16 rows, one k) fall on distinct banks and the
+    // staging writes are whole 16-byte vectors.
+    static constexpr int LDA_S = BK + V;
     static constexpr int LDB_S = BN + PAD;
     // A tile: BM rows of BK elements, BK/V threads per row
     static constexpr int A_TPR = BK / V;
@@ -107,21 +116,21 @@ struct Cfg {
     static_assert(BK % 4 == 0 && BK % V == 0, "K tile");
     static_assert(NT % A_TPR == 0 && A_RPP > 0 && BM % A_RPP == 0 && A_PASS >= 1, "A loads");
     static_assert(NT % B_TPR == 0 && B_RPP > 0 && BK % B_RPP == 0 && B_PASS >= 1, "B loads");
-    static constexpr size_t LDS_BYTES = 2 * (size_t)BK * (LDA_S + LDB_S) * sizeof(T);
+    static constexpr size_t LDS_BYTES = 2 * ((size_t)BM * LDA_S + (size_t)BK * LDB_S) * sizeof(T);
 };
 
 // One BM x BN output tile (tm, tn) of C = epilogue(A * B); the block's
 // partial sums (if any) go to pair `part` of ep.partials.
-template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1, int SPLIT = 1>
 __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, int64_t lda,
                                  const T* __restrict__ B, int64_t ldb, const EpilogueT<T>& ep,
-                                 int tm, int tn, int part) {
+                                 int tm, int tn, int part, int split = 0) {
     using C = Cfg<T, BM, BN, BK, WM, WN>;
     using VT = typename Vec16<T>::type;
     using ACC = typename Mfma<T>::acc_t;
     constexpr int V = C::V;
-    __shared__ T As[2][BK][C::LDA_S];
-    __shared__ T Bs[2][BK][C::LDB_S];
+    __shared__ __attribute__((aligned(16))) T As[2][BM][C::LDA_S];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BK][C::LDB_S];
     __shared__ double red[2][C::WAVES];
 
     const int tid = threadIdx.x;
@@ -168,11 +177,11 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
     auto store = [&](int set, int buf, int k0) {
 #pragma unroll
         for (int p = 0; p < C::A_PASS; ++p) {
+            VT v = ra[set][p];
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const bool ok = a_row_ok[p] && (k0 + a_k + e < K);
-                As[buf][a_k + e][a_r + C::A_RPP * p] = ok ? ra[set][p][e] : T(0);
-            }
+            for (int e = 0; e < V; ++e)
+                if (!(a_row_ok[p] && (k0 + a_k + e < K))) v[e] = T(0);
+            *reinterpret_cast<VT*>(&As[buf][a_r + C::A_RPP * p][a_k]) = v;
         }
 #pragma unroll
         for (int p = 0; p < C::B_PASS; ++p) {
@@ -192,24 +201,24 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
         for (int j = 0; j < C::TJ; ++j) acc[i][j] = ACC{};
 
     const int fr = lane & 15, fg = lane >> 4;
-    auto compute = [&](int buf) {
-#pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-            T a[C::TI], b[C::TJ];
-#pragma unroll
-            for (int i = 0; i < C::TI; ++i) a[i] = As[buf][ks + fg][wm + i * 16 + fr];
-#pragma unroll
-            for (int j = 0; j < C::TJ; ++j) b[j] = Bs[buf][ks + fg][wn + j * 16 + fr];
-#pragma unroll
-            for (int i = 0; i < C::TI; ++i)
-#pragma unroll
-                for (int j = 0; j < C::TJ; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
-        }
-    };
-
     const int nk = (K + BK - 1) / BK;
     if constexpr (PF == 1) {
-        // one K-tile ahead: load t+1 into registers while tile t is multiplied
+        // One K-tile ahead: tile kt+1 is loaded into registers while tile kt
+        // is multiplied. Each k-step q gives lane group fg the k = 4q + fg.
+        auto compute = [&](int buf) {
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 4) {
+                T a[C::TI], b[C::TJ];
+#pragma unroll
+                for (int i = 0; i < C::TI; ++i) a[i] = As[buf][wm + i * 16 + fr][ks + fg];
+#pragma unroll
+                for (int j = 0; j < C::TJ; ++j) b[j] = Bs[buf][ks + fg][wn + j * 16 + fr];
+#pragma unroll
+                for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < C::TJ; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
+            }
+        };
         load(0, 0);
         store(0, 0, 0);
         __syncthreads();
@@ -221,24 +230,127 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
             __syncthreads();
         }
     } else {
-        // two K-tiles ahead: tile kt lives in LDS buffer kt % 2 and, until
-        // stored, in register set kt % 2; the body handles an even and an odd
-        // tile so that both register sets are indexed statically
+        // Two K-tiles ahead, with the LDS reads spread over the MFMAs (for
+        // blocks that have a compute unit to themselves and must hide their
+        // own latencies). k-step q gives lane group fg the k = NQ*fg + q, so
+        // the V steps of a fragment group are V consecutive elements of a row
+        // of A (one 16-byte LDS read) and of V consecutive rows of B; a K-tile
+        // is NG groups. The fragments of group g+1 are read while the MFMAs of
+        // group g run; the next tile is stored and the block synchronised
+        // before the last group, so the first group of the next tile is read
+        // while the last MFMAs of this one run. The scheduling barriers keep
+        // the compiler from gathering the LDS reads back together. Until
+        // stored, tile t sits in register set t % 2; the loop body takes an
+        // even and an odd tile so both sets are indexed statically.
+        constexpr int NQ = BK / 4, NG = NQ / V;
+        static_assert(NQ % V == 0 && NG >= 2, "fragment groups");
+        VT fa[2][C::TI];
+        T fb[2][C::TJ][V];
+        auto frag = [&](int buf, int g, int slot) {
+            const int k = NQ * fg + V * g;
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i)
+                fa[slot][i] = *reinterpret_cast<const VT*>(&As[buf][wm + i * 16 + fr][k]);
+#pragma unroll
+            for (int j = 0; j < C::TJ; ++j)
+#pragma unroll
+                for (int e = 0; e < V; ++e) fb[slot][j][e] = Bs[buf][k + e][wn + j * 16 + fr];
+        };
+        auto mma = [&](int slot) {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+#pragma unroll
+                for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < C::TJ; ++j)
+                        acc[i][j] = Mfma<T>::mma(fa[slot][i][e], fb[slot][j][e], acc[i][j]);
+        };
+        // register set `ld` receives tile kt+2, set `st` holds tile kt+1
+        auto tile = [&](int kt, auto ld, auto st) {
+            const int cur = kt & 1;
+            if (kt + 2 < nk) load(decltype(ld)::value, (kt + 2) * BK);
+#pragma unroll
+            for (int g = 0; g + 1 < NG; ++g) {
+                frag(cur, g + 1, (g + 1) & 1);
+                mma(g & 1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (kt + 1 < nk) store(decltype(st)::value, cur ^ 1, (kt + 1) * BK);
+            __syncthreads();
+            if (kt + 1 < nk) frag(cur ^ 1, 0, 0);
+            mma((NG - 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
         load(0, 0);
         store(0, 0, 0);
         if (nk > 1) load(1, BK);
         __syncthreads();
+        frag(0, 0, 0);
         for (int kt = 0; kt < nk; kt += 2) {
-            if (kt + 2 < nk) load(0, (kt + 2) * BK);
-            compute(0);
-            if (kt + 1 < nk) store(1, 1, (kt + 1) * BK);
-            __syncthreads();
-            if (kt + 1 >= nk) break;
-            if (kt + 3 < nk) load(1, (kt + 3) * BK);
-            compute(1);
-            if (kt + 2 < nk) store(0, 0, (kt + 2) * BK);
-            __syncthreads();
+            tile(kt, I0{}, I1{});
+            if (kt + 1 < nk) tile(kt + 1, I1{}, I0{});
         }
+    }
+
+    if constexpr (SPLIT > 1) {
+        // ---- split-K: this block holds the K-range `split` of tile `part` ----
+        // Every block stores its partial tile (in accumulator order, so the
+        // stores are contiguous across the block), publishes it, and counts
+        // itself in; the last to arrive adds the SPLIT partials in an order
+        // that does not depend on which block that is.
+        constexpr int TILE = BM * BN;
+        static_assert(TILE == C::TI * C::TJ * 4 * C::NT, "partial layout");
+        T* slots = ep.split_part + (int64_t)part * SPLIT * TILE;
+        __shared__ unsigned arrived;
+#pragma unroll
+        for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+            for (int j = 0; j < C::TJ; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    slots[split * TILE + ((i * C::TJ + j) * 4 + r) * C::NT + tid] = acc[i][j][r];
+        // Each thread's stores complete (workgroup release), then one thread
+        // makes them all visible device-wide (an agent-scope release writes
+        // back this XCD's L2) before counting the block in; an agent-scope
+        // acquire after the count invalidates stale cached lines for the
+        // whole block. One write-back and one invalidate per block.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            arrived = __hip_atomic_fetch_add(&ep.split_cnt[part], 1u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (arrived != SPLIT - 1) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+        for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+            for (int j = 0; j < C::TJ; ++j) {
+                // one fragment at a time: the empty asm statements keep the
+                // compiler from issuing every fragment's loads at once (which
+                // would hold them all in registers and spill)
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = ((i * C::TJ + j) * 4 + r) * C::NT + tid;
+                    T v;
+                    if constexpr (SPLIT == 2) {
+                        // a + b == b + a exactly: same bits whichever block is last
+                        v = acc[i][j][r] + slots[(split ^ 1) * TILE + e];
+                    } else {
+                        // all four from memory (its own as stored), summed in one order
+                        v = (slots[e] + slots[TILE + e]) + (slots[2 * TILE + e] + slots[3 * TILE + e]);
+                    }
+                    asm volatile("" : "+v"(v));
+                    acc[i][j][r] = v;
+                }
+            }
+        if (tid == 0) __hip_atomic_store(&ep.split_cnt[part], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
     // ---- epilogue ----
@@ -302,6 +414,22 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm(
     int tm, tn;
     tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
     gemm_tile<T, BM, BN, BK, WM, WN, PF>(M, N, K, A, lda, B, ldb, ep, tm, tn, blockIdx.x);
+}
+
+// Split-K launch: SPLIT consecutive (XCD-local) blocks per output tile, block
+// `split` multiplying the K-range [split * kchunk, min(K, (split + 1) * kchunk)).
+template <typename T, int BM, int BN, int BK, int WM, int WN, int SPLIT>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN))
+__attribute__((amdgpu_waves_per_eu(4))) void k_gemm_split(
+    int M, int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+    int64_t ldb, EpilogueT<T> ep, int tiles_m, int tiles_n, int kchunk) {
+    const int p = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int t = p / SPLIT, split = p % SPLIT;
+    int tm, tn;
+    tile_of(t, tiles_m, tiles_n, tm, tn);
+    const int k0 = split * kchunk;
+    gemm_tile<T, BM, BN, BK, WM, WN, 1, SPLIT>(M, N, min(kchunk, K - k0), A + k0, lda,
+                                               B + (int64_t)k0 * ldb, ldb, ep, tm, tn, t, split);
 }
 
 // Persistent grouped launch: the grid walks the tiles of every product in
@@ -562,6 +690,29 @@ hipError_t launch(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, cons
     return hipGetLastError();
 }
 
+// Split-K launch of the 8-wave 128 x 128 tile. Runs unsplit, still on 128 x
+// 128 tiles (so the block count, and the partial sums of the stopping test,
+// match gemm_blocks), when the epilogue brings no scratch, too little, or K
+// too short for every block to get a K-range.
+template <typename T, int BK, int SPLIT>
+hipError_t launch_split(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
+                        int64_t ldb, const EpilogueT<T>& ep, hipStream_t s) {
+    using C = Cfg<T, 128, 128, BK, 64, 32>;
+    const int tm = (int)cdiv(M, 128), tn = (int)cdiv(N, 128);
+    const int64_t tiles = (int64_t)tm * tn;
+    const int64_t kchunk = cdiv(cdiv(K, SPLIT), BK) * BK;
+    const bool ok = ep.split_part && ep.split_cnt && ep.split_slots >= SPLIT * tiles &&
+                    (SPLIT - 1) * kchunk < K;
+    if (!ok) {
+        if (tiles >= 512) return launch<T, 128, 128, BK, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        return launch<T, 128, 128, BK, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
+    }
+    hipLaunchKernelGGL((k_gemm_split<T, 128, 128, BK, 64, 32, SPLIT>), dim3(tiles * SPLIT),
+                       dim3(C::NT), 0, s, (int)M, (int)N, (int)K, A, lda, B, ldb, ep, tm, tn,
+                       (int)kchunk);
+    return hipGetLastError();
+}
+
 // Tile configurations, indexed by GemmTile.
 struct TileShape {
     int bm, bn;
@@ -578,6 +729,8 @@ constexpr TileShape kShapes[] = {
     {128, 128},  // TILE_128x128_W16: 16 waves of 32x32
     {128, 128},  // TILE_128x128_W8_P2: 8 waves, loads two K-tiles ahead
     {128, 128},  // TILE_128x128_W16_P2: 16 waves, loads two K-tiles ahead
+    {128, 128},  // TILE_128x128_W8_S2: K split over 2 blocks
+    {128, 128},  // TILE_128x128_W8_S4: K split over 4 blocks
 };
 static_assert(sizeof(kShapes) / sizeof(kShapes[0]) == TILE_COUNT, "tile table");
 
@@ -597,6 +750,8 @@ hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int
         case TILE_128x128_W16: return launch<T, 128, 128, BKF, 32, 32>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W8_P2: return launch<T, 128, 128, BKF, 64, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W16_P2: return launch<T, 128, 128, BKF, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W8_S2: return launch_split<T, BKF, 2>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W8_S4: return launch_split<T, BKF, 4>(M, N, K, A, lda, B, ldb, ep, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -627,7 +782,9 @@ hipError_t dispatch_lp(GemmTile t, int64_t M, int64_t N, int64_t K, const float*
         case TILE_128x128_W8_K2: return launch_lp<L, 128, 128, 128, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W16:
         case TILE_128x128_W8_P2:
-        case TILE_128x128_W16_P2: return launch_lp<L, 128, 128, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W16_P2:
+        case TILE_128x128_W8_S2:
+        case TILE_128x128_W8_S4: return launch_lp<L, 128, 128, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -669,18 +826,53 @@ int gemm_max_blocks(int64_t M, int64_t N) {
     return b;
 }
 
-GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K) {
-    (void)K;
-    // From the MI355X sweep: with two or more 128x128 tiles per CU (256 CUs)
-    // the 8-wave tile with one K-tile of prefetch is fastest (58 TFLOP/s FP64
-    // at 8192^3); with fewer, a single block per CU must hide its own load
-    // latency and the 16-wave tile loading two K-tiles ahead wins (47.7 vs
-    // 44.9 at 2048^3). Smaller tiles lose more to LDS traffic than they gain
-    // in occupancy; tiny products use 64x64 tiles to spread over the CUs.
+GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow_split) {
+    // From MI355X sweeps of every tile over square and 2:1 products. With
+    // four or more 128x128 tiles per CU (256 CUs) the 8-wave tile loading
+    // one K-tile ahead is fastest (FP64 63 TFLOP/s at 8192^3). FP64 with one
+    // to four tiles per CU: the 16-wave tile loading two K-tiles ahead with
+    // its LDS reads spread over the MFMAs (51.9 vs 49.2 TFLOP/s at 2048^3);
+    // FP32 keeps the 8-wave tile there. With fewer tiles than CUs and a long
+    // K, splitting K four ways fills the chip (FP64 1024x1024x2048: 33.6
+    // TFLOP/s against 14.6 unsplit and 27.7 on 64x64 tiles); short K or the
+    // FP32 1536^2 case favour 64x64 tiles. The 16-bit kernel does not split.
     const int64_t tiles = cdiv(M, 128) * cdiv(N, 128);
-    if (tiles >= 512) return TILE_128x128_W8;
-    if (tiles >= 64) return TILE_128x128_W16_P2;
+    if (gt == GT_LOWP) {
+        if (tiles >= 512) return TILE_128x128_W8;
+        if (tiles >= 64) return TILE_128x128_W16_P2;
+        return TILE_64x64_W4;
+    }
+    if (gt == GT_F64) {
+        if (tiles >= 1024) return TILE_128x128_W8;
+        if (tiles >= 256) return TILE_128x128_W16_P2;
+        if (allow_split && K >= 1024) return TILE_128x128_W8_S4;
+        return TILE_64x64_W4;
+    }
+    if (tiles >= 256) return TILE_128x128_W8;
+    if (allow_split && ((tiles < 128 && K >= 2048) || K >= 4096)) return TILE_128x128_W8_S4;
     return TILE_64x64_W4;
+}
+
+template <int SPLIT>
+static bool split_fits(int64_t M, int64_t N, int64_t K, int bk, int64_t slots) {
+    const int64_t kchunk = cdiv(cdiv(K, SPLIT), bk) * bk;
+    return slots >= SPLIT * cdiv(M, 128) * cdiv(N, 128) && (SPLIT - 1) * kchunk < K;
+}
+
+bool gemm_split_runs(GemmTile t, int64_t M, int64_t N, int64_t K, GemmType gt, int64_t slots) {
+    if (gt == GT_LOWP) return false;
+    const int bk = gt == GT_F64 ? 16 : 32;  // BKF of the element type
+    if (t == TILE_128x128_W8_S2) return split_fits<2>(M, N, K, bk, slots);
+    if (t == TILE_128x128_W8_S4) return split_fits<4>(M, N, K, bk, slots);
+    return false;
+}
+
+int64_t gemm_split_slots(GemmTile t, int64_t M, int64_t N, int64_t K) {
+    (void)K;
+    const int64_t tiles = cdiv(M, 128) * cdiv(N, 128);
+    if (t == TILE_128x128_W8_S2) return 2 * tiles;
+    if (t == TILE_128x128_W8_S4) return 4 * tiles;
+    return 0;
 }
 
 hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,

@@ -37,13 +37,26 @@ struct hp_handle {
 
 namespace hp {
 
+inline GemmType gemm_type(int dtype) {
+    return dtype == HP_DTYPE_F64 ? GT_F64 : dtype == HP_DTYPE_F32 ? GT_F32 : GT_LOWP;
+}
+
 // The tile a product of this dtype (HP_DTYPE_*) and shape runs on: the
 // environment override, else the handle's autotuned entry, else the default.
-inline GemmTile choose_tile(const hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K) {
-    if (h->forced_tile >= 0) return (GemmTile)h->forced_tile;
+// A split tile that cannot run split (too little scratch: `split_slots`
+// partial tiles available) is replaced by the default unsplit choice, so that
+// gemm_blocks of the returned tile is the launch's block count.
+inline GemmTile choose_tile(const hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
+                            int64_t split_slots = 0) {
+    GemmTile t;
     auto it = h->tuned.find({dtype, M, N, K});
-    if (it != h->tuned.end()) return (GemmTile)it->second;
-    return gemm_pick_tile(M, N, K);
+    if (h->forced_tile >= 0) t = (GemmTile)h->forced_tile;
+    else if (it != h->tuned.end()) t = (GemmTile)it->second;
+    else t = gemm_pick_tile(M, N, K, gemm_type(dtype));
+    if ((t == TILE_128x128_W8_S2 || t == TILE_128x128_W8_S4) &&
+        !gemm_split_runs(t, M, N, K, gemm_type(dtype), split_slots))
+        t = gemm_pick_tile(M, N, K, gemm_type(dtype), false);
+    return t;
 }
 
 // Constants of the factored polynomial: the closed forms printed in Section 2
@@ -73,9 +86,15 @@ struct Plan {
     size_t offA32 = 0, offX32[3] = {}, offS32[7] = {};
     bool has_proj = false;      // A^T (n x m) and X^T (m x n) for the projection
     size_t offAt = 0, offXt = 0;
+    // split-K scratch: splitSlots partial tiles (128 x 128 doubles), then
+    // splitSlots arrival counters; none when no product of the solve splits
+    int64_t splitSlots = 0;
+    size_t offSplit = 0, offSplitCnt = 0;
     size_t offSmall = 0, nSmall = 0, offScal = 0, total = 0;
 };
-Plan make_plan(const hp_params* p, int64_t m, int64_t n);
+// `split_area`: reserve the split-K scratch the default tile choice needs for
+// the solve's products (single solves; the grouped launches never split).
+Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area = true);
 int validate(const hp_params* p, int64_t m, int64_t n);
 
 // Which MFMA path a product runs on.
@@ -97,6 +116,8 @@ struct Buffers {
     double* Xt = nullptr;  // m x n, ld b64.ldA
     double* small = nullptr;
     double* scal = nullptr;
+    double* split_part = nullptr;  // Plan::splitSlots tiles of 128 x 128 doubles
+    unsigned* split_cnt = nullptr;
 };
 Buffers carve(const Plan& pl, char* ws);
 

@@ -42,6 +42,14 @@ struct EpilogueT {
     const T* ref;
     int64_t ldref;
     double* partials;
+    // Split-K scratch, read only by the split tiles (TILE_128x128_W8_S2/S4):
+    // split_slots partial tiles of 128 x 128 elements, then one arrival
+    // counter per output tile. The counters are zero before a launch and every
+    // launch leaves them zero. Without scratch (or too little) those tiles run
+    // unsplit.
+    T* split_part;
+    unsigned* split_cnt;
+    int64_t split_slots;
 };
 using Epilogue = EpilogueT<double>;
 
@@ -68,15 +76,27 @@ enum GemmTile : int {
     TILE_128x128_W16 = 8, // 16 waves, 32x32 each
     TILE_128x128_W8_P2 = 9,   // TILE_128x128_W8 loading two K-tiles ahead
     TILE_128x128_W16_P2 = 10, // TILE_128x128_W16 loading two K-tiles ahead
-    TILE_COUNT = 11
+    TILE_128x128_W8_S2 = 11,  // TILE_128x128_W8 with K split over 2 blocks per tile
+    TILE_128x128_W8_S4 = 12,  // TILE_128x128_W8 with K split over 4 blocks per tile
+    TILE_COUNT = 13
 };
 
 // Blocks (and partial-sum pairs) a launch with this tile uses for M x N.
 int gemm_blocks(GemmTile t, int64_t M, int64_t N);
 // The largest of gemm_blocks over every tile (sizes the partials buffer).
 int gemm_max_blocks(int64_t M, int64_t N);
-// Tile choice for an M x N x K product.
-GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K);
+// Tile choice for an M x N x K product of element type `gt`.
+// With allow_split false the choice is among the unsplit tiles.
+enum GemmType : int { GT_F64 = 0, GT_F32 = 1, GT_LOWP = 2 };
+GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow_split = true);
+// Whether split tile t runs split for this product given `slots` partial
+// tiles of scratch (it runs unsplit otherwise).
+bool gemm_split_runs(GemmTile t, int64_t M, int64_t N, int64_t K, GemmType gt, int64_t slots);
+// Split-K scratch (partial tiles of 128 x 128 elements; as many arrival
+// counters) that tile t needs for an M x N x K product: 0 for unsplit tiles.
+int64_t gemm_split_slots(GemmTile t, int64_t M, int64_t N, int64_t K);
+// Zero n unsigned counters (a fill kernel: safe inside stream capture).
+hipError_t zero_u32(unsigned* p, int64_t n, hipStream_t s);
 
 // C = epilogue(A[M x K] * B[K x N]); all row-major, lda/ldb multiples of 16
 // bytes, pointers 16-byte aligned.

@@ -161,6 +161,11 @@ __global__ __launch_bounds__(kThreads) void k_identity(double* __restrict__ Y, i
         Y[(int64_t)r * ldy + c] = (r == c) ? 1.0 : 0.0;
 }
 
+__global__ __launch_bounds__(kThreads) void k_zero_u32(unsigned* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        p[i] = 0u;
+}
+
 __global__ __launch_bounds__(kThreads) void k_reduce_pairs(const double* __restrict__ part, int nb,
                                                            double* __restrict__ scal) {
     double s0 = 0.0, s1 = 0.0;
@@ -348,6 +353,13 @@ hipError_t scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y, 
 hipError_t set_identity(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s) {
     const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N, kThreads), 16);
     hipLaunchKernelGGL(k_identity, dim3(gx, (unsigned)M), dim3(kThreads), 0, s, Y, ldy, (int)M, (int)N);
+    return hipGetLastError();
+}
+
+hipError_t zero_u32(unsigned* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>(cdiv(n, kThreads), 1024);
+    hipLaunchKernelGGL(k_zero_u32, dim3(g), dim3(kThreads), 0, s, p, n);
     return hipGetLastError();
 }
 

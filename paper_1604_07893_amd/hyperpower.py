@@ -77,6 +77,11 @@ SIGNATURES = {
                          POINTER(HpResult)]),
     "hp_gemm": (c_int, [c_void_p, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
                         c_void_p, c_int64, c_double, c_void_p, c_int64, c_void_p]),
+    "hp_autotune_scratch_bytes": (c_int, [c_int, c_int64, c_int64, c_int64, POINTER(c_size_t)]),
+    "hp_gemm_workspace_bytes": (c_int, [c_int, c_int64, c_int64, c_int64, POINTER(c_size_t)]),
+    "hp_gemm_ws": (c_int, [c_void_p, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
+                           c_void_p, c_int64, c_double, c_void_p, c_int64, c_void_p, c_size_t,
+                           c_void_p]),
     "hp_autotune": (c_int, [c_void_p, c_int, c_int64, c_int64, c_int64, c_void_p, c_size_t, c_int,
                             c_void_p, POINTER(c_int), POINTER(c_double)]),
     "hp_tune_export": (c_int, [c_void_p, POINTER(c_int64), c_int, POINTER(c_int)]),
@@ -258,12 +263,24 @@ def drazin(A: torch.Tensor, l: int, **kw) -> tuple[torch.Tensor, dict]:
     return solve(A, kind="drazin", l=l, **kw)
 
 
+def gemm_workspace_bytes(M: int, N: int, K: int, dtype: str = "f64") -> int:
+    """Split-K workspace the default tile choice needs for an M x N x K
+    product (0 when it would not split)."""
+    nb = c_size_t()
+    rc = load_library().hp_gemm_workspace_bytes(GEMM_DTYPES[dtype], M, N, K, ctypes.byref(nb))
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_gemm_workspace_bytes")
+    return nb.value
+
+
 def gemm(A: torch.Tensor, B: torch.Tensor, *, alpha: float = 1.0, beta_identity: float = 0.0,
          out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
-         operands: str | None = None) -> torch.Tensor:
+         operands: str | None = None, workspace: torch.Tensor | bool | None = None) -> torch.Tensor:
     """C = alpha A B + beta_identity I on the library's MFMA GEMM kernel.
     operands: None (the tensors' type), or "bf16" / "f16" for float32 tensors
-    whose products run on 16-bit MFMA with FP32 accumulation."""
+    whose products run on 16-bit MFMA with FP32 accumulation.
+    workspace: None (hp_gemm, never split), True (allocate what the default
+    tile choice needs and call hp_gemm_ws) or a device uint8 tensor."""
     if A.dtype != B.dtype or A.dtype not in DTYPE:
         raise ValueError("unsupported dtype")
     code = DTYPE[A.dtype]
@@ -282,11 +299,25 @@ def gemm(A: torch.Tensor, B: torch.Tensor, *, alpha: float = 1.0, beta_identity:
         out = torch.empty((M, N), dtype=A.dtype, device=A.device)
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
     dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
-    rc = load_library().hp_gemm(handle(dev).ptr, code, M, N, K, alpha, A.data_ptr(),
-                                A.stride(0), B.data_ptr(), B.stride(0), beta_identity,
-                                out.data_ptr(), out.stride(0), s.cuda_stream)
+    if workspace is None or workspace is False:
+        rc = load_library().hp_gemm(handle(dev).ptr, code, M, N, K, alpha, A.data_ptr(),
+                                    A.stride(0), B.data_ptr(), B.stride(0), beta_identity,
+                                    out.data_ptr(), out.stride(0), s.cuda_stream)
+        if rc != HP_OK:
+            raise HyperpowerError(rc, "hp_gemm")
+        return out
+    if workspace is True:
+        nb = c_size_t()
+        rc = load_library().hp_gemm_workspace_bytes(code, M, N, K, ctypes.byref(nb))
+        if rc != HP_OK:
+            raise HyperpowerError(rc, "hp_gemm_workspace_bytes")
+        workspace = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=A.device)
+    rc = load_library().hp_gemm_ws(handle(dev).ptr, code, M, N, K, alpha, A.data_ptr(),
+                                   A.stride(0), B.data_ptr(), B.stride(0), beta_identity,
+                                   out.data_ptr(), out.stride(0), workspace.data_ptr(),
+                                   workspace.numel() * workspace.element_size(), s.cuda_stream)
     if rc != HP_OK:
-        raise HyperpowerError(rc, "hp_gemm")
+        raise HyperpowerError(rc, "hp_gemm_ws")
     return out
 
 
@@ -401,12 +432,13 @@ def autotune(shapes, dtype: str = "f64", reps: int = 3, device: int | None = Non
     dev = torch.cuda.current_device() if device is None else device
     h = handle(dev)
     code = GEMM_DTYPES[dtype]
-    esz = 8 if code == 0 else 4
     out = []
     for (M, N, K) in shapes:
-        v = 16 // esz
-        lda, ldb = (K + v - 1) // v * v, (N + v - 1) // v * v
-        nbytes = esz * (M * lda + K * ldb + M * N) + 64
+        nb = c_size_t()
+        rc = load_library().hp_autotune_scratch_bytes(code, M, N, K, ctypes.byref(nb))
+        if rc != HP_OK:
+            raise HyperpowerError(rc, "hp_autotune_scratch_bytes")
+        nbytes = nb.value
         scratch = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{dev}")
         t, ms = c_int(), c_double()
         rc = load_library().hp_autotune(h.ptr, code, M, N, K, scratch.data_ptr(), nbytes, reps,

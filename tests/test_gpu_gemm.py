@@ -135,3 +135,89 @@ def test_autotune_picks_a_tile_and_keeps_results_correct():
     ref = A @ B
     bound = (np.abs(A) @ np.abs(B)) * 204 * U64
     assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
+
+
+# Products with fewer 128 x 128 output tiles than compute units and a long K
+# split K over 4 blocks per tile when a workspace is given (FP64: K >= 1024;
+# FP32: K >= 2048 below 128 tiles); ragged shapes leave a short last K-range.
+SPLIT_SHAPES = {
+    "f64": [(1024, 1024, 2048), (1500, 1400, 1500), (1100, 1300, 2100), (600, 700, 1030)],
+    "f32": [(1024, 1024, 2048), (1100, 1300, 2100), (700, 600, 4100)],
+}
+
+
+def _dev_pad(a, dtype):
+    vec = 2 if dtype == torch.float64 else 4
+    r, c = a.shape
+    buf = torch.zeros((r, (c + vec - 1) // vec * vec), dtype=dtype, device="cuda:0")
+    buf[:, :c] = torch.from_numpy(a).to(dtype).cuda()
+    return buf[:, :c]
+
+
+@pytest.mark.parametrize("dt,M,N,K", [(d, *s) for d in SPLIT_SHAPES for s in SPLIT_SHAPES[d]])
+def test_split_k_gemm_matches_numpy_and_is_reproducible(dt, M, N, K):
+    hpw = need_gpu()
+    say(f"split-K gemm {dt} M={M} N={N} K={K}")
+    assert hpw.gemm_workspace_bytes(M, N, K, dt) > 0
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    u = U64 if dt == "f64" else 2.0**-24
+    rng = np.random.default_rng(M + 13 * N + 17 * K)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    if dt == "f32":
+        A, B = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+    Ad, Bd = _dev_pad(A, tdt), _dev_pad(B, tdt)
+    C1 = hpw.gemm(Ad, Bd, workspace=True)
+    C2 = hpw.gemm(Ad, Bd, workspace=True)
+    C3 = hpw.gemm(Ad, Bd, workspace=True)
+    torch.cuda.synchronize()
+    # which block of a tile finishes last varies between launches; the sum
+    # order does not
+    assert torch.equal(C1, C2) and torch.equal(C1, C3)
+    ref = A @ B
+    bound = (np.abs(A) @ np.abs(B)) * (2 * K + 8) * u
+    err = np.abs(C1.cpu().double().numpy() - ref)
+    assert np.all(err <= bound + 1e-300), float((err / (bound + 1e-300)).max())
+
+
+def test_split_k_epilogue_and_undersized_workspace():
+    hpw = need_gpu()
+    M, N, K = 1536, 1536, 2048          # 144 tiles: splits four ways
+    rng = np.random.default_rng(21)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    Ad, Bd = _dev_pad(A, torch.float64), _dev_pad(B, torch.float64)
+    C = hpw.gemm(Ad, Bd, alpha=-1.0, beta_identity=1.0, workspace=True)
+    ref = np.eye(M, N) - A @ B
+    bound = (np.abs(A) @ np.abs(B)) * (2 * K + 8) * U64 + 2 * U64
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= bound)
+    # too small a workspace: runs unsplit, exactly as hp_gemm does
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda:0")
+    C_small = hpw.gemm(Ad, Bd, alpha=-1.0, beta_identity=1.0, workspace=small)
+    C_plain = hpw.gemm(Ad, Bd, alpha=-1.0, beta_identity=1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(C_small, C_plain)
+    assert hpw.gemm_workspace_bytes(8192, 8192, 8192) == 0    # enough tiles: never splits
+
+
+def test_two_way_split_from_tuning_table(tmp_path):
+    """The two-way split tile, chosen through the handle's tuning table, on a
+    ragged FP64 product."""
+    import json
+    hpw = need_gpu()
+    M, N, K = 1280, 1152, 1800
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"rows": [[0, M, N, K, 11]]}))
+    hpw.load_tuning(str(path))
+    rng = np.random.default_rng(33)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    Ad, Bd = _dev_pad(A, torch.float64), _dev_pad(B, torch.float64)
+    ws = torch.empty(2 * 10 * 9 * 128 * 128 * 8 + 4096, dtype=torch.uint8, device="cuda:0")
+    C1 = hpw.gemm(Ad, Bd, workspace=ws)
+    C2 = hpw.gemm(Ad, Bd, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    ref = A @ B
+    bound = (np.abs(A) @ np.abs(B)) * (2 * K + 8) * U64
+    assert np.all(np.abs(C1.cpu().numpy() - ref) <= bound)
