@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define HP_ABI_VERSION 1
+#define HP_ABI_VERSION 2
 
 /* ---- status codes ------------------------------------------------------ */
 #define HP_OK 0
@@ -82,10 +82,29 @@ extern "C" {
 #define HP_SIDE_RIGHT 1  /* R = I - A X (m x m), X_{k+1} = X W: the paper's form */
 #define HP_SIDE_LEFT 2   /* R = I - X A (n x n), X_{k+1} = W X */
 
+/* which iteration of the hyperpower family runs each loop. PM is the paper's
+   method; the others are the schemes it is compared with (Section 1.3 and
+   Section 2), evaluated on the GPU with the same kernels so that the
+   comparison of Section 8 can be repeated. Each loop's update is X W (right
+   form) or W X (left form) with W a polynomial in R. */
+#define HP_METHOD_PM 0 /* (PM), Section 2: order 18, 7 products */
+#define HP_METHOD_SM 1 /* Newton-Schulz-Hotelling (schulz): X(2I - AX), order 2,
+                          2 products */
+#define HP_METHOD_CM 2 /* Chebyshev-Sen-Prabhu (chebyshev): X(3I - AX(3I - AX)),
+                          order 3, 3 products */
+#define HP_METHOD_FM 3 /* the seventh-order factorisation (SoleymaniN):
+                          psi = I - AX, zeta = I + psi + psi^2,
+                          upsilon = psi + psi^4, X(I + upsilon zeta); 5 products */
+#define HP_METHOD_HM 4 /* (hyper18-2): X(I+R)(R^2-R+I)(R^2+R+I)(R^6-R^3+I)
+                          (R^6+R^3+I), order 18, 9 products; the five factors
+                          are multiplied together before the update */
+
 /* stopping rule (Section 4, Section 8) */
 #define HP_STOP_REL_FRO 0   /* ||X_{k+1}-X_k||_F / ||X_k||_F < tol */
-#define HP_STOP_PAPER_4_1 1 /* ||X_{k+1}-X_k||_F / (18^k alpha) < tol, rule
-                               (stopreliable) with the Frobenius norm */
+#define HP_STOP_PAPER_4_1 1 /* ||X_{k+1}-X_k||_F / (p^k alpha) < tol, rule
+                               (stopreliable) with the Frobenius norm; p is the
+                               method's order (18 for PM and HM) and k counts
+                               loops from 0 */
 #define HP_STOP_ABS_INF 2   /* ||X_{k+1}-X_k||_inf <= tol (Example 8.1) */
 
 /* arithmetic of the loops */
@@ -147,7 +166,10 @@ typedef struct hp_params {
     int32_t precision;     /* HP_PREC_* */
     int32_t flags;         /* HP_FLAG_* */
     int32_t low_dtype;     /* HP_LOWP_*, HP_PREC_MIXED only */
-    int32_t reserved[6];   /* must be zero */
+    int32_t method;        /* HP_METHOD_* (default PM). Methods other than PM
+                              run in HP_PREC_FP64 or HP_PREC_FP32 in hp_solve
+                              only (HP_EUNSUPPORTED otherwise) */
+    int32_t reserved[5];   /* must be zero */
 } hp_params;
 
 #define HP_HIST 128

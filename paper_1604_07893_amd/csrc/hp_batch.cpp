@@ -249,8 +249,8 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
         LoopState& st = P.st;
         int tiles = 0;
         if (st.stage == 2) {
-            GemmCall<double> calls[kSlots];
-            const int nc = describe_pm_loop<double>(P.pl, P.bf.b64, P.bf.b64.X[st.ik],
+            GemmCall<double> calls[kMaxLoopGemms];
+            const int nc = describe_loop<double>(HP_METHOD_PM, P.pl, P.bf.b64, P.bf.b64.X[st.ik],
                                                     P.bf.b64.X[st.in_], P.bf.b64.X[2],
                                                     st.stabilising, P.bf.small, calls);
             for (int j = 0; j < nc; ++j) {
@@ -262,8 +262,8 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
             P.res.gemms += nc;
         } else {
             if (st.engine() != ENG_F32) return HP_EUNSUPPORTED;
-            GemmCall<float> calls[kSlots];
-            const int nc = describe_pm_loop<float>(P.pl, P.bf.b32, P.bf.b32.X[st.ik],
+            GemmCall<float> calls[kMaxLoopGemms];
+            const int nc = describe_loop<float>(HP_METHOD_PM, P.pl, P.bf.b32, P.bf.b32.X[st.ik],
                                                    P.bf.b32.X[st.in_], P.bf.b32.X[2],
                                                    st.stabilising, P.bf.small, calls);
             for (int j = 0; j < nc; ++j) {
@@ -314,6 +314,7 @@ int validate_group_params(const hp_params* p) {
         p->precision != HP_PREC_FP32_FP64)
         return HP_EUNSUPPORTED;
     if (p->stop_rule == HP_STOP_ABS_INF || (p->flags & HP_FLAG_INF_NORM)) return HP_EUNSUPPORTED;
+    if (p->method != HP_METHOD_PM) return HP_EUNSUPPORTED;
     return HP_OK;
 }
 

@@ -152,9 +152,14 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
     if (p->stop_rule < HP_STOP_REL_FRO || p->stop_rule > HP_STOP_ABS_INF) return HP_EINVAL;
     if (p->precision < HP_PREC_FP64 || p->precision > HP_PREC_FP32_FP64) return HP_EINVAL;
     if (p->low_dtype != HP_LOWP_BF16 && p->low_dtype != HP_LOWP_F16) return HP_EINVAL;
+    if (p->method < HP_METHOD_PM || p->method > HP_METHOD_HM) return HP_EINVAL;
+    // the comparison methods run without precision stages (the stage exits
+    // are tuned to the contraction of an order-18 loop)
+    if (p->method != HP_METHOD_PM && p->precision != HP_PREC_FP64 && p->precision != HP_PREC_FP32)
+        return HP_EUNSUPPORTED;
     if (p->max_iter < 1 || p->max_iter > 100000) return HP_EINVAL;
     if (!(p->tol >= 0.0) || !(p->tau_switch > 0.0) || !(p->diverge_limit > 0.0)) return HP_EINVAL;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
         if (p->reserved[i] != 0) return HP_EINVAL;
     return HP_OK;
 }
@@ -298,7 +303,7 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         sval = dinf;
         passed = dinf <= p->tol;
     } else {
-        sval = std::sqrt(diff2) / (std::pow(18.0, (double)(k - 1)) * alpha);
+        sval = std::sqrt(diff2) / (std::pow((double)method_order(p->method), (double)(k - 1)) * alpha);
         passed = sval < p->tol;
     }
     res->stop_last = sval;
@@ -435,14 +440,16 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
     while (st.k < p->max_iter) {
         S.stage = st.stage;
         if (st.stage == 2) {
-            GemmCall<double> calls[9];
-            const int nc = describe_pm_loop<double>(pl, bf.b64, bf.b64.X[st.ik], bf.b64.X[st.in_],
-                                                    bf.b64.X[2], st.stabilising, bf.small, calls);
+            GemmCall<double> calls[kMaxLoopGemms];
+            const int nc = describe_loop<double>(p->method, pl, bf.b64, bf.b64.X[st.ik],
+                                                 bf.b64.X[st.in_], bf.b64.X[2], st.stabilising,
+                                                 bf.small, calls);
             for (int i = 0; i < nc; ++i) CHK(S.gemm<double>(ENG_F64, calls[i]));
         } else {
-            GemmCall<float> calls[9];
-            const int nc = describe_pm_loop<float>(pl, bf.b32, bf.b32.X[st.ik], bf.b32.X[st.in_],
-                                                   bf.b32.X[2], st.stabilising, bf.small, calls);
+            GemmCall<float> calls[kMaxLoopGemms];
+            const int nc = describe_loop<float>(p->method, pl, bf.b32, bf.b32.X[st.ik],
+                                                bf.b32.X[st.in_], bf.b32.X[2], st.stabilising,
+                                                bf.small, calls);
             for (int i = 0; i < nc; ++i) CHK(S.gemm<float>(st.engine(), calls[i]));
         }
         HIPCHK(reduce_pairs(bf.small, S.last_blocks, bf.scal, s));

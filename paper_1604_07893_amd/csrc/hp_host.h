@@ -132,64 +132,26 @@ struct GemmCall {
     EpilogueT<T> ep;
 };
 
-// The products of one loop of (PM), Section 2, in the association printed
-// there: R = I - A X (right form) or I - X A (left form); R^2; R^4 with
-// F1 = I + c1 R^2 + R^4 and F2 = I + c2 R^2 + R^4 in its epilogue; F1 F2 with
-// T = M + c3 R^2 and S = M + d1 R^2 + d2 R^4; T S + mu R^2 + psi R^4 = V;
-// V + R V = W; the update X W (right) or W X (left). With `stab`, the update
-// writes X_{k+1/2} and the stabilising product X_{k+1/2} A X_{k+1/2} of
-// (PM-modified), Section 7, follows, associated so that the middle product is
-// the smaller square. The last product writes the partial sums of the
-// stopping test against X_k into `partials`. Returns the number of calls.
+// Most products a loop can take (HM: 9, plus 2 for the stabilising product).
+constexpr int kMaxLoopGemms = 11;
+
+// Order p of each HP_METHOD_* (the p of rule (stopreliable)).
+inline int method_order(int method) {
+    static const int kOrder[] = {18, 2, 3, 7, 18};
+    return kOrder[method];
+}
+
+// The update product X_{k+1} = X W (right form) or W X (left form), writing
+// the partial sums of the stopping test against X_k into `partials`; with
+// `stab`, it writes X_{k+1/2} instead and the stabilising product
+// X_{k+1/2} A X_{k+1/2} of (PM-modified), Section 7, follows, associated so
+// that the middle product is the smaller square (into `mid`, an s x s buffer
+// that is dead by then). Appends to out[c..]; returns the new count.
 template <typename T>
-int describe_pm_loop(const Plan& pl, const Set<T>& b, T* Xk, T* Xn, T* Xh, bool stab,
-                     double* partials, GemmCall<T> out[9]) {
-    const PMConst K = pm_const();
-    const int64_t m = pl.m, n = pl.n, sd = pl.s;
+int describe_update(const Plan& pl, const Set<T>& b, const T* W, T* Xk, T* Xn, T* Xh, bool stab,
+                    double* partials, T* mid, GemmCall<T>* out, int c) {
+    const int64_t m = pl.m, n = pl.n;
     const int64_t ldS = b.ldS, ldX = b.ldX, ldA = b.ldA;
-    T* R = b.S[0];
-    T* R2 = b.S[1];
-    T* R4 = b.S[2];
-    T* F1 = b.S[3];
-    T* F2 = b.S[4];
-    T* Tm = b.S[5];
-    T* Sm = b.S[6];
-    T* V = F1;  // F1, F2 are dead once T and S exist
-    T* W = F2;
-    int c = 0;
-    {
-        EpilogueT<T> e = epilogue_plain(R, ldS, -1.0, 1.0);
-        if (pl.left) out[c++] = {n, n, m, Xk, ldX, b.A, ldA, e};
-        else out[c++] = {m, m, n, b.A, ldA, Xk, ldX, e};
-    }
-    out[c++] = {sd, sd, sd, R, ldS, R, ldS, epilogue_plain(R2, ldS)};
-    {
-        EpilogueT<T> e{};
-        e.out[0] = R4; e.ldo[0] = ldS; e.acc_c[0] = 1.0;
-        e.out[1] = F1; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.id[1] = 1.0; e.g1[1] = K.c1;
-        e.out[2] = F2; e.ldo[2] = ldS; e.acc_c[2] = 1.0; e.id[2] = 1.0; e.g1[2] = K.c2;
-        e.D1 = R2; e.ld1 = ldS;
-        out[c++] = {sd, sd, sd, R2, ldS, R2, ldS, e};
-    }
-    {
-        EpilogueT<T> e{};
-        e.out[0] = Tm; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.c3;
-        e.out[1] = Sm; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.g1[1] = K.d1; e.g2[1] = K.d2;
-        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
-        out[c++] = {sd, sd, sd, F1, ldS, F2, ldS, e};
-    }
-    {
-        EpilogueT<T> e{};
-        e.out[0] = V; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.mu; e.g2[0] = K.psi;
-        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
-        out[c++] = {sd, sd, sd, Tm, ldS, Sm, ldS, e};
-    }
-    {
-        EpilogueT<T> e{};
-        e.out[0] = W; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = 1.0;
-        e.D1 = V; e.ld1 = ldS;
-        out[c++] = {sd, sd, sd, R, ldS, V, ldS, e};
-    }
     {
         EpilogueT<T> e = epilogue_plain(stab ? Xh : Xn, ldX);
         if (!stab) {
@@ -201,17 +163,149 @@ int describe_pm_loop(const Plan& pl, const Set<T>& b, T* Xk, T* Xn, T* Xh, bool 
     if (stab) {
         EpilogueT<T> e = epilogue_plain(Xn, ldX);
         e.ref = Xk; e.ldref = ldX; e.partials = partials;
-        // the middle product goes to R^2's buffer (dead by now) so that R
-        // stays available after the loop
         if (m >= n) {
-            out[c++] = {n, n, m, Xh, ldX, b.A, ldA, epilogue_plain(R2, ldS)};
-            out[c++] = {n, m, n, R2, ldS, Xh, ldX, e};
+            out[c++] = {n, n, m, Xh, ldX, b.A, ldA, epilogue_plain(mid, ldS)};
+            out[c++] = {n, m, n, mid, ldS, Xh, ldX, e};
         } else {
-            out[c++] = {m, m, n, b.A, ldA, Xh, ldX, epilogue_plain(R2, ldS)};
-            out[c++] = {n, m, m, Xh, ldX, R2, ldS, e};
+            out[c++] = {m, m, n, b.A, ldA, Xh, ldX, epilogue_plain(mid, ldS)};
+            out[c++] = {n, m, m, Xh, ldX, mid, ldS, e};
         }
     }
     return c;
+}
+
+// out[c] = the residual product: out0 = id0 I + acc0 P (and more outputs as
+// given in `e`), P = A X (right form, m x m) or X A (left form, n x n).
+template <typename T>
+int describe_residual(const Plan& pl, const Set<T>& b, const T* Xk, EpilogueT<T> e,
+                      GemmCall<T>* out, int c) {
+    const int64_t m = pl.m, n = pl.n;
+    if (pl.left) out[c++] = {n, n, m, Xk, b.ldX, b.A, b.ldA, e};
+    else out[c++] = {m, m, n, b.A, b.ldA, Xk, b.ldX, e};
+    return c;
+}
+
+// The products of one loop of HP_METHOD_* `method`. Every method keeps
+// R = I - AX (or I - XA) in b.S[0] through the loop (a lower precision stage's
+// last R decides the projection).
+//
+// PM, Section 2, in the association printed there: R; R^2; R^4 with
+// F1 = I + c1 R^2 + R^4 and F2 = I + c2 R^2 + R^4 in its epilogue; F1 F2 with
+// T = M + c3 R^2 and S = M + d1 R^2 + d2 R^4; T S + mu R^2 + psi R^4 = V;
+// V + R V = W; the update. 7 products.
+// SM (schulz): R and W = I + R = 2I - AX from one product; the update. 2.
+// CM (chebyshev): P = AX with R = I - P and Q = 3I - P; W = 3I - P Q; the
+// update. 3.
+// FM (SoleymaniN): psi; psi^2 with zeta = I + psi + psi^2; upsilon =
+// psi + psi^4 from psi^2 psi^2; W = I + upsilon zeta; the update. 5.
+// HM (hyper18-2): R; R^2 with F2 = R^2 - R + I and F3 = R^2 + R + I; R^3;
+// R^6 only as F4 = R^6 - R^3 + I and F5 = R^6 + R^3 + I; G = F2 + R F2
+// (= (I + R) F2); G F3; G F4; G F5; the update. 9.
+// Returns the number of calls (at most kMaxLoopGemms).
+template <typename T>
+int describe_loop(int method, const Plan& pl, const Set<T>& b, T* Xk, T* Xn, T* Xh, bool stab,
+                  double* partials, GemmCall<T> out[kMaxLoopGemms]) {
+    const int64_t sd = pl.s, ldS = b.ldS;
+    T* const* S = b.S;
+    int c = 0;
+    auto sq = [&](const T* A, const T* B, EpilogueT<T> e) {
+        out[c++] = {sd, sd, sd, A, ldS, B, ldS, e};
+    };
+    auto ep = [&](T* o0, double acc0, double id0) { return epilogue_plain(o0, ldS, acc0, id0); };
+    switch (method) {
+        case HP_METHOD_SM: {
+            EpilogueT<T> e = ep(S[0], -1.0, 1.0);
+            e.out[1] = S[1]; e.ldo[1] = ldS; e.acc_c[1] = -1.0; e.id[1] = 2.0;
+            c = describe_residual(pl, b, Xk, e, out, c);
+            return describe_update(pl, b, S[1], Xk, Xn, Xh, stab, partials, S[2], out, c);
+        }
+        case HP_METHOD_CM: {
+            EpilogueT<T> e = ep(S[0], -1.0, 1.0);
+            e.out[1] = S[1]; e.ldo[1] = ldS; e.acc_c[1] = -1.0; e.id[1] = 3.0;
+            e.out[2] = S[2]; e.ldo[2] = ldS; e.acc_c[2] = 1.0;
+            c = describe_residual(pl, b, Xk, e, out, c);
+            sq(S[2], S[1], ep(S[3], -1.0, 3.0));
+            return describe_update(pl, b, S[3], Xk, Xn, Xh, stab, partials, S[1], out, c);
+        }
+        case HP_METHOD_FM: {
+            c = describe_residual(pl, b, Xk, ep(S[0], -1.0, 1.0), out, c);
+            EpilogueT<T> e2 = ep(S[1], 1.0, 0.0);
+            e2.out[1] = S[2]; e2.ldo[1] = ldS; e2.acc_c[1] = 1.0; e2.id[1] = 1.0; e2.g1[1] = 1.0;
+            e2.D1 = S[0]; e2.ld1 = ldS;
+            sq(S[0], S[0], e2);
+            EpilogueT<T> e3 = ep(S[3], 1.0, 0.0);
+            e3.g1[0] = 1.0; e3.D1 = S[0]; e3.ld1 = ldS;
+            sq(S[1], S[1], e3);
+            sq(S[3], S[2], ep(S[4], 1.0, 1.0));
+            return describe_update(pl, b, S[4], Xk, Xn, Xh, stab, partials, S[1], out, c);
+        }
+        case HP_METHOD_HM: {
+            c = describe_residual(pl, b, Xk, ep(S[0], -1.0, 1.0), out, c);
+            EpilogueT<T> e2 = ep(S[1], 1.0, 0.0);
+            e2.out[1] = S[2]; e2.ldo[1] = ldS; e2.acc_c[1] = 1.0; e2.id[1] = 1.0; e2.g1[1] = -1.0;
+            e2.out[2] = S[3]; e2.ldo[2] = ldS; e2.acc_c[2] = 1.0; e2.id[2] = 1.0; e2.g1[2] = 1.0;
+            e2.D1 = S[0]; e2.ld1 = ldS;
+            sq(S[0], S[0], e2);                       // R^2, F2, F3
+            sq(S[1], S[0], ep(S[4], 1.0, 0.0));       // R^3
+            EpilogueT<T> e4{};
+            e4.out[0] = S[5]; e4.ldo[0] = ldS; e4.acc_c[0] = 1.0; e4.id[0] = 1.0; e4.g1[0] = -1.0;
+            e4.out[1] = S[6]; e4.ldo[1] = ldS; e4.acc_c[1] = 1.0; e4.id[1] = 1.0; e4.g1[1] = 1.0;
+            e4.D1 = S[4]; e4.ld1 = ldS;
+            sq(S[4], S[4], e4);                       // F4, F5
+            EpilogueT<T> e5 = ep(S[1], 1.0, 0.0);
+            e5.g1[0] = 1.0; e5.D1 = S[2]; e5.ld1 = ldS;
+            sq(S[0], S[2], e5);                       // G = (I + R) F2
+            sq(S[1], S[3], ep(S[4], 1.0, 0.0));       // G F3
+            sq(S[4], S[5], ep(S[1], 1.0, 0.0));       // G F3 F4
+            sq(S[1], S[6], ep(S[4], 1.0, 0.0));       // G F3 F4 F5
+            return describe_update(pl, b, S[4], Xk, Xn, Xh, stab, partials, S[1], out, c);
+        }
+        default:
+            break;
+    }
+    // PM
+    const PMConst K = pm_const();
+    T* R = S[0];
+    T* R2 = S[1];
+    T* R4 = S[2];
+    T* F1 = S[3];
+    T* F2 = S[4];
+    T* Tm = S[5];
+    T* Sm = S[6];
+    T* V = F1;  // F1, F2 are dead once T and S exist
+    T* W = F2;
+    c = describe_residual(pl, b, Xk, ep(R, -1.0, 1.0), out, c);
+    sq(R, R, ep(R2, 1.0, 0.0));
+    {
+        EpilogueT<T> e{};
+        e.out[0] = R4; e.ldo[0] = ldS; e.acc_c[0] = 1.0;
+        e.out[1] = F1; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.id[1] = 1.0; e.g1[1] = K.c1;
+        e.out[2] = F2; e.ldo[2] = ldS; e.acc_c[2] = 1.0; e.id[2] = 1.0; e.g1[2] = K.c2;
+        e.D1 = R2; e.ld1 = ldS;
+        sq(R2, R2, e);
+    }
+    {
+        EpilogueT<T> e{};
+        e.out[0] = Tm; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.c3;
+        e.out[1] = Sm; e.ldo[1] = ldS; e.acc_c[1] = 1.0; e.g1[1] = K.d1; e.g2[1] = K.d2;
+        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
+        sq(F1, F2, e);
+    }
+    {
+        EpilogueT<T> e{};
+        e.out[0] = V; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = K.mu; e.g2[0] = K.psi;
+        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
+        sq(Tm, Sm, e);
+    }
+    {
+        EpilogueT<T> e{};
+        e.out[0] = W; e.ldo[0] = ldS; e.acc_c[0] = 1.0; e.g1[0] = 1.0;
+        e.D1 = V; e.ld1 = ldS;
+        sq(R, V, e);
+    }
+    // the middle product goes to R^2's buffer (dead by now) so that R stays
+    // available after the loop
+    return describe_update(pl, b, W, Xk, Xn, Xh, stab, partials, R2, out, c);
 }
 
 // Forms X0 = alpha G (Section 4) in the FP64 iterate b64.X[0] on stream s

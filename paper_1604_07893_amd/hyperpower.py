@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhyperpower.so")
 
 # ---- constants mirrored from include/hyperpower.h ---------------------------
-HP_ABI_VERSION = 1
+HP_ABI_VERSION = 2
 HP_OK, HP_MAXITER, HP_STAGNATED, HP_DIVERGED, HP_NONFINITE, HP_PENDING = 0, 1, 2, 3, 4, 5
 HP_EINVAL, HP_EWORKSPACE, HP_EBUDGET, HP_EHIP, HP_EUNSUPPORTED = -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "stagnated", 3: "diverged", 4: "nonfinite", 5: "pending"}
@@ -29,6 +29,9 @@ ALPHA = {"norm1inf": 0, "user": 1, "trace": 2}
 VARIANT = {"plain": 0, "stabilised": 1, "stabilized": 1, "stab_always": 2}
 SIDE = {"auto": 0, "right": 1, "left": 2}
 STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2}
+METHOD = {"pm": 0, "sm": 1, "cm": 2, "fm": 3, "hm": 4}
+METHOD_ORDER = {"pm": 18, "sm": 2, "cm": 3, "fm": 7, "hm": 18}
+METHOD_PRODUCTS = {"pm": 7, "sm": 2, "cm": 3, "fm": 5, "hm": 9}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2, "fp32_fp64": 3}
 LOWP = {"bf16": 0, "f16": 1, "fp16": 1}
 FLAG_TIME_KERNELS, FLAG_INF_NORM, FLAG_NO_GRAPH = 1, 2, 4
@@ -41,7 +44,8 @@ class HpParams(ctypes.Structure):
         ("kind", c_int32), ("drazin_l", c_int32), ("alpha_rule", c_int32), ("variant", c_int32),
         ("alpha", c_double), ("tau_switch", c_double), ("tol", c_double), ("diverge_limit", c_double),
         ("max_iter", c_int32), ("stop_rule", c_int32), ("side", c_int32), ("precision", c_int32),
-        ("flags", c_int32), ("low_dtype", c_int32), ("reserved", c_int32 * 6),
+        ("flags", c_int32), ("low_dtype", c_int32), ("method", c_int32),
+        ("reserved", c_int32 * 5),
     ]
 
 
@@ -164,7 +168,7 @@ def handle(device: int | None = None) -> Handle:
 def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", tau_switch=0.1,
                 tol=1e-12, max_iter=100, stop="rel_fro", side="auto", precision="fp64",
                 diverge_limit=1e6, time_kernels=False, inf_norm=False,
-                low_dtype="bf16", graph=True) -> HpParams:
+                low_dtype="bf16", graph=True, method="pm") -> HpParams:
     p = HpParams()
     load_library().hp_params_default(ctypes.byref(p))
     p.kind = KIND[kind]
@@ -182,6 +186,7 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
     p.precision = PREC[precision]
     p.low_dtype = LOWP[low_dtype]
     p.diverge_limit = float(diverge_limit)
+    p.method = METHOD[method]
     p.flags = ((FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
                | (0 if graph else FLAG_NO_GRAPH))
     return p

@@ -111,6 +111,33 @@ def test_pm_step_equals_18_term_definition_fp64():
         assert np.linalg.norm(x_pm - x_def) <= 1e-12 * np.linalg.norm(x_def)
 
 
+@pytest.mark.parametrize("method,p", [("sm", 2), ("cm", 3), ("fm", 7), ("hm", 18), ("pm", 18)])
+def test_comparison_steps_equal_the_hyperpower_sum_mp(method, p):
+    """Each scheme of Sections 1.3 and 2 is the order-p member of (Hyperpower1):
+    X (I + R + ... + R^{p-1}), R = I - A X, checked in 60-digit arithmetic on a
+    rectangular A with R far from I (every power matters), with the sum formed
+    here term by term."""
+    rng = np.random.default_rng(11 + p)
+    A64 = rng.uniform(-1, 1, (7, 5))
+    with mpmath.workdps(60):
+        A = O.MP.asarray(A64)
+        X, _ = O.x0_moore_penrose(A, "norm1inf", ar=O.MP)
+        X = X * 3
+        I = O.MP.eye(7)
+        R = I - A @ X
+        S, P = I, I
+        for _ in range(1, p):
+            P = P @ R
+            S = S + P
+        want = X @ S
+        K = O.pm_constants(O.MP)
+        got = O.STEP_FUNCTIONS[method](A, X, K, ar=O.MP)
+        err = max(abs(v) for v in (got - want).ravel())
+        scale = max(abs(v) for v in want.ravel())
+        assert err <= mpmath.mpf("1e-50") * scale
+        assert O.ORDER[method] == p
+
+
 def test_order_18_residual_map_mp():
     """Theorem 3.1 for nonsingular A: R_{k+1} = R_k^18 exactly."""
     rng = np.random.default_rng(3)
