@@ -129,9 +129,13 @@ def extra_mixed(hpw, torch, steps):
     out = {"workload": f"square {n}x{n}, s log-uniform [1e-3,1], Haar U/V (seed 1003, built on "
                        "the GPU); X0=A^T; plain; tol 1e-10"}
     ref = None
-    for prec in ("fp64", "mixed"):
+    # "*_bound": the same with the residual-bound stop (skips the loop that only
+    # confirms convergence: ||I - AX||_F / (1 - ||I - AX||_F) < tol)
+    for prec, stop in (("fp64", "rel_fro"), ("mixed", "rel_fro"), ("fp64_bound", "rel_fro_bound"),
+                       ("mixed_bound", "rel_fro_bound")):
         sec, infos, X = timed_solves(hpw, torch, A, steps, 1, alpha_rule="user", alpha=1.0,
-                                     tol=TOL, precision=prec, time_kernels=True)
+                                     tol=TOL, precision=prec.split("_")[0], stop=stop,
+                                     time_kernels=True)
         inf = infos[-1]
         if ref is None:
             # closed form V diag(1/s) U^T, on the GPU in FP64 (a reference, not the method)
@@ -150,10 +154,13 @@ def extra_mixed(hpw, torch, steps):
                 Xs, _ = hpw.solve(A, alpha_rule="user", alpha=1.0, tol=TOL, precision=prec,
                                   max_iter=int(cap))
                 per_stage.append(float(torch.linalg.norm(Xs - ref) / torch.linalg.norm(ref)))
+                del Xs
             per_stage.append(err)
             out[prec]["rel_err_after_stage"] = per_stage
         log(f"mixed-vs-fp64 {prec}: {out[prec]}")
     out["speedup_mixed_vs_fp64"] = out["mixed"]["inverses_per_s"] / out["fp64"]["inverses_per_s"]
+    out["speedup_mixed_bound_vs_fp64"] = (out["mixed_bound"]["inverses_per_s"]
+                                          / out["fp64"]["inverses_per_s"])
     del A, U, s, V, ref
     torch.cuda.empty_cache()
     return out

@@ -106,6 +106,18 @@ extern "C" {
                                method's order (18 for PM and HM) and k counts
                                loops from 0 */
 #define HP_STOP_ABS_INF 2   /* ||X_{k+1}-X_k||_inf <= tol (Example 8.1) */
+#define HP_STOP_REL_FRO_BOUND 3 /* HP_STOP_REL_FRO, and in the final precision
+                               stage, before a plain loop that follows a change
+                               d with d^p < tol, the loop's residual R is formed
+                               first: if ||R||_F / (1 - ||R||_F) < tol, the
+                               change that loop would make is below tol
+                               (||X(R + R^2 + ...)||_F <= ||X||_F ||R||_2 /
+                               (1 - ||R||_2)), so it is skipped and X_{k+1} is
+                               returned; otherwise the loop goes on with that R.
+                               Saves the confirming loop on nonsingular input
+                               (R -> 0); on singular input ||R||_F stays >= 1
+                               and the rule is the relative change. An
+                               addition to the paper's stopping rules. */
 
 /* arithmetic of the loops */
 #define HP_PREC_FP64 0  /* every loop in FP64 (FP64 MFMA, FP64 accumulate) */

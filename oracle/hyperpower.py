@@ -285,6 +285,7 @@ class Result:
     stop_hist: list = field(default_factory=list)   # the stopping rule's values
     diff_inf_hist: list = field(default_factory=list)  # ||X_{k+1}-X_k||_inf
     switch_iter: int = -1       # first loop run stabilised (-1: never)
+    bound_hist: list = field(default_factory=list)  # ||R||_F of "rel_fro_bound" checks
 
 
 def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1inf",
@@ -307,6 +308,11 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
               "abs_inf":  ||X_{k+1}-X_k||_inf <= tol (Example 8.1).
               "paper_4_1": ||X_{k+1}-X_k||_F / (p^k alpha) < tol, rule
               (stopreliable) of Section 4 with the Frobenius norm (Example 8.2).
+              "rel_fro_bound": "rel_fro", and before a plain loop that follows
+              a change d with d^p < tol, r = ||I - A X_{k+1}||_F is formed;
+              r/(1-r) < tol (r < 1) bounds the change that loop would make
+              below tol, so X_{k+1} is returned without it (an addition to the
+              paper's rules).
     Guards (the warning of Section 6 that looping past convergence can
     diverge): a non-finite iterate ends with "nonfinite" and the last finite
     iterate; once some relative change below tau_switch has been seen, a change
@@ -349,7 +355,7 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
         d = norm_fro(D, ar) / norm_fro(X, ar)
         res.d_hist.append(d)
         res.diff_inf_hist.append(norm_inf(D))
-        if stop == "rel_fro":
+        if stop in ("rel_fro", "rel_fro_bound"):
             sval, passed = d, d < tol
         elif stop == "abs_inf":
             sval = res.diff_inf_hist[-1]
@@ -374,6 +380,19 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
             if variant == "stabilised" and not stabilising:
                 stabilising = True
                 res.switch_iter = k + 1
+        if (stop == "rel_fro_bound" and not stabilising and k + 1 < max_iter
+                and d ** p < tol):
+            # The next (plain) loop changes X by X (R + R^2 + ... + R^{p-1})
+            # with R = I - A X, whose Frobenius norm is at most
+            # ||X||_F ||R||_2 / (1 - ||R||_2) <= ||X||_F r / (1 - r),
+            # r = ||R||_F < 1: when that is below tol the loop need not run.
+            # (An addition to the paper's stopping rules.)
+            R = ar.eye(A.shape[0]) - A @ Xn
+            r = norm_fro(R, ar)
+            res.bound_hist.append(r)
+            if r < 1 and r / (1 - r) < tol:
+                res.status, res.X = "ok", Xn
+                return res
         X = Xn
     res.X = X
     return res

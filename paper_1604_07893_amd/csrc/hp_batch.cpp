@@ -314,7 +314,7 @@ int validate_group_params(const hp_params* p) {
         p->precision != HP_PREC_FP32_FP64)
         return HP_EUNSUPPORTED;
     if (p->stop_rule == HP_STOP_ABS_INF || (p->flags & HP_FLAG_INF_NORM)) return HP_EUNSUPPORTED;
-    if (p->method != HP_METHOD_PM) return HP_EUNSUPPORTED;
+    if (p->method != HP_METHOD_PM || p->stop_rule == HP_STOP_REL_FRO_BOUND) return HP_EUNSUPPORTED;
     return HP_OK;
 }
 

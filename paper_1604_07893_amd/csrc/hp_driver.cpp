@@ -149,7 +149,7 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
     if (p->alpha_rule == HP_ALPHA_USER && !(p->alpha > 0.0 && std::isfinite(p->alpha))) return HP_EINVAL;
     if (p->variant < HP_VARIANT_PLAIN || p->variant > HP_VARIANT_STAB_ALWAYS) return HP_EINVAL;
     if (p->side < HP_SIDE_AUTO || p->side > HP_SIDE_LEFT) return HP_EINVAL;
-    if (p->stop_rule < HP_STOP_REL_FRO || p->stop_rule > HP_STOP_ABS_INF) return HP_EINVAL;
+    if (p->stop_rule < HP_STOP_REL_FRO || p->stop_rule > HP_STOP_REL_FRO_BOUND) return HP_EINVAL;
     if (p->precision < HP_PREC_FP64 || p->precision > HP_PREC_FP32_FP64) return HP_EINVAL;
     if (p->low_dtype != HP_LOWP_BF16 && p->low_dtype != HP_LOWP_F16) return HP_EINVAL;
     if (p->method < HP_METHOD_PM || p->method > HP_METHOD_HM) return HP_EINVAL;
@@ -296,7 +296,7 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
     }
     double sval;
     bool passed;
-    if (p->stop_rule == HP_STOP_REL_FRO) {
+    if (p->stop_rule == HP_STOP_REL_FRO || p->stop_rule == HP_STOP_REL_FRO_BOUND) {
         sval = d;
         passed = d < p->tol;
     } else if (p->stop_rule == HP_STOP_ABS_INF) {
@@ -327,6 +327,11 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
     d_prev = d;
     std::swap(ik, in_);
     return CONTINUE;
+}
+
+bool LoopState::bound_ready() const {
+    if (p->stop_rule != HP_STOP_REL_FRO_BOUND || stage != final_stage || stabilising) return false;
+    return std::pow(d_prev, (double)method_order(p->method)) < p->tol;
 }
 
 }  // namespace hp
@@ -437,21 +442,59 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
     }
     const bool want_inf = (p->flags & HP_FLAG_INF_NORM) || p->stop_rule == HP_STOP_ABS_INF;
 
-    while (st.k < p->max_iter) {
-        S.stage = st.stage;
+    // The loop's products from `first` on (the residual product, call 0, may
+    // already have run for the residual bound).
+    auto run_loop = [&](int first) -> int {
         if (st.stage == 2) {
             GemmCall<double> calls[kMaxLoopGemms];
             const int nc = describe_loop<double>(p->method, pl, bf.b64, bf.b64.X[st.ik],
                                                  bf.b64.X[st.in_], bf.b64.X[2], st.stabilising,
                                                  bf.small, calls);
-            for (int i = 0; i < nc; ++i) CHK(S.gemm<double>(ENG_F64, calls[i]));
+            for (int i = first; i < nc; ++i) CHK(S.gemm<double>(ENG_F64, calls[i]));
         } else {
             GemmCall<float> calls[kMaxLoopGemms];
             const int nc = describe_loop<float>(p->method, pl, bf.b32, bf.b32.X[st.ik],
                                                 bf.b32.X[st.in_], bf.b32.X[2], st.stabilising,
                                                 bf.small, calls);
-            for (int i = 0; i < nc; ++i) CHK(S.gemm<float>(st.engine(), calls[i]));
+            for (int i = first; i < nc; ++i) CHK(S.gemm<float>(st.engine(), calls[i]));
         }
+        return HP_OK;
+    };
+    // HP_STOP_REL_FRO_BOUND: form the next loop's residual R (its first
+    // product, into S[0]) and ||R||_F^2; true if ||R||_F/(1-||R||_F) < tol.
+    auto residual_bound = [&](bool* settled) -> int {
+        *settled = false;
+        const int64_t sd = pl.s;
+        if (st.stage == 2) {
+            GemmCall<double> calls[kMaxLoopGemms];
+            describe_loop<double>(p->method, pl, bf.b64, bf.b64.X[st.ik], bf.b64.X[st.in_],
+                                  bf.b64.X[2], false, bf.small, calls);
+            CHK(S.gemm<double>(ENG_F64, calls[0]));
+            HIPCHK(diffsq(bf.b64.S[0], bf.b64.ldS, nullptr, 0, 0.0, sd, sd, bf.small, bf.scal,
+                          SLOT_RNORM2, s));
+        } else {
+            GemmCall<float> calls[kMaxLoopGemms];
+            describe_loop<float>(p->method, pl, bf.b32, bf.b32.X[st.ik], bf.b32.X[st.in_],
+                                 bf.b32.X[2], false, bf.small, calls);
+            CHK(S.gemm<float>(st.engine(), calls[0]));
+            HIPCHK(sumsq(bf.b32.S[0], bf.b32.ldS, sd, sd, bf.small, bf.scal, SLOT_RNORM2, s));
+        }
+        HIPCHK(hipMemcpyAsync(hs, bf.scal, sizeof(double) * SLOT_COUNT, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        S.timer.harvest();
+        const double r = std::sqrt(hs[SLOT_RNORM2]);
+        if (std::isfinite(r) && r < 1.0 && r / (1.0 - r) < p->tol) {
+            st.stop_bound(r / (1.0 - r));
+            *settled = true;
+        }
+        return HP_OK;
+    };
+    bool r_ready = false;
+
+    while (st.k < p->max_iter) {
+        S.stage = st.stage;
+        CHK(run_loop(r_ready ? 1 : 0));
+        r_ready = false;
         HIPCHK(reduce_pairs(bf.small, S.last_blocks, bf.scal, s));
         const bool inf_now = want_inf && st.stage == 2;
         if (inf_now)
@@ -463,6 +506,12 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
 
         const LoopState::Action a = st.step(hs[SLOT_DIFF2], hs[SLOT_REF2], hs[SLOT_DINF], inf_now);
         if (a == LoopState::DONE) break;
+        if (a == LoopState::CONTINUE && st.k < p->max_iter && st.bound_ready()) {
+            bool settled = false;
+            CHK(residual_bound(&settled));
+            if (settled) break;
+            r_ready = true;
+        }
         if (a == LoopState::NEXT_STAGE) {
             const int next = st.stage + 1;
             if (next == 2) {

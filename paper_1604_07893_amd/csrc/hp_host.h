@@ -438,6 +438,16 @@ struct LoopState {
     // stage's set; this resets the indices (FP64 stage: X[0]).
     void enter_stage(int next);
     bool done() const { return result_idx >= 0; }
+    // HP_STOP_REL_FRO_BOUND: after a CONTINUE, whether the next loop is a
+    // plain loop of the final stage whose change the residual bound may
+    // already settle (the last change d has d^p < tol).
+    bool bound_ready() const;
+    // The residual bound settled it: return the current iterate.
+    void stop_bound(double bound) {
+        status = HP_OK;
+        result_idx = ik;
+        res->stop_last = bound;
+    }
     void finish_maxiter() {
         if (result_idx < 0) result_idx = ik;
     }

@@ -28,7 +28,7 @@ KIND = {"mp": 0, "moore_penrose": 0, "drazin": 1}
 ALPHA = {"norm1inf": 0, "user": 1, "trace": 2}
 VARIANT = {"plain": 0, "stabilised": 1, "stabilized": 1, "stab_always": 2}
 SIDE = {"auto": 0, "right": 1, "left": 2}
-STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2}
+STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2, "rel_fro_bound": 3}
 METHOD = {"pm": 0, "sm": 1, "cm": 2, "fm": 3, "hm": 4}
 METHOD_ORDER = {"pm": 18, "sm": 2, "cm": 3, "fm": 7, "hm": 18}
 METHOD_PRODUCTS = {"pm": 7, "sm": 2, "cm": 3, "fm": 5, "hm": 9}
