@@ -705,7 +705,7 @@ hipError_t launch_split(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda
                     (SPLIT - 1) * kchunk < K;
     if (!ok) {
         if (tiles >= 512) return launch<T, 128, 128, BK, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
-        return launch<T, 128, 128, BK, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
+        return launch<T, 128, 128, 2 * BK, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
     }
     hipLaunchKernelGGL((k_gemm_split<T, 128, 128, BK, 64, 32, SPLIT>), dim3(tiles * SPLIT),
                        dim3(C::NT), 0, s, (int)M, (int)N, (int)K, A, lda, B, ldb, ep, tm, tn,
@@ -731,6 +731,7 @@ constexpr TileShape kShapes[] = {
     {128, 128},  // TILE_128x128_W16_P2: 16 waves, loads two K-tiles ahead
     {128, 128},  // TILE_128x128_W8_S2: K split over 2 blocks
     {128, 128},  // TILE_128x128_W8_S4: K split over 4 blocks
+    {128, 128},  // TILE_128x128_W16_K2_P2: 16 waves, double K-tile, two ahead
 };
 static_assert(sizeof(kShapes) / sizeof(kShapes[0]) == TILE_COUNT, "tile table");
 
@@ -752,6 +753,7 @@ hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int
         case TILE_128x128_W16_P2: return launch<T, 128, 128, BKF, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W8_S2: return launch_split<T, BKF, 2>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W8_S4: return launch_split<T, BKF, 4>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W16_K2_P2: return launch<T, 128, 128, 2 * BKF, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -784,7 +786,8 @@ hipError_t dispatch_lp(GemmTile t, int64_t M, int64_t N, int64_t K, const float*
         case TILE_128x128_W8_P2:
         case TILE_128x128_W16_P2:
         case TILE_128x128_W8_S2:
-        case TILE_128x128_W8_S4: return launch_lp<L, 128, 128, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W8_S4:
+        case TILE_128x128_W16_K2_P2: return launch_lp<L, 128, 128, 64, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -827,15 +830,16 @@ int gemm_max_blocks(int64_t M, int64_t N) {
 }
 
 GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow_split) {
-    // From MI355X sweeps of every tile over square and 2:1 products. With
-    // four or more 128x128 tiles per CU (256 CUs) the 8-wave tile loading
-    // one K-tile ahead is fastest (FP64 63 TFLOP/s at 8192^3). FP64 with one
-    // to four tiles per CU: the 16-wave tile loading two K-tiles ahead with
-    // its LDS reads spread over the MFMAs (51.9 vs 49.2 TFLOP/s at 2048^3);
-    // FP32 keeps the 8-wave tile there. With fewer tiles than CUs and a long
-    // K, splitting K four ways fills the chip (FP64 1024x1024x2048: 33.6
-    // TFLOP/s against 14.6 unsplit and 27.7 on 64x64 tiles); short K or the
-    // FP32 1536^2 case favour 64x64 tiles. The 16-bit kernel does not split.
+    // From MI355X sweeps of every tile over square and 2:1 products. FP64 with
+    // at least one 128x128 tile per CU (256 CUs): the 16-wave tile with a
+    // 32-deep K-tile, loading two K-tiles ahead with its LDS reads spread over
+    // the MFMAs (2048^3: 52.8 TFLOP/s against 49.2 for the 8-wave tile
+    // loading one ahead; 8192^3: 64.6 against 63.3). FP32: the 8-wave tile
+    // from two tiles per CU (8192^3: 121.9 against 118.9), the 16-wave one
+    // below. With fewer tiles than CUs and a long K, splitting K four ways
+    // fills the chip (FP64 1024x1024x2048: 33.6 TFLOP/s against 14.6 unsplit
+    // and 27.7 on 64x64 tiles); short K or the FP32 1536^2 case favour 64x64
+    // tiles. The 16-bit kernel does not split.
     const int64_t tiles = cdiv(M, 128) * cdiv(N, 128);
     if (gt == GT_LOWP) {
         if (tiles >= 512) return TILE_128x128_W8;
@@ -843,12 +847,12 @@ GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow
         return TILE_64x64_W4;
     }
     if (gt == GT_F64) {
-        if (tiles >= 1024) return TILE_128x128_W8;
-        if (tiles >= 256) return TILE_128x128_W16_P2;
+        if (tiles >= 256) return TILE_128x128_W16_K2_P2;
         if (allow_split && K >= 1024) return TILE_128x128_W8_S4;
         return TILE_64x64_W4;
     }
-    if (tiles >= 256) return TILE_128x128_W8;
+    if (tiles >= 512) return TILE_128x128_W8;
+    if (tiles >= 256) return TILE_128x128_W16_K2_P2;
     if (allow_split && ((tiles < 128 && K >= 2048) || K >= 4096)) return TILE_128x128_W8_S4;
     return TILE_64x64_W4;
 }

@@ -78,7 +78,8 @@ enum GemmTile : int {
     TILE_128x128_W16_P2 = 10, // TILE_128x128_W16 loading two K-tiles ahead
     TILE_128x128_W8_S2 = 11,  // TILE_128x128_W8 with K split over 2 blocks per tile
     TILE_128x128_W8_S4 = 12,  // TILE_128x128_W8 with K split over 4 blocks per tile
-    TILE_COUNT = 13
+    TILE_128x128_W16_K2_P2 = 13,  // TILE_128x128_W16_P2 with a K-tile twice as deep
+    TILE_COUNT = 14
 };
 
 // Blocks (and partial-sum pairs) a launch with this tile uses for M x N.
