@@ -131,7 +131,9 @@ extern "C" {
                            FP32; stage 2: FP64 loops until the stop test
                            passes. A stage ends when its relative change stops
                            halving (below 1), falls under 10x its unit
-                           roundoff, or one loop after it first fell below 0.2;
+                           roundoff, or after a loop (not its first) whose
+                           change falls below 0.2 (that loop's output is at
+                           the stage's floor: about 0.2^18 relative error);
                            the FP64 stage alone applies the stop test
                            and the stagnation guard. For Moore-Penrose input
                            that is not square, or square with

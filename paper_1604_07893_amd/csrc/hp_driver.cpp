@@ -200,9 +200,11 @@ Buffers carve(const Plan& pl, char* ws) {
 // ---------------------------------------------------------------------------
 
 static constexpr double kUnitRoundoffF32 = 5.960464477539063e-08;
-// A lower stage ends one loop after its relative change first falls below
-// this: the order-18 contraction then takes the next iterate to the stage's
-// rounding floor, so a further loop would only confirm it.
+// A lower stage ends after a loop (other than its first) whose relative
+// change falls below this. That change measures the error of the loop's
+// input; the loop's output has about that error to the 18th power (0.2^18 <
+// 1e-12), i.e. it is already at the stage's rounding floor, and a further
+// loop would only confirm it.
 static constexpr double kPredict = 0.2;
 
 void LoopState::init(const hp_params* prm, hp_result* r, double a) {
@@ -217,7 +219,6 @@ void LoopState::init(const hp_params* prm, hp_result* r, double a) {
     res->switch_iter = stabilising ? 0 : -1;
     converging = false;
     stage_first = true;
-    armed = false;
     d_prev = 0.0;
     ik = 0;
     in_ = 1;
@@ -235,7 +236,6 @@ Engine LoopState::engine() const {
 void LoopState::enter_stage(int next) {
     stage = next;
     stage_first = true;
-    armed = false;
     if (next == 2) {
         ik = 0;
         in_ = 1;
@@ -276,13 +276,15 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         const bool stalled = !stage_first && d < 1.0 && d >= 0.5 * d_prev;
         const bool floor = d < 10.0 * u || d < p->tol;
         if (finite) note_switch();
-        if (!finite || stalled || floor || armed) {
+        // (not on a stage's first loop: its change is mostly the step between
+        // the two precisions and says little about the slow directions)
+        const bool settled = finite && d < kPredict && !stage_first;
+        if (!finite || stalled || floor || settled) {
             const bool keep_new = finite && !(stalled && d >= d_prev);
             from_idx = keep_new ? in_ : ik;
             d_prev = d;
             return NEXT_STAGE;
         }
-        armed = d < kPredict;
         stage_first = false;
         d_prev = d;
         std::swap(ik, in_);

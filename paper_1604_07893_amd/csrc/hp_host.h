@@ -422,7 +422,6 @@ struct LoopState {
     bool stabilising = false;
     bool converging = false;
     bool stage_first = true;  // no stagnation test on a stage's first loop
-    bool armed = false;       // lower stage: the previous change was below kPredict
     double d_prev = 0.0;
     int ik = 0, in_ = 1;  // current and next iterate (index into the stage's set)
     int k = 0;            // loops run
