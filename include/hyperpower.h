@@ -64,6 +64,12 @@ extern "C" {
 #define HP_ALPHA_USER 1      /* alpha = hp_params.alpha (e.g. 1/sigma_max^2 or
                                 2/(sigma_1^2 + sigma_r^2) when known) */
 #define HP_ALPHA_TRACE 2     /* Drazin: alpha = 1/Tr(A^{l+1}) */
+#define HP_ALPHA_SIGMA_MAX2 3 /* Moore-Penrose: alpha = 1/rho with rho an estimate
+                                of sigma_1(A)^2 from 50 power-iteration steps on
+                                A^T A on the GPU (a fixed generic start vector;
+                                rho <= sigma_1^2, so alpha sigma_1^2 >= 1, and it
+                                stays below 2 as long as rho > sigma_1^2 / 2,
+                                the convergence condition of Section 4) */
 
 /* iteration variant */
 #define HP_VARIANT_PLAIN 0       /* (PM), Section 2: 7 products per loop */

@@ -122,7 +122,7 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area) {
     const int64_t big = std::max(m, n);
     const int64_t blocks = (int64_t)hp::gemm_max_blocks(big, big);
     int64_t small = 2 * blocks;
-    small = std::max<int64_t>(small, ((m + 255) / 256 + 1) * n + m);
+    small = std::max<int64_t>(small, ((m + 255) / 256 + 2) * n + m);
     small = std::max<int64_t>(small, ((n + 31) / 32) * ((n + 31) / 32));
     small = std::max<int64_t>(small, big);
     pl.offSmall = off;
@@ -143,7 +143,8 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
         // lower-precision stages are not stable on the nilpotent part
         if (p->precision != HP_PREC_FP64) return HP_EUNSUPPORTED;
         if (p->alpha_rule != HP_ALPHA_TRACE && p->alpha_rule != HP_ALPHA_USER) return HP_EINVAL;
-    } else if (p->alpha_rule != HP_ALPHA_NORM1INF && p->alpha_rule != HP_ALPHA_USER) {
+    } else if (p->alpha_rule != HP_ALPHA_NORM1INF && p->alpha_rule != HP_ALPHA_USER &&
+               p->alpha_rule != HP_ALPHA_SIGMA_MAX2) {
         return HP_EINVAL;
     }
     if (p->alpha_rule == HP_ALPHA_USER && !(p->alpha > 0.0 && std::isfinite(p->alpha))) return HP_EINVAL;

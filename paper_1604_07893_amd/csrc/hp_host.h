@@ -308,6 +308,9 @@ int describe_loop(int method, const Plan& pl, const Set<T>& b, T* Xk, T* Xn, T* 
     return describe_update(pl, b, W, Xk, Xn, Xh, stab, partials, R2, out, c);
 }
 
+// Power-iteration steps of HP_ALPHA_SIGMA_MAX2.
+constexpr int kPowerIters = 50;
+
 // Forms X0 = alpha G (Section 4) in the FP64 iterate b64.X[0] on stream s
 // (products go through `gemm`), synchronises, and returns alpha.
 template <typename GemmFn>
@@ -333,6 +336,8 @@ int setup_x0(const hp_params* p, const Plan& pl, const Buffers& bf, const double
     if (p->kind == HP_KIND_MOORE_PENROSE) {
         if (p->alpha_rule == HP_ALPHA_NORM1INF)
             HIPCHK(alpha_norm1inf(b.A, b.ldA, m, n, bf.small, bf.scal, s));
+        else if (p->alpha_rule == HP_ALPHA_SIGMA_MAX2)
+            HIPCHK(alpha_sigma_max2(b.A, b.ldA, m, n, kPowerIters, bf.small, bf.scal, s));
         HIPCHK(transpose_scale(b.A, b.ldA, m, n, X0w, b.ldX, bf.scal + SLOT_ALPHA, s));
     } else {
         // G = A^l by repeated products, alpha = 1/Tr(A^{l+1}) = 1/Tr(A^l A)

@@ -143,6 +143,14 @@ hipError_t gemm_lowp(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, co
 hipError_t alpha_norm1inf(const double* A, int64_t lda, int64_t M, int64_t N, double* tmp,
                           double* scal, hipStream_t s);
 
+// Power iteration on A^T A (A M x N) from a fixed generic start vector:
+// `iters` steps v <- A^T A v / ||A^T A v||; scal[SLOT_ALPHA] = 1/rho and
+// scal[SLOT_TRACE] = rho, rho = ||A v||^2 for the last unit v (a lower bound
+// on sigma_max(A)^2 that rises toward it). `tmp` needs N + M +
+// ceil(M/256)*N doubles.
+hipError_t alpha_sigma_max2(const double* A, int64_t lda, int64_t M, int64_t N, int iters,
+                            double* tmp, double* scal, hipStream_t s);
+
 // scal[SLOT_TRACE] = sum_ij P[i][j] * A[j][i] = Tr(P A), scal[SLOT_ALPHA] =
 // 1/that (n x n). `tmp` needs ceil(n/32)^2 doubles.
 hipError_t alpha_trace(const double* P, int64_t ldp, const double* A, int64_t lda, int64_t n,

@@ -94,6 +94,81 @@ __global__ __launch_bounds__(kThreads) void k_alpha_norm1inf(const double* __res
     }
 }
 
+// ---- power iteration on A^T A for sigma_max(A)^2 ----
+// y = A v: one wave per row, lanes striding along the row.
+__global__ __launch_bounds__(kThreads) void k_gemv_rows(const double* __restrict__ A, int64_t lda,
+                                                        int M, int N, const double* __restrict__ v,
+                                                        double* __restrict__ y) {
+    const int r = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= M) return;
+    double s = 0.0;
+    for (int c = lane; c < N; c += 64) s += A[(int64_t)r * lda + c] * v[c];
+    s = wave_sum(s);
+    if (lane == 0) y[r] = s;
+}
+
+// part[chunk][col] = sum over the chunk's 256 rows of A[r][col] y[r].
+__global__ __launch_bounds__(kThreads) void k_gemv_cols_part(const double* __restrict__ A,
+                                                             int64_t lda, int M, int N,
+                                                             const double* __restrict__ y,
+                                                             double* __restrict__ part) {
+    const int col = blockIdx.x * kThreads + threadIdx.x;
+    const int chunk = blockIdx.y;
+    if (col >= N) return;
+    const int r0 = chunk * 256, r1 = min(M, r0 + 256);
+    double s = 0.0;
+    for (int r = r0; r < r1; ++r) s += A[(int64_t)r * lda + col] * y[r];
+    part[(int64_t)chunk * N + col] = s;
+}
+
+// z = A^T y from the chunk partials (fixed order), then v = z / ||z|| and
+// scal[SLOT_ALPHA] = 1 / ||y||^2 (||y||^2 = v_old^T A^T A v_old, the Rayleigh
+// quotient of the unit vector the step started from). One block.
+__global__ __launch_bounds__(kThreads) void k_power_step(const double* __restrict__ part, int nchunk,
+                                                         int N, const double* __restrict__ y, int M,
+                                                         double* __restrict__ v,
+                                                         double* __restrict__ scal) {
+    __shared__ double zz;
+    double yy = 0.0;
+    for (int r = threadIdx.x; r < M; r += kThreads) yy += y[r] * y[r];
+    double sz = 0.0;
+    for (int c = threadIdx.x; c < N; c += kThreads) {
+        double z = 0.0;
+        for (int ch = 0; ch < nchunk; ++ch) z += part[(int64_t)ch * N + c];
+        v[c] = z;  // unnormalised for now; scaled below
+        sz += z * z;
+    }
+    yy = block_sum(yy);
+    sz = block_sum(sz);
+    if (threadIdx.x == 0) {
+        zz = sz;
+        scal[SLOT_TRACE] = yy;  // the Rayleigh quotient, kept for the caller
+        scal[SLOT_ALPHA] = 1.0 / yy;
+    }
+    __syncthreads();
+    const double inv = zz > 0.0 ? 1.0 / sqrt(zz) : 0.0;
+    for (int c = threadIdx.x; c < N; c += kThreads) v[c] *= inv;
+}
+
+// v0: a fixed, unit, generic start vector (a multiplicative hash of the index
+// spread over [0.5, 1.5], normalised).
+__global__ __launch_bounds__(kThreads) void k_power_start(int N, double* __restrict__ v) {
+    double s = 0.0;
+    for (int c = threadIdx.x; c < N; c += kThreads) {
+        const uint32_t h = (uint32_t)c * 2654435761u;
+        const double x = 0.5 + (double)h * (1.0 / 4294967296.0);
+        v[c] = x;
+        s += x * x;
+    }
+    s = block_sum(s);
+    __shared__ double tot;
+    if (threadIdx.x == 0) tot = s;
+    __syncthreads();
+    const double inv = 1.0 / sqrt(tot);
+    for (int c = threadIdx.x; c < N; c += kThreads) v[c] *= inv;
+}
+
 // Partial sums of P[i][j] * A[j][i] over 32x32 tiles (A read through LDS so
 // that both operands are read along rows).
 __global__ __launch_bounds__(kThreads) void k_trace_part(const double* __restrict__ P, int64_t ldp,
@@ -324,6 +399,24 @@ hipError_t alpha_norm1inf(const double* A, int64_t lda, int64_t M, int64_t N, do
     hipLaunchKernelGGL(k_abs_rowsum, dim3((unsigned)M), dim3(kThreads), 0, s, A, lda, (int)N, rows);
     hipLaunchKernelGGL(k_alpha_norm1inf, dim3(1), dim3(kThreads), 0, s, part, nchunk, (int)N, rows,
                        (int)M, scal);
+    return hipGetLastError();
+}
+
+hipError_t alpha_sigma_max2(const double* A, int64_t lda, int64_t M, int64_t N, int iters,
+                            double* tmp, double* scal, hipStream_t s) {
+    const int nchunk = (int)cdiv(M, 256);
+    double* v = tmp;
+    double* y = v + N;
+    double* part = y + M;
+    hipLaunchKernelGGL(k_power_start, dim3(1), dim3(kThreads), 0, s, (int)N, v);
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(k_gemv_rows, dim3((unsigned)cdiv(M, kThreads / 64)), dim3(kThreads), 0, s,
+                           A, lda, (int)M, (int)N, v, y);
+        hipLaunchKernelGGL(k_gemv_cols_part, dim3((unsigned)cdiv(N, kThreads), nchunk),
+                           dim3(kThreads), 0, s, A, lda, (int)M, (int)N, y, part);
+        hipLaunchKernelGGL(k_power_step, dim3(1), dim3(kThreads), 0, s, part, nchunk, (int)N, y,
+                           (int)M, v, scal);
+    }
     return hipGetLastError();
 }
 

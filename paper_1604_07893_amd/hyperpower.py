@@ -25,7 +25,7 @@ HP_EINVAL, HP_EWORKSPACE, HP_EBUDGET, HP_EHIP, HP_EUNSUPPORTED = -1, -2, -3, -4,
 STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "stagnated", 3: "diverged", 4: "nonfinite", 5: "pending"}
 
 KIND = {"mp": 0, "moore_penrose": 0, "drazin": 1}
-ALPHA = {"norm1inf": 0, "user": 1, "trace": 2}
+ALPHA = {"norm1inf": 0, "user": 1, "trace": 2, "sigma_max2": 3}
 VARIANT = {"plain": 0, "stabilised": 1, "stabilized": 1, "stab_always": 2}
 SIDE = {"auto": 0, "right": 1, "left": 2}
 STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2, "rel_fro_bound": 3}

@@ -225,3 +225,20 @@ def test_gpu_residuals_match_oracle_residuals():
     want = O.drazin_residuals(dz.A, Xd, 3)
     np.testing.assert_allclose(got[:3], want, rtol=1e-6)
     assert got[3] == 0.0
+
+
+@pytest.mark.parametrize("shape", [(300, 200), (200, 300), (257, 257)])
+def test_sigma_max2_rule_estimates_sigma_1(shape):
+    """HP_ALPHA_SIGMA_MAX2: power iteration on A^T A gives alpha within 1% above
+    the oracle's 1/sigma_1^2 (LAPACK SVD there) and never below it (the
+    Rayleigh quotient is a lower bound on sigma_1^2); the solve ends at the
+    same Moore-Penrose inverse."""
+    m, n = shape
+    say(f"sigma_max2 {m}x{n}")
+    A = inputs.uniform(m, n, seed=m + 7 * n)
+    ref = O.solve(A, kind="mp", alpha_rule="sigma_max2", tol=1e-12)
+    X, info = run(A, alpha_rule="sigma_max2", tol=1e-12)
+    assert info["status"] == ref.status == "ok"
+    assert ref.alpha * (1 - 1e-12) <= info["alpha"] <= ref.alpha * 1.01
+    assert rel(X, ref.X) <= 1e-10
+    assert abs(info["iters"] - ref.iters) <= 1
