@@ -88,3 +88,22 @@ def test_method_fp32_and_unsupported_combinations():
         run(A, method="sm", precision="mixed")
     with pytest.raises(hpw.HyperpowerError):
         hpw.solve_batched([to_dev(A)], method="hm")
+
+
+@pytest.mark.parametrize("method", ["sm", "cm", "hm", "pm"])
+def test_hilbert_example_8_2_matches_oracle(method):
+    """Example 8.2's setting on H_{100x90}: X0 = 2/(sigma_1^2 + sigma_r^2) H^T
+    (the oracle's SVD gives alpha; the GPU is handed the same value), rule
+    (stopreliable) with eps = 1e-5. kappa(H) is near 1e17, so iterates past
+    the first loops carry rounding amplified by it: the loop count and the
+    first relative changes are compared exactly / to 1e-6, X to 1e-5 (a
+    1e-14 change of alpha alone moves the oracle's own X by ~4e-8)."""
+    say(f"hilbert 100x90 {method}")
+    H = inputs.hilbert(100, 90)
+    ref = O.solve(H, kind="mp", method=method, alpha_rule="sigma_opt", stop="paper_4_1", tol=1e-5)
+    X, info = run(H, method=method, alpha_rule="user", alpha=float(ref.alpha), stop="paper_4_1",
+                  tol=1e-5)
+    assert info["status"] == ref.status == "ok"
+    assert info["iters"] == ref.iters
+    np.testing.assert_allclose(info["d_hist"][:5], ref.d_hist[:5], rtol=1e-6)
+    assert rel(X, ref.X) <= 1e-5
