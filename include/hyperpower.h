@@ -169,6 +169,11 @@ extern "C" {
 #define HP_DTYPE_BF16_F32 2 /* FP32 in memory, operands rounded to bf16,
                                v_mfma_f32_16x16x32_bf16, FP32 accumulate and C */
 #define HP_DTYPE_F16_F32 3  /* as above with fp16 operands (f16 MFMA) */
+#define HP_DTYPE_BF16 4 /* 16-bit operands in memory: A (M x K) bf16 row-major and
+                           B passed TRANSPOSED, Bt = B^T (N x K) bf16 row-major
+                           (ldb >= K); v_mfma_f32_16x16x32_bf16, FP32 accumulate
+                           and C (float). lda, ldb multiples of 8 elements */
+#define HP_DTYPE_F16 5  /* as HP_DTYPE_BF16 with fp16 operands */
 
 typedef struct hp_params {
     int32_t kind;          /* HP_KIND_* */

@@ -28,6 +28,11 @@ HIPCC_FLAGS = [
     "-Wno-unused-result",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # let `#pragma unroll` fully unroll the epilogues of the large 16-bit tiles
+    # (128 accumulators per lane); past the default size limit the loop stays
+    # rolled and the accumulators go to scratch memory. The other kernels
+    # compile to the same code either way.
+    "-mllvm", "-pragma-unroll-threshold=200000",
 ]
 
 

@@ -100,6 +100,31 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area) {
             off = align_up(off + sizeof(float) * (size_t)(pl.s * pl.ldS32));
         }
     }
+    pl.has16 = p->precision == HP_PREC_MIXED;
+    if (pl.has16) {
+        constexpr size_t h = 2;  // bytes per 16-bit element
+        pl.ldA16 = pad_ld(n);
+        pl.ldAt16 = pad_ld(m);
+        pl.ldX16 = pad_ld(m);
+        pl.ldXt16 = pad_ld(n);
+        pl.ldS16 = pad_ld(pl.s);
+        pl.offA16 = off;
+        off = align_up(off + h * (size_t)(m * pl.ldA16));
+        pl.offAt16 = off;
+        off = align_up(off + h * (size_t)(n * pl.ldAt16));
+        for (int i = 0; i < 3; ++i) {
+            pl.offX16[i] = off;
+            off = align_up(off + h * (size_t)(n * pl.ldX16));
+            pl.offXt16[i] = off;
+            off = align_up(off + h * (size_t)(m * pl.ldXt16));
+        }
+        for (int i = 0; i < 7; ++i) {
+            pl.offS16[i] = off;
+            off = align_up(off + h * (size_t)(pl.s * pl.ldS16));
+            pl.offSt16[i] = off;
+            off = align_up(off + h * (size_t)(pl.s * pl.ldS16));
+        }
+    }
     if (split_area) {
         // every product of a solve is (m or n) x (m or n) x (m or n)
         const int64_t dims[2] = {m, n};
@@ -182,6 +207,13 @@ Buffers carve(const Plan& pl, char* ws) {
         bf.b32.ldA = pl.ldA32;
         bf.b32.ldX = pl.ldX32;
         bf.b32.ldS = pl.ldS32;
+    }
+    if (pl.has16) {
+        bf.A16 = {ws + pl.offA16, pl.ldA16, ws + pl.offAt16, pl.ldAt16};
+        for (int i = 0; i < 3; ++i)
+            bf.X16[i] = {ws + pl.offX16[i], pl.ldX16, ws + pl.offXt16[i], pl.ldXt16};
+        for (int i = 0; i < 7; ++i)
+            bf.S16[i] = {ws + pl.offS16[i], pl.ldS16, ws + pl.offSt16[i], pl.ldS16};
     }
     if (pl.has_proj) {
         bf.At = d(pl.offAt);
@@ -381,9 +413,10 @@ struct Solver {
     int stage = 2;        // for per-stage accounting
     double* split_part = nullptr;  // split-K scratch of the workspace (Plan)
     unsigned* split_cnt = nullptr;
+    const Buffers* bf = nullptr;   // for the 16-bit copies of the first mixed stage
 
     template <typename T>
-    int gemm(Engine eng, const GemmCall<T>& g) {
+    int gemm(Engine eng, const GemmCall<T>& g, const CopyUse* use = nullptr) {
         int dt = HP_DTYPE_F64;
         if constexpr (!std::is_same<T, double>::value)
             dt = eng == ENG_F32 ? HP_DTYPE_F32 : (eng == ENG_BF16 ? HP_DTYPE_BF16_F32 : HP_DTYPE_F16_F32);
@@ -400,9 +433,42 @@ struct Solver {
             (void)eng;
             e = hp::gemm(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, ep, s);
         } else {
-            if (eng == ENG_F32) e = hp::gemm(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, ep, s);
-            else e = gemm_lowp(t, eng == ENG_BF16 ? LOWP_BF16 : LOWP_F16, g.M, g.N, g.K, g.A, g.lda,
-                               g.B, g.ldb, ep, s);
+            const Copy16* ca = (eng != ENG_F32 && bf) ? bf->copy16(g.A) : nullptr;
+            const Copy16* cb = (eng != ENG_F32 && bf) ? bf->copy16(g.B) : nullptr;
+            if (eng == ENG_F32) {
+                e = hp::gemm(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, ep, s);
+            } else if (ca && cb) {
+                // operands from their 16-bit copies (A row-major, B transposed);
+                // the outputs leave their own copies for the next products
+                const int dt16 = eng == ENG_BF16 ? HP_DTYPE_BF16 : HP_DTYPE_F16;
+                const GemmTile t16 = choose_tile(h, dt16, g.M, g.N, g.K);
+                for (int o = 0; o < 3; ++o) {
+                    const Copy16* co = ep.out[o] ? bf->copy16(ep.out[o]) : nullptr;
+                    if (!co) continue;
+                    if (!use || use->row[o]) {
+                        ep.h[o] = co->h;
+                        ep.ldh[o] = co->ld;
+                    }
+                    if (!use || use->t[o]) {
+                        ep.ht[o] = co->ht;
+                        ep.ldht[o] = co->ldt;
+                    }
+                    if (use && !use->f32[o]) ep.skip32[o] = 1;
+                }
+                e = gemm_h16(t16, eng == ENG_BF16 ? LOWP_BF16 : LOWP_F16, g.M, g.N, g.K, ca->h,
+                             ca->ld, cb->ht, cb->ldt, ep, s);
+                last_blocks = gemm_blocks(t16, g.M, g.N);
+                timer.after();
+                if (e != hipSuccess) return HP_EHIP;
+                const double gf = 2.0 * (double)g.M * (double)g.N * (double)g.K * 1e-9;
+                gflop += gf;
+                res->gflop_stage[stage] += gf;
+                ++gemms;
+                return HP_OK;
+            } else {
+                e = gemm_lowp(t, eng == ENG_BF16 ? LOWP_BF16 : LOWP_F16, g.M, g.N, g.K, g.A, g.lda,
+                              g.B, g.ldb, ep, s);
+            }
         }
         timer.after();
         last_blocks = gemm_blocks(t, g.M, g.N);
@@ -429,6 +495,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         S.split_part = bf.split_part;
         S.split_cnt = bf.split_cnt;
     }
+    S.bf = &bf;
 
     double alpha = 0.0;
     S.stage = 2;
@@ -442,6 +509,14 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
     if (st.stage < 2) {
         HIPCHK(convert(bf.b64.A, bf.b64.ldA, m, n, bf.b32.A, bf.b32.ldA, s));
         HIPCHK(convert(bf.b64.X[0], bf.b64.ldX, n, m, bf.b32.X[0], bf.b32.ldX, s));
+    }
+    if (st.stage == 0 && pl.has16) {
+        // the 16-bit stage's operands: A and X0 rounded, row-major and transposed
+        const LowPrec lp = p->low_dtype == HP_LOWP_F16 ? LOWP_F16 : LOWP_BF16;
+        HIPCHK(convert_h16(bf.b32.A, bf.b32.ldA, m, n, lp, bf.A16.h, bf.A16.ld, bf.A16.ht,
+                           bf.A16.ldt, s));
+        HIPCHK(convert_h16(bf.b32.X[0], bf.b32.ldX, n, m, lp, bf.X16[0].h, bf.X16[0].ld,
+                           bf.X16[0].ht, bf.X16[0].ldt, s));
     }
     const bool want_inf = (p->flags & HP_FLAG_INF_NORM) || p->stop_rule == HP_STOP_ABS_INF;
 
@@ -459,7 +534,10 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
             const int nc = describe_loop<float>(p->method, pl, bf.b32, bf.b32.X[st.ik],
                                                 bf.b32.X[st.in_], bf.b32.X[2], st.stabilising,
                                                 bf.small, calls);
-            for (int i = first; i < nc; ++i) CHK(S.gemm<float>(st.engine(), calls[i]));
+            CopyUse use[kMaxLoopGemms];
+            copy_uses(calls, nc, bf.b32, use);
+            for (int i = first; i < nc; ++i)
+                CHK(S.gemm<float>(st.engine(), calls[i], st.stage == 0 ? &use[i] : nullptr));
         }
         return HP_OK;
     };
@@ -678,10 +756,11 @@ static size_t gemm_ws_bytes(int dtype, int64_t slots) {
 static int gemm_args(int dtype, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
                      const void* B, int64_t ldb, const void* C, int64_t ldc) {
     if (!A || !B || !C) return HP_EINVAL;
-    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16_F32) return HP_EINVAL;
+    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16) return HP_EINVAL;
     if (M < 1 || N < 1 || K < 1 || M > (1 << 24) || N > (1 << 24) || K > (1 << 24)) return HP_EINVAL;
-    if (lda < K || ldb < N || ldc < N) return HP_EINVAL;
-    const int64_t vec = dtype == HP_DTYPE_F64 ? 2 : 4;  // elements per 16 bytes
+    const bool h16 = dtype == HP_DTYPE_BF16 || dtype == HP_DTYPE_F16;  // B given as B^T
+    if (lda < K || ldb < (h16 ? K : N) || ldc < N) return HP_EINVAL;
+    const int64_t vec = dtype == HP_DTYPE_F64 ? 2 : h16 ? 8 : 4;  // elements per 16 bytes
     if (lda % vec || ldb % vec) return HP_EINVAL;
     if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
          reinterpret_cast<uintptr_t>(C)) & 15)
@@ -718,6 +797,9 @@ static int gemm_run(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, do
     } else if (dtype == HP_DTYPE_F32) {
         e = hp::gemm(t, M, N, K, static_cast<const float*>(A), lda, static_cast<const float*>(B),
                      ldb, split(hp::epilogue_plain(static_cast<float*>(C), ldc, alpha, beta_identity)), s);
+    } else if (dtype == HP_DTYPE_BF16 || dtype == HP_DTYPE_F16) {
+        e = hp::gemm_h16(t, dtype == HP_DTYPE_BF16 ? hp::LOWP_BF16 : hp::LOWP_F16, M, N, K, A, lda, B,
+                         ldb, hp::epilogue_plain(static_cast<float*>(C), ldc, alpha, beta_identity), s);
     } else {
         e = hp::gemm_lowp(t, dtype == HP_DTYPE_BF16_F32 ? hp::LOWP_BF16 : hp::LOWP_F16, M, N, K,
                           static_cast<const float*>(A), lda, static_cast<const float*>(B), ldb,
@@ -738,7 +820,7 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alp
 
 int hp_gemm_workspace_bytes(int dtype, int64_t M, int64_t N, int64_t K, size_t* bytes) {
     if (!bytes) return HP_EINVAL;
-    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16_F32) return HP_EINVAL;
+    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16) return HP_EINVAL;
     if (M < 1 || N < 1 || K < 1 || M > (1 << 24) || N > (1 << 24) || K > (1 << 24)) return HP_EINVAL;
     *bytes = gemm_ws_bytes(dtype, gemm_ws_slots(nullptr, dtype, M, N, K));
     return HP_OK;
@@ -865,16 +947,21 @@ struct TuneLayout {
     int64_t lda, ldb, ldc, slots;
     size_t ops, part, total;
 };
+static size_t operand_bytes(int dtype) {
+    return dtype == HP_DTYPE_F64 ? 8 : (dtype == HP_DTYPE_BF16 || dtype == HP_DTYPE_F16) ? 2 : 4;
+}
+
 static int tune_layout(int dtype, int64_t M, int64_t N, int64_t K, TuneLayout* L) {
-    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16_F32) return HP_EINVAL;
+    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16) return HP_EINVAL;
     if (M < 1 || N < 1 || K < 1 || M > 65535 || N > 65535 || K > 65535) return HP_EINVAL;
-    const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;
-    const int64_t vec = 16 / (int64_t)esz;
+    const size_t esz = operand_bytes(dtype) == 2 ? 4 : operand_bytes(dtype);  // C is float
+    const int64_t vec = 16 / (int64_t)operand_bytes(dtype);
+    const bool h16 = operand_bytes(dtype) == 2;  // B held as B^T (N x K)
     L->lda = (K + vec - 1) / vec * vec;
-    L->ldb = (N + vec - 1) / vec * vec;
+    L->ldb = h16 ? L->lda : (N + vec - 1) / vec * vec;
     L->ldc = N;
     L->slots = 4 * ((M + 127) / 128) * ((N + 127) / 128);
-    L->ops = hp::align_up(esz * (size_t)(M * L->lda + K * L->ldb + M * L->ldc));
+    L->ops = hp::align_up(esz * (size_t)(M * L->lda + (h16 ? N : K) * L->ldb + M * L->ldc));
     L->part = hp::align_up(esz * 128 * 128 * (size_t)L->slots);
     L->total = L->ops + L->part + sizeof(unsigned) * (size_t)L->slots;
     return HP_OK;
@@ -893,7 +980,8 @@ int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* 
     if (!h || !scratch || !tile || !ms || reps < 1) return HP_EINVAL;
     TuneLayout L;
     CHK(tune_layout(dtype, M, N, K, &L));
-    const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;
+    const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;  // 16-bit operands get 4-byte room
+    const bool h16 = dtype == HP_DTYPE_BF16 || dtype == HP_DTYPE_F16;
     const int64_t lda = L.lda, ldb = L.ldb, ldc = L.ldc, slots = L.slots;
     const size_t ops = L.ops;
     if (scratch_bytes < L.total) return HP_EWORKSPACE;
@@ -903,7 +991,7 @@ int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* 
     char* base = static_cast<char*>(scratch);
     void* A = base;
     void* B = base + esz * (size_t)(M * lda);
-    void* C = base + esz * (size_t)(M * lda + K * ldb);
+    void* C = base + esz * (size_t)(M * lda + (h16 ? N : K) * ldb);
     void* split_part = base + ops;
     unsigned* split_cnt = reinterpret_cast<unsigned*>(base + ops + L.part);
     HIPCHK(hp::zero_u32(split_cnt, slots, s));
@@ -920,7 +1008,7 @@ int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* 
         HIPCHK(hp::set_identity(static_cast<double*>(B), ldb, K, N, s));
     } else {
         HIPCHK(hipMemsetAsync(A, 0, esz * (size_t)(M * lda), s));
-        HIPCHK(hipMemsetAsync(B, 0, esz * (size_t)(K * ldb), s));
+        HIPCHK(hipMemsetAsync(B, 0, esz * (size_t)((h16 ? N : K) * ldb), s));
     }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -937,6 +1025,10 @@ int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* 
                 return hp::gemm((hp::GemmTile)t, M, N, K, static_cast<const float*>(A), lda,
                                 static_cast<const float*>(B), ldb,
                                 with_split(hp::epilogue_plain(static_cast<float*>(C), ldc)), s);
+            if (h16)
+                return hp::gemm_h16((hp::GemmTile)t, dtype == HP_DTYPE_BF16 ? hp::LOWP_BF16 : hp::LOWP_F16,
+                                    M, N, K, A, lda, B, ldb,
+                                    hp::epilogue_plain(static_cast<float*>(C), ldc), s);
             return hp::gemm_lowp((hp::GemmTile)t, dtype == HP_DTYPE_BF16_F32 ? hp::LOWP_BF16 : hp::LOWP_F16,
                                  M, N, K, static_cast<const float*>(A), lda,
                                  static_cast<const float*>(B), ldb,
@@ -982,7 +1074,7 @@ int hp_tune_import(hp_handle* h, const int64_t* rows, int count) {
     if (!h || count < 0 || (count > 0 && !rows)) return HP_EINVAL;
     for (int i = 0; i < count; ++i) {
         const int64_t* r = rows + 5 * i;
-        if (r[0] < HP_DTYPE_F64 || r[0] > HP_DTYPE_F16_F32 || r[4] < 0 || r[4] >= hp::TILE_COUNT)
+        if (r[0] < HP_DTYPE_F64 || r[0] > HP_DTYPE_F16 || r[4] < 0 || r[4] >= hp::TILE_COUNT)
             return HP_EINVAL;
         h->tuned[{r[0], r[1], r[2], r[3]}] = (int)r[4];
     }

@@ -678,6 +678,213 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_lp(
     }
 }
 
+// ---------------------------------------------------------------------------
+// 16-bit operands held in memory: A (M x K) and Bt = B^T (N x K), both
+// row-major and so both k-contiguous, the layout a lane's fragment of
+// v_mfma_f32_16x16x32_{bf16,f16} wants (8 consecutive k of one row of A or
+// one column of B). Tiles are copied to LDS as read, 16 bytes at a time, with
+// no conversion; a fragment is one 16-byte LDS read. FP32 accumulation and
+// the FP32 epilogue of k_gemm_lp, which can also write the outputs rounded
+// to 16 bits (nearest even), row-major and transposed, for later products.
+// ---------------------------------------------------------------------------
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int BK, int WM, int WN>
+struct CfgH {
+    static constexpr int WAVES = (BM / WM) * (BN / WN);
+    static constexpr int NT = 64 * WAVES;
+    static constexpr int KP = BK + 8;      // LDS row pitch (16-bit elements)
+    static constexpr int TPR = BK / 8;     // 16-byte loads per tile row
+    static constexpr int RPP = NT / TPR;   // tile rows per pass
+    static constexpr int A_PASS = BM / RPP, B_PASS = BN / RPP;
+    static constexpr int TI = WM / 16, TJ = WN / 16;
+    static_assert(BK % 32 == 0 && NT % TPR == 0, "K tile");
+    static_assert(BM % RPP == 0 && BN % RPP == 0 && A_PASS >= 1 && B_PASS >= 1, "loads");
+    static_assert(BM % WM == 0 && BN % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "waves");
+};
+
+template <typename L, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_h16(
+    int M, int N, int K, const L* __restrict__ A, int64_t lda, const L* __restrict__ Bt,
+    int64_t ldbt, EpilogueT<float> ep, int tiles_m, int tiles_n) {
+    using C = CfgH<BM, BN, BK, WM, WN>;
+    using FR = typename Mfma16<L>::frag_t;
+    __shared__ __attribute__((aligned(16))) L As[2][BM][C::KP];
+    __shared__ __attribute__((aligned(16))) L Bs[2][BN][C::KP];
+    __shared__ double red[2][C::WAVES];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int tm, tn;
+    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    const int bm = tm * BM, bn = tn * BN;
+    const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
+
+    // Branch-free staging: every 16-byte load comes from an address inside
+    // the operand (rows or k beyond the edge read element 0 instead) and the
+    // out-of-range 16-bit elements are zeroed on their way to LDS.
+    const int kc = 8 * (tid % C::TPR), r0 = tid / C::TPR;
+    u32x4 ra[C::A_PASS], rb[C::B_PASS];
+    const L* a_ptr[C::A_PASS];
+    const L* b_ptr[C::B_PASS];
+    bool a_ok[C::A_PASS], b_ok[C::B_PASS];
+#pragma unroll
+    for (int p = 0; p < C::A_PASS; ++p) {
+        const int row = bm + r0 + C::RPP * p;
+        a_ok[p] = row < M;
+        a_ptr[p] = A + (int64_t)(a_ok[p] ? row : 0) * lda + kc;
+    }
+#pragma unroll
+    for (int p = 0; p < C::B_PASS; ++p) {
+        const int row = bn + r0 + C::RPP * p;
+        b_ok[p] = row < N;
+        b_ptr[p] = Bt + (int64_t)(b_ok[p] ? row : 0) * ldbt + kc;
+    }
+    auto load = [&](int k0) {
+        const bool kin = k0 + kc < K;
+#pragma unroll
+        for (int p = 0; p < C::A_PASS; ++p)
+            ra[p] = *reinterpret_cast<const u32x4*>((a_ok[p] && kin) ? a_ptr[p] + k0 : A);
+#pragma unroll
+        for (int p = 0; p < C::B_PASS; ++p)
+            rb[p] = *reinterpret_cast<const u32x4*>((b_ok[p] && kin) ? b_ptr[p] + k0 : Bt);
+    };
+    // keep the first `rem` 16-bit elements of v (all if rem >= 8)
+    auto keep = [](u32x4 v, int rem) {
+        if (rem >= 8) return v;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const unsigned lo = 2 * w < rem ? 0xFFFFu : 0u;
+            const unsigned hi = 2 * w + 1 < rem ? 0xFFFF0000u : 0u;
+            v[w] &= (lo | hi);
+        }
+        return v;
+    };
+    auto store = [&](int buf, int k0) {
+        const int rem = K - (k0 + kc);
+#pragma unroll
+        for (int p = 0; p < C::A_PASS; ++p)
+            *reinterpret_cast<u32x4*>(&As[buf][r0 + C::RPP * p][kc]) =
+                a_ok[p] ? keep(ra[p], rem) : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int p = 0; p < C::B_PASS; ++p)
+            *reinterpret_cast<u32x4*>(&Bs[buf][r0 + C::RPP * p][kc]) =
+                b_ok[p] ? keep(rb[p], rem) : u32x4{0u, 0u, 0u, 0u};
+    };
+
+    flt4 acc[C::TI][C::TJ];
+#pragma unroll
+    for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TJ; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    const int fr = lane & 15, fg = lane >> 4;
+    const int nk = (K + BK - 1) / BK;
+    load(0);
+    store(0, 0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 32) {
+            FR a[C::TI], b[C::TJ];
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i)
+                a[i] = *reinterpret_cast<const FR*>(&As[cur][wm + i * 16 + fr][ks + 8 * fg]);
+#pragma unroll
+            for (int j = 0; j < C::TJ; ++j)
+                b[j] = *reinterpret_cast<const FR*>(&Bs[cur][wn + j * 16 + fr][ks + 8 * fg]);
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < C::TJ; ++j) acc[i][j] = Mfma16<L>::mma(a[i], b[j], acc[i][j]);
+            // one k-step's fragments live at a time (large wave tiles would
+            // otherwise run out of registers)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (kt + 1 < nk) store(cur ^ 1, (kt + 1) * BK);
+        __syncthreads();
+    }
+
+    // ---- epilogue (accumulator register r of lane l: row 4(l/16) + r) ----
+    double s_diff = 0.0, s_ref = 0.0;
+#pragma unroll
+    for (int i = 0; i < C::TI; ++i) {
+#pragma unroll
+        for (int j = 0; j < C::TJ; ++j) {
+            const int row0 = bm + wm + i * 16 + 4 * fg;
+            const int col = bn + wn + j * 16 + fr;
+            float vo[3][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + r;
+                if (row < M && col < N) {
+                    const float a = acc[i][j][r];
+                    const float d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : 0.f;
+                    const float d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : 0.f;
+                    const float idv = (row == col) ? 1.f : 0.f;
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) {
+                        vo[o][r] = 0.f;
+                        if (ep.out[o]) {
+                            float v = (float)ep.acc_c[o] * a;
+                            if (ep.id[o] != 0.0) v += (float)ep.id[o] * idv;
+                            if (ep.g1[o] != 0.0) v += (float)ep.g1[o] * d1;
+                            if (ep.g2[o] != 0.0) v += (float)ep.g2[o] * d2;
+                            vo[o][r] = v;
+                            if (!ep.skip32[o]) ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
+                            if (ep.h[o]) static_cast<L*>(ep.h[o])[(int64_t)row * ep.ldh[o] + col] = (L)v;
+                            if (o == 0 && ep.ref) {
+                                const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];
+                                const double df = (double)v - x0;
+                                s_diff += df * df;
+                                s_ref += x0 * x0;
+                            }
+                        }
+                    }
+                }
+            }
+            // transposed copies: the lane's 4 rows are 4 consecutive elements
+            // of column `col` of the output, i.e. of row `col` of its transpose
+            if (col < N) {
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    if (!ep.out[o] || !ep.ht[o]) continue;
+                    L* dst = static_cast<L*>(ep.ht[o]) + (int64_t)col * ep.ldht[o] + row0;
+                    if (row0 + 3 < M) {
+                        typedef L l4 __attribute__((ext_vector_type(4)));
+                        *reinterpret_cast<l4*>(dst) = l4{(L)vo[o][0], (L)vo[o][1], (L)vo[o][2], (L)vo[o][3]};
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (row0 + r < M) dst[r] = (L)vo[o][r];
+                    }
+                }
+            }
+        }
+    }
+    if (ep.ref) {
+        const double sd = wave_sum(s_diff), sr = wave_sum(s_ref);
+        if (lane == 0) {
+            red[0][wave] = sd;
+            red[1][wave] = sr;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < C::WAVES; ++w) {
+                a += red[0][w];
+                b += red[1][w];
+            }
+            ep.partials[2 * blockIdx.x] = a;
+            ep.partials[2 * blockIdx.x + 1] = b;
+        }
+    }
+}
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1>
@@ -732,6 +939,8 @@ constexpr TileShape kShapes[] = {
     {128, 128},  // TILE_128x128_W8_S2: K split over 2 blocks
     {128, 128},  // TILE_128x128_W8_S4: K split over 4 blocks
     {128, 128},  // TILE_128x128_W16_K2_P2: 16 waves, double K-tile, two ahead
+    {256, 256},  // TILE_256x256_W8 (16-bit-operand kernel)
+    {256, 256},  // TILE_256x256_W16 (16-bit-operand kernel)
 };
 static_assert(sizeof(kShapes) / sizeof(kShapes[0]) == TILE_COUNT, "tile table");
 
@@ -792,6 +1001,32 @@ hipError_t dispatch_lp(GemmTile t, int64_t M, int64_t N, int64_t K, const float*
     }
 }
 
+template <typename L, int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_h16(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* Bt,
+                      int64_t ldbt, const EpilogueT<float>& ep, hipStream_t s) {
+    using C = CfgH<BM, BN, BK, WM, WN>;
+    const int tm = (int)cdiv(M, BM), tn = (int)cdiv(N, BN);
+    hipLaunchKernelGGL((k_gemm_h16<L, BM, BN, BK, WM, WN>), dim3(tm * tn), dim3(C::NT), 0, s,
+                       (int)M, (int)N, (int)K, static_cast<const L*>(A), lda,
+                       static_cast<const L*>(Bt), ldbt, ep, tm, tn);
+    return hipGetLastError();
+}
+
+template <typename L>
+hipError_t dispatch_h16(GemmTile t, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+                        const void* Bt, int64_t ldbt, const EpilogueT<float>& ep, hipStream_t s) {
+    switch (t) {
+        case TILE_64x64_W4: return launch_h16<L, 64, 64, 64, 32, 32>(M, N, K, A, lda, Bt, ldbt, ep, s);
+        case TILE_128x64_W4: return launch_h16<L, 128, 64, 64, 64, 32>(M, N, K, A, lda, Bt, ldbt, ep, s);
+        case TILE_128x128_W4: return launch_h16<L, 128, 128, 64, 64, 64>(M, N, K, A, lda, Bt, ldbt, ep, s);
+        case TILE_256x128_W8: return launch_h16<L, 256, 128, 64, 64, 64>(M, N, K, A, lda, Bt, ldbt, ep, s);
+        case TILE_256x256_W8: return launch_h16<L, 256, 256, 32, 128, 64>(M, N, K, A, lda, Bt, ldbt, ep, s);
+        case TILE_256x256_W16: return launch_h16<L, 256, 256, 32, 64, 64>(M, N, K, A, lda, Bt, ldbt, ep, s);
+        case TILE_128x128_W16: return launch_h16<L, 128, 128, 64, 32, 32>(M, N, K, A, lda, Bt, ldbt, ep, s);
+        default: return launch_h16<L, 128, 128, 64, 64, 32>(M, N, K, A, lda, Bt, ldbt, ep, s);
+    }
+}
+
 }  // namespace
 
 int grouped_tile_m() { return 64; }
@@ -818,6 +1053,13 @@ hipError_t gemm_lowp(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, co
     return dispatch_lp<_Float16>(t, M, N, K, A, lda, B, ldb, ep, s);
 }
 
+hipError_t gemm_h16(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, const void* A,
+                    int64_t lda, const void* Bt, int64_t ldbt, const EpilogueT<float>& ep,
+                    hipStream_t s) {
+    if (lp == LOWP_BF16) return dispatch_h16<__bf16>(t, M, N, K, A, lda, Bt, ldbt, ep, s);
+    return dispatch_h16<_Float16>(t, M, N, K, A, lda, Bt, ldbt, ep, s);
+}
+
 int gemm_blocks(GemmTile t, int64_t M, int64_t N) {
     const TileShape sh = kShapes[(int)t];
     return (int)(cdiv(M, sh.bm) * cdiv(N, sh.bn));
@@ -841,6 +1083,11 @@ GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow
     // and 27.7 on 64x64 tiles); short K or the FP32 1536^2 case favour 64x64
     // tiles. The 16-bit kernel does not split.
     const int64_t tiles = cdiv(M, 128) * cdiv(N, 128);
+    if (gt == GT_H16) {
+        if (cdiv(M, 256) * cdiv(N, 256) >= 256) return TILE_256x256_W8;
+        if (tiles >= 64) return TILE_128x128_W8;
+        return TILE_64x64_W4;
+    }
     if (gt == GT_LOWP) {
         if (tiles >= 512) return TILE_128x128_W8;
         if (tiles >= 64) return TILE_128x128_W16_P2;
@@ -864,7 +1111,7 @@ static bool split_fits(int64_t M, int64_t N, int64_t K, int bk, int64_t slots) {
 }
 
 bool gemm_split_runs(GemmTile t, int64_t M, int64_t N, int64_t K, GemmType gt, int64_t slots) {
-    if (gt == GT_LOWP) return false;
+    if (gt == GT_LOWP || gt == GT_H16) return false;
     const int bk = gt == GT_F64 ? 16 : 32;  // BKF of the element type
     if (t == TILE_128x128_W8_S2) return split_fits<2>(M, N, K, bk, slots);
     if (t == TILE_128x128_W8_S4) return split_fits<4>(M, N, K, bk, slots);

@@ -38,7 +38,10 @@ struct hp_handle {
 namespace hp {
 
 inline GemmType gemm_type(int dtype) {
-    return dtype == HP_DTYPE_F64 ? GT_F64 : dtype == HP_DTYPE_F32 ? GT_F32 : GT_LOWP;
+    if (dtype == HP_DTYPE_F64) return GT_F64;
+    if (dtype == HP_DTYPE_F32) return GT_F32;
+    if (dtype == HP_DTYPE_BF16 || dtype == HP_DTYPE_F16) return GT_H16;
+    return GT_LOWP;
 }
 
 // The tile a product of this dtype (HP_DTYPE_*) and shape runs on: the
@@ -82,6 +85,11 @@ struct Plan {
     int64_t ldA32 = 0, ldX32 = 0, ldS32 = 0;
     int nX64 = 0, nS64 = 0, nX32 = 0, nS32 = 0;
     bool has32 = false;
+    // HP_PREC_MIXED: 16-bit copies of the FP32 set for the first stage's
+    // products, each matrix row-major and transposed (k-contiguous operands)
+    bool has16 = false;
+    int64_t ldA16 = 0, ldAt16 = 0, ldX16 = 0, ldXt16 = 0, ldS16 = 0;
+    size_t offA16 = 0, offAt16 = 0, offX16[3] = {}, offXt16[3] = {}, offS16[7] = {}, offSt16[7] = {};
     size_t offA = 0, offX[3] = {}, offS[7] = {};
     size_t offA32 = 0, offX32[3] = {}, offS32[7] = {};
     bool has_proj = false;      // A^T (n x m) and X^T (m x n) for the projection
@@ -109,9 +117,29 @@ struct Set {
     int64_t ldA = 0, ldX = 0, ldS = 0;
 };
 
+// The 16-bit copies of one FP32 matrix: row-major (ld) and transposed (ldt).
+struct Copy16 {
+    void* h = nullptr;
+    int64_t ld = 0;
+    void* ht = nullptr;
+    int64_t ldt = 0;
+};
+
 struct Buffers {
     Set<double> b64;
     Set<float> b32;
+    // copies of b32.A, b32.X[i], b32.S[i] (HP_PREC_MIXED only)
+    Copy16 A16, X16[3], S16[7];
+    // the copies of an FP32 set matrix (given by its base pointer), or null
+    const Copy16* copy16(const float* p) const {
+        if (!A16.h) return nullptr;
+        if (p == b32.A) return &A16;
+        for (int i = 0; i < 3; ++i)
+            if (p == b32.X[i]) return &X16[i];
+        for (int i = 0; i < 7; ++i)
+            if (p == b32.S[i]) return &S16[i];
+        return nullptr;
+    }
     double* At = nullptr;  // n x m, ld b64.ldX
     double* Xt = nullptr;  // m x n, ld b64.ldA
     double* small = nullptr;
@@ -131,6 +159,39 @@ struct GemmCall {
     int64_t ldb;
     EpilogueT<T> ep;
 };
+
+// Which copies of its outputs a product of the 16-bit stage must leave: the
+// row-major 16-bit copy where a later product of the loop reads the matrix as
+// its left operand, the transposed copy where one reads it as its right
+// operand, and the FP32 value where an epilogue or the stopping test reads it
+// (or it is an iterate or R, which the next stage and the projection test
+// read). Uses end where a later product writes the same buffer again.
+struct CopyUse {
+    bool row[3] = {}, t[3] = {}, f32[3] = {};
+};
+template <typename T>
+void copy_uses(const GemmCall<T>* c, int nc, const Set<T>& b, CopyUse* u) {
+    for (int i = 0; i < nc; ++i) {
+        u[i] = CopyUse{};
+        for (int o = 0; o < 3; ++o) {
+            const T* P = c[i].ep.out[o];
+            if (!P) continue;
+            bool iterate = P == b.S[0];
+            for (int x = 0; x < 3; ++x) iterate = iterate || P == b.X[x];
+            if (iterate) {
+                u[i].row[o] = u[i].t[o] = u[i].f32[o] = true;
+                continue;
+            }
+            for (int j = i + 1; j < nc; ++j) {
+                const EpilogueT<T>& e = c[j].ep;
+                if (c[j].A == P) u[i].row[o] = true;
+                if (c[j].B == P) u[i].t[o] = true;
+                if (e.D1 == P || e.D2 == P || e.ref == P) u[i].f32[o] = true;
+                if (e.out[0] == P || e.out[1] == P || e.out[2] == P) break;
+            }
+        }
+    }
+}
 
 // Most products a loop can take (HM: 9, plus 2 for the stabilising product).
 constexpr int kMaxLoopGemms = 11;

@@ -50,6 +50,16 @@ struct EpilogueT {
     T* split_part;
     unsigned* split_cnt;
     int64_t split_slots;
+    // 16-bit copies of the outputs, written by the 16-bit-operand kernel only
+    // (gemm_h16) in its own operand type: h[o] row-major (ld ldh[o]) and ht[o]
+    // transposed (ld ldht[o]); either may be null.
+    void* h[3];
+    int64_t ldh[3];
+    void* ht[3];
+    int64_t ldht[3];
+    // gemm_h16 only: nonzero skips the FP32 store of output o (when only its
+    // 16-bit copies are read later); the stopping sums still use the value
+    int skip32[3];
 };
 using Epilogue = EpilogueT<double>;
 
@@ -79,7 +89,9 @@ enum GemmTile : int {
     TILE_128x128_W8_S2 = 11,  // TILE_128x128_W8 with K split over 2 blocks per tile
     TILE_128x128_W8_S4 = 12,  // TILE_128x128_W8 with K split over 4 blocks per tile
     TILE_128x128_W16_K2_P2 = 13,  // TILE_128x128_W16_P2 with a K-tile twice as deep
-    TILE_COUNT = 14
+    TILE_256x256_W8 = 14,   // 16-bit-operand kernel only: 8 waves, 128x64 each
+    TILE_256x256_W16 = 15,  // 16-bit-operand kernel only: 16 waves, 64x64 each
+    TILE_COUNT = 16
 };
 
 // Blocks (and partial-sum pairs) a launch with this tile uses for M x N.
@@ -88,7 +100,7 @@ int gemm_blocks(GemmTile t, int64_t M, int64_t N);
 int gemm_max_blocks(int64_t M, int64_t N);
 // Tile choice for an M x N x K product of element type `gt`.
 // With allow_split false the choice is among the unsplit tiles.
-enum GemmType : int { GT_F64 = 0, GT_F32 = 1, GT_LOWP = 2 };
+enum GemmType : int { GT_F64 = 0, GT_F32 = 1, GT_LOWP = 2, GT_H16 = 3 };
 GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow_split = true);
 // Whether split tile t runs split for this product given `slots` partial
 // tiles of scratch (it runs unsplit otherwise).
@@ -137,6 +149,18 @@ enum LowPrec : int { LOWP_BF16 = 0, LOWP_F16 = 1 };
 hipError_t gemm_lowp(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, const float* A,
                      int64_t lda, const float* B, int64_t ldb, const EpilogueT<float>& ep,
                      hipStream_t s);
+
+// Product of 16-bit operands (type `lp`) held in memory: A M x K row-major,
+// Bt = B^T N x K row-major (both k-contiguous; lda, ldbt multiples of 8
+// elements, 16-byte aligned), v_mfma_f32_16x16x32 with FP32 accumulation;
+// C = epilogue(A B) in FP32, plus the 16-bit copies ep.h / ep.ht if set.
+hipError_t gemm_h16(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, const void* A,
+                    int64_t lda, const void* Bt, int64_t ldbt, const EpilogueT<float>& ep,
+                    hipStream_t s);
+// H = X rounded to 16 bits (row-major, ld ldh) and/or Ht = X^T rounded (ld
+// ldht), X M x N FP32; either output may be null.
+hipError_t convert_h16(const float* X, int64_t ldx, int64_t M, int64_t N, LowPrec lp, void* H,
+                       int64_t ldh, void* Ht, int64_t ldht, hipStream_t s);
 
 // ||A||_1 and ||A||_inf of an M x N matrix, then scal[SLOT_ALPHA] =
 // 1/(||A||_1 ||A||_inf). `tmp` needs (ceil(M/256)+1)*N + M doubles.

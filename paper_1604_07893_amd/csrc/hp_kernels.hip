@@ -94,6 +94,33 @@ __global__ __launch_bounds__(kThreads) void k_alpha_norm1inf(const double* __res
     }
 }
 
+// H = X and Ht = X^T rounded to 16 bits (nearest even), through a 32x32 LDS
+// tile so that both the reads and the transposed writes run along rows.
+template <typename L>
+__global__ __launch_bounds__(kThreads) void k_convert_h16(const float* __restrict__ X, int64_t ldx,
+                                                          int M, int N, L* __restrict__ H,
+                                                          int64_t ldh, L* __restrict__ Ht,
+                                                          int64_t ldht) {
+    __shared__ float tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += kThreads / 32) {
+        const int row = by + r, col = bx + tx;
+        float v = 0.f;
+        if (row < M && col < N) {
+            v = X[(int64_t)row * ldx + col];
+            if (H) H[(int64_t)row * ldh + col] = (L)v;
+        }
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    if (!Ht) return;
+    for (int r = ty; r < 32; r += kThreads / 32) {
+        const int col = bx + r, row = by + tx;
+        if (col < N && row < M) Ht[(int64_t)col * ldht + row] = (L)tile[tx][r];
+    }
+}
+
 // ---- power iteration on A^T A for sigma_max(A)^2 ----
 // y = A v: one wave per row, lanes striding along the row.
 __global__ __launch_bounds__(kThreads) void k_gemv_rows(const double* __restrict__ A, int64_t lda,
@@ -400,6 +427,23 @@ hipError_t alpha_norm1inf(const double* A, int64_t lda, int64_t M, int64_t N, do
     hipLaunchKernelGGL(k_alpha_norm1inf, dim3(1), dim3(kThreads), 0, s, part, nchunk, (int)N, rows,
                        (int)M, scal);
     return hipGetLastError();
+}
+
+template <typename L>
+hipError_t convert_h16_t(const float* X, int64_t ldx, int64_t M, int64_t N, L* H, int64_t ldh,
+                         L* Ht, int64_t ldht, hipStream_t s) {
+    hipLaunchKernelGGL(k_convert_h16<L>, dim3((unsigned)cdiv(N, 32), (unsigned)cdiv(M, 32)),
+                       dim3(kThreads), 0, s, X, ldx, (int)M, (int)N, H, ldh, Ht, ldht);
+    return hipGetLastError();
+}
+
+hipError_t convert_h16(const float* X, int64_t ldx, int64_t M, int64_t N, LowPrec lp, void* H,
+                       int64_t ldh, void* Ht, int64_t ldht, hipStream_t s) {
+    if (lp == LOWP_BF16)
+        return convert_h16_t<__bf16>(X, ldx, M, N, static_cast<__bf16*>(H), ldh,
+                                     static_cast<__bf16*>(Ht), ldht, s);
+    return convert_h16_t<_Float16>(X, ldx, M, N, static_cast<_Float16*>(H), ldh,
+                                   static_cast<_Float16*>(Ht), ldht, s);
 }
 
 hipError_t alpha_sigma_max2(const double* A, int64_t lda, int64_t M, int64_t N, int iters,

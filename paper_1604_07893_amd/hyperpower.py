@@ -326,6 +326,34 @@ def gemm(A: torch.Tensor, B: torch.Tensor, *, alpha: float = 1.0, beta_identity:
     return out
 
 
+def gemm_bt(A: torch.Tensor, Bt: torch.Tensor, *, alpha: float = 1.0, beta_identity: float = 0.0,
+            out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """C = alpha A B + beta_identity I for 16-bit operands held in memory
+    (HP_DTYPE_BF16 / HP_DTYPE_F16): A (M x K) and Bt = B^T (N x K), both
+    bfloat16 or both float16, row-major with rows of a multiple of 8 elements;
+    C is float32 (M x N)."""
+    code = {torch.bfloat16: 4, torch.float16: 5}.get(A.dtype)
+    if code is None or Bt.dtype != A.dtype:
+        raise ValueError("A and Bt must both be bfloat16 or both float16")
+    for t, nm in ((A, "A"), (Bt, "Bt")):
+        if not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError(f"{nm} must be a row-major device matrix")
+    M, K = A.shape
+    N, K2 = Bt.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    rc = load_library().hp_gemm(handle(dev).ptr, code, M, N, K, alpha, A.data_ptr(), A.stride(0),
+                                Bt.data_ptr(), Bt.stride(0), beta_identity, out.data_ptr(),
+                                out.stride(0), s.cuda_stream)
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_gemm")
+    return out
+
+
 def _problem(A: torch.Tensor, X: torch.Tensor, X0: torch.Tensor | None = None) -> HpProblem:
     _check_matrix(A, "A")
     _check_matrix(X, "X")
@@ -428,7 +456,7 @@ class Server:
             pass
 
 
-GEMM_DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+GEMM_DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16s": 4, "f16s": 5}
 
 
 def autotune(shapes, dtype: str = "f64", reps: int = 3, device: int | None = None) -> list:

@@ -221,3 +221,42 @@ def test_two_way_split_from_tuning_table(tmp_path):
     ref = A @ B
     bound = (np.abs(A) @ np.abs(B)) * (2 * K + 8) * U64
     assert np.all(np.abs(C1.cpu().numpy() - ref) <= bound)
+
+
+def _h16(a, dt, pad=8):
+    r, c = a.shape
+    buf = torch.zeros((r, (c + pad - 1) // pad * pad), dtype=dt, device="cuda:0")
+    buf[:, :c] = torch.from_numpy(a).to(dt).cuda()
+    return buf[:, :c]
+
+
+@pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16])
+@pytest.mark.parametrize("M,N,K,tile", [(16, 16, 32, None), (127, 129, 17, None), (333, 444, 555, None),
+                                        (1024, 1024, 1024, None), (600, 520, 200, 14),
+                                        (530, 610, 300, 15), (700, 300, 100, 4), (300, 700, 90, 2)])
+def test_gemm_16bit_operands_in_memory(dt, M, N, K, tile, tmp_path):
+    """HP_DTYPE_BF16 / HP_DTYPE_F16: A and B^T held in 16 bits, FP32
+    accumulation: compare with the FP64 product of the same 16-bit values
+    (every tile configuration of the kernel, ragged shapes)."""
+    import json
+    hpw = need_gpu()
+    say(f"gemm h16 {dt} M={M} N={N} K={K} tile={tile}")
+    if tile is not None:
+        code = 4 if dt == torch.bfloat16 else 5
+        path = tmp_path / "tune.json"
+        path.write_text(json.dumps({"rows": [[code, M, N, K, tile]]}))
+        hpw.load_tuning(str(path))
+    rng = np.random.default_rng(M + 3 * N + 5 * K)
+    A = rng.standard_normal((M, K))
+    Bt = rng.standard_normal((N, K))
+    Ad, Btd = _h16(A, dt), _h16(Bt, dt)
+    C = hpw.gemm_bt(Ad, Btd)
+    C2 = hpw.gemm_bt(Ad, Btd)
+    torch.cuda.synchronize()
+    assert torch.equal(C, C2)
+    Ar = Ad.double().cpu().numpy()
+    Br = Btd.double().cpu().numpy().T
+    ref = Ar @ Br
+    bound = (np.abs(Ar) @ np.abs(Br)) * (2 * K + 4) * 2.0**-24
+    err = np.abs(C.cpu().numpy().astype(np.float64) - ref)
+    assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
