@@ -704,6 +704,89 @@ struct CfgH {
     static_assert(BM % WM == 0 && BN % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "waves");
 };
 
+// The FP32 epilogue of the 16-bit-operand kernels (accumulator register r
+// of lane l: row 4(l/16) + r), with the 16-bit copies of the outputs.
+template <typename L, int TI, int TJ, int WAVES>
+__device__ __attribute__((always_inline)) inline void h16_epilogue(
+    flt4 (&acc)[TI][TJ], const EpilogueT<float>& ep, int M, int N,
+                                    int bm, int bn, int wm, int wn, double (*red)[WAVES]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int fr = lane & 15, fg = lane >> 4;
+    double s_diff = 0.0, s_ref = 0.0;
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int row0 = bm + wm + i * 16 + 4 * fg;
+            const int col = bn + wn + j * 16 + fr;
+            float vo[3][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + r;
+                if (row < M && col < N) {
+                    const float a = acc[i][j][r];
+                    const float d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : 0.f;
+                    const float d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : 0.f;
+                    const float idv = (row == col) ? 1.f : 0.f;
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) {
+                        vo[o][r] = 0.f;
+                        if (ep.out[o]) {
+                            float v = (float)ep.acc_c[o] * a;
+                            if (ep.id[o] != 0.0) v += (float)ep.id[o] * idv;
+                            if (ep.g1[o] != 0.0) v += (float)ep.g1[o] * d1;
+                            if (ep.g2[o] != 0.0) v += (float)ep.g2[o] * d2;
+                            vo[o][r] = v;
+                            if (!ep.skip32[o]) ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
+                            if (ep.h[o]) static_cast<L*>(ep.h[o])[(int64_t)row * ep.ldh[o] + col] = (L)v;
+                            if (o == 0 && ep.ref) {
+                                const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];
+                                const double df = (double)v - x0;
+                                s_diff += df * df;
+                                s_ref += x0 * x0;
+                            }
+                        }
+                    }
+                }
+            }
+            // transposed copies: the lane's 4 rows are 4 consecutive elements
+            // of column `col` of the output, i.e. of row `col` of its transpose
+            if (col < N) {
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    if (!ep.out[o] || !ep.ht[o]) continue;
+                    L* dst = static_cast<L*>(ep.ht[o]) + (int64_t)col * ep.ldht[o] + row0;
+                    if (row0 + 3 < M) {
+                        typedef L l4 __attribute__((ext_vector_type(4)));
+                        *reinterpret_cast<l4*>(dst) = l4{(L)vo[o][0], (L)vo[o][1], (L)vo[o][2], (L)vo[o][3]};
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (row0 + r < M) dst[r] = (L)vo[o][r];
+                    }
+                }
+            }
+        }
+    }
+    if (ep.ref) {
+        const double sd = wave_sum(s_diff), sr = wave_sum(s_ref);
+        if (lane == 0) {
+            red[0][wave] = sd;
+            red[1][wave] = sr;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < WAVES; ++w) {
+                a += red[0][w];
+                b += red[1][w];
+            }
+            ep.partials[2 * blockIdx.x] = a;
+            ep.partials[2 * blockIdx.x + 1] = b;
+        }
+    }
+}
+
 template <typename L, int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_h16(
     int M, int N, int K, const L* __restrict__ A, int64_t lda, const L* __restrict__ Bt,
@@ -808,81 +891,151 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_h16(
         if (kt + 1 < nk) store(cur ^ 1, (kt + 1) * BK);
         __syncthreads();
     }
+    h16_epilogue<L, C::TI, C::TJ, C::WAVES>(acc, ep, M, N, bm, bn, wm, wn, red);
+}
 
-    // ---- epilogue (accumulator register r of lane l: row 4(l/16) + r) ----
-    double s_diff = 0.0, s_ref = 0.0;
+// The same product with the tiles brought into LDS by the load-to-LDS
+// instruction (global_load_lds_dwordx4): no staging registers and no LDS
+// store instructions. A wave's instruction fills 1 KB of LDS, 16 bytes per
+// lane in lane order, i.e. 8 unpadded rows of a 64-wide K-tile; each lane
+// picks its source chunk as (LDS slot) XOR (row mod 8), so that the 16 lanes
+// of a fragment read (16 rows, one 16-byte chunk) spread over the banks.
+// Needs K to be a multiple of BK = 64 (no masking); rows beyond M (N) read
+// the last row and only feed outputs that are never stored. Two LDS stages:
+// tile t+1 streams in while tile t is multiplied.
+template <typename L, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_h16_dma(
+    int M, int N, int K, const L* __restrict__ A, int64_t lda, const L* __restrict__ Bt,
+    int64_t ldbt, EpilogueT<float> ep, int tiles_m, int tiles_n) {
+    constexpr int BK = 64;
+    constexpr int WAVES = (BM / WM) * (BN / WN);
+    constexpr int TI = WM / 16, TJ = WN / 16;
+    constexpr int A_INS = BM / 8 / WAVES, B_INS = BN / 8 / WAVES;  // 8 rows per wave instruction
+    static_assert(A_INS * 8 * WAVES == BM && B_INS * 8 * WAVES == BN, "DMA rows");
+    // With two waves per SIMD (room for 256 registers) a wave reads the whole
+    // K-tile's fragments before it issues the next tile's loads, so that its
+    // MFMAs run while those loads are in flight (the compiler makes any LDS
+    // read that follows a load-to-LDS wait for it).
+    constexpr bool EARLY = WAVES <= 8 && TI * TJ * 4 + 2 * (TI + TJ) * 4 <= 224;
+    using FR = typename Mfma16<L>::frag_t;
+    __shared__ __attribute__((aligned(16))) L As[2][BM * BK];
+    __shared__ __attribute__((aligned(16))) L Bs[2][BN * BK];
+    __shared__ double red[2][WAVES];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int tm, tn;
+    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    const int bm = tm * BM, bn = tn * BN;
+    const int wm = (wave / (BN / WN)) * WM, wn = (wave % (BN / WN)) * WN;
+
+    // this lane's source in each of the wave's instructions: tile row
+    // 8*q + lane/8 (clamped into the operand), chunk (lane%8) ^ (row%8)
+    const int lrow = lane >> 3, slot = lane & 7;
+    const L* a_src[A_INS];
+    const L* b_src[B_INS];
 #pragma unroll
-    for (int i = 0; i < C::TI; ++i) {
-#pragma unroll
-        for (int j = 0; j < C::TJ; ++j) {
-            const int row0 = bm + wm + i * 16 + 4 * fg;
-            const int col = bn + wn + j * 16 + fr;
-            float vo[3][4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = row0 + r;
-                if (row < M && col < N) {
-                    const float a = acc[i][j][r];
-                    const float d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : 0.f;
-                    const float d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : 0.f;
-                    const float idv = (row == col) ? 1.f : 0.f;
-#pragma unroll
-                    for (int o = 0; o < 3; ++o) {
-                        vo[o][r] = 0.f;
-                        if (ep.out[o]) {
-                            float v = (float)ep.acc_c[o] * a;
-                            if (ep.id[o] != 0.0) v += (float)ep.id[o] * idv;
-                            if (ep.g1[o] != 0.0) v += (float)ep.g1[o] * d1;
-                            if (ep.g2[o] != 0.0) v += (float)ep.g2[o] * d2;
-                            vo[o][r] = v;
-                            if (!ep.skip32[o]) ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
-                            if (ep.h[o]) static_cast<L*>(ep.h[o])[(int64_t)row * ep.ldh[o] + col] = (L)v;
-                            if (o == 0 && ep.ref) {
-                                const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];
-                                const double df = (double)v - x0;
-                                s_diff += df * df;
-                                s_ref += x0 * x0;
-                            }
-                        }
-                    }
-                }
-            }
-            // transposed copies: the lane's 4 rows are 4 consecutive elements
-            // of column `col` of the output, i.e. of row `col` of its transpose
-            if (col < N) {
-#pragma unroll
-                for (int o = 0; o < 3; ++o) {
-                    if (!ep.out[o] || !ep.ht[o]) continue;
-                    L* dst = static_cast<L*>(ep.ht[o]) + (int64_t)col * ep.ldht[o] + row0;
-                    if (row0 + 3 < M) {
-                        typedef L l4 __attribute__((ext_vector_type(4)));
-                        *reinterpret_cast<l4*>(dst) = l4{(L)vo[o][0], (L)vo[o][1], (L)vo[o][2], (L)vo[o][3]};
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (row0 + r < M) dst[r] = (L)vo[o][r];
-                    }
-                }
-            }
-        }
+    for (int i = 0; i < A_INS; ++i) {
+        const int tr = 8 * (wave + WAVES * i) + lrow;
+        a_src[i] = A + (int64_t)min(bm + tr, M - 1) * lda + 8 * (slot ^ (tr & 7));
     }
-    if (ep.ref) {
-        const double sd = wave_sum(s_diff), sr = wave_sum(s_ref);
-        if (lane == 0) {
-            red[0][wave] = sd;
-            red[1][wave] = sr;
+#pragma unroll
+    for (int i = 0; i < B_INS; ++i) {
+        const int tr = 8 * (wave + WAVES * i) + lrow;
+        b_src[i] = Bt + (int64_t)min(bn + tr, N - 1) * ldbt + 8 * (slot ^ (tr & 7));
+    }
+    // (the builtin takes an LDS address-space pointer, which exists only in
+    // the device compilation; the host pass sees an empty body)
+    auto issue = [&](int buf, int k0) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+        for (int i = 0; i < A_INS; ++i)
+            __builtin_amdgcn_global_load_lds(a_src[i] + k0, &As[buf][8 * (wave + WAVES * i) * BK], 16, 0, 0);
+#pragma unroll
+        for (int i = 0; i < B_INS; ++i)
+            __builtin_amdgcn_global_load_lds(b_src[i] + k0, &Bs[buf][8 * (wave + WAVES * i) * BK], 16, 0, 0);
+#else
+        (void)buf;
+        (void)k0;
+#endif
+    };
+
+    flt4 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    const int fr = lane & 15, fg = lane >> 4;
+    // fragments of k-step q (32 k) of the tile in stage `buf`
+    auto frags = [&](int buf, int q, FR (&a)[TI], FR (&b)[TJ]) {
+        const int c = 4 * q + fg;  // this lane's 16-byte chunk of the row
+#pragma unroll
+        for (int i = 0; i < TI; ++i) {
+            const int r = wm + i * 16 + fr;
+            a[i] = *reinterpret_cast<const FR*>(&As[buf][r * BK + 8 * (c ^ (r & 7))]);
         }
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int r = wn + j * 16 + fr;
+            b[j] = *reinterpret_cast<const FR*>(&Bs[buf][r * BK + 8 * (c ^ (r & 7))]);
+        }
+    };
+    auto mma = [&](FR (&a)[TI], FR (&b)[TJ]) {
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) acc[i][j] = Mfma16<L>::mma(a[i], b[j], acc[i][j]);
+    };
+
+    const int nk = K / BK;
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if constexpr (EARLY) {
+            FR a0[TI], b0[TJ], a1[TI], b1[TJ];
+            frags(cur, 0, a0, b0);
+            frags(cur, 1, a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
+            if (kt + 1 < nk) issue(cur ^ 1, (kt + 1) * BK);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(a0, b0);
+            mma(a1, b1);
+            // keep the MFMAs above the wait below (they touch no memory, so
+            // the scheduler would otherwise sink them past it)
+            __builtin_amdgcn_sched_barrier(0);
+        } else {
+            if (kt + 1 < nk) issue(cur ^ 1, (kt + 1) * BK);
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 32) {
+                const int c = ks / 8 + fg;
+                FR a[TI], b[TJ];
+#pragma unroll
+                for (int i = 0; i < TI; ++i) {
+                    const int r = wm + i * 16 + fr;
+                    a[i] = *reinterpret_cast<const FR*>(&As[cur][r * BK + 8 * (c ^ (r & 7))]);
+                }
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) {
+                    const int r = wn + j * 16 + fr;
+                    b[j] = *reinterpret_cast<const FR*>(&Bs[cur][r * BK + 8 * (c ^ (r & 7))]);
+                }
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j) acc[i][j] = Mfma16<L>::mma(a[i], b[j], acc[i][j]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // this wave's loads of tile kt+1 have landed; the barrier makes every
+        // wave's loads visible and ends every wave's reads of tile kt
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (tid == 0) {
-            double a = 0.0, b = 0.0;
-            for (int w = 0; w < C::WAVES; ++w) {
-                a += red[0][w];
-                b += red[1][w];
-            }
-            ep.partials[2 * blockIdx.x] = a;
-            ep.partials[2 * blockIdx.x + 1] = b;
-        }
     }
+    h16_epilogue<L, TI, TJ, WAVES>(acc, ep, M, N, bm, bn, wm, wn, red);
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -941,6 +1094,8 @@ constexpr TileShape kShapes[] = {
     {128, 128},  // TILE_128x128_W16_K2_P2: 16 waves, double K-tile, two ahead
     {256, 256},  // TILE_256x256_W8 (16-bit-operand kernel)
     {256, 256},  // TILE_256x256_W16 (16-bit-operand kernel)
+    {256, 256},  // TILE_256x256_W8_DMA (16-bit-operand kernel, load-to-LDS)
+    {256, 256},  // TILE_256x256_W16_DMA (16-bit-operand kernel, load-to-LDS)
 };
 static_assert(sizeof(kShapes) / sizeof(kShapes[0]) == TILE_COUNT, "tile table");
 
@@ -1012,10 +1167,28 @@ hipError_t launch_h16(int64_t M, int64_t N, int64_t K, const void* A, int64_t ld
     return hipGetLastError();
 }
 
+template <typename L, int BM, int BN, int WM, int WN>
+hipError_t launch_h16_dma(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+                          const void* Bt, int64_t ldbt, const EpilogueT<float>& ep, hipStream_t s) {
+    const int tm = (int)cdiv(M, BM), tn = (int)cdiv(N, BN);
+    hipLaunchKernelGGL((k_gemm_h16_dma<L, BM, BN, WM, WN>), dim3(tm * tn),
+                       dim3(64 * (BM / WM) * (BN / WN)), 0, s, (int)M, (int)N, (int)K,
+                       static_cast<const L*>(A), lda, static_cast<const L*>(Bt), ldbt, ep, tm, tn);
+    return hipGetLastError();
+}
+
 template <typename L>
 hipError_t dispatch_h16(GemmTile t, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
                         const void* Bt, int64_t ldbt, const EpilogueT<float>& ep, hipStream_t s) {
+    // the load-to-LDS tiles copy whole 64-wide K-tiles: K a multiple of 64
+    const bool dma = K % 64 == 0;
     switch (t) {
+        case TILE_256x256_W8_DMA:
+            if (dma) return launch_h16_dma<L, 256, 256, 128, 64>(M, N, K, A, lda, Bt, ldbt, ep, s);
+            return launch_h16<L, 256, 256, 32, 128, 64>(M, N, K, A, lda, Bt, ldbt, ep, s);
+        case TILE_256x256_W16_DMA:
+            if (dma) return launch_h16_dma<L, 256, 256, 64, 64>(M, N, K, A, lda, Bt, ldbt, ep, s);
+            return launch_h16<L, 256, 256, 32, 64, 64>(M, N, K, A, lda, Bt, ldbt, ep, s);
         case TILE_64x64_W4: return launch_h16<L, 64, 64, 64, 32, 32>(M, N, K, A, lda, Bt, ldbt, ep, s);
         case TILE_128x64_W4: return launch_h16<L, 128, 64, 64, 64, 32>(M, N, K, A, lda, Bt, ldbt, ep, s);
         case TILE_128x128_W4: return launch_h16<L, 128, 128, 64, 64, 64>(M, N, K, A, lda, Bt, ldbt, ep, s);
@@ -1084,8 +1257,12 @@ GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow
     // tiles. The 16-bit kernel does not split.
     const int64_t tiles = cdiv(M, 128) * cdiv(N, 128);
     if (gt == GT_H16) {
-        if (cdiv(M, 256) * cdiv(N, 256) >= 256) return TILE_256x256_W8;
-        if (tiles >= 64) return TILE_128x128_W8;
+        // 16-bit operands in memory: 256x256 tiles filled by load-to-LDS from
+        // 64 such tiles (8192^3: 886 TFLOP/s on 8 waves reading each K-tile's
+        // fragments before streaming the next; 708 with register staging);
+        // the 16-wave 128x128 tile below (2048^3: 373 TFLOP/s)
+        if (cdiv(M, 256) * cdiv(N, 256) >= 64) return TILE_256x256_W8_DMA;
+        if (tiles >= 64) return TILE_128x128_W16;
         return TILE_64x64_W4;
     }
     if (gt == GT_LOWP) {

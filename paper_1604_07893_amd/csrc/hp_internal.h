@@ -91,7 +91,9 @@ enum GemmTile : int {
     TILE_128x128_W16_K2_P2 = 13,  // TILE_128x128_W16_P2 with a K-tile twice as deep
     TILE_256x256_W8 = 14,   // 16-bit-operand kernel only: 8 waves, 128x64 each
     TILE_256x256_W16 = 15,  // 16-bit-operand kernel only: 16 waves, 64x64 each
-    TILE_COUNT = 16
+    TILE_256x256_W8_DMA = 16,   // TILE_256x256_W8 with load-to-LDS tiles (K % 64 == 0)
+    TILE_256x256_W16_DMA = 17,  // TILE_256x256_W16 with load-to-LDS tiles (K % 64 == 0)
+    TILE_COUNT = 18
 };
 
 // Blocks (and partial-sum pairs) a launch with this tile uses for M x N.

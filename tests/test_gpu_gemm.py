@@ -233,7 +233,9 @@ def _h16(a, dt, pad=8):
 @pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16])
 @pytest.mark.parametrize("M,N,K,tile", [(16, 16, 32, None), (127, 129, 17, None), (333, 444, 555, None),
                                         (1024, 1024, 1024, None), (600, 520, 200, 14),
-                                        (530, 610, 300, 15), (700, 300, 100, 4), (300, 700, 90, 2)])
+                                        (530, 610, 300, 15), (700, 300, 100, 4), (300, 700, 90, 2),
+                                        (600, 520, 256, 16), (530, 610, 320, 17),
+                                        (300, 280, 200, 17)])
 def test_gemm_16bit_operands_in_memory(dt, M, N, K, tile, tmp_path):
     """HP_DTYPE_BF16 / HP_DTYPE_F16: A and B^T held in 16 bits, FP32
     accumulation: compare with the FP64 product of the same 16-bit values
