@@ -119,6 +119,68 @@ struct Cfg {
     static constexpr size_t LDS_BYTES = 2 * ((size_t)BM * LDA_S + (size_t)BK * LDB_S) * sizeof(T);
 };
 
+// The fused epilogue of a BM x BN tile held as TI x TJ MFMA accumulators per
+// wave: up to three outputs id*I + acc_c*acc + g1*D1 + g2*D2 and, with
+// ep.ref, the block's FP64 partial sums of the stopping test in pair `part`.
+template <typename T, int TI, int TJ, int WAVES>
+__device__ __attribute__((always_inline)) inline void tile_epilogue(
+    typename Mfma<T>::acc_t (&acc)[TI][TJ], const EpilogueT<T>& ep, int M, int N, int bm, int bn,
+    int wm, int wn, int part, double (*red)[WAVES]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int fr = lane & 15, fg = lane >> 4;
+    double s_diff = 0.0, s_ref = 0.0;
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = bm + wm + i * 16 + Mfma<T>::row(fg, r);
+                const int col = bn + wn + j * 16 + fr;
+                if (row < M && col < N) {
+                    const T a = acc[i][j][r];
+                    const T d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : T(0);
+                    const T d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : T(0);
+                    const T idv = (row == col) ? T(1) : T(0);
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) {
+                        if (ep.out[o]) {
+                            T v = T(ep.acc_c[o]) * a;
+                            if (ep.id[o] != 0.0) v += T(ep.id[o]) * idv;
+                            if (ep.g1[o] != 0.0) v += T(ep.g1[o]) * d1;
+                            if (ep.g2[o] != 0.0) v += T(ep.g2[o]) * d2;
+                            ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
+                            if (o == 0 && ep.ref) {
+                                const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];
+                                const double df = (double)v - x0;
+                                s_diff += df * df;
+                                s_ref += x0 * x0;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (ep.ref) {
+        const double sd = wave_sum(s_diff), sr = wave_sum(s_ref);
+        if (lane == 0) {
+            red[0][wave] = sd;
+            red[1][wave] = sr;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < WAVES; ++w) {
+                a += red[0][w];
+                b += red[1][w];
+            }
+            ep.partials[2 * part] = a;
+            ep.partials[2 * part + 1] = b;
+        }
+    }
+}
+
 // One BM x BN output tile (tm, tn) of C = epilogue(A * B); the block's
 // partial sums (if any) go to pair `part` of ep.partials.
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1, int SPLIT = 1>
@@ -236,14 +298,22 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
         // the V steps of a fragment group are V consecutive elements of a row
         // of A (one 16-byte LDS read) and of V consecutive rows of B; a K-tile
         // is NG groups. The fragments of group g+1 are read while the MFMAs of
-        // group g run; the next tile is stored and the block synchronised
-        // before the last group, so the first group of the next tile is read
-        // while the last MFMAs of this one run. The scheduling barriers keep
-        // the compiler from gathering the LDS reads back together. Until
-        // stored, tile t sits in register set t % 2; the loop body takes an
-        // even and an odd tile so both sets are indexed statically.
+        // group g run; the block synchronises before the last group, so the
+        // first group of the next tile is read while the last MFMAs of this
+        // one run. The scheduling barriers keep the compiler from gathering
+        // the LDS reads back together. Until stored, tile t sits in register
+        // set t % 2; the loop body takes an even and an odd tile so both sets
+        // are indexed statically. The loads are issued for every tile, also
+        // past the end of K (they then read element 0 and are never stored):
+        // with the same loads on every path the compiler's wait before a
+        // store covers only the older set, not the loads just issued.
         constexpr int NQ = BK / 4, NG = NQ / V;
         static_assert(NQ % V == 0 && NG >= 2, "fragment groups");
+        // tile kt+1 goes to LDS after the MFMAs of group STORE_G (its buffer
+        // was last read before the previous barrier, its loads were issued a
+        // tile earlier), so the LDS writes overlap MFMAs instead of sitting
+        // in front of the barrier
+        constexpr int STORE_G = NG > 2 ? 1 : NG - 1;
         VT fa[2][C::TI];
         T fb[2][C::TJ][V];
         auto frag = [&](int buf, int g, int slot) {
@@ -268,14 +338,15 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
         // register set `ld` receives tile kt+2, set `st` holds tile kt+1
         auto tile = [&](int kt, auto ld, auto st) {
             const int cur = kt & 1;
-            if (kt + 2 < nk) load(decltype(ld)::value, (kt + 2) * BK);
+            load(decltype(ld)::value, (kt + 2) * BK);
 #pragma unroll
             for (int g = 0; g + 1 < NG; ++g) {
                 frag(cur, g + 1, (g + 1) & 1);
                 mma(g & 1);
+                if (g == STORE_G && kt + 1 < nk) store(decltype(st)::value, cur ^ 1, (kt + 1) * BK);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (kt + 1 < nk) store(decltype(st)::value, cur ^ 1, (kt + 1) * BK);
+            if (STORE_G == NG - 1 && kt + 1 < nk) store(decltype(st)::value, cur ^ 1, (kt + 1) * BK);
             __syncthreads();
             if (kt + 1 < nk) frag(cur ^ 1, 0, 0);
             mma((NG - 1) & 1);
@@ -285,7 +356,7 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
         using I1 = std::integral_constant<int, 1>;
         load(0, 0);
         store(0, 0, 0);
-        if (nk > 1) load(1, BK);
+        load(1, BK);
         __syncthreads();
         frag(0, 0, 0);
         for (int kt = 0; kt < nk; kt += 2) {
@@ -353,58 +424,7 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
         if (tid == 0) __hip_atomic_store(&ep.split_cnt[part], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
-    // ---- epilogue ----
-    double s_diff = 0.0, s_ref = 0.0;
-#pragma unroll
-    for (int i = 0; i < C::TI; ++i) {
-#pragma unroll
-        for (int j = 0; j < C::TJ; ++j) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = bm + wm + i * 16 + Mfma<T>::row(fg, r);
-                const int col = bn + wn + j * 16 + fr;
-                if (row < M && col < N) {
-                    const T a = acc[i][j][r];
-                    const T d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : T(0);
-                    const T d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : T(0);
-                    const T idv = (row == col) ? T(1) : T(0);
-#pragma unroll
-                    for (int o = 0; o < 3; ++o) {
-                        if (ep.out[o]) {
-                            T v = T(ep.acc_c[o]) * a;
-                            if (ep.id[o] != 0.0) v += T(ep.id[o]) * idv;
-                            if (ep.g1[o] != 0.0) v += T(ep.g1[o]) * d1;
-                            if (ep.g2[o] != 0.0) v += T(ep.g2[o]) * d2;
-                            ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
-                            if (o == 0 && ep.ref) {
-                                const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];
-                                const double df = (double)v - x0;
-                                s_diff += df * df;
-                                s_ref += x0 * x0;
-                            }
-                        }
-                    }
-                }
-            }
-        }
-    }
-    if (ep.ref) {
-        const double sd = wave_sum(s_diff), sr = wave_sum(s_ref);
-        if (lane == 0) {
-            red[0][wave] = sd;
-            red[1][wave] = sr;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double a = 0.0, b = 0.0;
-            for (int w = 0; w < C::WAVES; ++w) {
-                a += red[0][w];
-                b += red[1][w];
-            }
-            ep.partials[2 * part] = a;
-            ep.partials[2 * part + 1] = b;
-        }
-    }
+    tile_epilogue<T, C::TI, C::TJ, C::WAVES>(acc, ep, M, N, bm, bn, wm, wn, part, red);
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>

@@ -262,3 +262,4 @@ def test_gemm_16bit_operands_in_memory(dt, M, N, K, tile, tmp_path):
     bound = (np.abs(Ar) @ np.abs(Br)) * (2 * K + 4) * 2.0**-24
     err = np.abs(C.cpu().numpy().astype(np.float64) - ref)
     assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
+
