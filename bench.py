@@ -198,6 +198,32 @@ def extra_small(hpw, torch, steps):
             "rel_err_vs_lapack_pinv": rel(X.cpu().numpy(), np.linalg.pinv(A64))}
 
 
+def extra_precond(hpw, torch, steps):
+    """Example 8.3's preconditioners on the GPU: X_1 of PM, X_3 of CM and X_5
+    of SM from X0 = diag(1/a_ii) (choice3) with Chop[X, 1e-5] after each loop,
+    on the seeded 841 x 841 grid-stencil stand-in (the paper's MatrixMarket
+    matrix is not available; GMRES and the ILU comparison are not built).
+    Reports the time to build each preconditioner, its residual
+    ||I - X A||_F / ||I - X0 A||_F and the fraction of nonzero entries."""
+    from paper_1604_07893_amd import inputs
+    A64 = inputs.grid_stencil()
+    A = torch.from_numpy(A64).cuda()
+    n = A64.shape[0]
+    I = np.eye(n)
+    r0 = np.linalg.norm(I - A64 / np.diag(A64)[:, None])
+    out = {"workload": "grid stencil 29x29 (841x841, 4089 nonzeros, seed 1006), X0 = diag(1/a_ii), "
+                       "Chop[X, 1e-5] after each loop"}
+    for mth, loops in (("pm", 1), ("cm", 3), ("sm", 5)):
+        sec, infos, X = timed_solves(hpw, torch, A, steps, 3, method=mth, alpha_rule="diag",
+                                     max_iter=loops, chop=1e-5)
+        Xh = X.cpu().numpy()
+        out[f"{mth}_x{loops}"] = {
+            "us_per_preconditioner": sec * 1e6, "products": infos[-1]["gemms"],
+            "residual_vs_x0": float(np.linalg.norm(I - Xh @ A64) / r0),
+            "nonzero_fraction": float(np.count_nonzero(Xh) / Xh.size)}
+    return out
+
+
 def extra_methods(hpw, torch, steps):
     """The comparison of Section 8 on the GPU: every scheme (SM, CM, FM, HM,
     PM) on (a) a square 4096^2 input with kappa = 1e3 (s log-uniform in
@@ -389,6 +415,7 @@ def main() -> int:
                          ("drazin_2048", lambda: extra_drazin(hpw, torch, 3)),
                          ("small_200x100", lambda: extra_small(hpw, torch, 50)),
                          ("methods", lambda: extra_methods(hpw, torch, 2)),
+                         ("preconditioner_example_8_3", lambda: extra_precond(hpw, torch, 20)),
                          ("served_stream", lambda: extra_served(hpw, torch, 1000, 100))):
             t0 = time.perf_counter()
             try:

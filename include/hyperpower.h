@@ -70,6 +70,13 @@ extern "C" {
                                 rho <= sigma_1^2, so alpha sigma_1^2 >= 1, and it
                                 stays below 2 as long as rho > sigma_1^2 / 2,
                                 the convergence condition of Section 4) */
+#define HP_ALPHA_DIAG 4      /* Moore-Penrose kind, square A only: X0 =
+                                diag(1/a_11, ..., 1/a_nn), the initial matrix
+                                (choice3) of Example 8.3 (G = D^{-1}, so the
+                                limit is A^{-1} when A is nonsingular and the
+                                loops converge, e.g. for a strictly diagonally
+                                dominant A); alpha is reported as 1. A zero
+                                diagonal entry gives HP_NONFINITE */
 
 /* iteration variant */
 #define HP_VARIANT_PLAIN 0       /* (PM), Section 2: 7 products per loop */
@@ -194,7 +201,15 @@ typedef struct hp_params {
     int32_t method;        /* HP_METHOD_* (default PM). Methods other than PM
                               run in HP_PREC_FP64 or HP_PREC_FP32 in hp_solve
                               only (HP_EUNSUPPORTED otherwise) */
-    int32_t reserved[5];   /* must be zero */
+    int32_t reserved0;     /* must be zero */
+    double chop;           /* > 0: at the end of every loop, entries of X_{k+1}
+                              with |x| < chop are set to zero before the
+                              stopping test measures the change (the sparsity
+                              control of Example 8.3); 0 = off. hp_solve with
+                              HP_PREC_FP64 or HP_PREC_FP32 and a stopping rule
+                              other than HP_STOP_REL_FRO_BOUND only
+                              (HP_EUNSUPPORTED otherwise) */
+    int32_t reserved[2];   /* must be zero */
 } hp_params;
 
 #define HP_HIST 128

@@ -24,6 +24,8 @@ from .hyperpower import (  # noqa: F401
     norm_fro,
     x0_moore_penrose,
     x0_drazin,
+    x0_diag,
+    chop,
     pm_step,
     stabilise,
     sm_step,

@@ -186,6 +186,27 @@ def x0_moore_penrose(A, rule: str = "norm1inf", alpha=None, ar: Arith = F64):
     return alpha * A.T, alpha
 
 
+def x0_diag(A, ar: Arith = F64):
+    """X0 = diag(1/a_11, ..., 1/a_nn), the initial matrix (choice3) of
+    Example 8.3 (square A). Here G = X0 itself, so the limit is A^{-1} when A
+    is nonsingular and the loops converge. Returns (X0, 1)."""
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("the diagonal initial matrix needs a square A")
+    X0 = ar.eye(n) * 0
+    for i in range(n):
+        X0[i, i] = 1 / A[i, i]
+    return X0, ar.num(1)
+
+
+def chop(X, eps):
+    """The sparsity control of Example 8.3 (Mathematica's Chop[X, eps]): every
+    entry with |x| < eps becomes 0."""
+    Y = X.copy()
+    Y[np.abs(X) < eps] = 0
+    return Y
+
+
 def x0_drazin(A, l: int, ar: Arith = F64):
     """X0 = A^l / Tr(A^{l+1}) with l >= ind(A) (Section 4; Example 8.1).
     Returns (X0, alpha) with alpha = 1 / Tr(A^{l+1})."""
@@ -291,10 +312,13 @@ class Result:
 def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1inf",
           alpha=None, X0=None, method: str = "pm", variant: str = "plain",
           tau_switch: float = 0.1, stop: str = "rel_fro", tol: float = 1e-12,
-          max_iter: int = 100, diverge_limit: float = 1e6, ar: Arith = F64) -> Result:
+          max_iter: int = 100, diverge_limit: float = 1e6, chop_eps: float = 0.0,
+          ar: Arith = F64) -> Result:
     """Run a hyperpower iteration to a generalized inverse of A.
 
-    kind      "mp": Moore-Penrose, X0 = alpha A^T (Section 4).
+    kind      "mp": Moore-Penrose, X0 = alpha A^T (Section 4); with
+              alpha_rule "diag", X0 = diag(1/a_ii) of Example 8.3 instead
+              (square A, limit A^{-1}).
               "drazin": X0 = A^l / Tr(A^{l+1}), l >= ind(A) (Section 4).
     method    "pm" (the paper's 7-product scheme) or one of the comparison
               schemes "sm", "cm", "fm", "hm" (Sections 1.3 and 2).
@@ -313,6 +337,9 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
               r/(1-r) < tol (r < 1) bounds the change that loop would make
               below tol, so X_{k+1} is returned without it (an addition to the
               paper's rules).
+    chop_eps  > 0: entries of each new iterate below chop_eps in magnitude are
+              set to 0 at the end of the loop, before its change is measured
+              (Example 8.3).
     Guards (the warning of Section 6 that looping past convergence can
     diverge): a non-finite iterate ends with "nonfinite" and the last finite
     iterate; once some relative change below tau_switch has been seen, a change
@@ -326,6 +353,8 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
     if X0 is not None:
         X = X0
         alpha = ar.num(alpha) if alpha is not None else ar.num(1)
+    elif kind == "mp" and alpha_rule == "diag":
+        X, alpha = x0_diag(A, ar)
     elif kind == "mp":
         X, alpha = x0_moore_penrose(A, alpha_rule, alpha, ar)
     elif kind == "drazin":
@@ -347,6 +376,8 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
         Xn = step(A, X, K, ar)
         if stabilising:
             Xn = stabilise(A, Xn)
+        if chop_eps > 0:
+            Xn = chop(Xn, chop_eps)
         res.iters = k + 1
         if not ar.isfinite(Xn):
             res.status, res.X = "nonfinite", X

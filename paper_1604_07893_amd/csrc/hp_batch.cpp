@@ -315,6 +315,7 @@ int validate_group_params(const hp_params* p) {
         return HP_EUNSUPPORTED;
     if (p->stop_rule == HP_STOP_ABS_INF || (p->flags & HP_FLAG_INF_NORM)) return HP_EUNSUPPORTED;
     if (p->method != HP_METHOD_PM || p->stop_rule == HP_STOP_REL_FRO_BOUND) return HP_EUNSUPPORTED;
+    if (p->chop > 0.0 || p->alpha_rule == HP_ALPHA_DIAG) return HP_EUNSUPPORTED;
     return HP_OK;
 }
 

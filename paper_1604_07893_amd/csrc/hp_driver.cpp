@@ -169,9 +169,14 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
         if (p->precision != HP_PREC_FP64) return HP_EUNSUPPORTED;
         if (p->alpha_rule != HP_ALPHA_TRACE && p->alpha_rule != HP_ALPHA_USER) return HP_EINVAL;
     } else if (p->alpha_rule != HP_ALPHA_NORM1INF && p->alpha_rule != HP_ALPHA_USER &&
-               p->alpha_rule != HP_ALPHA_SIGMA_MAX2) {
+               p->alpha_rule != HP_ALPHA_SIGMA_MAX2 && p->alpha_rule != HP_ALPHA_DIAG) {
         return HP_EINVAL;
     }
+    if (p->alpha_rule == HP_ALPHA_DIAG && m != n) return HP_EINVAL;
+    if (!(p->chop >= 0.0) || !std::isfinite(p->chop)) return HP_EINVAL;
+    if (p->chop > 0.0 && ((p->precision != HP_PREC_FP64 && p->precision != HP_PREC_FP32) ||
+                          p->stop_rule == HP_STOP_REL_FRO_BOUND))
+        return HP_EUNSUPPORTED;
     if (p->alpha_rule == HP_ALPHA_USER && !(p->alpha > 0.0 && std::isfinite(p->alpha))) return HP_EINVAL;
     if (p->variant < HP_VARIANT_PLAIN || p->variant > HP_VARIANT_STAB_ALWAYS) return HP_EINVAL;
     if (p->side < HP_SIDE_AUTO || p->side > HP_SIDE_LEFT) return HP_EINVAL;
@@ -185,8 +190,7 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
         return HP_EUNSUPPORTED;
     if (p->max_iter < 1 || p->max_iter > 100000) return HP_EINVAL;
     if (!(p->tol >= 0.0) || !(p->tau_switch > 0.0) || !(p->diverge_limit > 0.0)) return HP_EINVAL;
-    for (int i = 0; i < 5; ++i)
-        if (p->reserved[i] != 0) return HP_EINVAL;
+    if (p->reserved0 != 0 || p->reserved[0] != 0 || p->reserved[1] != 0) return HP_EINVAL;
     return HP_OK;
 }
 
@@ -481,6 +485,15 @@ struct Solver {
     }
 };
 
+// hp_params.chop: the product that writes X_{k+1} (the update, or the
+// stabilising product after it) drops its entries below `chop`.
+template <typename T>
+void set_chop(GemmCall<T>* calls, int nc, const T* Xn, double chop) {
+    if (chop <= 0.0) return;
+    for (int i = 0; i < nc; ++i)
+        if (calls[i].ep.out[0] == Xn) calls[i].ep.chop = chop;
+}
+
 int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X0, int64_t ldx0,
               double* X, int64_t ldx) {
     const hp_params* p = S.p;
@@ -528,12 +541,14 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
             const int nc = describe_loop<double>(p->method, pl, bf.b64, bf.b64.X[st.ik],
                                                  bf.b64.X[st.in_], bf.b64.X[2], st.stabilising,
                                                  bf.small, calls);
+            set_chop(calls, nc, bf.b64.X[st.in_], p->chop);
             for (int i = first; i < nc; ++i) CHK(S.gemm<double>(ENG_F64, calls[i]));
         } else {
             GemmCall<float> calls[kMaxLoopGemms];
             const int nc = describe_loop<float>(p->method, pl, bf.b32, bf.b32.X[st.ik],
                                                 bf.b32.X[st.in_], bf.b32.X[2], st.stabilising,
                                                 bf.small, calls);
+            set_chop(calls, nc, bf.b32.X[st.in_], p->chop);
             CopyUse use[kMaxLoopGemms];
             copy_uses(calls, nc, bf.b32, use);
             for (int i = first; i < nc; ++i)

@@ -120,8 +120,9 @@ struct Cfg {
 };
 
 // The fused epilogue of a BM x BN tile held as TI x TJ MFMA accumulators per
-// wave: up to three outputs id*I + acc_c*acc + g1*D1 + g2*D2 and, with
-// ep.ref, the block's FP64 partial sums of the stopping test in pair `part`.
+// wave: up to three outputs id*I + acc_c*acc + g1*D1 + g2*D2 (output 0 chopped
+// with ep.chop) and, with ep.ref, the block's FP64 partial sums of the stopping
+// test in pair `part`.
 template <typename T, int TI, int TJ, int WAVES>
 __device__ __attribute__((always_inline)) inline void tile_epilogue(
     typename Mfma<T>::acc_t (&acc)[TI][TJ], const EpilogueT<T>& ep, int M, int N, int bm, int bn,
@@ -149,6 +150,7 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(
                             if (ep.id[o] != 0.0) v += T(ep.id[o]) * idv;
                             if (ep.g1[o] != 0.0) v += T(ep.g1[o]) * d1;
                             if (ep.g2[o] != 0.0) v += T(ep.g2[o]) * d2;
+                            if (o == 0 && ep.chop > 0.0 && fabs((double)v) < ep.chop) v = T(0);
                             ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
                             if (o == 0 && ep.ref) {
                                 const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];

@@ -389,8 +389,8 @@ int setup_x0(const hp_params* p, const Plan& pl, const Buffers& bf, const double
         *alpha_out = p->alpha > 0.0 ? p->alpha : 1.0;
         return HP_OK;
     }
-    if (p->alpha_rule == HP_ALPHA_USER) {
-        host_scal[SLOT_ALPHA] = p->alpha;
+    if (p->alpha_rule == HP_ALPHA_USER || p->alpha_rule == HP_ALPHA_DIAG) {
+        host_scal[SLOT_ALPHA] = p->alpha_rule == HP_ALPHA_DIAG ? 1.0 : p->alpha;
         HIPCHK(hipMemcpyAsync(bf.scal + SLOT_ALPHA, host_scal + SLOT_ALPHA, sizeof(double),
                               hipMemcpyHostToDevice, s));
     }
@@ -399,7 +399,10 @@ int setup_x0(const hp_params* p, const Plan& pl, const Buffers& bf, const double
             HIPCHK(alpha_norm1inf(b.A, b.ldA, m, n, bf.small, bf.scal, s));
         else if (p->alpha_rule == HP_ALPHA_SIGMA_MAX2)
             HIPCHK(alpha_sigma_max2(b.A, b.ldA, m, n, kPowerIters, bf.small, bf.scal, s));
-        HIPCHK(transpose_scale(b.A, b.ldA, m, n, X0w, b.ldX, bf.scal + SLOT_ALPHA, s));
+        if (p->alpha_rule == HP_ALPHA_DIAG)
+            HIPCHK(diag_inv(b.A, b.ldA, n, X0w, b.ldX, s));  // (choice3), Example 8.3
+        else
+            HIPCHK(transpose_scale(b.A, b.ldA, m, n, X0w, b.ldX, bf.scal + SLOT_ALPHA, s));
     } else {
         // G = A^l by repeated products, alpha = 1/Tr(A^{l+1}) = 1/Tr(A^l A)
         const double* P = b.A;

@@ -42,6 +42,9 @@ struct EpilogueT {
     const T* ref;
     int64_t ldref;
     double* partials;
+    // > 0: values of output 0 with |v| < chop are stored as 0 (and enter the
+    // stopping sums as 0); 0 = off
+    double chop;
     // Split-K scratch, read only by the split tiles (TILE_128x128_W8_S2/S4):
     // split_slots partial tiles of 128 x 128 elements, then one arrival
     // counter per output tile. The counters are zero before a launch and every
@@ -189,6 +192,9 @@ hipError_t transpose_scale(const double* A, int64_t lda, int64_t M, int64_t N, d
 // Y = (*alpha_dev) * A elementwise (M x N).
 hipError_t scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y, int64_t ldy,
                  const double* alpha_dev, hipStream_t s);
+
+// Y = diag(1/A[0][0], ..., 1/A[n-1][n-1]) (n x n, zero off the diagonal).
+hipError_t diag_inv(const double* A, int64_t lda, int64_t n, double* Y, int64_t ldy, hipStream_t s);
 
 // Y = I (M x N identity).
 hipError_t set_identity(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s);

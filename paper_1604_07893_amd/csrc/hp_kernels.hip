@@ -263,6 +263,15 @@ __global__ __launch_bounds__(kThreads) void k_identity(double* __restrict__ Y, i
         Y[(int64_t)r * ldy + c] = (r == c) ? 1.0 : 0.0;
 }
 
+// X0 = diag(1/a_11, ..., 1/a_nn), zero elsewhere (n x n)
+__global__ __launch_bounds__(kThreads) void k_diag_inv(const double* __restrict__ A, int64_t lda,
+                                                       int n, double* __restrict__ Y, int64_t ldy) {
+    const int r = blockIdx.y;
+    const double d = 1.0 / A[(int64_t)r * lda + r];
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < n; c += gridDim.x * kThreads)
+        Y[(int64_t)r * ldy + c] = (r == c) ? d : 0.0;
+}
+
 __global__ __launch_bounds__(kThreads) void k_zero_u32(unsigned* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
         p[i] = 0u;
@@ -490,6 +499,12 @@ hipError_t scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y, 
 hipError_t set_identity(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s) {
     const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N, kThreads), 16);
     hipLaunchKernelGGL(k_identity, dim3(gx, (unsigned)M), dim3(kThreads), 0, s, Y, ldy, (int)M, (int)N);
+    return hipGetLastError();
+}
+
+hipError_t diag_inv(const double* A, int64_t lda, int64_t n, double* Y, int64_t ldy, hipStream_t s) {
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(n, kThreads), 16);
+    hipLaunchKernelGGL(k_diag_inv, dim3(gx, (unsigned)n), dim3(kThreads), 0, s, A, lda, (int)n, Y, ldy);
     return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ HP_EINVAL, HP_EWORKSPACE, HP_EBUDGET, HP_EHIP, HP_EUNSUPPORTED = -1, -2, -3, -4,
 STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "stagnated", 3: "diverged", 4: "nonfinite", 5: "pending"}
 
 KIND = {"mp": 0, "moore_penrose": 0, "drazin": 1}
-ALPHA = {"norm1inf": 0, "user": 1, "trace": 2, "sigma_max2": 3}
+ALPHA = {"norm1inf": 0, "user": 1, "trace": 2, "sigma_max2": 3, "diag": 4}
 VARIANT = {"plain": 0, "stabilised": 1, "stabilized": 1, "stab_always": 2}
 SIDE = {"auto": 0, "right": 1, "left": 2}
 STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2, "rel_fro_bound": 3}
@@ -45,7 +45,7 @@ class HpParams(ctypes.Structure):
         ("alpha", c_double), ("tau_switch", c_double), ("tol", c_double), ("diverge_limit", c_double),
         ("max_iter", c_int32), ("stop_rule", c_int32), ("side", c_int32), ("precision", c_int32),
         ("flags", c_int32), ("low_dtype", c_int32), ("method", c_int32),
-        ("reserved", c_int32 * 5),
+        ("reserved0", c_int32), ("chop", c_double), ("reserved", c_int32 * 2),
     ]
 
 
@@ -168,7 +168,7 @@ def handle(device: int | None = None) -> Handle:
 def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", tau_switch=0.1,
                 tol=1e-12, max_iter=100, stop="rel_fro", side="auto", precision="fp64",
                 diverge_limit=1e6, time_kernels=False, inf_norm=False,
-                low_dtype="bf16", graph=True, method="pm") -> HpParams:
+                low_dtype="bf16", graph=True, method="pm", chop=0.0) -> HpParams:
     p = HpParams()
     load_library().hp_params_default(ctypes.byref(p))
     p.kind = KIND[kind]
@@ -187,6 +187,7 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
     p.low_dtype = LOWP[low_dtype]
     p.diverge_limit = float(diverge_limit)
     p.method = METHOD[method]
+    p.chop = float(chop)
     p.flags = ((FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
                | (0 if graph else FLAG_NO_GRAPH))
     return p

@@ -24,6 +24,13 @@ Recipes (all FP64, row-major, numpy ``default_rng(seed)``):
   r uniform in {1, 2, 4}, entries iid N(0, 1), a fraction rank-deficient at
   half rank (A = G1 G2 / sqrt(k)).
 * ``hilbert``      -- H_{m x n} = [1 / (i + j - 1)] (Example 8.2).
+* ``grid_stencil`` -- stand-in for Example 8.3's sparse 841 x 841 matrix
+  (MatrixMarket YOUNG1C, which is not available here): the 5-point stencil
+  of a 29 x 29 grid, diagonal 4 + shift, each neighbour weight
+  -1 + spread U(-1, 1) (nonsymmetric, not tridiagonal, strictly diagonally
+  dominant for shift > 4 spread).
+* ``spd``          -- symmetric positive definite Q diag(w) Q^T, Q Haar, w
+  log-spaced in [1, cond] (weights of a weighted Moore-Penrose inverse).
 """
 
 from __future__ import annotations
@@ -153,6 +160,30 @@ def hilbert(m: int, n: int) -> np.ndarray:
     i = np.arange(1, m + 1)[:, None]
     j = np.arange(1, n + 1)[None, :]
     return 1.0 / (i + j - 1)
+
+
+def grid_stencil(side: int = 29, shift: float = 0.5, spread: float = 0.1,
+                 seed: int = 1006) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    n = side * side
+    A = np.zeros((n, n))
+    for r in range(side):
+        for c in range(side):
+            i = r * side + c
+            A[i, i] = 4.0 + shift
+            for dr, dc in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                rr, cc = r + dr, c + dc
+                if 0 <= rr < side and 0 <= cc < side:
+                    A[i, rr * side + cc] = -1.0 + spread * rng.uniform(-1.0, 1.0)
+    return A
+
+
+def spd(n: int, cond: float = 10.0, seed: int = 1007) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    Q = haar_columns(rng, n, n)
+    w = np.logspace(0.0, np.log10(cond), n)
+    S = (Q * w) @ Q.T
+    return (S + S.T) / 2
 
 
 @dataclass

@@ -376,3 +376,104 @@ def test_stop_rules_order_and_iteration_counting():
     D = np.linalg.norm(r_41.X - O.solve(A, kind="mp", stop="paper_4_1", tol=1e-5,
                                         max_iter=k).X)
     assert abs(D / (18.0**k * r_41.alpha) - r_41.stop_hist[-1]) <= 1e-6 * r_41.stop_hist[-1]
+
+
+# ---------------------------------------------------------------------------
+# Example 8.3: X0 = diag(1/a_ii) (choice3) and Chop at the end of each loop;
+# other outer inverses through a user-supplied G (Section 1.2: A^(2)_{T,S}
+# with T = R(G), S = N(G)).
+# ---------------------------------------------------------------------------
+
+def test_diag_x0_reaches_the_lapack_inverse():
+    """G = D^{-1} has T = R^n, S = {0}: the limit is A^{-1} (LAPACK)."""
+    A = inputs.grid_stencil(side=8)
+    res = O.solve(A, kind="mp", alpha_rule="diag", tol=1e-13)
+    assert res.status == "ok" and res.alpha == 1
+    Ainv = np.linalg.inv(A)
+    assert np.linalg.norm(res.X - Ainv) / np.linalg.norm(Ainv) < 1e-13
+    # its first loop is the order-18 hyperpower sum from X0 = D^{-1}
+    X0 = np.diag(1.0 / np.diag(A))
+    one = O.solve(A, kind="mp", alpha_rule="diag", max_iter=1)
+    ref = O.hyperpower_direct_step(A, X0, 18)
+    assert np.linalg.norm(one.X - ref) / np.linalg.norm(ref) < 1e-14
+
+
+def _chop_margin(X, eps):
+    """Smallest relative distance of |x| from the threshold (how far every
+    entry is from flipping under a rounding-level change)."""
+    return float(np.min(np.abs(np.abs(X) - eps)) / eps)
+
+
+@pytest.mark.parametrize("loops", [1, 2])
+def test_chop_applies_after_each_loop(loops):
+    """With Chop[X, 1e-5] after every loop, the iterate is the chopped
+    18-term hyperpower sum of the previous chopped iterate."""
+    A = inputs.grid_stencil(side=10)
+    eps = 1e-5
+    X = np.diag(1.0 / np.diag(A))
+    for _ in range(loops):
+        pre = O.hyperpower_direct_step(A, X, 18)
+        assert _chop_margin(pre, eps) > 1e-6
+        X = np.where(np.abs(pre) < eps, 0.0, pre)
+    res = O.solve(A, kind="mp", alpha_rule="diag", max_iter=loops, chop_eps=eps)
+    assert res.iters == loops
+    assert np.array_equal(res.X == 0, X == 0)
+    assert 0 < np.count_nonzero(X) < X.size
+    assert np.max(np.abs(res.X - X)) <= 1e-14 * np.max(np.abs(X))
+
+
+def test_weighted_moore_penrose_from_user_g():
+    """A^dagger_{MN} (weighted Moore-Penrose, M and N SPD) from G = N^{-1} A^T M:
+    the closed form N^{-1/2} (M^{1/2} A N^{-1/2})^dagger M^{1/2} and the four
+    weighted Penrose equations."""
+    rng = np.random.default_rng(3)
+    m, n = 60, 40
+    A = rng.standard_normal((m, n))
+    Mw, Nw = inputs.spd(m, 5.0, seed=11), inputs.spd(n, 5.0, seed=12)
+    G = np.linalg.solve(Nw, A.T @ Mw)
+    alpha = 1.0 / np.max(np.linalg.eigvals(G @ A).real)
+    res = O.solve(A, X0=alpha * G, alpha=alpha, tol=1e-13)
+    assert res.status == "ok"
+
+    def sqrtm(S, p):
+        w, Q = np.linalg.eigh(S)
+        return (Q * w ** p) @ Q.T
+    closed = sqrtm(Nw, -0.5) @ np.linalg.pinv(sqrtm(Mw, 0.5) @ A @ sqrtm(Nw, -0.5)) @ sqrtm(Mw, 0.5)
+    X = res.X
+    assert np.linalg.norm(X - closed) / np.linalg.norm(closed) < 1e-12
+    MAX, NXA = Mw @ A @ X, Nw @ X @ A
+    for r in (A @ X @ A - A, X @ A @ X - X, MAX - MAX.T, NXA - NXA.T):
+        assert np.linalg.norm(r) < 1e-10
+
+
+def test_group_inverse_is_drazin_with_index_one():
+    """Index-1 A = P diag(B, 0) P^{-1}: the group inverse A^# =
+    P diag(B^{-1}, 0) P^{-1} (G = A, l = 1); A A^# A = A, A^# A A^# = A^#,
+    A A^# = A^# A."""
+    dz = inputs.drazin_jordan(n=80, nb=60, block=1, seed=8)
+    assert dz.index == 1
+    res = O.solve(dz.A, kind="drazin", l=1, variant="stabilised", tol=1e-12)
+    assert res.status == "ok"
+    Binv = (dz.Q / dz.lam) @ dz.Q.T
+    J = np.zeros((80, 80))
+    J[:60, :60] = Binv
+    closed = dz.P @ J @ dz.Pinv
+    X, A = res.X, dz.A
+    assert np.linalg.norm(X - closed) / np.linalg.norm(closed) < 1e-11
+    for r in (A @ X @ A - A, X @ A @ X - X, A @ X - X @ A):
+        assert np.linalg.norm(r) < 1e-10
+
+
+def test_bott_duffin_inverse_from_projector():
+    """A_(L)^{-1} = P_L (A P_L + P_{L-perp})^{-1} (Bott-Duffin) from G = P_L:
+    the outer inverse with T = L, S = L-perp (Section 1.2)."""
+    rng = np.random.default_rng(21)
+    n, k = 50, 30
+    A = inputs.spd(n, 20.0, seed=13) + 0.05 * rng.standard_normal((n, n))
+    QL = inputs.haar_columns(rng, n, k)
+    PL = QL @ QL.T
+    alpha = 1.0 / np.max(np.abs(np.linalg.eigvals(PL @ A)))
+    res = O.solve(A, X0=alpha * PL, alpha=alpha, variant="stabilised", tol=1e-13)
+    assert res.status == "ok"
+    closed = PL @ np.linalg.inv(A @ PL + (np.eye(n) - PL))
+    assert np.linalg.norm(res.X - closed) / np.linalg.norm(closed) < 1e-11
