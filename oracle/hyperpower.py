@@ -307,6 +307,7 @@ class Result:
     diff_inf_hist: list = field(default_factory=list)  # ||X_{k+1}-X_k||_inf
     switch_iter: int = -1       # first loop run stabilised (-1: never)
     bound_hist: list = field(default_factory=list)  # ||R||_F of "rel_fro_bound" checks
+    fro_hist: list = field(default_factory=list)    # (||X_{k+1}-X_k||_F, ||X_k||_F) per loop
 
 
 def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1inf",
@@ -383,7 +384,9 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
             res.status, res.X = "nonfinite", X
             return res
         D = Xn - X
-        d = norm_fro(D, ar) / norm_fro(X, ar)
+        nD, nX = norm_fro(D, ar), norm_fro(X, ar)
+        d = nD / nX
+        res.fro_hist.append((nD, nX))
         res.d_hist.append(d)
         res.diff_inf_hist.append(norm_inf(D))
         if stop in ("rel_fro", "rel_fro_bound"):

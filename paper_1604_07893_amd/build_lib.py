@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libhyperpower.so")
 
-SOURCES = ["hp_gemm.hip", "hp_kernels.hip", "hp_driver.cpp", "hp_batch.cpp"]
+SOURCES = ["hp_gemm.hip", "hp_kernels.hip", "hp_driver.cpp", "hp_batch.cpp", "hp_loop.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "hp_host.h"
+#include "hp_sched.h"
 
 namespace hp {
 
@@ -351,41 +352,9 @@ struct hp_server {
     Group g;
     char* arena = nullptr;
     size_t budget = 0;
-    int max_slots = 0;
-    std::map<size_t, size_t> free_list;  // offset -> bytes
+    Admission adm;
     uint64_t next_ticket = 1;
     std::map<uint64_t, Problem> reqs;
-    std::deque<uint64_t> waiting;
-    std::vector<uint64_t> active;
-
-    bool alloc(size_t bytes, size_t* off) {
-        for (auto it = free_list.begin(); it != free_list.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t roff = it->first + bytes;
-                free_list.erase(it);
-                if (rest) free_list[roff] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        auto it = free_list.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_list.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_list.erase(nx);
-        }
-        if (it != free_list.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_list.erase(it);
-            }
-        }
-    }
 };
 
 extern "C" {
@@ -469,12 +438,11 @@ int hp_serve_create(hp_handle* h, const hp_params* p, size_t hbm_budget, int max
     sv->g.s = reinterpret_cast<hipStream_t>(stream);
     sv->g.use_graph = (p->flags & HP_FLAG_NO_GRAPH) == 0;
     sv->budget = hbm_budget / kAlign * kAlign;
-    sv->max_slots = max_slots;
+    sv->adm = Admission(sv->budget, max_slots);
     if (hipMalloc(reinterpret_cast<void**>(&sv->arena), sv->budget) != hipSuccess) {
         delete sv;
         return HP_EHIP;
     }
-    sv->free_list[0] = sv->budget;
     if (tables_alloc(sv->g.tb, max_slots) != HP_OK) {
         (void)hipFree(sv->arena);
         tables_free(sv->g.tb);
@@ -496,7 +464,7 @@ int hp_serve_submit(hp_server* sv, const hp_problem* prob, uint64_t* ticket) {
     P.pl = pl;
     P.ws_bytes = align_up(pl.total);
     P.t_submit = Clock::now();
-    sv->waiting.push_back(t);
+    sv->adm.submit(t, P.ws_bytes);
     *ticket = t;
     return HP_OK;
 }
@@ -505,38 +473,31 @@ int hp_serve_step(hp_server* sv, int* active, int* waiting) {
     if (!sv) return HP_EINVAL;
     if (hipSetDevice(sv->g.h->device) != hipSuccess) return HP_EHIP;
     // admit in arrival order while a slot and memory are free
-    while (!sv->waiting.empty() && (int)sv->active.size() < sv->max_slots) {
-        Problem& P = sv->reqs[sv->waiting.front()];
-        size_t off = 0;
-        if (!sv->alloc(P.ws_bytes, &off)) break;
+    CHK(sv->adm.admit([&](uint64_t t, size_t off) {
+        Problem& P = sv->reqs[t];
         P.ws_off = off;
         P.ws = sv->arena + off;
-        CHK(admit(sv->g, P));
         P.t_admit = Clock::now();
-        sv->active.push_back(sv->waiting.front());
-        sv->waiting.pop_front();
-    }
-    if (!sv->active.empty()) {
+        return admit(sv->g, P);
+    }));
+    const std::vector<uint64_t> act_t = sv->adm.active();
+    if (!act_t.empty()) {
         std::vector<Problem*> act;
-        for (uint64_t t : sv->active) act.push_back(&sv->reqs[t]);
+        for (uint64_t t : act_t) act.push_back(&sv->reqs[t]);
         CHK(group_loop(sv->g, act));
-        std::vector<uint64_t> still;
-        for (uint64_t t : sv->active) {
+        for (uint64_t t : act_t) {
             Problem& P = sv->reqs[t];
             if (P.finished) {
                 P.res.queue_ms = ms_between(P.t_submit, P.t_admit);
                 P.res.run_ms = ms_between(P.t_admit, P.t_finish);
                 P.res.time_ms = ms_between(P.t_submit, P.t_finish);
-                sv->release(P.ws_off, P.ws_bytes);
+                sv->adm.finish(t);
                 P.ws = nullptr;
-            } else {
-                still.push_back(t);
             }
         }
-        sv->active.swap(still);
     }
-    if (active) *active = (int)sv->active.size();
-    if (waiting) *waiting = (int)sv->waiting.size();
+    if (active) *active = (int)sv->adm.active_count();
+    if (waiting) *waiting = (int)sv->adm.waiting();
     return HP_OK;
 }
 

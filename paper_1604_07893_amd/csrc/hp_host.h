@@ -12,6 +12,7 @@
 #include <type_traits>
 
 #include "hp_internal.h"
+#include "hp_loop.h"
 #include "hyperpower.h"
 
 struct hp_handle {
@@ -105,8 +106,6 @@ struct Plan {
 Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area = true);
 int validate(const hp_params* p, int64_t m, int64_t n);
 
-// Which MFMA path a product runs on.
-enum Engine { ENG_F64, ENG_F32, ENG_BF16, ENG_F16 };
 
 // The buffers of one precision.
 template <typename T>
@@ -196,11 +195,6 @@ void copy_uses(const GemmCall<T>* c, int nc, const Set<T>& b, CopyUse* u) {
 // Most products a loop can take (HM: 9, plus 2 for the stabilising product).
 constexpr int kMaxLoopGemms = 11;
 
-// Order p of each HP_METHOD_* (the p of rule (stopreliable)).
-inline int method_order(int method) {
-    static const int kOrder[] = {18, 2, 3, 7, 18};
-    return kOrder[method];
-}
 
 // The update product X_{k+1} = X W (right form) or W X (left form), writing
 // the partial sums of the stopping test against X_k into `partials`; with
@@ -478,47 +472,5 @@ inline int needs_projection(const Plan& pl, const Buffers& bf, double* host_scal
     *out = !(host_scal[SLOT_RNORM2] < 0.5);
     return HP_OK;
 }
-
-// Host-side state of one problem's iteration: the stopping rule, the switch
-// to the stabilised variant, the precision stages and the guards.
-struct LoopState {
-    enum Action { CONTINUE, NEXT_STAGE, DONE };
-    const hp_params* p = nullptr;
-    hp_result* res = nullptr;
-    double alpha = 0.0;
-    int stage = 2;        // 0 16-bit, 1 FP32, 2 FP64
-    int final_stage = 2;
-    bool stabilising = false;
-    bool converging = false;
-    bool stage_first = true;  // no stagnation test on a stage's first loop
-    double d_prev = 0.0;
-    int ik = 0, in_ = 1;  // current and next iterate (index into the stage's set)
-    int k = 0;            // loops run
-    int status = HP_MAXITER;
-    int result_idx = -1;  // iterate to return (index into the final stage's set)
-    int from_idx = 0;     // NEXT_STAGE: iterate the next stage starts from
-
-    void init(const hp_params* prm, hp_result* r, double a);
-    Engine engine() const;
-    // Digest one loop's sums; `dinf` is used if have_dinf.
-    Action step(double diff2, double ref2, double dinf, bool have_dinf);
-    // After NEXT_STAGE the caller moves the iterate `from_idx` into the next
-    // stage's set; this resets the indices (FP64 stage: X[0]).
-    void enter_stage(int next);
-    bool done() const { return result_idx >= 0; }
-    // HP_STOP_REL_FRO_BOUND: after a CONTINUE, whether the next loop is a
-    // plain loop of the final stage whose change the residual bound may
-    // already settle (the last change d has d^p < tol).
-    bool bound_ready() const;
-    // The residual bound settled it: return the current iterate.
-    void stop_bound(double bound) {
-        status = HP_OK;
-        result_idx = ik;
-        res->stop_last = bound;
-    }
-    void finish_maxiter() {
-        if (result_idx < 0) result_idx = ik;
-    }
-};
 
 }  // namespace hp

@@ -1,0 +1,65 @@
+// The host-side control of one problem's iteration (stopping rules, the
+// switch to the stabilised variant, precision stages, guards): plain C++ with
+// no GPU dependence, shared by single, batched and served solves.
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+#include <utility>
+
+#include "hyperpower.h"
+
+namespace hp {
+
+// Which MFMA path a product runs on.
+enum Engine { ENG_F64, ENG_F32, ENG_BF16, ENG_F16 };
+
+// Order p of each HP_METHOD_* (the p of rule (stopreliable)).
+inline int method_order(int method) {
+    static const int kOrder[] = {18, 2, 3, 7, 18};
+    return kOrder[method];
+}
+
+// Host-side state of one problem's iteration: the stopping rule, the switch
+// to the stabilised variant, the precision stages and the guards.
+struct LoopState {
+    enum Action { CONTINUE, NEXT_STAGE, DONE };
+    const hp_params* p = nullptr;
+    hp_result* res = nullptr;
+    double alpha = 0.0;
+    int stage = 2;        // 0 16-bit, 1 FP32, 2 FP64
+    int final_stage = 2;
+    bool stabilising = false;
+    bool converging = false;
+    bool stage_first = true;  // no stagnation test on a stage's first loop
+    double d_prev = 0.0;
+    int ik = 0, in_ = 1;  // current and next iterate (index into the stage's set)
+    int k = 0;            // loops run
+    int status = HP_MAXITER;
+    int result_idx = -1;  // iterate to return (index into the final stage's set)
+    int from_idx = 0;     // NEXT_STAGE: iterate the next stage starts from
+
+    void init(const hp_params* prm, hp_result* r, double a);
+    Engine engine() const;
+    // Digest one loop's sums; `dinf` is used if have_dinf.
+    Action step(double diff2, double ref2, double dinf, bool have_dinf);
+    // After NEXT_STAGE the caller moves the iterate `from_idx` into the next
+    // stage's set; this resets the indices (FP64 stage: X[0]).
+    void enter_stage(int next);
+    bool done() const { return result_idx >= 0; }
+    // HP_STOP_REL_FRO_BOUND: after a CONTINUE, whether the next loop is a
+    // plain loop of the final stage whose change the residual bound may
+    // already settle (the last change d has d^p < tol).
+    bool bound_ready() const;
+    // The residual bound settled it: return the current iterate.
+    void stop_bound(double bound) {
+        status = HP_OK;
+        result_idx = ik;
+        res->stop_last = bound;
+    }
+    void finish_maxiter() {
+        if (result_idx < 0) result_idx = ik;
+    }
+};
+
+}  // namespace hp

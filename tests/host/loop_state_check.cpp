@@ -1,0 +1,51 @@
+// Drives hp::LoopState (the library's per-loop control: stopping rules,
+// stabilised switch, precision stages, guards) from a scripted sequence of
+// per-loop stopping sums, with no GPU. Test infrastructure.
+//
+// stdin:  precision stop_rule tol tau_switch variant max_iter method alpha
+//         diverge_limit low_dtype
+//         then one line per loop: diff2 ref2 dinf
+// stdout: one JSON object with the action after each loop, the final status,
+//         loop count, switch loop, per-stage loop counts, whether the returned
+//         iterate is the newest one, and the last stopping-rule value.
+#include <cstdio>
+#include <vector>
+
+#include "hp_loop.h"
+
+int main() {
+    hp_params p{};  // the fields the loop control reads come from stdin
+    if (std::scanf("%d %d %lf %lf %d %d %d %lf %lf %d", &p.precision, &p.stop_rule, &p.tol,
+                   &p.tau_switch, &p.variant, &p.max_iter, &p.method, &p.alpha, &p.diverge_limit,
+                   &p.low_dtype) != 10)
+        return 2;
+    hp_result r{};
+    hp::LoopState st;
+    st.init(&p, &r, p.alpha);
+    std::vector<int> actions;
+    bool returns_new = false, done = false;
+    double diff2, ref2, dinf;
+    while (!done && st.k < p.max_iter && std::scanf("%lf %lf %lf", &diff2, &ref2, &dinf) == 3) {
+        const int newest = st.in_;
+        const hp::LoopState::Action a =
+            st.step(diff2, ref2, dinf, p.stop_rule == HP_STOP_ABS_INF);
+        actions.push_back((int)a);
+        if (a == hp::LoopState::DONE) {
+            done = true;
+            returns_new = st.result_idx == newest;
+        } else if (a == hp::LoopState::NEXT_STAGE) {
+            st.enter_stage(st.stage + 1);
+        }
+    }
+    if (!done) {
+        st.finish_maxiter();
+        returns_new = true;  // after a CONTINUE the newest iterate is the current one
+    }
+    std::printf("{\"actions\": [");
+    for (size_t i = 0; i < actions.size(); ++i) std::printf("%s%d", i ? ", " : "", actions[i]);
+    std::printf("], \"status\": %d, \"iters\": %d, \"switch_iter\": %d, \"iters_stage\": [%d, %d, %d], "
+                "\"returns_new\": %s, \"stop_last\": %.17g}\n",
+                st.status, r.iters, r.switch_iter, r.iters_stage[0], r.iters_stage[1],
+                r.iters_stage[2], returns_new ? "true" : "false", r.stop_last);
+    return 0;
+}

@@ -63,3 +63,56 @@ def test_host_only_calls():
         hpw.workspace_bytes(hpw.make_params(kind="drazin", l=0), 10, 10)
     with pytest.raises(hpw.HyperpowerError):
         hpw.workspace_bytes(hpw.make_params(alpha_rule="user", alpha=-1.0), 10, 10)
+
+
+EINVAL, EUNSUPPORTED = -1, -5
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
+@pytest.mark.parametrize("kw,m,n,code", [
+    (dict(chop=-1.0), 10, 10, EINVAL),
+    (dict(chop=1e-5, precision="mixed"), 10, 10, EUNSUPPORTED),
+    (dict(chop=1e-5, stop="rel_fro_bound"), 10, 10, EUNSUPPORTED),
+    (dict(alpha_rule="diag"), 12, 10, EINVAL),
+    (dict(method="sm", precision="mixed"), 10, 10, EUNSUPPORTED),
+    (dict(kind="drazin", l=2, precision="fp32"), 10, 10, EUNSUPPORTED),
+    (dict(kind="drazin", l=2, alpha_rule="norm1inf"), 10, 10, EINVAL),
+    (dict(tol=-1.0), 10, 10, EINVAL),
+    (dict(max_iter=0), 10, 10, EINVAL),
+    (dict(), 0, 10, EINVAL),
+    (dict(), 65536, 10, EINVAL),
+])
+def test_parameter_validation_on_the_host(kw, m, n, code):
+    """hp_workspace_bytes runs the same validation as hp_solve, with no GPU."""
+    from paper_1604_07893_amd import hyperpower as hpw
+    with pytest.raises(hpw.HyperpowerError) as e:
+        hpw.workspace_bytes(hpw.make_params(**kw), m, n)
+    assert e.value.code == code
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
+def test_reserved_fields_must_be_zero():
+    from paper_1604_07893_amd import hyperpower as hpw
+    for field in ("reserved0",):
+        p = hpw.make_params()
+        setattr(p, field, 1)
+        with pytest.raises(hpw.HyperpowerError):
+            hpw.workspace_bytes(p, 10, 10)
+    p = hpw.make_params()
+    p.reserved[1] = 7
+    with pytest.raises(hpw.HyperpowerError):
+        hpw.workspace_bytes(p, 10, 10)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
+def test_workspace_follows_the_plan():
+    """The left form keeps its loop matrices n x n (smaller for m > n); the
+    FP32 and 16-bit stages add their own sets; FP32-only keeps one FP64
+    iterate."""
+    from paper_1604_07893_amd import hyperpower as hpw
+    wb = lambda **kw: hpw.workspace_bytes(hpw.make_params(**kw), 4096, 2048)
+    left, right = wb(side="left"), wb(side="right")
+    assert wb() == left < right
+    assert 7 * 4096 * 4096 * 8 < right
+    assert wb(precision="fp32") < wb() < wb(precision="fp32_fp64") < wb(precision="mixed")
+    assert hpw.workspace_bytes(hpw.make_params(), 8192, 8192) > 10 * 8192 * 8192 * 8

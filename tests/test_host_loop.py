@@ -1,0 +1,160 @@
+"""The library's per-loop control, hp::LoopState (paper_1604_07893_amd/csrc/
+hp_loop.cpp: stopping rules of Section 4 and Example 8.1, the switch to
+(PM-modified) of Section 7, the guards, the precision stages), compiled for
+the CPU with g++ and driven by tests/host/loop_state_check.cpp; no GPU.
+
+Against the oracle: fed the oracle's own per-loop sums (||X_{k+1}-X_k||_F^2,
+||X_k||_F^2 and the inf-norm change), it must take the oracle's decisions --
+loop count, status, switch loop, and whether the newest iterate or its
+predecessor is returned. The precision-stage exits have no counterpart in the
+paper or the oracle (they are this library's rule); they are checked on
+scripted change sequences against the rule as documented in hp_loop.cpp.
+"""
+
+import json
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1604_07893_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2}
+VARIANT = {"plain": 0, "stabilised": 1, "stab_always": 2}
+METHOD = {"pm": 0, "sm": 1, "cm": 2, "fm": 3, "hm": 4}
+STATUS = {0: "ok", 1: "maxiter", 2: "stagnated", 3: "diverged", 4: "nonfinite"}
+CONTINUE, NEXT_STAGE, DONE = 0, 1, 2
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = tmp_path_factory.mktemp("host") / "loop_state_check"
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-I", os.path.join(ROOT, "include"),
+                    "-I", os.path.join(ROOT, "paper_1604_07893_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "loop_state_check.cpp"),
+                    os.path.join(ROOT, "paper_1604_07893_amd", "csrc", "hp_loop.cpp"),
+                    "-o", str(exe)], check=True)
+
+    def run(loops, *, precision=0, stop="rel_fro", tol=1e-12, tau=0.1, variant="plain",
+            max_iter=100, method="pm", alpha=1.0, diverge=1e6, low=0):
+        head = (f"{precision} {STOP[stop]} {tol!r} {tau!r} {VARIANT[variant]} {max_iter} "
+                f"{METHOD[method]} {float(alpha)!r} {diverge!r} {low}\n")
+        body = "".join(f"{a!r} {b!r} {c!r}\n" for a, b, c in loops)
+        out = subprocess.run([str(exe)], input=head + body, capture_output=True, text=True,
+                             check=True)
+        return json.loads(out.stdout)
+    return run
+
+
+def oracle_loops(res):
+    return [(float(nD) ** 2, float(nX) ** 2, float(di))
+            for (nD, nX), di in zip(res.fro_hist, res.diff_inf_hist)]
+
+
+def check_against_oracle(harness, res, **kw):
+    got = harness(oracle_loops(res), **kw)
+    assert STATUS[got["status"]] == res.status
+    assert got["iters"] == res.iters
+    assert got["switch_iter"] == res.switch_iter
+    # the oracle returns X_{k+1} on success and at the loop cap, X_k otherwise
+    assert got["returns_new"] == (res.status in ("ok", "maxiter"))
+    assert got["actions"][-1] == (DONE if res.status != "maxiter" else CONTINUE)
+    return got
+
+
+def test_relative_change_stop_on_full_rank_input(harness):
+    A = inputs.uniform(60, 30, seed=1)
+    res = O.solve(A, tol=1e-12)
+    assert res.status == "ok"
+    check_against_oracle(harness, res, tol=1e-12)
+
+
+@pytest.mark.parametrize("variant", ["plain", "stabilised", "stab_always"])
+def test_guard_and_switch_on_rank_deficient_input(harness, variant):
+    """Plain PM stagnates (the guard of Section 6); the stabilised variant
+    switches at the first change below tau_switch and passes."""
+    lr = inputs.lowrank_svd(120, 60, 40, smin=1e-3, seed=6)
+    res = O.solve(lr.A, variant=variant, tol=1e-10)
+    check_against_oracle(harness, res, variant=variant, tol=1e-10)
+
+
+@pytest.mark.parametrize("alpha_scale", [2.5, 4.0])
+def test_divergence_guard(harness, alpha_scale):
+    """alpha sigma_1^2 > 2 breaks the convergence condition of Section 4."""
+    A = inputs.uniform(60, 30, seed=1)
+    a = alpha_scale / np.linalg.svd(A, compute_uv=False)[0] ** 2
+    res = O.solve(A, alpha_rule="user", alpha=a, tol=1e-12)
+    assert res.status == "diverged"
+    check_against_oracle(harness, res, alpha=a, tol=1e-12)
+
+
+@pytest.mark.parametrize("method", ["pm", "sm", "cm", "fm", "hm"])
+def test_paper_rule_divides_by_p_to_the_k_alpha(harness, method):
+    d = inputs.square_svd(48, smin=1e-2, seed=7)
+    res = O.solve(d.A, method=method, stop="paper_4_1", tol=1e-8)
+    got = check_against_oracle(harness, res, method=method, stop="paper_4_1", tol=1e-8,
+                               alpha=float(res.alpha))
+    assert got["stop_last"] == pytest.approx(float(res.stop_hist[-1]), rel=1e-12)
+
+
+def test_absolute_inf_norm_rule_on_drazin_input(harness):
+    dz = inputs.drazin_jordan(n=40, nb=30, seed=5)
+    res = O.solve(dz.A, kind="drazin", l=dz.index, stop="abs_inf", tol=1e-10)
+    check_against_oracle(harness, res, stop="abs_inf", tol=1e-10)
+
+
+def test_loop_cap(harness):
+    A = inputs.uniform(60, 30, seed=1)
+    res = O.solve(A, tol=1e-12, max_iter=3)
+    assert res.status == "maxiter"
+    check_against_oracle(harness, res, tol=1e-12, max_iter=3)
+
+
+def test_non_finite_change_returns_the_last_finite_iterate(harness):
+    got = harness([(1.0, 1.0, 0.0), (float("nan"), 1.0, 0.0), (1e-30, 1.0, 0.0)])
+    assert STATUS[got["status"]] == "nonfinite" and got["iters"] == 2
+    assert got["returns_new"] is False
+
+
+# ---- precision stages (HP_PREC_MIXED = 2, HP_PREC_FP32 = 1) ------------------
+
+def rel_loops(ds):
+    return [(d * d, 1.0, 0.0) for d in ds]
+
+
+def test_mixed_stages_exit_on_a_settled_change(harness):
+    """16-bit: 0.9 (first), 0.4 (halved), then 0.15 < 0.2 on a non-first loop
+    -> next stage; FP32: its first loop never exits on that rule, 1e-3 does;
+    FP64 runs the stopping rule."""
+    got = harness(rel_loops([0.9, 0.4, 0.15, 0.1, 1e-3, 1e-6, 1e-13]), precision=2, tol=1e-10)
+    assert got["actions"] == [CONTINUE, CONTINUE, NEXT_STAGE, CONTINUE, NEXT_STAGE, CONTINUE, DONE]
+    assert got["iters_stage"] == [3, 2, 2] and STATUS[got["status"]] == "ok"
+    assert got["returns_new"] is True
+
+
+def test_mixed_stage_exits_when_the_change_stops_halving(harness):
+    # 0.6 >= 0.5 * 0.9: stalled -> next stage; then 1e-8 is below the FP32
+    # floor on the FP32 stage's first loop -> FP64
+    got = harness(rel_loops([0.9, 0.6, 1e-8, 1e-13]), precision=2, tol=1e-10)
+    assert got["actions"] == [CONTINUE, NEXT_STAGE, NEXT_STAGE, DONE]
+    assert got["iters_stage"] == [2, 1, 1]
+
+
+def test_fp32_floor_exits_even_on_a_first_loop(harness):
+    # below 10 u_fp32 = 6e-7: the FP32 stage has nothing left to gain
+    got = harness(rel_loops([0.5, 1e-7, 1e-9, 1e-13]), precision=3, tol=1e-10)
+    assert got["actions"] == [CONTINUE, NEXT_STAGE, CONTINUE, DONE]
+    assert got["iters_stage"] == [0, 2, 2]
+
+
+def test_fp32_only_precision_stops_on_its_own_tolerance(harness):
+    got = harness(rel_loops([0.5, 1e-3, 1e-6]), precision=1, tol=1e-5)
+    assert got["actions"] == [CONTINUE, CONTINUE, DONE]
+    assert got["iters_stage"] == [0, 3, 0] and STATUS[got["status"]] == "ok"
