@@ -415,10 +415,9 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         }
         return HP_OK;
     };
-    // HP_STOP_REL_FRO_BOUND: form the next loop's residual R (its first
-    // product, into S[0]) and ||R||_F^2; true if ||R||_F/(1-||R||_F) < tol.
-    auto residual_bound = [&](bool* settled) -> int {
-        *settled = false;
+    // Form the next loop's residual R (its first product, into S[0]) and
+    // return ||R||_F in *r.
+    auto next_residual = [&](double* r) -> int {
         const int64_t sd = pl.s;
         if (st.stage == 2) {
             GemmCall<double> calls[kMaxLoopGemms];
@@ -437,7 +436,14 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         HIPCHK(hipMemcpyAsync(hs, bf.scal, sizeof(double) * SLOT_COUNT, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         S.timer.harvest();
-        const double r = std::sqrt(hs[SLOT_RNORM2]);
+        *r = std::sqrt(hs[SLOT_RNORM2]);
+        return HP_OK;
+    };
+    // HP_STOP_REL_FRO_BOUND: R as above; true if ||R||_F/(1-||R||_F) < tol.
+    auto residual_bound = [&](bool* settled) -> int {
+        *settled = false;
+        double r = 0.0;
+        CHK(next_residual(&r));
         if (std::isfinite(r) && r < 1.0 && r / (1.0 - r) < p->tol) {
             st.stop_bound(r / (1.0 - r));
             *settled = true;
@@ -459,8 +465,14 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         HIPCHK(hipStreamSynchronize(s));
         S.timer.harvest();
 
-        const LoopState::Action a = st.step(hs[SLOT_DIFF2], hs[SLOT_REF2], hs[SLOT_DINF], inf_now);
+        LoopState::Action a = st.step(hs[SLOT_DIFF2], hs[SLOT_REF2], hs[SLOT_DINF], inf_now);
         if (a == LoopState::DONE) break;
+        if (a == LoopState::CONTINUE && st.k < p->max_iter && st.probe) {
+            double r = 0.0;
+            CHK(next_residual(&r));
+            if (st.probe_exit(r)) a = LoopState::NEXT_STAGE;
+            else r_ready = true;
+        }
         if (a == LoopState::CONTINUE && st.k < p->max_iter && st.bound_ready()) {
             bool settled = false;
             CHK(residual_bound(&settled));

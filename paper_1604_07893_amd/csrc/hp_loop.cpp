@@ -52,6 +52,7 @@ void LoopState::enter_stage(int next) {
 }
 
 LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool have_dinf) {
+    probe = false;
     res->iters = k + 1;
     res->iters_stage[stage] += 1;
     const double d = std::sqrt(diff2) / std::sqrt(ref2);
@@ -91,6 +92,9 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
             d_prev = d;
             return NEXT_STAGE;
         }
+        // the first FP32 loop's change says little about the slow directions
+        // (above), but the residual of its output measures them directly
+        probe = stage == 1 && final_stage == 2 && stage_first && d < kPredict;
         stage_first = false;
         d_prev = d;
         std::swap(ik, in_);

@@ -39,6 +39,12 @@ struct LoopState {
     int result_idx = -1;  // iterate to return (index into the final stage's set)
     int from_idx = 0;     // NEXT_STAGE: iterate the next stage starts from
 
+    // Set by step() after the first loop of the FP32 stage (when the FP64
+    // stage follows) if that loop changed X by less than kPredict: the caller
+    // may then form the next loop's residual R = I - A X_{k+1} (its first
+    // product) and call probe_exit(||R||_F).
+    bool probe = false;
+
     void init(const hp_params* prm, hp_result* r, double a);
     Engine engine() const;
     // Digest one loop's sums; `dinf` is used if have_dinf.
@@ -51,6 +57,14 @@ struct LoopState {
     // plain loop of the final stage whose change the residual bound may
     // already settle (the last change d has d^p < tol).
     bool bound_ready() const;
+    // After a probe: true (and the FP64 stage is to start from X_{k+1}) when
+    // one loop of order p from there would take the residual below tol,
+    // r^p < tol; otherwise the stage goes on (reusing R).
+    bool probe_exit(double r) {
+        if (!(std::isfinite(r) && std::pow(r, (double)method_order(p->method)) < p->tol)) return false;
+        from_idx = ik;
+        return true;
+    }
     // The residual bound settled it: return the current iterate.
     void stop_bound(double bound) {
         status = HP_OK;

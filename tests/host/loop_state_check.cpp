@@ -4,7 +4,9 @@
 //
 // stdin:  precision stop_rule tol tau_switch variant max_iter method alpha
 //         diverge_limit low_dtype
-//         then one line per loop: diff2 ref2 dinf
+//         then one line per loop: diff2 ref2 dinf [rnorm]; rnorm is the norm
+//         of the next loop's residual, handed to probe_exit when the loop
+//         asks for it (LoopState::probe)
 // stdout: one JSON object with the action after each loop, the final status,
 //         loop count, switch loop, per-stage loop counts, whether the returned
 //         iterate is the newest one, and the last stopping-rule value.
@@ -24,11 +26,16 @@ int main() {
     st.init(&p, &r, p.alpha);
     std::vector<int> actions;
     bool returns_new = false, done = false;
-    double diff2, ref2, dinf;
-    while (!done && st.k < p.max_iter && std::scanf("%lf %lf %lf", &diff2, &ref2, &dinf) == 3) {
+    char line[512];
+    while (!done && st.k < p.max_iter && std::fgets(line, sizeof line, stdin)) {
+        double diff2, ref2, dinf, rnorm = -1.0;
+        const int got = std::sscanf(line, "%lf %lf %lf %lf", &diff2, &ref2, &dinf, &rnorm);
+        if (got < 3) continue;
         const int newest = st.in_;
-        const hp::LoopState::Action a =
-            st.step(diff2, ref2, dinf, p.stop_rule == HP_STOP_ABS_INF);
+        hp::LoopState::Action a = st.step(diff2, ref2, dinf, p.stop_rule == HP_STOP_ABS_INF);
+        if (a == hp::LoopState::CONTINUE && st.k < p.max_iter && st.probe && got == 4 &&
+            st.probe_exit(rnorm))
+            a = hp::LoopState::NEXT_STAGE;
         actions.push_back((int)a);
         if (a == hp::LoopState::DONE) {
             done = true;

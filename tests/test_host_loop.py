@@ -46,7 +46,7 @@ def harness(tmp_path_factory):
             max_iter=100, method="pm", alpha=1.0, diverge=1e6, low=0):
         head = (f"{precision} {STOP[stop]} {tol!r} {tau!r} {VARIANT[variant]} {max_iter} "
                 f"{METHOD[method]} {float(alpha)!r} {diverge!r} {low}\n")
-        body = "".join(f"{a!r} {b!r} {c!r}\n" for a, b, c in loops)
+        body = "".join(" ".join(repr(float(v)) for v in row) + "\n" for row in loops)
         out = subprocess.run([str(exe)], input=head + body, capture_output=True, text=True,
                              check=True)
         return json.loads(out.stdout)
@@ -158,3 +158,19 @@ def test_fp32_only_precision_stops_on_its_own_tolerance(harness):
     got = harness(rel_loops([0.5, 1e-3, 1e-6]), precision=1, tol=1e-5)
     assert got["actions"] == [CONTINUE, CONTINUE, DONE]
     assert got["iters_stage"] == [0, 3, 0] and STATUS[got["status"]] == "ok"
+
+
+def test_fp32_stage_leaves_after_one_loop_when_its_residual_allows(harness):
+    """The first FP32 loop after the 16-bit stage changed X by 0.1 < 0.2; the
+    residual of its output, ||R||_F = 0.05, satisfies 0.05^18 < tol, so the FP64
+    stage starts from that output at once; with ||R||_F = 0.5 the FP32 stage
+    goes on (and its next loop reuses R)."""
+    seq = [(0.81, 1.0, 0.0), (0.16, 1.0, 0.0), (0.0225, 1.0, 0.0), (0.01, 1.0, 0.0, 0.05),
+           (1e-12, 1.0, 0.0), (1e-26, 1.0, 0.0)]
+    got = harness(seq, precision=2, tol=1e-10)
+    assert got["actions"] == [CONTINUE, CONTINUE, NEXT_STAGE, NEXT_STAGE, CONTINUE, DONE]
+    assert got["iters_stage"] == [3, 1, 2] and got["returns_new"] is True
+    seq[3] = (0.01, 1.0, 0.0, 0.5)
+    got = harness(seq, precision=2, tol=1e-10)
+    assert got["actions"][:5] == [CONTINUE, CONTINUE, NEXT_STAGE, CONTINUE, NEXT_STAGE]
+    assert got["iters_stage"][1] == 2
