@@ -280,6 +280,10 @@ def extra_served(hpw, torch, n_req: int, warm: int):
     mats = [torch.from_numpy(r.A).cuda() for r in reqs]
     torch.cuda.synchronize()
 
+    # accuracy sample: requests after the warm-up with m <= 768 (pinv on the host)
+    sample = [i for i in range(warm, len(reqs)) if reqs[i].A.shape[0] <= 768][:12]
+    kept = {}
+
     def run(arrivals):
         srv = hpw.Server(hbm_budget=budget, max_slots=64, **kw)
         t0 = time.perf_counter()
@@ -302,19 +306,53 @@ def extra_served(hpw, torch, n_req: int, warm: int):
                     i, arr = pending.pop(tk)
                     lat.append((i, t_now - arr))
                     res.append((i, r[1]))
+                    if i in sample or r[1]["status"] != "ok":
+                        kept[i] = r[0].cpu().numpy()
                     done += 1
         wall = time.perf_counter() - t0
         srv.close()
         return wall, lat, res
 
     # saturation: everything arrives at t = 0
-    wall0, _, _ = run([0.0] * len(mats))
+    wall0, _, res0 = run([0.0] * len(mats))
     sat = len(mats) / wall0
+    pinv = {i: np.linalg.pinv(reqs[i].A) for i in sample}
+    served_err = [rel(kept[i], pinv[i]) for i in sample]
+    # the requests that did not end "ok" (the stagnation guard): their error
+    not_ok = {i: (r["status"], rel(kept[i], np.linalg.pinv(reqs[i].A)), reqs[i].A.shape,
+                  reqs[i].rank_deficient)
+              for i, r in res0 if r["status"] != "ok"}
+    # the plain FP64 GPU method on the same requests, one hp_solve after another
+    kw64 = dict(variant="stabilised", tol=1e-10, precision="fp64")
+    for A in mats[:warm]:
+        hpw.solve(A, **kw64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_status, seq_err = [], []
+    for i, A in enumerate(mats):
+        X, info = hpw.solve(A, **kw64)
+        seq_status.append(info["status"])
+        if i in sample:
+            seq_err.append(rel(X.cpu().numpy(), pinv[i]))
+    torch.cuda.synchronize()
+    seq_rate = len(mats) / (time.perf_counter() - t0)
     out = {"workload": (f"{n_req} Poisson requests (+{warm} warm-up), m log-uniform [64,2048], "
                         "n=m/r r in {1,2,4}, N(0,1), 10% rank-deficient; FP32 loops + FP64 "
                         "final loops in grouped launches; budget 32 GiB, 64 slots; offered at "
                         "50/80/95% of the saturation rate (headline: 80%)"),
-           "saturation_req_per_s": sat}
+           "saturation_req_per_s": sat,
+           "plain_fp64_sequential": {
+               "what": "the same requests solved one after another by hp_solve, FP64, stabilised, "
+                       "tol 1e-10 (the plain FP64 GPU method)",
+               "inverses_per_s": seq_rate,
+               "ok_fraction": seq_status.count("ok") / len(seq_status),
+               "rel_err_vs_pinv_max_sample": max(seq_err)},
+           "served_rel_err_vs_pinv_max_sample": max(served_err),
+           "served_not_ok": [{"status": v[0], "rel_err_vs_pinv": v[1], "shape": list(v[2]),
+                              "rank_deficient": bool(v[3])} for v in not_ok.values()],
+           "accuracy_sample": f"{len(sample)} requests with m <= 768, relative Frobenius error "
+                              "against numpy.linalg.pinv",
+           "speedup_saturation_vs_plain_fp64": sat / seq_rate}
     pct = lambda v, q: float(np.percentile(v, q))
     for frac in (0.5, 0.8, 0.95):
         qps = frac * sat
@@ -330,7 +368,8 @@ def extra_served(hpw, torch, n_req: int, warm: int):
                "p50_ms": pct(lat_ms, 50), "p99_ms": pct(lat_ms, 99),
                "queue_p50_ms": pct(q_ms, 50), "queue_p99_ms": pct(q_ms, 99),
                "run_p50_ms": pct(r_ms, 50), "run_p99_ms": pct(r_ms, 99),
-               "ok_fraction": statuses.count("ok") / len(statuses)}
+               "ok_fraction": statuses.count("ok") / len(statuses),
+               "status_counts": {k: statuses.count(k) for k in sorted(set(statuses))}}
         out[f"at_{int(frac * 100)}pct"] = rec
         if frac == 0.8:
             out.update({k: rec[k] for k in ("offered_qps", "inverses_per_s", "p50_ms", "p99_ms",

@@ -287,6 +287,10 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
         Problem& P = *act[i];
         LoopState& st = P.st;
         const LoopState::Action a = st.step(hout[2 * i], hout[2 * i + 1], 0.0, false);
+        if (a == LoopState::CONTINUE && st.projection_due()) {
+            CHK(project_mp(P.pl, P.bf, st.ik, g.s, single_gemm(g, P)));
+            st.projected();
+        }
         if (a == LoopState::NEXT_STAGE) {
             const int next = st.stage + 1;
             if (next == 2) {
@@ -294,7 +298,8 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
                                P.bf.b64.X[0], P.bf.b64.ldX, g.s));
                 bool proj = false;
                 CHK(needs_projection(P.pl, P.bf, g.h->host_scal, g.s, &proj));
-                if (proj) CHK(project_mp(P.pl, P.bf, g.s, single_gemm(g, P)));
+                if (proj && st.exit_converged) CHK(project_mp(P.pl, P.bf, 0, g.s, single_gemm(g, P)));
+                else if (proj) st.proj_pending = true;
             }
             st.enter_stage(next);
         }

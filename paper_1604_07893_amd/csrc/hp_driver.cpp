@@ -473,7 +473,16 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
             if (st.probe_exit(r)) a = LoopState::NEXT_STAGE;
             else r_ready = true;
         }
-        if (a == LoopState::CONTINUE && st.k < p->max_iter && st.bound_ready()) {
+        auto project = [&](int xi) {
+            S.stage = 2;
+            return project_mp(pl, bf, xi, s, [&](const GemmCall<double>& g) {
+                return S.gemm<double>(ENG_F64, g);
+            });
+        };
+        if (a == LoopState::CONTINUE && st.projection_due()) {
+            CHK(project(st.ik));  // deferred from the stage change (below)
+            st.projected();
+        } else if (a == LoopState::CONTINUE && st.k < p->max_iter && st.bound_ready()) {
             bool settled = false;
             CHK(residual_bound(&settled));
             if (settled) break;
@@ -485,12 +494,10 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
                 HIPCHK(convert(bf.b32.X[st.from_idx], bf.b32.ldX, n, m, bf.b64.X[0], bf.b64.ldX, s));
                 bool proj = false;
                 CHK(needs_projection(pl, bf, hs, s, &proj));
-                if (proj) {
-                    S.stage = 2;
-                    CHK(project_mp(pl, bf, s, [&](const GemmCall<double>& g) {
-                        return S.gemm<double>(ENG_F64, g);
-                    }));
-                }
+                // the projection assumes an iterate in the converging regime;
+                // after an earlier exit it waits for the FP64 loops to get there
+                if (proj && st.exit_converged) CHK(project(0));
+                else if (proj) st.proj_pending = true;
             }
             st.enter_stage(next);
         }

@@ -427,13 +427,13 @@ int setup_x0(const hp_params* p, const Plan& pl, const Buffers& bf, const double
 // error blocks are carried unchanged). This step is not part of the paper: it
 // applies the third and fourth Penrose equations ((AX)^T = AX, (XA)^T = XA),
 // which the Moore-Penrose inverse satisfies. Associated so that every
-// intermediate is min(m, n) square; X is b64.X[0] in and out. A square
+// intermediate is min(m, n) square; X is b64.X[xi] in and out. A square
 // nonsingular input has no such blocks and skips it (see needs_projection).
 template <typename GemmFn>
-int project_mp(const Plan& pl, const Buffers& bf, hipStream_t s, GemmFn&& gemm) {
+int project_mp(const Plan& pl, const Buffers& bf, int xi, hipStream_t s, GemmFn&& gemm) {
     const int64_t m = pl.m, n = pl.n;
     const Set<double>& b = bf.b64;
-    double* X = b.X[0];
+    double* X = b.X[xi];
     HIPCHK(transpose_scale(b.A, b.ldA, m, n, bf.At, b.ldX, nullptr, s));  // A^T: n x m
     HIPCHK(transpose_scale(X, b.ldX, n, m, bf.Xt, b.ldA, nullptr, s));    // X^T: m x n
     if (m > n) {

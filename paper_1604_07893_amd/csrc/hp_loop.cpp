@@ -80,7 +80,10 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         // continues from the better of the last two iterates
         const double u = stage == 0 ? (p->low_dtype == HP_LOWP_F16 ? 4.8828125e-4 : 3.90625e-3)
                                     : kUnitRoundoffF32;
-        const bool stalled = !stage_first && d < 1.0 && d >= 0.5 * d_prev;
+        // (two changes below 1 in a row: while the slow directions still grow,
+        // on ill-conditioned input, the change can rise and fall above and
+        // around 1 without any stall)
+        const bool stalled = !stage_first && d < 1.0 && d_prev < 1.0 && d >= 0.5 * d_prev;
         const bool floor = d < 10.0 * u || d < p->tol;
         if (finite) note_switch();
         // (not on a stage's first loop: its change is mostly the step between
@@ -89,6 +92,7 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         if (!finite || stalled || floor || settled) {
             const bool keep_new = finite && !(stalled && d >= d_prev);
             from_idx = keep_new ? in_ : ik;
+            exit_converged = finite && d < kPredict;
             d_prev = d;
             return NEXT_STAGE;
         }
@@ -139,6 +143,10 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
     d_prev = d;
     std::swap(ik, in_);
     return CONTINUE;
+}
+
+bool LoopState::projection_due() const {
+    return proj_pending && stage == final_stage && d_prev < kPredict;
 }
 
 bool LoopState::bound_ready() const {

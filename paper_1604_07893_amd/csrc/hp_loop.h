@@ -63,7 +63,20 @@ struct LoopState {
     bool probe_exit(double r) {
         if (!(std::isfinite(r) && std::pow(r, (double)method_order(p->method)) < p->tol)) return false;
         from_idx = ik;
+        exit_converged = true;
         return true;
+    }
+    // On NEXT_STAGE: whether the lower stage ended in the converging regime
+    // (last change below kPredict). The Penrose projection on entering FP64
+    // assumes it; otherwise the caller defers the projection (proj_pending)
+    // until projection_due(), after an FP64 loop whose change is that small,
+    // and then calls projected().
+    bool exit_converged = false;
+    bool proj_pending = false;
+    bool projection_due() const;
+    void projected() {
+        proj_pending = false;
+        stage_first = true;  // the projection's own change is not a stall
     }
     // The residual bound settled it: return the current iterate.
     void stop_bound(double bound) {

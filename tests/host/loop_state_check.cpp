@@ -9,7 +9,9 @@
 //         asks for it (LoopState::probe)
 // stdout: one JSON object with the action after each loop, the final status,
 //         loop count, switch loop, per-stage loop counts, whether the returned
-//         iterate is the newest one, and the last stopping-rule value.
+//         iterate is the newest one, the last stopping-rule value, and (for an
+//         input that needs the Penrose projection on entering FP64) the loop
+//         after which the projection runs (0: at the stage change; -1: never).
 #include <cstdio>
 #include <vector>
 
@@ -25,6 +27,7 @@ int main() {
     hp::LoopState st;
     st.init(&p, &r, p.alpha);
     std::vector<int> actions;
+    int projected_at = -1;
     bool returns_new = false, done = false;
     char line[512];
     while (!done && st.k < p.max_iter && std::fgets(line, sizeof line, stdin)) {
@@ -37,10 +40,18 @@ int main() {
             st.probe_exit(rnorm))
             a = hp::LoopState::NEXT_STAGE;
         actions.push_back((int)a);
+        if (a == hp::LoopState::CONTINUE && st.projection_due()) {
+            st.projected();
+            projected_at = st.k;
+        }
         if (a == hp::LoopState::DONE) {
             done = true;
             returns_new = st.result_idx == newest;
         } else if (a == hp::LoopState::NEXT_STAGE) {
+            if (st.stage + 1 == st.final_stage) {  // as for an input that needs the projection
+                if (st.exit_converged) projected_at = 0;
+                else st.proj_pending = true;
+            }
             st.enter_stage(st.stage + 1);
         }
     }
@@ -51,8 +62,8 @@ int main() {
     std::printf("{\"actions\": [");
     for (size_t i = 0; i < actions.size(); ++i) std::printf("%s%d", i ? ", " : "", actions[i]);
     std::printf("], \"status\": %d, \"iters\": %d, \"switch_iter\": %d, \"iters_stage\": [%d, %d, %d], "
-                "\"returns_new\": %s, \"stop_last\": %.17g}\n",
+                "\"returns_new\": %s, \"stop_last\": %.17g, \"projected_at\": %d}\n",
                 st.status, r.iters, r.switch_iter, r.iters_stage[0], r.iters_stage[1],
-                r.iters_stage[2], returns_new ? "true" : "false", r.stop_last);
+                r.iters_stage[2], returns_new ? "true" : "false", r.stop_last, projected_at);
     return 0;
 }

@@ -174,3 +174,25 @@ def test_fp32_stage_leaves_after_one_loop_when_its_residual_allows(harness):
     got = harness(seq, precision=2, tol=1e-10)
     assert got["actions"][:5] == [CONTINUE, CONTINUE, NEXT_STAGE, CONTINUE, NEXT_STAGE]
     assert got["iters_stage"][1] == 2
+
+
+def test_fp32_stage_rides_out_the_transient_of_an_ill_conditioned_input(harness):
+    """Changes of a square N(0,1) 340x340 request (kappa 2.6e3) under FP32
+    loops: they rise and fall around 1 while the slow directions grow. A change
+    of 0.79 after 1.43 is no stall; the stage ends only at 1.5e-5 (settled), in
+    the converging regime, where the projection may run at once."""
+    seq = rel_loops([15.9, 7.97, 2.27, 1.62, 1.43, 0.79, 4.5, 0.34, 1.5e-5, 1.3e-5, 1e-16])
+    got = harness(seq, precision=3, tol=1e-10, variant="stabilised")
+    assert got["actions"][:9] == [CONTINUE] * 8 + [NEXT_STAGE]
+    assert got["iters_stage"] == [0, 9, 2] and STATUS[got["status"]] == "ok"
+    assert got["projected_at"] == 0
+
+
+def test_projection_waits_for_the_converging_regime(harness):
+    """A lower stage that ends on a stall above kPredict (0.6 after 0.9) hands
+    over an iterate that is not yet converging: the projection waits for the
+    first FP64 change below 0.2."""
+    got = harness(rel_loops([0.9, 0.6, 0.3, 0.01, 1e-9, 1e-16]), precision=3, tol=1e-12)
+    assert got["actions"][:2] == [CONTINUE, NEXT_STAGE]
+    assert got["projected_at"] == 4          # after the FP64 loop whose change was 0.01
+    assert STATUS[got["status"]] == "ok"
