@@ -388,7 +388,9 @@ int hp_serve_create(hp_handle* h, const hp_params* p, size_t hbm_budget, int max
 /* HP_EBUDGET if the request alone exceeds the budget, HP_EINVAL for a bad
  * shape; otherwise queues it and returns a ticket. */
 int hp_serve_submit(hp_server* sv, const hp_problem* prob, uint64_t* ticket);
-/* One scheduling step; reports the requests running and waiting after it. */
+/* One scheduling step; reports the requests running and waiting after it
+ * (either pointer may be NULL). A negative return (HP_EHIP) leaves the
+ * server's requests in an undefined state: destroy it. */
 int hp_serve_step(hp_server* sv, int* active, int* waiting);
 /* HP_PENDING while the request is queued or running; afterwards its final
  * status (out filled, ticket released). HP_EINVAL for an unknown ticket. */
