@@ -36,6 +36,10 @@ HIPCC_FLAGS = [
 ]
 
 
+# roctx ranges around the solve's phases (rocprofv3 --marker-trace)
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if c and os.path.exists(c):
@@ -46,7 +50,7 @@ def hipcc() -> str:
 def build(verbose: bool = True) -> str:
     tmp = OUT + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+           *[os.path.join(CSRC, s) for s in SOURCES], *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

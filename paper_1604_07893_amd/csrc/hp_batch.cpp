@@ -240,6 +240,7 @@ int retire(Group& g, Problem& P) {
 // One loop of every problem in `act` (all admitted, none finished). Problems
 // that finish are retired (X written, stream synchronised before return).
 int group_loop(Group& g, std::vector<Problem*>& act) {
+    Range range("grouped loop, %d problems", (int)act.size());
     Tables& tb = g.tb;
     std::memset(tb.host, 0, tb.off_red);
     const int np = (int)act.size();
@@ -382,6 +383,7 @@ int hp_solve_batched(hp_handle* h, const hp_params* p, int count, const hp_probl
     if (!h || !p || count < 1 || !probs) return HP_EINVAL;
     CHK(validate_group_params(p));
     for (int i = 0; i < count; ++i) CHK(validate_problem(p, probs[i]));
+    Range range("hp_solve_batched %d problems", count);
     size_t need = 0;
     CHK(hp_batched_workspace_bytes(p, count, probs, &need));
     if (!workspace || ws_bytes < need) return HP_EWORKSPACE;
@@ -476,6 +478,7 @@ int hp_serve_submit(hp_server* sv, const hp_problem* prob, uint64_t* ticket) {
 
 int hp_serve_step(hp_server* sv, int* active, int* waiting) {
     if (!sv) return HP_EINVAL;
+    Range range("hp_serve_step");
     if (hipSetDevice(sv->g.h->device) != hipSuccess) return HP_EHIP;
     // admit in arrival order while a slot and memory are free
     CHK(sv->adm.admit([&](uint64_t t, size_t off) {

@@ -147,7 +147,7 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area) {
     const int64_t big = std::max(m, n);
     const int64_t blocks = (int64_t)hp::gemm_max_blocks(big, big);
     int64_t small = 2 * blocks;
-    small = std::max<int64_t>(small, ((m + 255) / 256 + 2) * n + m);
+    small = std::max<int64_t>(small, ((m + hp::kColChunk - 1) / hp::kColChunk + 2) * n + m);
     small = std::max<int64_t>(small, ((n + 31) / 32) * ((n + 31) / 32));
     small = std::max<int64_t>(small, big);
     pl.offSmall = off;
@@ -371,8 +371,11 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
 
     double alpha = 0.0;
     S.stage = 2;
-    CHK(setup_x0(p, pl, bf, A, lda, X0, ldx0, hs, s,
-                 [&](const GemmCall<double>& g) { return S.gemm<double>(ENG_F64, g); }, &alpha));
+    {
+        Range setup_range("set-up X0");
+        CHK(setup_x0(p, pl, bf, A, lda, X0, ldx0, hs, s,
+                     [&](const GemmCall<double>& g) { return S.gemm<double>(ENG_F64, g); }, &alpha));
+    }
     S.timer.harvest();
     res->alpha = alpha;
 
@@ -453,6 +456,8 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
     bool r_ready = false;
 
     while (st.k < p->max_iter) {
+        Range loop_range("loop %d stage %d%s", st.k + 1, st.stage,
+                         st.stabilising ? " stabilised" : "");
         S.stage = st.stage;
         CHK(run_loop(r_ready ? 1 : 0));
         r_ready = false;
@@ -474,6 +479,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
             else r_ready = true;
         }
         auto project = [&](int xi) {
+            Range proj_range("projection");
             S.stage = 2;
             return project_mp(pl, bf, xi, s, [&](const GemmCall<double>& g) {
                 return S.gemm<double>(ENG_F64, g);
@@ -620,6 +626,7 @@ int hp_solve(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64
     res->switch_iter = -1;
     res->side_used = pl.left ? HP_SIDE_LEFT : HP_SIDE_RIGHT;
 
+    Range range("hp_solve %lldx%lld", (long long)m, (long long)n);
     Solver S{h, p, reinterpret_cast<hipStream_t>(stream), pl, res,
              GemmTimer{h, (p->flags & HP_FLAG_TIME_KERNELS) != 0, 0, 0.0,
                        reinterpret_cast<hipStream_t>(stream)}};

@@ -11,6 +11,11 @@
 #include <cstdint>
 #include <type_traits>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
+#include <cstdarg>
+#include <cstdio>
+
 #include "hp_internal.h"
 #include "hp_loop.h"
 #include "hyperpower.h"
@@ -38,6 +43,23 @@ struct hp_handle {
 
 namespace hp {
 
+// A named roctx range over a scope: shows the solve's phases (set-up, each
+// loop with its stage, projection, grouped loops) on the timeline of
+// `rocprofv3 --marker-trace`; without a tool attached it costs a call.
+struct Range {
+    explicit Range(const char* fmt, ...) {
+        char buf[96];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        roctxRangePushA(buf);
+    }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+
 inline GemmType gemm_type(int dtype) {
     if (dtype == HP_DTYPE_F64) return GT_F64;
     if (dtype == HP_DTYPE_F32) return GT_F32;
@@ -60,6 +82,8 @@ inline GemmTile choose_tile(const hp_handle* h, int dtype, int64_t M, int64_t N,
     if ((t == TILE_128x128_W8_S2 || t == TILE_128x128_W8_S4) &&
         !gemm_split_runs(t, M, N, K, gemm_type(dtype), split_slots))
         t = gemm_pick_tile(M, N, K, gemm_type(dtype), false);
+    // a forced or tuned tile that this GEMM type does not run: the default
+    if (!gemm_runs(t, gemm_type(dtype))) t = gemm_pick_tile(M, N, K, gemm_type(dtype), false);
     return t;
 }
 

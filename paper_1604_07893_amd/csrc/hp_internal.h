@@ -96,7 +96,8 @@ enum GemmTile : int {
     TILE_256x256_W16 = 15,  // 16-bit-operand kernel only: 16 waves, 64x64 each
     TILE_256x256_W8_DMA = 16,   // TILE_256x256_W8 with load-to-LDS tiles (K % 64 == 0)
     TILE_256x256_W16_DMA = 17,  // TILE_256x256_W16 with load-to-LDS tiles (K % 64 == 0)
-    TILE_COUNT = 18
+    TILE_32x32_W4_K4 = 18,  // 4 waves, 16x16 each, K-tile four times as deep (small products)
+    TILE_COUNT = 19
 };
 
 // Blocks (and partial-sum pairs) a launch with this tile uses for M x N.
@@ -106,6 +107,9 @@ int gemm_max_blocks(int64_t M, int64_t N);
 // Tile choice for an M x N x K product of element type `gt`.
 // With allow_split false the choice is among the unsplit tiles.
 enum GemmType : int { GT_F64 = 0, GT_F32 = 1, GT_LOWP = 2, GT_H16 = 3 };
+// Whether the kernels of GEMM type gt run tile t (with the shape gemm_blocks
+// assumes); gemm/gemm_lowp/gemm_h16 reject the others.
+bool gemm_runs(GemmTile t, GemmType gt);
 GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow_split = true);
 // Whether split tile t runs split for this product given `slots` partial
 // tiles of scratch (it runs unsplit otherwise).
@@ -167,8 +171,11 @@ hipError_t gemm_h16(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, con
 hipError_t convert_h16(const float* X, int64_t ldx, int64_t M, int64_t N, LowPrec lp, void* H,
                        int64_t ldh, void* Ht, int64_t ldht, hipStream_t s);
 
+// Rows per partial column sum of alpha_norm1inf.
+constexpr int kColChunk = 32;
+
 // ||A||_1 and ||A||_inf of an M x N matrix, then scal[SLOT_ALPHA] =
-// 1/(||A||_1 ||A||_inf). `tmp` needs (ceil(M/256)+1)*N + M doubles.
+// 1/(||A||_1 ||A||_inf). `tmp` needs (ceil(M/kColChunk)+1)*N + M doubles.
 hipError_t alpha_norm1inf(const double* A, int64_t lda, int64_t M, int64_t N, double* tmp,
                           double* scal, hipStream_t s);
 

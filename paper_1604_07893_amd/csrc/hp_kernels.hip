@@ -58,8 +58,9 @@ __global__ __launch_bounds__(kThreads) void k_abs_colsum_part(const double* __re
     const int col = blockIdx.x * kThreads + threadIdx.x;
     const int chunk = blockIdx.y;
     if (col >= N) return;
-    const int r0 = chunk * 256, r1 = min(M, r0 + 256);
+    const int r0 = chunk * kColChunk, r1 = min(M, r0 + kColChunk);
     double s = 0.0;
+#pragma unroll 8
     for (int r = r0; r < r1; ++r) s += fabs(A[(int64_t)r * lda + col]);
     part[(int64_t)chunk * N + col] = s;
 }
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void k_convert(const S* __restrict__ X, i
 
 hipError_t alpha_norm1inf(const double* A, int64_t lda, int64_t M, int64_t N, double* tmp,
                           double* scal, hipStream_t s) {
-    const int nchunk = (int)cdiv(M, 256);
+    const int nchunk = (int)cdiv(M, kColChunk);
     double* part = tmp;
     double* rows = tmp + (int64_t)nchunk * N;
     hipLaunchKernelGGL(k_abs_colsum_part, dim3((unsigned)cdiv(N, kThreads), nchunk), dim3(kThreads),
