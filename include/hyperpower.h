@@ -126,7 +126,12 @@ extern "C" {
                                change that loop would make is below tol
                                (||X(R + R^2 + ...)||_F <= ||X||_F ||R||_2 /
                                (1 - ||R||_2)), so it is skipped and X_{k+1} is
-                               returned; otherwise the loop goes on with that R.
+                               returned; otherwise the loop goes on with that R
+                               and, with HP_METHOD_PM, runs the scheme with the
+                               fewest products (SM, CM, FM, PM) whose order q
+                               has ||R||_F^q < tol/2. The check also runs
+                               before the first loop of the final stage when a
+                               lower stage ended in the converging regime.
                                Saves the confirming loop on nonsingular input
                                (R -> 0); on singular input ||R||_F stays >= 1
                                and the rule is the relative change. An

@@ -308,6 +308,7 @@ class Result:
     switch_iter: int = -1       # first loop run stabilised (-1: never)
     bound_hist: list = field(default_factory=list)  # ||R||_F of "rel_fro_bound" checks
     fro_hist: list = field(default_factory=list)    # (||X_{k+1}-X_k||_F, ||X_k||_F) per loop
+    method_hist: list = field(default_factory=list) # scheme run by each loop
 
 
 def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1inf",
@@ -336,7 +337,10 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
               "rel_fro_bound": "rel_fro", and before a plain loop that follows
               a change d with d^p < tol, r = ||I - A X_{k+1}||_F is formed;
               r/(1-r) < tol (r < 1) bounds the change that loop would make
-              below tol, so X_{k+1} is returned without it (an addition to the
+              below tol, so X_{k+1} is returned without it; otherwise, for
+              method "pm", that loop runs the scheme with the fewest products
+              (SM, CM, FM, PM: orders 2, 3, 7, 18) whose order q has
+              r^q < tol/2, which makes the next check settle (additions to the
               paper's rules).
     chop_eps  > 0: entries of each new iterate below chop_eps in magnitude are
               set to 0 at the end of the loop, before its change is measured
@@ -365,7 +369,6 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
     else:
         raise ValueError(f"unknown kind {kind!r}")
 
-    step = STEP_FUNCTIONS[method]
     p = ORDER[method]
     K = pm_constants(ar)
     res = Result(X=X, status="maxiter", iters=0, alpha=alpha)
@@ -373,8 +376,12 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
     if stabilising:
         res.switch_iter = 0
     converging = False
+    next_method = None
     for k in range(max_iter):
-        Xn = step(A, X, K, ar)
+        use = next_method or method
+        next_method = None
+        res.method_hist.append(use)
+        Xn = STEP_FUNCTIONS[use](A, X, K, ar)
         if stabilising:
             Xn = stabilise(A, Xn)
         if chop_eps > 0:
@@ -427,6 +434,13 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
             if r < 1 and r / (1 - r) < tol:
                 res.status, res.X = "ok", Xn
                 return res
+            if method == "pm" and r < 1:
+                # the next loop's residual is R^q: an order q with r^q < tol/2
+                # makes the check after it settle
+                for m in ("sm", "cm", "fm", "pm"):
+                    if r ** ORDER[m] < tol / 2:
+                        next_method = m
+                        break
         X = Xn
     res.X = X
     return res

@@ -397,19 +397,29 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
 
     // The loop's products from `first` on (the residual product, call 0, may
     // already have run for the residual bound).
-    auto run_loop = [&](int first) -> int {
+    // `scheme`: a plain final-stage loop after a residual check (first == 1) may run
+    // a lower-order scheme (LoopState::scheme_for)
+    auto run_loop = [&](int first, int scheme) -> int {
         if (st.stage == 2) {
             GemmCall<double> calls[kMaxLoopGemms];
-            const int nc = describe_loop<double>(p->method, pl, bf.b64, bf.b64.X[st.ik],
-                                                 bf.b64.X[st.in_], bf.b64.X[2], st.stabilising,
-                                                 bf.small, calls);
+            const int nc =
+                scheme != p->method && first == 1 && !st.stabilising
+                    ? describe_after_residual<double>(scheme, pl, bf.b64, bf.b64.X[st.ik],
+                                                      bf.b64.X[st.in_], bf.small, calls)
+                    : describe_loop<double>(p->method, pl, bf.b64, bf.b64.X[st.ik],
+                                            bf.b64.X[st.in_], bf.b64.X[2], st.stabilising,
+                                            bf.small, calls);
             set_chop(calls, nc, bf.b64.X[st.in_], p->chop);
             for (int i = first; i < nc; ++i) CHK(S.gemm<double>(ENG_F64, calls[i]));
         } else {
             GemmCall<float> calls[kMaxLoopGemms];
-            const int nc = describe_loop<float>(p->method, pl, bf.b32, bf.b32.X[st.ik],
-                                                bf.b32.X[st.in_], bf.b32.X[2], st.stabilising,
-                                                bf.small, calls);
+            const int nc =
+                scheme != p->method && first == 1 && !st.stabilising
+                    ? describe_after_residual<float>(scheme, pl, bf.b32, bf.b32.X[st.ik],
+                                                     bf.b32.X[st.in_], bf.small, calls)
+                    : describe_loop<float>(p->method, pl, bf.b32, bf.b32.X[st.ik],
+                                           bf.b32.X[st.in_], bf.b32.X[2], st.stabilising,
+                                           bf.small, calls);
             set_chop(calls, nc, bf.b32.X[st.in_], p->chop);
             CopyUse use[kMaxLoopGemms];
             copy_uses(calls, nc, bf.b32, use);
@@ -442,7 +452,9 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         *r = std::sqrt(hs[SLOT_RNORM2]);
         return HP_OK;
     };
-    // HP_STOP_REL_FRO_BOUND: R as above; true if ||R||_F/(1-||R||_F) < tol.
+    // HP_STOP_REL_FRO_BOUND: R as above; true if ||R||_F/(1-||R||_F) < tol,
+    // else the scheme for the loop that reuses R.
+    int scheme = p->method;
     auto residual_bound = [&](bool* settled) -> int {
         *settled = false;
         double r = 0.0;
@@ -450,6 +462,8 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         if (std::isfinite(r) && r < 1.0 && r / (1.0 - r) < p->tol) {
             st.stop_bound(r / (1.0 - r));
             *settled = true;
+        } else if (std::isfinite(r)) {
+            scheme = st.scheme_for(r);
         }
         return HP_OK;
     };
@@ -459,8 +473,9 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         Range loop_range("loop %d stage %d%s", st.k + 1, st.stage,
                          st.stabilising ? " stabilised" : "");
         S.stage = st.stage;
-        CHK(run_loop(r_ready ? 1 : 0));
+        CHK(run_loop(r_ready ? 1 : 0, scheme));
         r_ready = false;
+        scheme = p->method;
         HIPCHK(reduce_pairs(bf.small, S.last_blocks, bf.scal, s));
         const bool inf_now = want_inf && st.stage == 2;
         if (inf_now)
@@ -506,6 +521,14 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
                 else if (proj) st.proj_pending = true;
             }
             st.enter_stage(next);
+            // entering the final stage from a converged lower one: its first
+            // loop gets the residual check too (and with it its scheme)
+            if (st.k < p->max_iter && st.bound_ready() && !st.proj_pending) {
+                bool settled = false;
+                CHK(residual_bound(&settled));
+                if (settled) break;
+                r_ready = true;
+            }
         }
     }
     st.finish_maxiter();

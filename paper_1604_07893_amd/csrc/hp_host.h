@@ -226,15 +226,19 @@ constexpr int kMaxLoopGemms = 11;
 // X_{k+1/2} A X_{k+1/2} of (PM-modified), Section 7, follows, associated so
 // that the middle product is the smaller square (into `mid`, an s x s buffer
 // that is dead by then). Appends to out[c..]; returns the new count.
+// With `plus_x` (plain loops only) the product is X_k + X_k W (or X_k + W X_k).
 template <typename T>
 int describe_update(const Plan& pl, const Set<T>& b, const T* W, T* Xk, T* Xn, T* Xh, bool stab,
-                    double* partials, T* mid, GemmCall<T>* out, int c) {
+                    double* partials, T* mid, GemmCall<T>* out, int c, bool plus_x = false) {
     const int64_t m = pl.m, n = pl.n;
     const int64_t ldS = b.ldS, ldX = b.ldX, ldA = b.ldA;
     {
         EpilogueT<T> e = epilogue_plain(stab ? Xh : Xn, ldX);
         if (!stab) {
             e.ref = Xk; e.ldref = ldX; e.partials = partials;
+        }
+        if (plus_x) {
+            e.D1 = Xk; e.ld1 = ldX; e.g1[0] = 1.0;
         }
         if (pl.left) out[c++] = {n, m, n, W, ldS, Xk, ldX, e};
         else out[c++] = {n, m, m, Xk, ldX, W, ldS, e};
@@ -385,6 +389,27 @@ int describe_loop(int method, const Plan& pl, const Set<T>& b, T* Xk, T* Xn, T* 
     // the middle product goes to R^2's buffer (dead by now) so that R stays
     // available after the loop
     return describe_update(pl, b, W, Xk, Xn, Xh, stab, partials, R2, out, c);
+}
+
+// A plain loop of `method` whose residual R = I - A X_k (or I - X_k A) is
+// already in S[0] (formed by PM's first product): out[0] is that product (not
+// to be run again), the rest complete the loop. SM: X_k + X_k R; CM: W = I +
+// R + R^2 formed in one product, then X_k W; FM, PM: their own products after
+// the residual.
+template <typename T>
+int describe_after_residual(int method, const Plan& pl, const Set<T>& b, T* Xk, T* Xn,
+                            double* partials, GemmCall<T> out[kMaxLoopGemms]) {
+    if (method != HP_METHOD_SM && method != HP_METHOD_CM)
+        return describe_loop(method, pl, b, Xk, Xn, b.X[2], false, partials, out);
+    T* const* S = b.S;
+    const int64_t sd = pl.s, ldS = b.ldS;
+    int c = describe_residual(pl, b, Xk, epilogue_plain(S[0], ldS, -1.0, 1.0), out, 0);
+    if (method == HP_METHOD_SM)
+        return describe_update(pl, b, S[0], Xk, Xn, b.X[2], false, partials, S[2], out, c, true);
+    EpilogueT<T> e = epilogue_plain(S[1], ldS, 1.0, 1.0);
+    e.g1[0] = 1.0; e.D1 = S[0]; e.ld1 = ldS;
+    out[c++] = {sd, sd, sd, S[0], ldS, S[0], ldS, e};
+    return describe_update(pl, b, S[1], Xk, Xn, b.X[2], false, partials, S[2], out, c);
 }
 
 // Power-iteration steps of HP_ALPHA_SIGMA_MAX2.

@@ -78,6 +78,17 @@ struct LoopState {
         proj_pending = false;
         stage_first = true;  // the projection's own change is not a stall
     }
+    // HP_STOP_REL_FRO_BOUND with PM, after a residual check that did not
+    // settle (r = ||R||_F < 1): the scheme with the fewest products (SM, CM,
+    // FM, PM) whose order q has r^q < tol/2, so that the check after the
+    // loop settles.
+    int scheme_for(double r) const {
+        if (p->method != HP_METHOD_PM || !(r < 1.0)) return p->method;
+        static const int kByCost[] = {HP_METHOD_SM, HP_METHOD_CM, HP_METHOD_FM, HP_METHOD_PM};
+        for (int m : kByCost)
+            if (std::pow(r, (double)method_order(m)) < p->tol / 2) return m;
+        return HP_METHOD_PM;
+    }
     // The residual bound settled it: return the current iterate.
     void stop_bound(double bound) {
         status = HP_OK;
