@@ -82,3 +82,24 @@ def test_bound_rule_fp32_final_stage():
                   tol=1e-5)
     assert info["status"] == "ok"
     assert rel(X, closed) <= 1e-5
+
+
+@pytest.mark.parametrize("r1", [0.3, 0.6, 0.75])
+def test_bound_rule_scheme_choice_matches_oracle(r1):
+    """The loop after a residual check that does not settle runs SM, CM or FM
+    on the residual already formed (X + XR, X(I + R + R^2), FM's products):
+    same schemes, product count and result as the oracle's rule."""
+    say(f"bound scheme r1={r1}")
+    d = inputs.square_svd(128, smin=1e-3, seed=51)
+    r = np.zeros(128)
+    r[np.argmax(d.s)] = r1
+    X0 = (d.V * ((1 - r) / d.s)) @ d.U.T
+    ref = O.solve(d.A, X0=X0, stop="rel_fro_bound", tol=1e-10)
+    X, info = run(d.A, X0=to_dev(X0), stop="rel_fro_bound", tol=1e-10)
+    say(f"  oracle schemes {ref.method_hist} gemms {info['gemms']}")
+    assert info["status"] == ref.status == "ok"
+    assert info["iters"] == ref.iters
+    settled_by_check = len(ref.bound_hist) > len(ref.method_hist) - 1
+    assert info["gemms"] == sum(PRODUCTS[m] for m in ref.method_hist) + (1 if settled_by_check else 0)
+    closed = (d.V / d.s) @ d.U.T
+    assert rel(X, ref.X) <= 1e-10 and rel(X, closed) <= 1e-12

@@ -477,3 +477,28 @@ def test_bott_duffin_inverse_from_projector():
     assert res.status == "ok"
     closed = PL @ np.linalg.inv(A @ PL + (np.eye(n) - PL))
     assert np.linalg.norm(res.X - closed) / np.linalg.norm(closed) < 1e-11
+
+
+@pytest.mark.parametrize("r1,scheme", [(0.3, "sm"), (0.6, "cm"), (0.75, "fm")])
+def test_residual_bound_picks_the_cheapest_sufficient_scheme(r1, scheme):
+    """X0 = V diag((1 - r_i)/s_i) U^T has residual I - A X0 = U diag(r_i) U^T:
+    r_i = r1 in the direction of sigma_1, 0 elsewhere. One PM loop leaves
+    r1^18 there; the check after it finds ||R||_F = r1^18 and the next loop
+    must be the cheapest scheme whose order q has r1^(18 q) < tol/2; the check
+    after that settles, and X is V diag(1/s) U^T."""
+    d = inputs.square_svd(128, smin=1e-3, seed=51)
+    r = np.zeros(128)
+    r[np.argmax(d.s)] = r1
+    X0 = (d.V * ((1 - r) / d.s)) @ d.U.T
+    tol = 1e-10
+    res = O.solve(d.A, X0=X0, stop="rel_fro_bound", tol=tol)
+    assert res.status == "ok"
+    q = {"sm": 2, "cm": 3, "fm": 7}[scheme]
+    assert res.bound_hist[0] == pytest.approx(r1 ** 18, rel=1e-6)
+    assert (r1 ** 18) ** q < tol / 2 and all((r1 ** 18) ** p >= tol / 2 for p in (2, 3, 7) if p < q)
+    if scheme == "sm":   # r1^18 squared is already tiny: settles at the first check
+        assert res.method_hist == ["pm"] or res.method_hist == ["pm", "sm"]
+    else:
+        assert res.method_hist == ["pm", scheme]
+    closed = (d.V / d.s) @ d.U.T
+    assert np.linalg.norm(res.X - closed) / np.linalg.norm(closed) < 1e-12
