@@ -174,6 +174,9 @@ extern "C" {
 #define HP_FLAG_NO_GRAPH 4     /* batched/served: launch each loop's kernels one
                                   by one instead of replaying the captured
                                   hipGraph of the loop */
+#define HP_FLAG_NO_RETRY 8     /* served: do not retry in FP64 a request whose
+                                  lower-precision solve ended other than
+                                  HP_OK (see hp_serve_step) */
 
 /* GEMM element type for hp_gemm */
 #define HP_DTYPE_F64 0 /* FP64 operands, v_mfma_f64_16x16x4f64, FP64 accumulate */
@@ -394,7 +397,10 @@ int hp_serve_create(hp_handle* h, const hp_params* p, size_t hbm_budget, int max
  * shape; otherwise queues it and returns a ticket. */
 int hp_serve_submit(hp_server* sv, const hp_problem* prob, uint64_t* ticket);
 /* One scheduling step; reports the requests running and waiting after it
- * (either pointer may be NULL). A negative return (HP_EHIP) leaves the
+ * (either pointer may be NULL). A request whose solve with lower-precision
+ * loops ends with a status other than HP_OK is run again once, from its X0,
+ * in FP64 only (in its own arena space; its result then reports that run),
+ * unless HP_FLAG_NO_RETRY is set. A negative return (HP_EHIP) leaves the
  * server's requests in an undefined state: destroy it. */
 int hp_serve_step(hp_server* sv, int* active, int* waiting);
 /* HP_PENDING while the request is queued or running; afterwards its final

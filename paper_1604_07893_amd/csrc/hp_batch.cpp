@@ -48,6 +48,8 @@ constexpr int kSlots = 9;  // products per loop at most (7 plain + 2 stabilising
 
 struct Problem {
     hp_problem pr{};
+    hp_params prm{};      // the group's parameters (FP64 only on a retry)
+    bool retried = false;
     Plan pl;
     Buffers bf;
     char* ws = nullptr;
@@ -170,6 +172,7 @@ void group_release(Group& g) {
 // launches on the problem's own shapes.
 auto single_gemm(Group& g, Problem& P) {
     return [&g, &P](const GemmCall<double>& c) {
+        if (!c.A || !c.B || !c.ep.out[0]) return HP_EINVAL;
         const GemmTile t = choose_tile(g.h, HP_DTYPE_F64, c.M, c.N, c.K);
         if (hp::gemm(t, c.M, c.N, c.K, c.A, c.lda, c.B, c.ldb, c.ep, g.s) != hipSuccess) return HP_EHIP;
         const double gf = 2.0 * (double)c.M * (double)c.N * (double)c.K * 1e-9;
@@ -186,10 +189,10 @@ int admit(Group& g, Problem& P) {
     P.res.switch_iter = -1;
     P.res.side_used = P.pl.left ? HP_SIDE_LEFT : HP_SIDE_RIGHT;
     double alpha = 0.0;
-    CHK(setup_x0(&g.prm, P.pl, P.bf, P.pr.A, P.pr.lda, P.pr.X0, P.pr.ldx0, g.h->host_scal, g.s,
+    CHK(setup_x0(&P.prm, P.pl, P.bf, P.pr.A, P.pr.lda, P.pr.X0, P.pr.ldx0, g.h->host_scal, g.s,
                  single_gemm(g, P), &alpha));
     P.res.alpha = alpha;
-    P.st.init(&g.prm, &P.res, alpha);
+    P.st.init(&P.prm, &P.res, alpha);
     if (P.st.stage < 2) {
         HIPCHK(convert(P.bf.b64.A, P.bf.b64.ldA, P.pl.m, P.pl.n, P.bf.b32.A, P.bf.b32.ldA, g.s));
         HIPCHK(convert(P.bf.b64.X[0], P.bf.b64.ldX, P.pl.n, P.pl.m, P.bf.b32.X[0], P.bf.b32.ldX, g.s));
@@ -256,6 +259,7 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
                                                     P.bf.b64.X[st.in_], P.bf.b64.X[2],
                                                     st.stabilising, P.bf.small, calls);
             for (int j = 0; j < nc; ++j) {
+                if (!calls[j].A || !calls[j].B || !calls[j].ep.out[0]) return HP_EINVAL;
                 append(tb, 0, j, calls[j], &tiles);
                 const double gf = 2.0 * (double)calls[j].M * calls[j].N * calls[j].K * 1e-9;
                 P.res.gflop += gf;
@@ -269,6 +273,7 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
                                                    P.bf.b32.X[st.in_], P.bf.b32.X[2],
                                                    st.stabilising, P.bf.small, calls);
             for (int j = 0; j < nc; ++j) {
+                if (!calls[j].A || !calls[j].B || !calls[j].ep.out[0]) return HP_EINVAL;
                 append(tb, 1, j, calls[j], &tiles);
                 const double gf = 2.0 * (double)calls[j].M * calls[j].N * calls[j].K * 1e-9;
                 P.res.gflop += gf;
@@ -288,7 +293,7 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
         Problem& P = *act[i];
         LoopState& st = P.st;
         const LoopState::Action a = st.step(hout[2 * i], hout[2 * i + 1], 0.0, false);
-        if (a == LoopState::CONTINUE && st.projection_due()) {
+        if (a == LoopState::CONTINUE && st.projection_due() && P.pl.has_proj) {
             CHK(project_mp(P.pl, P.bf, st.ik, g.s, single_gemm(g, P)));
             st.projected();
         }
@@ -304,7 +309,7 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
             }
             st.enter_stage(next);
         }
-        if (a == LoopState::DONE || st.k >= g.prm.max_iter) {
+        if (a == LoopState::DONE || st.k >= P.prm.max_iter) {
             CHK(retire(g, P));
             any_done = true;
         }
@@ -407,6 +412,7 @@ int hp_solve_batched(hp_handle* h, const hp_params* p, int count, const hp_probl
     int rc = HP_OK;
     for (int i = 0; i < count && rc == HP_OK; ++i) {
         P[i].pr = probs[i];
+        P[i].prm = *p;
         P[i].pl = make_plan(p, probs[i].m, probs[i].n, false);
         P[i].ws = ws + off;
         off += align_up(P[i].pl.total);
@@ -468,6 +474,7 @@ int hp_serve_submit(hp_server* sv, const hp_problem* prob, uint64_t* ticket) {
     const uint64_t t = sv->next_ticket++;
     Problem& P = sv->reqs[t];
     P.pr = *prob;
+    P.prm = sv->g.prm;
     P.pl = pl;
     P.ws_bytes = align_up(pl.total);
     P.t_submit = Clock::now();
@@ -495,6 +502,19 @@ int hp_serve_step(hp_server* sv, int* active, int* waiting) {
         CHK(group_loop(sv->g, act));
         for (uint64_t t : act_t) {
             Problem& P = sv->reqs[t];
+            if (P.finished && P.res.status != HP_OK && !P.retried &&
+                P.prm.precision != HP_PREC_FP64 && !(sv->g.prm.flags & HP_FLAG_NO_RETRY)) {
+                // the lower precisions failed: once more from X0, FP64 only,
+                // in the same arena space (the FP64 plan needs less of it)
+                Problem& Q = P;
+                Q.retried = true;
+                Q.prm.precision = HP_PREC_FP64;
+                Q.pl = make_plan(&Q.prm, Q.pr.m, Q.pr.n, false);
+                if (align_up(Q.pl.total) <= Q.ws_bytes) {
+                    CHK(admit(sv->g, Q));
+                    continue;
+                }
+            }
             if (P.finished) {
                 P.res.queue_ms = ms_between(P.t_submit, P.t_admit);
                 P.res.run_ms = ms_between(P.t_admit, P.t_finish);

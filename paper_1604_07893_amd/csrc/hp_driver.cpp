@@ -280,6 +280,8 @@ struct Solver {
 
     template <typename T>
     int gemm(Engine eng, const GemmCall<T>& g, const CopyUse* use = nullptr) {
+        // every operand and the first output must exist in this plan
+        if (!g.A || !g.B || !g.ep.out[0]) return HP_EINVAL;
         int dt = HP_DTYPE_F64;
         if constexpr (!std::is_same<T, double>::value)
             dt = eng == ENG_F32 ? HP_DTYPE_F32 : (eng == ENG_BF16 ? HP_DTYPE_BF16_F32 : HP_DTYPE_F16_F32);
@@ -500,7 +502,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
                 return S.gemm<double>(ENG_F64, g);
             });
         };
-        if (a == LoopState::CONTINUE && st.projection_due()) {
+        if (a == LoopState::CONTINUE && st.projection_due() && pl.has_proj) {
             CHK(project(st.ik));  // deferred from the stage change (below)
             st.projected();
         } else if (a == LoopState::CONTINUE && st.k < p->max_iter && st.bound_ready()) {

@@ -482,6 +482,8 @@ template <typename GemmFn>
 int project_mp(const Plan& pl, const Buffers& bf, int xi, hipStream_t s, GemmFn&& gemm) {
     const int64_t m = pl.m, n = pl.n;
     const Set<double>& b = bf.b64;
+    // only plans with lower-precision stages carry the projection buffers
+    if (!pl.has_proj || !bf.At || !bf.Xt || xi < 0 || xi > 2) return HP_EINVAL;
     double* X = b.X[xi];
     HIPCHK(transpose_scale(b.A, b.ldA, m, n, bf.At, b.ldX, nullptr, s));  // A^T: n x m
     HIPCHK(transpose_scale(X, b.ldX, n, m, bf.Xt, b.ldA, nullptr, s));    // X^T: m x n

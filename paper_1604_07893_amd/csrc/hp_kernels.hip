@@ -484,6 +484,7 @@ hipError_t alpha_trace(const double* P, int64_t ldp, const double* A, int64_t ld
 
 hipError_t transpose_scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y,
                            int64_t ldy, const double* alpha_dev, hipStream_t s) {
+    if (!A || !Y) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_transpose_scale, dim3((unsigned)cdiv(N, 32), (unsigned)cdiv(M, 32)),
                        dim3(kThreads), 0, s, A, lda, (int)M, (int)N, Y, ldy, alpha_dev);
     return hipGetLastError();
@@ -491,6 +492,7 @@ hipError_t transpose_scale(const double* A, int64_t lda, int64_t M, int64_t N, d
 
 hipError_t scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y, int64_t ldy,
                  const double* alpha_dev, hipStream_t s) {
+    if (!A || !Y || !alpha_dev) return hipErrorInvalidValue;
     const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N, kThreads), 16);
     hipLaunchKernelGGL(k_scale, dim3(gx, (unsigned)M), dim3(kThreads), 0, s, A, lda, (int)M, (int)N,
                        Y, ldy, alpha_dev);
@@ -498,12 +500,14 @@ hipError_t scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y, 
 }
 
 hipError_t set_identity(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s) {
+    if (!Y) return hipErrorInvalidValue;
     const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N, kThreads), 16);
     hipLaunchKernelGGL(k_identity, dim3(gx, (unsigned)M), dim3(kThreads), 0, s, Y, ldy, (int)M, (int)N);
     return hipGetLastError();
 }
 
 hipError_t diag_inv(const double* A, int64_t lda, int64_t n, double* Y, int64_t ldy, hipStream_t s) {
+    if (!A || !Y) return hipErrorInvalidValue;
     const unsigned gx = (unsigned)std::min<int64_t>(cdiv(n, kThreads), 16);
     hipLaunchKernelGGL(k_diag_inv, dim3(gx, (unsigned)n), dim3(kThreads), 0, s, A, lda, (int)n, Y, ldy);
     return hipGetLastError();
@@ -536,6 +540,7 @@ namespace hp {
 template <typename S, typename D>
 static hipError_t convert_impl(const S* X, int64_t ldx, int64_t M, int64_t N, D* Y, int64_t ldy,
                                hipStream_t s) {
+    if (!X || !Y) return hipErrorInvalidValue;
     const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N, kThreads), 16);
     hipLaunchKernelGGL((k_convert<S, D>), dim3(gx, (unsigned)M), dim3(kThreads), 0, s, X, ldx,
                        (int)M, (int)N, Y, ldy);
@@ -576,6 +581,7 @@ namespace hp {
 
 hipError_t sumsq(const float* X, int64_t ldx, int64_t M, int64_t N, double* tmp, double* scal,
                  int slot, hipStream_t s) {
+    if (!X || !tmp || !scal) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rowsumsq<float>, dim3((unsigned)M), dim3(kThreads), 0, s, X, ldx, (int)N, tmp);
     hipLaunchKernelGGL(k_sum_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal, slot);
     return hipGetLastError();
@@ -587,6 +593,7 @@ namespace hp {
 
 hipError_t diffsq(const double* P, int64_t ldp, const double* Q, int64_t ldq, double c, int64_t M,
                   int64_t N, double* tmp, double* scal, int slot, hipStream_t s) {
+    if (!P || !tmp || !scal) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rowdiffsq, dim3((unsigned)M), dim3(kThreads), 0, s, P, ldp, Q, ldq, (int)M,
                        (int)N, c, tmp);
     hipLaunchKernelGGL(k_sum_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal, slot);

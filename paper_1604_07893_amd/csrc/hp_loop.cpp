@@ -31,6 +31,10 @@ void LoopState::init(const hp_params* prm, hp_result* r, double a) {
     k = 0;
     status = HP_MAXITER;
     result_idx = -1;
+    from_idx = 0;
+    probe = false;
+    exit_converged = false;
+    proj_pending = false;
 }
 
 Engine LoopState::engine() const {

@@ -34,7 +34,7 @@ METHOD_ORDER = {"pm": 18, "sm": 2, "cm": 3, "fm": 7, "hm": 18}
 METHOD_PRODUCTS = {"pm": 7, "sm": 2, "cm": 3, "fm": 5, "hm": 9}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2, "fp32_fp64": 3}
 LOWP = {"bf16": 0, "f16": 1, "fp16": 1}
-FLAG_TIME_KERNELS, FLAG_INF_NORM, FLAG_NO_GRAPH = 1, 2, 4
+FLAG_TIME_KERNELS, FLAG_INF_NORM, FLAG_NO_GRAPH, FLAG_NO_RETRY = 1, 2, 4, 8
 DTYPE = {torch.float64: 0, torch.float32: 1}
 HP_HIST = 128
 
@@ -168,7 +168,7 @@ def handle(device: int | None = None) -> Handle:
 def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", tau_switch=0.1,
                 tol=1e-12, max_iter=100, stop="rel_fro", side="auto", precision="fp64",
                 diverge_limit=1e6, time_kernels=False, inf_norm=False,
-                low_dtype="bf16", graph=True, method="pm", chop=0.0) -> HpParams:
+                low_dtype="bf16", graph=True, method="pm", chop=0.0, retry=True) -> HpParams:
     p = HpParams()
     load_library().hp_params_default(ctypes.byref(p))
     p.kind = KIND[kind]
@@ -189,7 +189,7 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
     p.method = METHOD[method]
     p.chop = float(chop)
     p.flags = ((FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
-               | (0 if graph else FLAG_NO_GRAPH))
+               | (0 if graph else FLAG_NO_GRAPH) | (0 if retry else FLAG_NO_RETRY))
     return p
 
 

@@ -160,3 +160,41 @@ def test_ill_conditioned_square_requests_stay_accurate():
     for A, X, info in zip(mats, Xs, infos):
         assert info["status"] == "ok"
         assert rel(X.cpu().numpy(), np.linalg.pinv(A)) <= 1e-10
+
+
+@pytest.mark.parametrize("retry", [True, False])
+def test_server_retries_a_failed_request_in_fp64(retry):
+    """A request with entries near 1e45: beyond FP32's range (the FP32 loop is
+    non-finite) and with X0 = alpha A^T near 1e-49, below FP32's smallest
+    subnormal, so the FP64 stage starts from X = 0 and ends non-finite too.
+    The server runs it once more in FP64 only (default), which reaches the
+    pseudo-inverse; with HP_FLAG_NO_RETRY the failure is reported. Its
+    neighbour is unaffected."""
+    hpw = need_gpu()
+    rng = np.random.default_rng(4)
+    A_ok = rng.standard_normal((96, 64))
+    A_big = rng.standard_normal((80, 80)) * 1e45
+    srv = hpw.Server(hbm_budget=1 << 28, max_slots=4, precision="fp32_fp64", tol=1e-10,
+                     variant="stabilised", retry=retry)
+    t1, t2 = srv.submit(to_dev(A_ok)), srv.submit(to_dev(A_big))
+    results = {}
+    for _ in range(400):
+        srv.step()
+        for t in (t1, t2):
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+        if len(results) == 2:
+            break
+    srv.close()
+    assert len(results) == 2
+    (X1, i1), (X2, i2) = results[t1], results[t2]
+    say(f"  retry={retry}: {i1['status']} {i2['status']} stages {i2['iters_stage']}")
+    assert i1["status"] == "ok"
+    assert rel(X1.cpu().numpy(), np.linalg.pinv(A_ok)) <= 1e-10
+    if retry:
+        assert i2["status"] == "ok" and list(i2["iters_stage"][:2]) == [0, 0]
+        assert rel(X2.cpu().numpy(), np.linalg.pinv(A_big)) <= 1e-10
+    else:
+        assert i2["status"] != "ok"

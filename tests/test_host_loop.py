@@ -196,3 +196,17 @@ def test_projection_waits_for_the_converging_regime(harness):
     assert got["actions"][:2] == [CONTINUE, NEXT_STAGE]
     assert got["projected_at"] == 4          # after the FP64 loop whose change was 0.01
     assert STATUS[got["status"]] == "ok"
+
+
+def test_reinit_clears_the_state_of_a_previous_attempt(tmp_path):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = tmp_path / "reinit"
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-I", os.path.join(ROOT, "include"),
+                    "-I", os.path.join(ROOT, "paper_1604_07893_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "loop_state_reinit.cpp"),
+                    os.path.join(ROOT, "paper_1604_07893_amd", "csrc", "hp_loop.cpp"),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
