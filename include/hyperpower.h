@@ -283,6 +283,25 @@ int hp_solve(hp_handle* h, const hp_params* p,
              void* workspace, size_t ws_bytes,
              void* stream, hp_result* out);
 
+/* Complex A (m x n, interleaved real and imaginary doubles, leading dimension
+ * lda >= n in complex elements): X (n x m, interleaved, ldx >= m) ~ the
+ * generalized inverse hp_solve defines, with G = A^* (conjugate transpose)
+ * for Moore-Penrose and A^l for Drazin (Section 1.2 states the method for
+ * complex matrices). Computed through the real 2m x 2n matrix
+ * [[Re A, -Im A], [Im A, Re A]]: that map turns products into products and
+ * A^* into the transpose, so the loop on it is the complex loop, twice the
+ * flops of a complex-arithmetic GEMM. m, n <= 32767; no X0 argument (the
+ * rule in p->alpha_rule; alpha from the norms of the real form, which has
+ * the singular values of A, each twice). hp_params.chop acts on real and
+ * imaginary parts separately (as Chop does on complex numbers). Drazin only
+ * with HP_ALPHA_USER and no HP_ALPHA_DIAG (HP_EUNSUPPORTED: those rules of the
+ * real form are not the complex rules). Errors as hp_solve. */
+int hp_complex_workspace_bytes(const hp_params* p, int64_t m, int64_t n, size_t* bytes);
+int hp_solve_complex(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64_t n,
+                     int64_t lda, double* X, int64_t ldx, void* workspace, size_t ws_bytes,
+                     void* stream, hp_result* out);
+
+
 /* One matrix product on the library's MFMA GEMM kernel, exposed so that the
  * kernel can be checked and timed on its own:
  *     C = alpha * A B + beta_identity * I      (A M x K, B K x N, C M x N)

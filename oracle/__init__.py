@@ -22,6 +22,7 @@ from .hyperpower import (  # noqa: F401
     norm_1,
     norm_inf,
     norm_fro,
+    adjoint,
     x0_moore_penrose,
     x0_drazin,
     x0_diag,

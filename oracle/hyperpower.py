@@ -59,7 +59,7 @@ class Arith:
     # arrays ------------------------------------------------------------
     def asarray(self, a):
         if self.name == "f64":
-            return np.asarray(a, dtype=np.float64)
+            return np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) else np.float64)
         a = np.asarray(a, dtype=object)
         return np.vectorize(mpmath.mpf, otypes=[object])(a)
 
@@ -147,7 +147,14 @@ def norm_inf(a):
 
 
 def norm_fro(a, ar: Arith = F64):
+    if np.iscomplexobj(a):
+        return ar.sqrt(float((np.abs(a) ** 2).sum()))
     return ar.sqrt((a * a).sum())
+
+
+def adjoint(A):
+    """A^* (conjugate transpose; the transpose for real A)."""
+    return A.conj().T if np.iscomplexobj(A) else A.T
 
 
 # ---------------------------------------------------------------------------
@@ -155,7 +162,7 @@ def norm_fro(a, ar: Arith = F64):
 # ---------------------------------------------------------------------------
 
 def x0_moore_penrose(A, rule: str = "norm1inf", alpha=None, ar: Arith = F64):
-    """X0 = alpha * A^T for the Moore-Penrose inverse (real case: A* = A^T).
+    """X0 = alpha * A^* for the Moore-Penrose inverse (A^T for real A).
 
     rule "norm1inf":   alpha = 1 / (||A||_1 ||A||_inf)          (Section 4)
     rule "sigma_max2": alpha = 1 / sigma_1^2                    (scaling that
@@ -169,7 +176,8 @@ def x0_moore_penrose(A, rule: str = "norm1inf", alpha=None, ar: Arith = F64):
     if rule == "norm1inf":
         alpha = 1 / (norm_1(A) * norm_inf(A))
     elif rule in ("sigma_max2", "sigma_opt"):
-        s = np.linalg.svd(np.asarray(A, dtype=np.float64), compute_uv=False)
+        s = np.linalg.svd(np.asarray(A, dtype=np.complex128 if np.iscomplexobj(A) else np.float64),
+                          compute_uv=False)
         s1 = s[0]
         if rule == "sigma_max2":
             alpha = 1.0 / (s1 * s1)
@@ -183,7 +191,7 @@ def x0_moore_penrose(A, rule: str = "norm1inf", alpha=None, ar: Arith = F64):
         alpha = ar.num(alpha)
     else:
         raise ValueError(f"unknown alpha rule {rule!r}")
-    return alpha * A.T, alpha
+    return alpha * adjoint(A), alpha
 
 
 def x0_diag(A, ar: Arith = F64):
@@ -466,7 +474,7 @@ def penrose_residuals(A, X):
     AX = A @ X
     XA = X @ A
     return (f(AX @ A - A) / f(A), f(XA @ X - X) / f(X),
-            f(AX - AX.T) / f(AX), f(XA - XA.T) / f(XA))
+            f(AX - adjoint(AX)) / f(AX), f(XA - adjoint(XA)) / f(XA))
 
 
 def drazin_residuals(A, X, l: int):

@@ -785,6 +785,60 @@ static void residual_layout(int kind, int l, int64_t m, int64_t n, size_t off[8]
     *total = o;
 }
 
+// Complex input through its real 2m x 2n form: the real form's workspace
+// after the two real-form matrices.
+static void complex_layout(int64_t m, int64_t n, size_t* offX, size_t* offW, int64_t* ldE,
+                           int64_t* ldXe) {
+    *ldE = hp::pad_ld(2 * n);
+    *ldXe = hp::pad_ld(2 * m);
+    *offX = hp::align_up(sizeof(double) * (size_t)(2 * m) * (size_t)*ldE);
+    *offW = *offX + hp::align_up(sizeof(double) * (size_t)(2 * n) * (size_t)*ldXe);
+}
+
+int hp_complex_workspace_bytes(const hp_params* p, int64_t m, int64_t n, size_t* bytes) {
+    if (!bytes || m < 1 || n < 1 || m > 32767 || n > 32767) return HP_EINVAL;
+    size_t inner = 0;
+    CHK(hp_workspace_bytes(p, 2 * m, 2 * n, &inner));
+    size_t offX, offW;
+    int64_t ldE, ldXe;
+    complex_layout(m, n, &offX, &offW, &ldE, &ldXe);
+    *bytes = offW + inner;
+    return HP_OK;
+}
+
+int hp_solve_complex(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64_t n,
+                     int64_t lda, double* X, int64_t ldx, void* workspace, size_t ws_bytes,
+                     void* stream, hp_result* out) {
+    if (!h || !A || !X || !p) return HP_EINVAL;
+    // rules whose real form is not the complex rule: Tr(A^{l+1}) of the real
+    // form is twice the real part of the complex trace, and its diagonal
+    // holds only the real parts
+    if ((p->kind == HP_KIND_DRAZIN && p->alpha_rule != HP_ALPHA_USER) ||
+        p->alpha_rule == HP_ALPHA_DIAG)
+        return HP_EUNSUPPORTED;
+    size_t need = 0;
+    CHK(hp_complex_workspace_bytes(p, m, n, &need));
+    if (lda < n || ldx < m) return HP_EINVAL;
+    if (!workspace || ws_bytes < need) return HP_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) % hp::kAlign) return HP_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
+    size_t offX, offW;
+    int64_t ldE, ldXe;
+    complex_layout(m, n, &offX, &offW, &ldE, &ldXe);
+    char* ws = static_cast<char*>(workspace);
+    double* E = reinterpret_cast<double*>(ws);
+    double* Xe = reinterpret_cast<double*>(ws + offX);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hp::Range range("hp_solve_complex %lldx%lld", (long long)m, (long long)n);
+    HIPCHK(hp::embed_complex(A, lda, m, n, E, ldE, s));
+    const int rc = hp_solve(h, p, E, 2 * m, 2 * n, ldE, nullptr, 0, Xe, ldXe, ws + offW,
+                            ws_bytes - offW, stream, out);
+    if (rc < 0) return rc;
+    HIPCHK(hp::extract_complex(Xe, ldXe, n, m, X, ldx, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return rc;
+}
+
 int hp_residuals_workspace_bytes(int kind, int l, int64_t m, int64_t n, size_t* bytes) {
     if (!bytes || m < 1 || n < 1 || m > 65535 || n > 65535) return HP_EINVAL;
     if (kind != HP_KIND_MOORE_PENROSE && kind != HP_KIND_DRAZIN) return HP_EINVAL;

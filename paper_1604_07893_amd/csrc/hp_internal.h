@@ -203,6 +203,16 @@ hipError_t scale(const double* A, int64_t lda, int64_t M, int64_t N, double* Y, 
 // Y = diag(1/A[0][0], ..., 1/A[n-1][n-1]) (n x n, zero off the diagonal).
 hipError_t diag_inv(const double* A, int64_t lda, int64_t n, double* Y, int64_t ldy, hipStream_t s);
 
+// E (2M x 2N, ld lde) = [[Re A, -Im A], [Im A, Re A]] for a complex M x N
+// matrix A stored as interleaved (re, im) doubles, leading dimension lda in
+// complex elements.
+hipError_t embed_complex(const double* A, int64_t lda, int64_t M, int64_t N, double* E, int64_t lde,
+                         hipStream_t s);
+// X (complex N x M, interleaved, ldx in complex elements) = the upper-left
+// block of E (2N x 2M) + i times its lower-left block.
+hipError_t extract_complex(const double* E, int64_t lde, int64_t N, int64_t M, double* X, int64_t ldx,
+                           hipStream_t s);
+
 // Y = I (M x N identity).
 hipError_t set_identity(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s);
 

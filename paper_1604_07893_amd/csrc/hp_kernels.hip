@@ -273,6 +273,33 @@ __global__ __launch_bounds__(kThreads) void k_diag_inv(const double* __restrict_
         Y[(int64_t)r * ldy + c] = (r == c) ? d : 0.0;
 }
 
+// Real form of a complex M x N matrix (interleaved re, im):
+// E = [[Re A, -Im A], [Im A, Re A]], 2M x 2N.
+__global__ __launch_bounds__(kThreads) void k_embed_complex(const double* __restrict__ A, int64_t lda,
+                                                            int M, int N, double* __restrict__ E,
+                                                            int64_t lde) {
+    const int r = blockIdx.y;
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < N; c += gridDim.x * kThreads) {
+        const double re = A[2 * ((int64_t)r * lda + c)], im = A[2 * ((int64_t)r * lda + c) + 1];
+        E[(int64_t)r * lde + c] = re;
+        E[(int64_t)r * lde + N + c] = -im;
+        E[(int64_t)(M + r) * lde + c] = im;
+        E[(int64_t)(M + r) * lde + N + c] = re;
+    }
+}
+
+// The complex N x M matrix whose real form is E (2N x 2M): the real part is
+// E's upper-left block, the imaginary part its lower-left block.
+__global__ __launch_bounds__(kThreads) void k_extract_complex(const double* __restrict__ E, int64_t lde,
+                                                              int N, int M, double* __restrict__ X,
+                                                              int64_t ldx) {
+    const int r = blockIdx.y;
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < M; c += gridDim.x * kThreads) {
+        X[2 * ((int64_t)r * ldx + c)] = E[(int64_t)r * lde + c];
+        X[2 * ((int64_t)r * ldx + c) + 1] = E[(int64_t)(N + r) * lde + c];
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_zero_u32(unsigned* __restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
         p[i] = 0u;
@@ -510,6 +537,24 @@ hipError_t diag_inv(const double* A, int64_t lda, int64_t n, double* Y, int64_t 
     if (!A || !Y) return hipErrorInvalidValue;
     const unsigned gx = (unsigned)std::min<int64_t>(cdiv(n, kThreads), 16);
     hipLaunchKernelGGL(k_diag_inv, dim3(gx, (unsigned)n), dim3(kThreads), 0, s, A, lda, (int)n, Y, ldy);
+    return hipGetLastError();
+}
+
+hipError_t embed_complex(const double* A, int64_t lda, int64_t M, int64_t N, double* E, int64_t lde,
+                         hipStream_t s) {
+    if (!A || !E || M < 1 || N < 1) return hipErrorInvalidValue;
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N, kThreads), 16);
+    hipLaunchKernelGGL(k_embed_complex, dim3(gx, (unsigned)M), dim3(kThreads), 0, s, A, lda, (int)M,
+                       (int)N, E, lde);
+    return hipGetLastError();
+}
+
+hipError_t extract_complex(const double* E, int64_t lde, int64_t N, int64_t M, double* X, int64_t ldx,
+                           hipStream_t s) {
+    if (!E || !X || M < 1 || N < 1) return hipErrorInvalidValue;
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(M, kThreads), 16);
+    hipLaunchKernelGGL(k_extract_complex, dim3(gx, (unsigned)N), dim3(kThreads), 0, s, E, lde, (int)N,
+                       (int)M, X, ldx);
     return hipGetLastError();
 }
 

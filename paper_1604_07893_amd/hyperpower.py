@@ -76,6 +76,9 @@ SIGNATURES = {
     "hp_create": (c_int, [POINTER(c_void_p), c_int]),
     "hp_destroy": (c_int, [c_void_p]),
     "hp_workspace_bytes": (c_int, [POINTER(HpParams), c_int64, c_int64, POINTER(c_size_t)]),
+    "hp_complex_workspace_bytes": (c_int, [POINTER(HpParams), c_int64, c_int64, POINTER(c_size_t)]),
+    "hp_solve_complex": (c_int, [c_void_p, POINTER(HpParams), c_void_p, c_int64, c_int64, c_int64,
+                                 c_void_p, c_int64, c_void_p, c_size_t, c_void_p, POINTER(HpResult)]),
     "hp_solve": (c_int, [c_void_p, POINTER(HpParams), c_void_p, c_int64, c_int64, c_int64,
                          c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t, c_void_p,
                          POINTER(HpResult)]),
@@ -257,6 +260,33 @@ def solve(A: torch.Tensor, *, X0: torch.Tensor | None = None, out: torch.Tensor 
     if rc < 0:
         raise HyperpowerError(rc, "hp_solve")
     return out, result_dict(res)
+
+
+def solve_complex(A: torch.Tensor, *, stream: torch.cuda.Stream | None = None,
+                  **kw) -> tuple[torch.Tensor, dict]:
+    """Generalized inverse of a complex A (m x n, complex128, on the GPU) with
+    G = A^* (Moore-Penrose) or A^l (Drazin), through its real 2m x 2n form
+    (hp_solve_complex); returns (X n x m complex128, info)."""
+    if A.dtype != torch.complex128 or A.dim() != 2 or not A.is_cuda or A.stride(1) != 1:
+        raise ValueError("A must be a row-major complex128 CUDA matrix")
+    m, n = A.shape
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    params = make_params(**kw)
+    lib = load_library()
+    nb = c_size_t()
+    rc = lib.hp_complex_workspace_bytes(ctypes.byref(params), m, n, ctypes.byref(nb))
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_complex_workspace_bytes")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=A.device)
+    X = torch.empty((n, m), dtype=torch.complex128, device=A.device)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    res = HpResult()
+    rc = lib.hp_solve_complex(handle(dev).ptr, ctypes.byref(params), A.data_ptr(), m, n,
+                              A.stride(0), X.data_ptr(), X.stride(0), ws.data_ptr(), ws.numel(),
+                              s.cuda_stream, ctypes.byref(res))
+    if rc < 0:
+        raise HyperpowerError(rc, "hp_solve_complex")
+    return X, result_dict(res)
 
 
 def pinv(A: torch.Tensor, **kw) -> tuple[torch.Tensor, dict]:

@@ -502,3 +502,26 @@ def test_residual_bound_picks_the_cheapest_sufficient_scheme(r1, scheme):
         assert res.method_hist == ["pm", scheme]
     closed = (d.V / d.s) @ d.U.T
     assert np.linalg.norm(res.X - closed) / np.linalg.norm(closed) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Complex A (Section 1.2 states the method over C): X0 = alpha A^*.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n,rank", [(40, 25, 25), (30, 30, 18)])
+def test_complex_moore_penrose_vs_lapack(m, n, rank):
+    rng = np.random.default_rng(m * n + rank)
+    G1 = rng.standard_normal((m, rank)) + 1j * rng.standard_normal((m, rank))
+    G2 = rng.standard_normal((rank, n)) + 1j * rng.standard_normal((rank, n))
+    A = G1 @ G2 / np.sqrt(rank)
+    res = O.solve(A, kind="mp", variant="stabilised", tol=1e-12)
+    assert res.status == "ok" and np.iscomplexobj(res.X)
+    P = np.linalg.pinv(A)
+    assert np.linalg.norm(res.X - P) / np.linalg.norm(P) < 1e-11
+    for r in O.penrose_residuals(A, res.X):
+        assert r < 1e-11
+    # the real form [[Re, -Im], [Im, Re]] of the result is the pseudo-inverse
+    # of the real form (the map respects products and A^* -> A^T)
+    E = np.block([[A.real, -A.imag], [A.imag, A.real]])
+    XE = np.block([[res.X.real, -res.X.imag], [res.X.imag, res.X.real]])
+    assert np.linalg.norm(XE - np.linalg.pinv(E)) / np.linalg.norm(XE) < 1e-11
