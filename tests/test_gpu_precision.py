@@ -85,3 +85,22 @@ def test_fp32_rank_deficient_stabilised_stagnates_at_its_floor():
     assert info["status"] in ("stagnated", "ok")
     assert np.all(np.isfinite(X))
     assert rel(X, closed) <= 1e-1
+
+
+@pytest.mark.parametrize("stop", ["rel_fro", "rel_fro_bound"])
+def test_mixed_8192_full_size_matches_closed_form(stop):
+    """The benchmark's mixed-precision workload at its full size (8192^2,
+    s log-uniform in [1e-3, 1], Haar factors built on the GPU; bf16 -> FP32
+    -> FP64, X0 = A^T, tol 1e-10): X equals V diag(1/s) U^T within 1e-10;
+    checked on the GPU with torch's FP64 products of the factors."""
+    hpw = need_gpu()
+    say(f"mixed 8192^2 {stop}")
+    A, U, s, V = inputs.square_svd_device(8192, smin=1e-3, seed=1003)
+    X, info = hpw.solve(A, precision="mixed", alpha_rule="user", alpha=1.0, tol=1e-10, stop=stop)
+    closed = (V / s) @ U.T.contiguous()
+    err = float(torch.linalg.norm(X - closed) / torch.linalg.norm(closed))
+    say(f"  {info['status']} stages {info['iters_stage']} gemms {info['gemms']} err {err:.2e}")
+    assert info["status"] == "ok"
+    assert err <= 1e-10
+    del A, U, V, X, closed
+    torch.cuda.empty_cache()
