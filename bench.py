@@ -131,11 +131,16 @@ def extra_mixed(hpw, torch, steps):
     ref = None
     # "*_bound": the same with the residual-bound stop (skips the loop that only
     # confirms convergence: ||I - AX||_F / (1 - ||I - AX||_F) < tol)
-    for prec, stop in (("fp64", "rel_fro"), ("mixed", "rel_fro"), ("fp64_bound", "rel_fro_bound"),
-                       ("mixed_bound", "rel_fro_bound")):
+    # "*_sym": with HP_FLAG_SYMMETRIC (A is nonsingular): the loop's n x n
+    # products, symmetric for X0 = alpha A^T, formed once per pair i <= j
+    for prec, stop, sym in (("fp64", "rel_fro", False), ("mixed", "rel_fro", False),
+                            ("fp64_bound", "rel_fro_bound", False),
+                            ("mixed_bound", "rel_fro_bound", False),
+                            ("fp64_sym", "rel_fro", True), ("fp64_bound_sym", "rel_fro_bound", True),
+                            ("mixed_bound_sym", "rel_fro_bound", True)):
         sec, infos, X = timed_solves(hpw, torch, A, steps, 1, alpha_rule="user", alpha=1.0,
                                      tol=TOL, precision=prec.split("_")[0], stop=stop,
-                                     time_kernels=True)
+                                     time_kernels=True, symmetric=sym)
         inf = infos[-1]
         if ref is None:
             # closed form V diag(1/s) U^T, on the GPU in FP64 (a reference, not the method)
@@ -147,6 +152,11 @@ def extra_mixed(hpw, torch, steps):
                      "gflop_stage": inf["gflop_stage"], "gflop_per_inverse": gf,
                      "gemm_tflops": gf / (sum(i["gemm_ms"] for i in infos) / len(infos)),
                      "rel_err_vs_closed_form": err}
+        if sym:
+            ms_sym = sum(i["gemm_ms_sym"] for i in infos)
+            out[prec]["sym_launches_per_inverse"] = sum(i["gemms_sym"] for i in infos) / len(infos)
+            out[prec]["sym_gemm_tflops"] = (sum(i["gflop_sym"] for i in infos) / ms_sym
+                                            if ms_sym > 0 else 0.0)
         if prec == "mixed":
             caps = np.cumsum(inf["iters_stage"])
             per_stage = []
@@ -161,6 +171,10 @@ def extra_mixed(hpw, torch, steps):
     out["speedup_mixed_vs_fp64"] = out["mixed"]["inverses_per_s"] / out["fp64"]["inverses_per_s"]
     out["speedup_mixed_bound_vs_fp64"] = (out["mixed_bound"]["inverses_per_s"]
                                           / out["fp64"]["inverses_per_s"])
+    out["speedup_fp64_sym_vs_fp64"] = (out["fp64_sym"]["inverses_per_s"]
+                                       / out["fp64"]["inverses_per_s"])
+    out["speedup_mixed_bound_sym_vs_fp64"] = (out["mixed_bound_sym"]["inverses_per_s"]
+                                              / out["fp64"]["inverses_per_s"])
     del A, U, s, V, ref
     torch.cuda.empty_cache()
     return out

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define HP_ABI_VERSION 2
+#define HP_ABI_VERSION 3
 
 /* ---- status codes ------------------------------------------------------ */
 #define HP_OK 0
@@ -177,6 +177,22 @@ extern "C" {
 #define HP_FLAG_NO_RETRY 8     /* served: do not retry in FP64 a request whose
                                   lower-precision solve ended other than
                                   HP_OK (see hp_serve_step) */
+#define HP_FLAG_SYMMETRIC 16  /* single Moore-Penrose solves from X0 = alpha A^T
+                                  (no caller's X0, no Chop), when the caller
+                                  knows that rank(A) equals the residual's
+                                  side s (min(m, n) with HP_SIDE_AUTO): form
+                                  the loop's s x s products (R, the
+                                  polynomials in R, the middle product X A
+                                  of the stabilising step), symmetric in
+                                  exact arithmetic because X_k = p(A^T A) A^T,
+                                  once per pair (i, j), i <= j, and mirror
+                                  them (hp_gemm_sym). Only while the last
+                                  change d has (d/2)^p >= tol: the loop
+                                  expected to meet the test forms full
+                                  products and corrects what the forced
+                                  symmetry left. With rank(A) < s the forced
+                                  symmetry feeds the null-space error block
+                                  back into the range block: do not set it */
 
 /* GEMM element type for hp_gemm */
 #define HP_DTYPE_F64 0 /* FP64 operands, v_mfma_f64_16x16x4f64, FP64 accumulate */
@@ -243,6 +259,11 @@ typedef struct hp_result {
     double run_ms;         /* served requests: admission -> result written */
     double d_hist[HP_HIST];    /* relative Frobenius change per loop */
     double dinf_hist[HP_HIST]; /* inf-norm change per loop (HP_FLAG_INF_NORM) */
+    int32_t gemms_sym;     /* launches of those that ran symmetric (hp_gemm_sym) */
+    int32_t reserved_r;
+    double gflop_sym;      /* their work, N*(N+1)*K per launch (included in gflop) */
+    double gemm_ms_sym;    /* their kernel time (HP_FLAG_TIME_KERNELS; included
+                              in gemm_ms) */
 } hp_result;
 
 typedef struct hp_handle hp_handle;
@@ -330,6 +351,30 @@ int hp_gemm_ws(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
                double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
                double beta_identity, void* C, int64_t ldc, void* workspace, size_t ws_bytes,
                void* stream);
+
+/* Workspace of hp_gemm_sym for an N x N x K product: partial tiles for the
+ * blocks that share an output tile, and arrival counters (the size depends on
+ * the current device's compute-unit count). dtype HP_DTYPE_F64 or F32. */
+int hp_gemm_sym_workspace_bytes(int dtype, int64_t N, int64_t K, size_t* bytes);
+
+/* C = alpha A B + beta_identity I (N x N) for a product that the caller knows
+ * to be symmetric in exact arithmetic, such as G G^T or a polynomial in a
+ * symmetric matrix (the loop products of Section 2 when X A or A X is
+ * symmetric). Only the output tiles on and above the diagonal are computed,
+ * in one launch that gives every block an equal share of their K-steps; a
+ * tile shared by several blocks is finished by the last of them, which adds
+ * the pieces in K order (the same result from run to run). Each element
+ * (i, j), i <= j, is formed once and stored at (i, j) and (j, i), so C is
+ * exactly symmetric; its upper triangle equals the full product's up to the
+ * rounding of the summation order. dtype HP_DTYPE_F64 or HP_DTYPE_F32; A, B,
+ * lda, ldb, C, ldc as for hp_gemm (A N x K, B K x N). With a workspace of
+ * fewer than hp_gemm_sym_workspace_bytes (or NULL and 0) the full product is
+ * formed instead. The workspace's counters are cleared on the stream by every
+ * call; calls that share a workspace must not overlap.
+ * Errors: as hp_gemm; another dtype or a misaligned workspace is HP_EINVAL. */
+int hp_gemm_sym(hp_handle* h, int dtype, int64_t N, int64_t K, double alpha, const void* A,
+                int64_t lda, const void* B, int64_t ldb, double beta_identity, void* C,
+                int64_t ldc, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---- residuals of the defining equations ---------------------------------- */
 

@@ -136,11 +136,32 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area) {
                         pl.splitSlots = std::max(
                             pl.splitSlots,
                             hp::gemm_split_slots(hp::gemm_pick_tile(M, N, K, gt), M, N, K));
+        pl.splitCnt = pl.splitSlots;
+        // the symmetric launches of the loop's s x s products (K = s, or m or
+        // n for the residual and the stabilising middle product)
+        pl.sym = p->kind == HP_KIND_MOORE_PENROSE && p->alpha_rule != HP_ALPHA_DIAG &&
+                 !(p->chop > 0.0) && (p->flags & HP_FLAG_SYMMETRIC);
+        if (pl.sym) {
+            for (hp::GemmType gt : types) {
+                if (gt == hp::GT_F64 && fp32only) continue;
+                if (gt == hp::GT_F32 && !pl.has32) continue;
+                for (int64_t K : dims) {
+                    int64_t slots = 0, cnt = 0;
+                    hp::gemm_sym_scratch(hp::gemm_pick_tile(pl.s, pl.s, K, gt), gt, pl.s, &slots,
+                                         &cnt);
+                    // slots of 128 x 128 elements of the GEMM type, in FP64 tiles
+                    if (gt == hp::GT_F32) slots = (slots + 1) / 2;
+                    pl.splitSlots = std::max(pl.splitSlots, slots);
+                    pl.splitCnt = std::max(pl.splitCnt, cnt);
+                }
+            }
+        }
         if (pl.splitSlots > 0) {
+            pl.splitCnt = std::max(pl.splitCnt, pl.splitSlots);
             pl.offSplit = off;
             off = align_up(off + sizeof(double) * 128 * 128 * (size_t)pl.splitSlots);
             pl.offSplitCnt = off;
-            off = align_up(off + sizeof(unsigned) * (size_t)pl.splitSlots);
+            off = align_up(off + sizeof(unsigned) * (size_t)pl.splitCnt);
         }
     }
     // small area: GEMM partial pairs, norm sums, trace partials, row sums
@@ -245,19 +266,25 @@ struct GemmTimer {
     int used = 0;
     double total_ms = 0.0;
     hipStream_t s;
+    double sym_ms = 0.0;  // the part of total_ms spent in symmetric launches
+    bool is_sym[hp_handle::kEvents / 2] = {};
     void before() {
         if (on && used + 2 <= hp_handle::kEvents) (void)hipEventRecord(h->ev[used], s);
     }
-    void after() {
+    void after(bool sym = false) {
         if (on && used + 2 <= hp_handle::kEvents) {
             (void)hipEventRecord(h->ev[used + 1], s);
+            is_sym[used / 2] = sym;
             used += 2;
         }
     }
     void harvest() {  // stream must be synchronised
         for (int i = 0; i < used; i += 2) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) total_ms += ms;
+            if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) {
+                total_ms += ms;
+                if (is_sym[i / 2]) sym_ms += ms;
+            }
         }
         used = 0;
     }
@@ -274,6 +301,10 @@ struct Solver {
     int gemms = 0;
     int last_blocks = 0;  // blocks (partial pairs) of the latest product
     int stage = 2;        // for per-stage accounting
+    double gflop_sym = 0.0;
+    int gemms_sym = 0;
+    bool sym = false;  // the loop's products may run symmetric (Plan::sym, no user X0)
+    bool sym_loop = false;  // ... and this loop may (LoopState::sym_ok)
     double* split_part = nullptr;  // split-K scratch of the workspace (Plan)
     unsigned* split_cnt = nullptr;
     const Buffers* bf = nullptr;   // for the 16-bit copies of the first mixed stage
@@ -290,8 +321,13 @@ struct Solver {
             ep.split_part = reinterpret_cast<T*>(split_part);
             ep.split_cnt = split_cnt;
             ep.split_slots = pl.splitSlots * (int64_t)(sizeof(double) / sizeof(T));
+            ep.split_ncnt = pl.splitCnt;
         }
+        if (!(sym && sym_loop)) ep.sym = 0;
         const GemmTile t = choose_tile(h, dt, g.M, g.N, g.K, ep.split_slots);
+        const bool sym_launch = eng == ENG_F64 || eng == ENG_F32
+                                    ? gemm_sym_launches(t, g.M, g.N, g.K, ep)
+                                    : false;
         timer.before();
         hipError_t e;
         if constexpr (std::is_same<T, double>::value) {
@@ -335,13 +371,19 @@ struct Solver {
                               g.B, g.ldb, ep, s);
             }
         }
-        timer.after();
+        timer.after(sym_launch);
         last_blocks = gemm_blocks(t, g.M, g.N);
         if (e != hipSuccess) return HP_EHIP;
-        const double gf = 2.0 * (double)g.M * (double)g.N * (double)g.K * 1e-9;
+        // a symmetric launch forms N (N + 1) / 2 distinct elements
+        const double gf = (sym_launch ? (double)g.N + 1.0 : 2.0 * (double)g.N) * (double)g.M *
+                          (double)g.K * 1e-9;
         gflop += gf;
         res->gflop_stage[stage] += gf;
         ++gemms;
+        if (sym_launch) {
+            gflop_sym += gf;
+            ++gemms_sym;
+        }
         return HP_OK;
     }
 };
@@ -365,10 +407,12 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
     const Buffers bf = carve(pl, ws);
     double* hs = S.h->host_scal;
     if (bf.split_cnt) {
-        HIPCHK(zero_u32(bf.split_cnt, pl.splitSlots, s));
+        HIPCHK(zero_u32(bf.split_cnt, pl.splitCnt, s));
         S.split_part = bf.split_part;
         S.split_cnt = bf.split_cnt;
     }
+    // X_k = p(A^T A) A^T needs X0 = alpha A^T (not a caller's X0)
+    S.sym = pl.sym && X0 == nullptr;
     S.bf = &bf;
 
     double alpha = 0.0;
@@ -402,6 +446,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
     // `scheme`: a plain final-stage loop after a residual check (first == 1) may run
     // a lower-order scheme (LoopState::scheme_for)
     auto run_loop = [&](int first, int scheme) -> int {
+        S.sym_loop = st.sym_ok();
         if (st.stage == 2) {
             GemmCall<double> calls[kMaxLoopGemms];
             const int nc =
@@ -434,6 +479,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
     // return ||R||_F in *r.
     auto next_residual = [&](double* r) -> int {
         const int64_t sd = pl.s;
+        S.sym_loop = false;  // the bound reads the full residual
         if (st.stage == 2) {
             GemmCall<double> calls[kMaxLoopGemms];
             describe_loop<double>(p->method, pl, bf.b64, bf.b64.X[st.ik], bf.b64.X[st.in_],
@@ -660,6 +706,9 @@ int hp_solve(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64
     res->gflop = S.gflop;
     res->gemms = S.gemms;
     res->gemm_ms = S.timer.total_ms;
+    res->gemms_sym = S.gemms_sym;
+    res->gflop_sym = S.gflop_sym;
+    res->gemm_ms_sym = S.timer.sym_ms;
     res->time_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return rc;
@@ -741,6 +790,77 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alp
     CHK(gemm_args(dtype, M, N, K, A, lda, B, ldb, C, ldc));
     return gemm_run(h, dtype, M, N, K, alpha, A, lda, B, ldb, beta_identity, C, ldc, nullptr, 0,
                     stream);
+}
+
+// Scratch of hp_gemm_sym: enough for either tile with a symmetric launch.
+static void gemm_sym_ws(int dtype, int64_t N, int64_t* slots, int64_t* cnt) {
+    *slots = *cnt = 0;
+    const hp::GemmType gt = hp::gemm_type(dtype);
+    for (hp::GemmTile t : {hp::TILE_128x128_W16_K2_P2, hp::TILE_128x128_W8}) {
+        int64_t sl = 0, c = 0;
+        hp::gemm_sym_scratch(t, gt, N, &sl, &c);
+        *slots = std::max(*slots, sl);
+        *cnt = std::max(*cnt, c);
+    }
+}
+static size_t gemm_sym_ws_bytes(int dtype, int64_t slots, int64_t cnt) {
+    if (slots <= 0 || cnt <= 0) return 0;
+    const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;
+    return hp::align_up(esz * 128 * 128 * (size_t)slots) + sizeof(unsigned) * (size_t)cnt;
+}
+
+int hp_gemm_sym_workspace_bytes(int dtype, int64_t N, int64_t K, size_t* bytes) {
+    if (!bytes) return HP_EINVAL;
+    if (dtype != HP_DTYPE_F64 && dtype != HP_DTYPE_F32) return HP_EINVAL;
+    if (N < 1 || K < 1 || N > (1 << 24) || K > (1 << 24)) return HP_EINVAL;
+    int64_t slots = 0, cnt = 0;
+    gemm_sym_ws(dtype, N, &slots, &cnt);
+    *bytes = gemm_sym_ws_bytes(dtype, slots, cnt);
+    return HP_OK;
+}
+
+int hp_gemm_sym(hp_handle* h, int dtype, int64_t N, int64_t K, double alpha, const void* A,
+                int64_t lda, const void* B, int64_t ldb, double beta_identity, void* C,
+                int64_t ldc, void* workspace, size_t ws_bytes, void* stream) {
+    if (!h) return HP_EINVAL;
+    if (dtype != HP_DTYPE_F64 && dtype != HP_DTYPE_F32) return HP_EINVAL;
+    CHK(gemm_args(dtype, N, N, K, A, lda, B, ldb, C, ldc));
+    if (!workspace && ws_bytes) return HP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % hp::kAlign) return HP_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
+    const hp::GemmType gt = hp::gemm_type(dtype);
+    hp::GemmTile t = hp::choose_tile(h, dtype, N, N, K, 0);
+    if (!hp::gemm_sym_runs(t, gt)) t = hp::TILE_128x128_W16_K2_P2;
+    int64_t slots = 0, cnt = 0;
+    gemm_sym_ws(dtype, N, &slots, &cnt);
+    const bool fits = workspace && slots > 0 && ws_bytes >= gemm_sym_ws_bytes(dtype, slots, cnt);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned* cp = nullptr;
+    if (fits) {
+        const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;
+        cp = reinterpret_cast<unsigned*>(static_cast<char*>(workspace) +
+                                         hp::align_up(esz * 128 * 128 * (size_t)slots));
+        HIPCHK(hp::zero_u32(cp, cnt, s));
+    }
+    auto sym = [&](auto ep) {
+        using E = std::remove_pointer_t<decltype(ep.split_part)>;
+        ep.sym = 1;
+        if (cp) {
+            ep.split_part = static_cast<E*>(workspace);
+            ep.split_cnt = cp;
+            ep.split_slots = slots;
+            ep.split_ncnt = cnt;
+        }
+        return ep;
+    };
+    hipError_t e;
+    if (dtype == HP_DTYPE_F64)
+        e = hp::gemm(t, N, N, K, static_cast<const double*>(A), lda, static_cast<const double*>(B),
+                     ldb, sym(hp::epilogue_plain(static_cast<double*>(C), ldc, alpha, beta_identity)), s);
+    else
+        e = hp::gemm(t, N, N, K, static_cast<const float*>(A), lda, static_cast<const float*>(B),
+                     ldb, sym(hp::epilogue_plain(static_cast<float*>(C), ldc, alpha, beta_identity)), s);
+    return e == hipSuccess ? HP_OK : HP_EHIP;
 }
 
 int hp_gemm_workspace_bytes(int dtype, int64_t M, int64_t N, int64_t K, size_t* bytes) {

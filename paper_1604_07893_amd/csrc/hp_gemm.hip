@@ -123,7 +123,9 @@ struct Cfg {
 // wave: up to three outputs id*I + acc_c*acc + g1*D1 + g2*D2 (output 0 chopped
 // with ep.chop) and, with ep.ref, the block's FP64 partial sums of the stopping
 // test in pair `part`.
-template <typename T, int TI, int TJ, int WAVES>
+// With SYM (a symmetric product, EpilogueT::sym), only the elements on and
+// above the diagonal are formed, each stored at (row, col) and (col, row).
+template <typename T, int TI, int TJ, int WAVES, bool SYM = false>
 __device__ __attribute__((always_inline)) inline void tile_epilogue(
     typename Mfma<T>::acc_t (&acc)[TI][TJ], const EpilogueT<T>& ep, int M, int N, int bm, int bn,
     int wm, int wn, int part, double (*red)[WAVES]) {
@@ -138,7 +140,7 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(
             for (int r = 0; r < 4; ++r) {
                 const int row = bm + wm + i * 16 + Mfma<T>::row(fg, r);
                 const int col = bn + wn + j * 16 + fr;
-                if (row < M && col < N) {
+                if (row < M && col < N && (!SYM || row <= col)) {
                     const T a = acc[i][j][r];
                     const T d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : T(0);
                     const T d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : T(0);
@@ -152,7 +154,8 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(
                             if (ep.g2[o] != 0.0) v += T(ep.g2[o]) * d2;
                             if (o == 0 && ep.chop > 0.0 && fabs((double)v) < ep.chop) v = T(0);
                             ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
-                            if (o == 0 && ep.ref) {
+                            if (SYM && row != col) ep.out[o][(int64_t)col * ep.ldo[o] + row] = v;
+                            if (!SYM && o == 0 && ep.ref) {
                                 const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];
                                 const double df = (double)v - x0;
                                 s_diff += df * df;
@@ -164,7 +167,7 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(
             }
         }
     }
-    if (ep.ref) {
+    if (!SYM && ep.ref) {
         const double sd = wave_sum(s_diff), sr = wave_sum(s_ref);
         if (lane == 0) {
             red[0][wave] = sd;
@@ -184,11 +187,16 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(
 }
 
 // One BM x BN output tile (tm, tn) of C = epilogue(A * B); the block's
-// partial sums (if any) go to pair `part` of ep.partials.
-template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1, int SPLIT = 1>
+// partial sums (if any) go to pair `part` of ep.partials. SPLIT < 0 (the
+// stream-K launch): the block holds piece `split` (in K order) of the
+// sk_np pieces of tile `part`; piece 0's partial tile is slot sk_slot0 of
+// ep.split_part and piece i > 0's is slot 2 (sk_b0 + i).
+template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1, int SPLIT = 1,
+          bool SYM = false>
 __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, int64_t lda,
                                  const T* __restrict__ B, int64_t ldb, const EpilogueT<T>& ep,
-                                 int tm, int tn, int part, int split = 0) {
+                                 int tm, int tn, int part, int split = 0, int sk_np = 1,
+                                 int sk_slot0 = 0, int sk_b0 = 0) {
     using C = Cfg<T, BM, BN, BK, WM, WN>;
     using VT = typename Vec16<T>::type;
     using ACC = typename Mfma<T>::acc_t;
@@ -426,7 +434,57 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
         if (tid == 0) __hip_atomic_store(&ep.split_cnt[part], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
-    tile_epilogue<T, C::TI, C::TJ, C::WAVES>(acc, ep, M, N, bm, bn, wm, wn, part, red);
+    if constexpr (SPLIT < 0) {
+        // ---- stream-K: a piece of a tile shared with other blocks ----
+        // As the split-K path above, with a tile-dependent piece count: every
+        // piece is stored, and the last block to arrive reads them all back
+        // and adds them in K order (the same bits whichever block is last).
+        if (sk_np > 1) {
+            constexpr int TILE = BM * BN;
+            static_assert(TILE == C::TI * C::TJ * 4 * C::NT, "partial layout");
+            auto slot = [&](int i) {
+                return ep.split_part + (int64_t)(i == 0 ? sk_slot0 : 2 * (sk_b0 + i)) * TILE;
+            };
+            __shared__ unsigned sk_arrived;
+            T* mine = slot(split);
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < C::TJ; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        mine[((i * C::TJ + j) * 4 + r) * C::NT + tid] = acc[i][j][r];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __syncthreads();
+            if (tid == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                sk_arrived = __hip_atomic_fetch_add(&ep.split_cnt[part], 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+            if (sk_arrived != (unsigned)(sk_np - 1)) return;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+                for (int j = 0; j < C::TJ; ++j) {
+                    asm volatile("" ::: "memory");
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int e = ((i * C::TJ + j) * 4 + r) * C::NT + tid;
+                        T v = slot(0)[e];
+                        for (int q = 1; q < sk_np; ++q) v += slot(q)[e];
+                        asm volatile("" : "+v"(v));
+                        acc[i][j][r] = v;
+                    }
+                }
+            if (tid == 0)
+                __hip_atomic_store(&ep.split_cnt[part], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+
+    tile_epilogue<T, C::TI, C::TJ, C::WAVES, SYM>(acc, ep, M, N, bm, bn, wm, wn, part, red);
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
@@ -452,6 +510,53 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_split(
     const int k0 = split * kchunk;
     gemm_tile<T, BM, BN, BK, WM, WN, 1, SPLIT>(M, N, min(kchunk, K - k0), A + k0, lda,
                                                B + (int64_t)k0 * ldb, ldb, ep, tm, tn, t, split);
+}
+
+// Upper-triangle tile t (row-major: row 0 holds tiles (0, 0..nt-1), row 1
+// (1, 1..nt-1), ...) of an nt x nt tile grid.
+__device__ inline void tri_of(int t, int nt, int& tm, int& tn) {
+    int r = 0;
+    while (t >= nt - r) {
+        t -= nt - r;
+        ++r;
+    }
+    tm = r;
+    tn = r + t;
+}
+
+// Symmetric product (EpilogueT::sym) as one stream-K launch over the tiles on
+// and above the diagonal: the triangle's tiles * ipt K-steps (ipt = K-tiles
+// per tile), laid end to end, are cut into gridDim.x ranges of ipc steps, one
+// per block. A block walks its range tile by tile; a tile that lies wholly in
+// one range is finished there, one that spans several ranges (sk_np pieces)
+// by the last of their blocks to arrive. A block's first piece uses partial
+// slot 2b and its last slot 2b + 1, so 2 * gridDim.x slots suffice.
+template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN))
+__attribute__((amdgpu_waves_per_eu(4))) void k_gemm_sym(
+    int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+    EpilogueT<T> ep, int nt, int tiles, int ipt, int ipc) {
+    static_assert(BM == 128 && BN == 128, "partial slots hold 128 x 128 tiles");
+    const int b = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int64_t total = (int64_t)tiles * ipt;
+    int64_t it = (int64_t)b * ipc;
+    const int64_t end = min(it + (int64_t)ipc, total);
+    while (it < end) {
+        const int t = (int)(it / ipt);
+        const int k0 = (int)(it - (int64_t)t * ipt);
+        const int k1 = (int)min((int64_t)ipt, k0 + (end - it));
+        const int64_t ts = (int64_t)t * ipt;
+        const int b0 = (int)(ts / ipc), b1 = (int)((ts + ipt - 1) / ipc);
+        const int slot0 = 2 * b0 + ((int64_t)b0 * ipc >= ts ? 0 : 1);
+        int tm, tn;
+        tri_of(t, nt, tm, tn);
+        const int kb = k0 * BK, ke = min(K, k1 * BK);
+        gemm_tile<T, BM, BN, BK, WM, WN, PF, -1, true>(N, N, ke - kb, A + kb, lda,
+                                                      B + (int64_t)kb * ldb, ldb, ep, tm, tn, t,
+                                                      b - b0, b1 - b0 + 1, slot0, b0);
+        it += k1 - k0;
+        __syncthreads();  // the next piece's staging reuses the LDS tiles
+    }
 }
 
 // Persistent grouped launch: the grid walks the tiles of every product in
@@ -1095,6 +1200,63 @@ hipError_t launch_split(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda
     return hipGetLastError();
 }
 
+// Blocks of k_gemm_sym<T, ...> that the device holds at once (compute units
+// times blocks per unit): the stream-K grid. Queried once per kernel.
+template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
+int sym_grid() {
+    static int g = 0;
+    if (g == 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per, reinterpret_cast<const void*>(&k_gemm_sym<T, BM, BN, BK, WM, WN, PF>),
+                64 * (BM / WM) * (BN / WN), 0) != hipSuccess)
+            return 0;
+        g = cus * std::max(per, 1);
+    }
+    return g;
+}
+
+struct SymShape {
+    int grid, nt, tiles, ipt, ipc;
+};
+template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
+SymShape sym_shape(int64_t N, int64_t K) {
+    SymShape sh{};
+    const int g = sym_grid<T, BM, BN, BK, WM, WN, PF>();
+    if (g <= 0) return sh;
+    sh.nt = (int)cdiv(N, BM);
+    sh.tiles = sh.nt * (sh.nt + 1) / 2;
+    sh.ipt = (int)cdiv(K, BK);
+    const int64_t total = (int64_t)sh.tiles * sh.ipt;
+    sh.ipc = (int)cdiv(total, g);
+    sh.grid = (int)cdiv(total, sh.ipc);
+    return sh;
+}
+
+template <typename T>
+bool sym_fits(const SymShape& sh, const EpilogueT<T>& ep) {
+    const int64_t ncnt = ep.split_ncnt > 0 ? ep.split_ncnt : ep.split_slots;
+    return sh.grid > 0 && ep.split_part && ep.split_cnt && ep.split_slots >= 2 * (int64_t)sh.grid &&
+           ncnt >= sh.tiles;
+}
+
+// The symmetric launch; returns false (nothing launched) when the epilogue
+// brings too little scratch for it.
+template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
+bool launch_sym(int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
+                const EpilogueT<T>& ep, hipStream_t s, hipError_t* err) {
+    using C = Cfg<T, BM, BN, BK, WM, WN>;
+    if (K <= 0) return false;
+    const SymShape sh = sym_shape<T, BM, BN, BK, WM, WN, PF>(N, K);
+    if (!sym_fits(sh, ep)) return false;
+    hipLaunchKernelGGL((k_gemm_sym<T, BM, BN, BK, WM, WN, PF>), dim3(sh.grid), dim3(C::NT), 0, s,
+                       (int)N, (int)K, A, lda, B, ldb, ep, sh.nt, sh.tiles, sh.ipt, sh.ipc);
+    *err = hipGetLastError();
+    return true;
+}
+
 // Tile configurations, indexed by GemmTile.
 struct TileShape {
     int bm, bn;
@@ -1126,6 +1288,14 @@ template <typename T>
 hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
                     const T* B, int64_t ldb, const EpilogueT<T>& ep, hipStream_t s) {
     constexpr int BKF = 16 * sizeof(double) / sizeof(T);  // 128-byte K-tile rows
+    if (ep.sym && M == N && !ep.ref) {
+        hipError_t e = hipSuccess;
+        if (t == TILE_128x128_W16_K2_P2 &&
+            launch_sym<T, 128, 128, 2 * BKF, 32, 32, 2>(N, K, A, lda, B, ldb, ep, s, &e))
+            return e;
+        if (t == TILE_128x128_W8 && launch_sym<T, 128, 128, BKF, 64, 32, 1>(N, K, A, lda, B, ldb, ep, s, &e))
+            return e;
+    }
     switch (t) {
         case TILE_128x128_W4: return launch<T, 128, 128, BKF, 64, 64>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W8: return launch<T, 128, 128, BKF, 64, 32>(M, N, K, A, lda, B, ldb, ep, s);
@@ -1323,6 +1493,43 @@ GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow
     if (small) return TILE_32x32_W4_K4;
     if (allow_split && ((tiles < 128 && K >= 2048) || K >= 4096)) return TILE_128x128_W8_S4;
     return TILE_64x64_W4;
+}
+
+template <typename T>
+static bool sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<T>& ep) {
+    constexpr int BKF = 16 * sizeof(double) / sizeof(T);
+    if (!ep.sym || M != N || ep.ref || K <= 0) return false;
+    if (t == TILE_128x128_W16_K2_P2)
+        return sym_fits(sym_shape<T, 128, 128, 2 * BKF, 32, 32, 2>(N, K), ep);
+    if (t == TILE_128x128_W8) return sym_fits(sym_shape<T, 128, 128, BKF, 64, 32, 1>(N, K), ep);
+    return false;
+}
+bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<double>& ep) {
+    return sym_launches(t, M, N, K, ep);
+}
+bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<float>& ep) {
+    return sym_launches(t, M, N, K, ep);
+}
+
+bool gemm_sym_runs(GemmTile t, GemmType gt) {
+    return (gt == GT_F64 || gt == GT_F32) && (t == TILE_128x128_W16_K2_P2 || t == TILE_128x128_W8);
+}
+
+void gemm_sym_scratch(GemmTile t, GemmType gt, int64_t n, int64_t* slots, int64_t* counters) {
+    *slots = *counters = 0;
+    if (!gemm_sym_runs(t, gt) || n <= 0) return;
+    // the grid is at most the resident block count, whatever K is
+    int g = 0;
+    if (gt == GT_F64)
+        g = t == TILE_128x128_W8 ? sym_grid<double, 128, 128, 16, 64, 32, 1>()
+                                 : sym_grid<double, 128, 128, 32, 32, 32, 2>();
+    else
+        g = t == TILE_128x128_W8 ? sym_grid<float, 128, 128, 32, 64, 32, 1>()
+                                 : sym_grid<float, 128, 128, 64, 32, 32, 2>();
+    if (g <= 0) return;
+    const int64_t nt = cdiv(n, 128);
+    *slots = 2 * (int64_t)g;
+    *counters = nt * (nt + 1) / 2;
 }
 
 template <int SPLIT>

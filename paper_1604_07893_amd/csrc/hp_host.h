@@ -120,8 +120,12 @@ struct Plan {
     bool has_proj = false;      // A^T (n x m) and X^T (m x n) for the projection
     size_t offAt = 0, offXt = 0;
     // split-K scratch: splitSlots partial tiles (128 x 128 doubles), then
-    // splitSlots arrival counters; none when no product of the solve splits
-    int64_t splitSlots = 0;
+    // splitCnt arrival counters; none when no product of the solve splits.
+    // The symmetric launches of the loop products share it.
+    int64_t splitSlots = 0, splitCnt = 0;
+    // the loop's s x s products may run symmetric (HP_FLAG_SYMMETRIC: X_k =
+    // p(A^T A) A^T for a Moore-Penrose solve from alpha A^T without Chop)
+    bool sym = false;
     size_t offSplit = 0, offSplitCnt = 0;
     size_t offSmall = 0, nSmall = 0, offScal = 0, total = 0;
 };
@@ -246,11 +250,13 @@ int describe_update(const Plan& pl, const Set<T>& b, const T* W, T* Xk, T* Xn, T
     if (stab) {
         EpilogueT<T> e = epilogue_plain(Xn, ldX);
         e.ref = Xk; e.ldref = ldX; e.partials = partials;
+        EpilogueT<T> em = epilogue_plain(mid, ldS);
+        em.sym = 1;  // X A (or A X) is symmetric for X = p(A^T A) A^T
         if (m >= n) {
-            out[c++] = {n, n, m, Xh, ldX, b.A, ldA, epilogue_plain(mid, ldS)};
+            out[c++] = {n, n, m, Xh, ldX, b.A, ldA, em};
             out[c++] = {n, m, n, mid, ldS, Xh, ldX, e};
         } else {
-            out[c++] = {m, m, n, b.A, ldA, Xh, ldX, epilogue_plain(mid, ldS)};
+            out[c++] = {m, m, n, b.A, ldA, Xh, ldX, em};
             out[c++] = {n, m, m, Xh, ldX, mid, ldS, e};
         }
     }
@@ -263,6 +269,7 @@ template <typename T>
 int describe_residual(const Plan& pl, const Set<T>& b, const T* Xk, EpilogueT<T> e,
                       GemmCall<T>* out, int c) {
     const int64_t m = pl.m, n = pl.n;
+    e.sym = 1;
     if (pl.left) out[c++] = {n, n, m, Xk, b.ldX, b.A, b.ldA, e};
     else out[c++] = {m, m, n, b.A, b.ldA, Xk, b.ldX, e};
     return c;
@@ -291,7 +298,9 @@ int describe_loop(int method, const Plan& pl, const Set<T>& b, T* Xk, T* Xn, T* 
     const int64_t sd = pl.s, ldS = b.ldS;
     T* const* S = b.S;
     int c = 0;
+    // every s x s product of a loop is a polynomial in R: symmetric when R is
     auto sq = [&](const T* A, const T* B, EpilogueT<T> e) {
+        e.sym = 1;
         out[c++] = {sd, sd, sd, A, ldS, B, ldS, e};
     };
     auto ep = [&](T* o0, double acc0, double id0) { return epilogue_plain(o0, ldS, acc0, id0); };
@@ -408,6 +417,7 @@ int describe_after_residual(int method, const Plan& pl, const Set<T>& b, T* Xk, 
         return describe_update(pl, b, S[0], Xk, Xn, b.X[2], false, partials, S[2], out, c, true);
     EpilogueT<T> e = epilogue_plain(S[1], ldS, 1.0, 1.0);
     e.g1[0] = 1.0; e.D1 = S[0]; e.ld1 = ldS;
+    e.sym = 1;
     out[c++] = {sd, sd, sd, S[0], ldS, S[0], ldS, e};
     return describe_update(pl, b, S[1], Xk, Xn, b.X[2], false, partials, S[2], out, c);
 }

@@ -53,6 +53,15 @@ struct EpilogueT {
     T* split_part;
     unsigned* split_cnt;
     int64_t split_slots;
+    // arrival counters available at split_cnt (0: as many as split_slots)
+    int64_t split_ncnt;
+    // nonzero: the caller guarantees that the product is symmetric in exact
+    // arithmetic (M == N; e.g. a polynomial in R = I - X A when X A is
+    // symmetric). The symmetric launch (gemm_sym_runs) then computes the
+    // tiles on and above the diagonal only, each element i <= j once, and
+    // stores every output at (i, j) and (j, i); D1/D2 are read at i <= j only.
+    // Requires ref == nullptr; other launches compute the full product.
+    int sym;
     // 16-bit copies of the outputs, written by the 16-bit-operand kernel only
     // (gemm_h16) in its own operand type: h[o] row-major (ld ldh[o]) and ht[o]
     // transposed (ld ldht[o]); either may be null.
@@ -117,6 +126,21 @@ bool gemm_split_runs(GemmTile t, int64_t M, int64_t N, int64_t K, GemmType gt, i
 // Split-K scratch (partial tiles of 128 x 128 elements; as many arrival
 // counters) that tile t needs for an M x N x K product: 0 for unsplit tiles.
 int64_t gemm_split_slots(GemmTile t, int64_t M, int64_t N, int64_t K);
+// Symmetric products (EpilogueT::sym) of GEMM type gt run on tile t as one
+// balanced launch over the upper-triangle tiles (stream-K: every block takes
+// an equal share of the triangle's K-steps; a tile split between blocks is
+// finished by the last of them to arrive, adding the pieces in K order).
+bool gemm_sym_runs(GemmTile t, GemmType gt);
+// Scratch the symmetric launch of an n x n x K product on tile t needs:
+// partial tiles (of 128 x 128 elements of the GEMM type) and arrival counters;
+// 0 and 0 when t has no symmetric launch.
+void gemm_sym_scratch(GemmTile t, GemmType gt, int64_t n, int64_t* slots, int64_t* counters);
+// Whether gemm() runs this call as the symmetric launch (ep.sym set, M == N,
+// no stopping sums, a tile with that launch and enough scratch); it runs the
+// full product otherwise.
+bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<double>& ep);
+bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<float>& ep);
+
 // Zero n unsigned counters (a fill kernel: safe inside stream capture).
 hipError_t zero_u32(unsigned* p, int64_t n, hipStream_t s);
 

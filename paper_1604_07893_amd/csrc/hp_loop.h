@@ -89,6 +89,18 @@ struct LoopState {
             if (std::pow(r, (double)method_order(m)) < p->tol / 2) return m;
         return HP_METHOD_PM;
     }
+    // Whether the next loop may form its s x s products symmetric (they are
+    // symmetric in exact arithmetic for X0 = alpha A^T; forcing it leaves
+    // uncorrected the part of the rounding that is not): on the solve's first
+    // loop, and later while the last change d has (d/2)^p >= tol, p the
+    // method's order. The loop expected to meet the stopping test follows a
+    // change below tol^(1/p) and so forms full products, which correct that
+    // part to the rounding of one loop.
+    bool sym_ok() const {
+        if (k == 0) return true;
+        if (stage_first || !std::isfinite(d_prev)) return false;
+        return std::pow(d_prev / 2.0, (double)method_order(p->method)) >= p->tol;
+    }
     // The residual bound settled it: return the current iterate.
     void stop_bound(double bound) {
         status = HP_OK;

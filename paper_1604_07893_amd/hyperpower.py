@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhyperpower.so")
 
 # ---- constants mirrored from include/hyperpower.h ---------------------------
-HP_ABI_VERSION = 2
+HP_ABI_VERSION = 3
 HP_OK, HP_MAXITER, HP_STAGNATED, HP_DIVERGED, HP_NONFINITE, HP_PENDING = 0, 1, 2, 3, 4, 5
 HP_EINVAL, HP_EWORKSPACE, HP_EBUDGET, HP_EHIP, HP_EUNSUPPORTED = -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "stagnated", 3: "diverged", 4: "nonfinite", 5: "pending"}
@@ -34,7 +34,7 @@ METHOD_ORDER = {"pm": 18, "sm": 2, "cm": 3, "fm": 7, "hm": 18}
 METHOD_PRODUCTS = {"pm": 7, "sm": 2, "cm": 3, "fm": 5, "hm": 9}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2, "fp32_fp64": 3}
 LOWP = {"bf16": 0, "f16": 1, "fp16": 1}
-FLAG_TIME_KERNELS, FLAG_INF_NORM, FLAG_NO_GRAPH, FLAG_NO_RETRY = 1, 2, 4, 8
+FLAG_TIME_KERNELS, FLAG_INF_NORM, FLAG_NO_GRAPH, FLAG_NO_RETRY, FLAG_SYMMETRIC = 1, 2, 4, 8, 16
 DTYPE = {torch.float64: 0, torch.float32: 1}
 HP_HIST = 128
 
@@ -58,6 +58,8 @@ class HpResult(ctypes.Structure):
         ("d_stage", c_double * 3), ("gflop_stage", c_double * 3),
         ("queue_ms", c_double), ("run_ms", c_double),
         ("d_hist", c_double * HP_HIST), ("dinf_hist", c_double * HP_HIST),
+        ("gemms_sym", c_int32), ("reserved_r", c_int32), ("gflop_sym", c_double),
+        ("gemm_ms_sym", c_double),
     ]
 
 
@@ -86,6 +88,10 @@ SIGNATURES = {
                         c_void_p, c_int64, c_double, c_void_p, c_int64, c_void_p]),
     "hp_autotune_scratch_bytes": (c_int, [c_int, c_int64, c_int64, c_int64, POINTER(c_size_t)]),
     "hp_gemm_workspace_bytes": (c_int, [c_int, c_int64, c_int64, c_int64, POINTER(c_size_t)]),
+    "hp_gemm_sym_workspace_bytes": (c_int, [c_int, c_int64, c_int64, POINTER(c_size_t)]),
+    "hp_gemm_sym": (c_int, [c_void_p, c_int, c_int64, c_int64, c_double, c_void_p, c_int64,
+                            c_void_p, c_int64, c_double, c_void_p, c_int64, c_void_p, c_size_t,
+                            c_void_p]),
     "hp_gemm_ws": (c_int, [c_void_p, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
                            c_void_p, c_int64, c_double, c_void_p, c_int64, c_void_p, c_size_t,
                            c_void_p]),
@@ -171,7 +177,8 @@ def handle(device: int | None = None) -> Handle:
 def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", tau_switch=0.1,
                 tol=1e-12, max_iter=100, stop="rel_fro", side="auto", precision="fp64",
                 diverge_limit=1e6, time_kernels=False, inf_norm=False,
-                low_dtype="bf16", graph=True, method="pm", chop=0.0, retry=True) -> HpParams:
+                low_dtype="bf16", graph=True, method="pm", chop=0.0, retry=True,
+                symmetric=False) -> HpParams:
     p = HpParams()
     load_library().hp_params_default(ctypes.byref(p))
     p.kind = KIND[kind]
@@ -192,7 +199,8 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
     p.method = METHOD[method]
     p.chop = float(chop)
     p.flags = ((FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
-               | (0 if graph else FLAG_NO_GRAPH) | (0 if retry else FLAG_NO_RETRY))
+               | (0 if graph else FLAG_NO_GRAPH) | (0 if retry else FLAG_NO_RETRY)
+               | (FLAG_SYMMETRIC if symmetric else 0))
     return p
 
 
@@ -224,6 +232,7 @@ def result_dict(r: HpResult) -> dict:
         "iters_stage": list(r.iters_stage), "d_stage": list(r.d_stage),
         "gflop_stage": list(r.gflop_stage), "queue_ms": r.queue_ms, "run_ms": r.run_ms,
         "d_hist": list(r.d_hist[:it]), "dinf_hist": list(r.dinf_hist[:it]),
+        "gemms_sym": r.gemms_sym, "gflop_sym": r.gflop_sym, "gemm_ms_sym": r.gemm_ms_sym,
     }
 
 
@@ -354,6 +363,45 @@ def gemm(A: torch.Tensor, B: torch.Tensor, *, alpha: float = 1.0, beta_identity:
                                    workspace.numel() * workspace.element_size(), s.cuda_stream)
     if rc != HP_OK:
         raise HyperpowerError(rc, "hp_gemm_ws")
+    return out
+
+
+def gemm_sym(A: torch.Tensor, B: torch.Tensor, *, alpha: float = 1.0, beta_identity: float = 0.0,
+             out: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
+             workspace: torch.Tensor | bool = True) -> torch.Tensor:
+    """C = alpha A B + beta_identity I for a product the caller knows to be
+    symmetric (hp_gemm_sym): the upper triangle's tiles are computed and
+    mirrored. workspace: True (allocate hp_gemm_sym_workspace_bytes), False
+    (none: the full product is formed) or a device uint8 tensor."""
+    if A.dtype != B.dtype or A.dtype not in DTYPE:
+        raise ValueError("unsupported dtype")
+    code = DTYPE[A.dtype]
+    for t, nm in ((A, "A"), (B, "B")):
+        if not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError(f"{nm} must be a row-major device matrix")
+    N, K = A.shape
+    if tuple(B.shape) != (K, N):
+        raise ValueError("B must be K x N for an N x K A")
+    if out is None:
+        out = torch.empty((N, N), dtype=A.dtype, device=A.device)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    lib = load_library()
+    if workspace is True:
+        nb = c_size_t()
+        rc = lib.hp_gemm_sym_workspace_bytes(code, N, K, ctypes.byref(nb))
+        if rc != HP_OK:
+            raise HyperpowerError(rc, "hp_gemm_sym_workspace_bytes")
+        workspace = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=A.device)
+    if workspace is False:
+        ws_ptr, ws_bytes = None, 0
+    else:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    rc = lib.hp_gemm_sym(handle(dev).ptr, code, N, K, alpha, A.data_ptr(), A.stride(0),
+                         B.data_ptr(), B.stride(0), beta_identity, out.data_ptr(), out.stride(0),
+                         ws_ptr, ws_bytes, s.cuda_stream)
+    if rc != HP_OK:
+        raise HyperpowerError(rc, "hp_gemm_sym")
     return out
 
 

@@ -50,7 +50,7 @@ def test_host_only_calls():
     assert p.tol == 1e-12 and p.max_iter == 100 and abs(p.tau_switch - 0.1) < 1e-15
     # struct layouts mirror the header
     assert ctypes.sizeof(hpw.HpParams) == 96
-    assert ctypes.sizeof(hpw.HpResult) == 32 + 7 * 8 + 8 * 8 + 2 * 128 * 8
+    assert ctypes.sizeof(hpw.HpResult) == 32 + 7 * 8 + 8 * 8 + 2 * 128 * 8 + 8 + 2 * 8
     assert ctypes.sizeof(hpw.HpProblem) == 8 * 8
     # workspace sizes grow with the problem and reject bad arguments
     small = hpw.workspace_bytes(p, 200, 100)

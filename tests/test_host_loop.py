@@ -210,3 +210,19 @@ def test_reinit_clears_the_state_of_a_previous_attempt(tmp_path):
                     "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
+
+
+def test_symmetric_products_only_far_from_the_tolerance(tmp_path):
+    """LoopState::sym_ok (tests/host/loop_state_sym.cpp): the loop expected to
+    meet the stopping test forms full products."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = tmp_path / "sym"
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-I", os.path.join(ROOT, "include"),
+                    "-I", os.path.join(ROOT, "paper_1604_07893_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "loop_state_sym.cpp"),
+                    os.path.join(ROOT, "paper_1604_07893_amd", "csrc", "hp_loop.cpp"),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
