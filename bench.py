@@ -16,6 +16,7 @@ stream), a CPU baseline (the oracle on this host, bounded sample), and under
 Drazin input (index 3); and a served Poisson stream with p50/p99 latency.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline] [--no-extras]
+                    [--extras name,name,...]
 """
 
 from __future__ import annotations
@@ -398,6 +399,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="",
+                    help="comma-separated names of the extras to run (default: all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hyperpower "
@@ -470,6 +473,8 @@ def main() -> int:
                          ("methods", lambda: extra_methods(hpw, torch, 2)),
                          ("preconditioner_example_8_3", lambda: extra_precond(hpw, torch, 20)),
                          ("served_stream", lambda: extra_served(hpw, torch, 1000, 100))):
+            if args.extras and name not in args.extras.split(","):
+                continue
             t0 = time.perf_counter()
             try:
                 extras[name] = fn()
