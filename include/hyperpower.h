@@ -177,22 +177,27 @@ extern "C" {
 #define HP_FLAG_NO_RETRY 8     /* served: do not retry in FP64 a request whose
                                   lower-precision solve ended other than
                                   HP_OK (see hp_serve_step) */
-#define HP_FLAG_SYMMETRIC 16  /* single Moore-Penrose solves from X0 = alpha A^T
-                                  (no caller's X0, no Chop), when the caller
-                                  knows that rank(A) equals the residual's
-                                  side s (min(m, n) with HP_SIDE_AUTO): form
-                                  the loop's s x s products (R, the
-                                  polynomials in R, the middle product X A
-                                  of the stabilising step), symmetric in
-                                  exact arithmetic because X_k = p(A^T A) A^T,
-                                  once per pair (i, j), i <= j, and mirror
-                                  them (hp_gemm_sym). Only while the last
-                                  change d has (d/2)^p >= tol: the loop
-                                  expected to meet the test forms full
-                                  products and corrects what the forced
-                                  symmetry left. With rank(A) < s the forced
-                                  symmetry feeds the null-space error block
-                                  back into the range block: do not set it */
+#define HP_FLAG_SYMMETRIC 16  /* single FP64 Moore-Penrose solves from
+                                  X0 = alpha A^T (no caller's X0, no Chop),
+                                  when the caller knows that rank(A) equals
+                                  the residual's side s (min(m, n) with
+                                  HP_SIDE_AUTO): form the loop's s x s
+                                  products (R, the polynomials in R, the
+                                  middle product X A of the stabilising
+                                  step), symmetric in exact arithmetic
+                                  because X_k = p(A^T A) A^T, once per pair
+                                  (i, j), i <= j, and mirror them
+                                  (hp_gemm_sym). Only on the first L loops
+                                  with p^L 2^-52 <= 1e-7 (p the order) and,
+                                  after the first, while the last change d
+                                  has (d/2)^p >= tol: the loop expected to
+                                  meet the test forms full products and
+                                  corrects what the forced symmetry left.
+                                  Ignored in staged precisions (mirroring
+                                  their rounding diverges). With
+                                  rank(A) < s the forced symmetry feeds the
+                                  null-space error block back into the
+                                  range block: do not set it */
 
 /* GEMM element type for hp_gemm */
 #define HP_DTYPE_F64 0 /* FP64 operands, v_mfma_f64_16x16x4f64, FP64 accumulate */

@@ -21,6 +21,7 @@ void LoopState::init(const hp_params* prm, hp_result* r, double a) {
             : (p->precision == HP_PREC_FP32 || p->precision == HP_PREC_FP32_FP64) ? 1
                                                                                   : 2;
     final_stage = p->precision == HP_PREC_FP32 ? 1 : 2;
+    first_stage = stage;
     stabilising = p->variant == HP_VARIANT_STAB_ALWAYS;
     res->switch_iter = stabilising ? 0 : -1;
     converging = false;

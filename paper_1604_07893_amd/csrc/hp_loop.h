@@ -29,6 +29,7 @@ struct LoopState {
     double alpha = 0.0;
     int stage = 2;        // 0 16-bit, 1 FP32, 2 FP64
     int final_stage = 2;
+    int first_stage = 2;  // the stage the solve started in
     bool stabilising = false;
     bool converging = false;
     bool stage_first = true;  // no stagnation test on a stage's first loop
@@ -89,17 +90,23 @@ struct LoopState {
             if (std::pow(r, (double)method_order(m)) < p->tol / 2) return m;
         return HP_METHOD_PM;
     }
-    // Whether the next loop may form its s x s products symmetric (they are
-    // symmetric in exact arithmetic for X0 = alpha A^T; forcing it leaves
-    // uncorrected the part of the rounding that is not): on the solve's first
-    // loop, and later while the last change d has (d/2)^p >= tol, p the
-    // method's order. The loop expected to meet the stopping test follows a
-    // change below tol^(1/p) and so forms full products, which correct that
-    // part to the rounding of one loop.
+    // Whether the next loop may form its s x s products symmetric. They are
+    // symmetric in exact arithmetic for X0 = alpha A^T; computing the upper
+    // triangle and mirroring it turns the part K of R that is not symmetric
+    // into a symmetric error of the same size, and that error grows by the
+    // order p per loop in the directions not yet converged. So: FP64 solves
+    // only (K at 1e-16; an FP32 stage's symmetric loops reached order one),
+    // at most the first L loops with p^L * 2^-52 <= 1e-7, and after the first
+    // loop only while the last change d has (d/2)^p >= tol. The loop expected
+    // to meet the stopping test follows a change below tol^(1/p) and so forms
+    // full products, which correct what the symmetric loops left.
     bool sym_ok() const {
+        if (stage != 2 || first_stage != 2) return false;
+        const double order = (double)method_order(p->method);
+        if (std::pow(order, (double)(k + 1)) * 0x1p-52 > 1e-7) return false;
         if (k == 0) return true;
         if (stage_first || !std::isfinite(d_prev)) return false;
-        return std::pow(d_prev / 2.0, (double)method_order(p->method)) >= p->tol;
+        return std::pow(d_prev / 2.0, order) >= p->tol;
     }
     // The residual bound settled it: return the current iterate.
     void stop_bound(double bound) {

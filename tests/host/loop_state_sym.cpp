@@ -1,7 +1,8 @@
 // LoopState::sym_ok: the loops that may form their s x s products symmetric
-// are the solve's first and those after a change d with (d/2)^p >= tol, so the
-// loop expected to meet the stopping test (after a change below tol^(1/p))
-// forms full products. Test infrastructure; prints "ok" or the first failed
+// are, in FP64 solves, the first and those after a change d with
+// (d/2)^p >= tol (so the loop expected to meet the stopping test, after a
+// change below tol^(1/p), forms full products), at most L loops with
+// p^L 2^-52 <= 1e-7; staged solves form full products throughout. Test infrastructure; prints "ok" or the first failed
 // check.
 #include <cmath>
 #include <cstdio>
@@ -60,14 +61,33 @@ int main() {
         CHECK(!st.sym_ok());
     }
     {
-        // a stage's first loop (after a lower stage) forms full products
-        hp_params p = params(HP_METHOD_PM, HP_PREC_FP32_FP64);
+        // staged solves (X from FP32 or 16 bits) form full products throughout
+        for (int prec : {HP_PREC_FP32_FP64, HP_PREC_MIXED, HP_PREC_FP32}) {
+            hp_params p = params(HP_METHOD_PM, prec);
+            hp::LoopState st;
+            st.init(&p, &r, 1.0);
+            CHECK(!st.sym_ok());
+            CHECK(st.step(4.0, 1.0, 0.0, false) == hp::LoopState::CONTINUE);  // d = 2
+            CHECK(!st.sym_ok());
+        }
+    }
+    {
+        // the loop budget: 18^(k+1) 2^-52 <= 1e-7 for k + 1 <= 6
+        hp_params p = params(HP_METHOD_PM, HP_PREC_FP64);
         hp::LoopState st;
         st.init(&p, &r, 1.0);
-        CHECK(st.sym_ok());
-        CHECK(st.step(4.0, 1.0, 0.0, false) == hp::LoopState::CONTINUE);  // d = 2
-        CHECK(st.sym_ok());
-        st.enter_stage(2);
+        for (int k = 0; k < 6; ++k) {
+            CHECK(st.sym_ok());
+            CHECK(st.step(16.0, 1.0, 0.0, false) == hp::LoopState::CONTINUE);  // d = 4
+        }
+        CHECK(!st.sym_ok());
+        // SM (order 2): 2^(k+1) 2^-52 <= 1e-7 up to k + 1 = 28
+        hp_params q = params(HP_METHOD_SM, HP_PREC_FP64);
+        st.init(&q, &r, 1.0);
+        for (int k = 0; k < 28; ++k) {
+            CHECK(st.sym_ok());
+            CHECK(st.step(1.0, 1.0, 0.0, false) == hp::LoopState::CONTINUE);  // d = 1
+        }
         CHECK(!st.sym_ok());
     }
     std::printf("ok\n");

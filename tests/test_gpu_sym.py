@@ -137,3 +137,30 @@ def test_solve_with_user_x0_or_drazin_keeps_full_products():
     dz = inputs.drazin_jordan(n=2048, nb=1792, cond_p=10.0, seed=1004)
     _, info = hpw.drazin(to_dev(dz.A), 3, tol=1e-8, symmetric=True)
     assert info["gemms_sym"] == 0
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32_fp64"])
+def test_staged_solves_with_symmetric_products(precision):
+    """HP_FLAG_SYMMETRIC in staged solves. Mirroring the upper triangle turns
+    the part of R that is not symmetric into a symmetric error of the same
+    size, which grows by the order per loop in the unconverged directions:
+    harmless from FP64 rounding over a few loops, not from FP32 or 16-bit
+    rounding (rules that let FP32 loops run symmetric diverged, to 1e50 and
+    1e67 on this input). Staged solves therefore form full products: no
+    symmetric launches, the same result as without the flag."""
+    hpw = need_gpu()
+    say(f"{precision} sym 2100")
+    d = inputs.square_svd(2100, smin=1e-3, seed=31)
+    closed = (d.V / d.s) @ d.U.T
+    A = to_dev(d.A)
+    kw = dict(alpha_rule="user", alpha=1.0, precision=precision, tol=1e-10)
+    Xs, i_s = hpw.solve(A, symmetric=True, **kw)
+    Xf, i_f = hpw.solve(A, **kw)
+    torch.cuda.synchronize()
+    es, ef = rel(Xs.cpu().numpy(), closed), rel(Xf.cpu().numpy(), closed)
+    say(f"  stages {i_s['iters_stage']} vs {i_f['iters_stage']}, sym launches {i_s['gemms_sym']}, "
+        f"err {es:.2e} vs {ef:.2e}")
+    assert i_s["status"] == i_f["status"] == "ok"
+    assert i_f["gemms_sym"] == 0
+    assert i_s["gemms_sym"] == 0
+    assert es <= 1e-10 and es <= 2.0 * ef + 1e-11
