@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as O
 from gpu_common import need_gpu, rel, say, to_dev
 from paper_1604_07893_amd import inputs
 
@@ -114,14 +115,20 @@ def test_solve_symmetric_matches_full_products(m, n, variant):
     assert i_s["gemms_sym"] > 0 and i_f["gemms_sym"] == 0
     assert i_s["iters"] == i_f["iters"] and i_s["switch_iter"] == i_f["switch_iter"]
     xs, xf = Xs.cpu().numpy(), Xf.cpu().numpy()
-    es, ef, d = rel(xs, closed), rel(xf, closed), rel(xs, xf)
-    say(f"  iters {i_s['iters']}: err sym {es:.2e}, full {ef:.2e}, sym vs full {d:.2e}")
+    es, ef, dsf = rel(xs, closed), rel(xf, closed), rel(xs, xf)
+    say(f"  iters {i_s['iters']}: err sym {es:.2e}, full {ef:.2e}, sym vs full {dsf:.2e}")
     # both at the inverse to the method's tolerance; the two differ by the
     # rounding of the summation order, amplified as any rounding is (kappa 1e3)
-    assert es <= 1e-10 and ef <= 1e-10 and d <= 1e-10
+    assert es <= 1e-10 and ef <= 1e-10 and dsf <= 1e-10
     assert es <= 2.0 * ef + 1e-11
     # the symmetric launches count N (N + 1) K flops each
     assert i_s["gflop"] < i_f["gflop"]
+    if m == n:
+        # and the FP64 oracle (right form, full products) takes the same loops
+        ref = O.solve(d.A, kind="mp", alpha_rule="user", alpha=1.0, variant=variant, tol=1e-10)
+        say(f"  oracle iters {ref.iters}, sym vs oracle {rel(xs, ref.X):.2e}")
+        assert ref.iters == i_s["iters"]
+        assert rel(xs, ref.X) <= 1e-10
 
 
 def test_solve_with_user_x0_or_drazin_keeps_full_products():
