@@ -359,7 +359,9 @@ int hp_gemm_ws(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K,
 
 /* Workspace of hp_gemm_sym for an N x N x K product: partial tiles for the
  * blocks that share an output tile, and arrival counters (the size depends on
- * the current device's compute-unit count). dtype HP_DTYPE_F64 or F32. */
+ * the current device's compute-unit count; 0 when no device is visible, and
+ * hp_gemm_sym then forms the full product). dtype HP_DTYPE_F64 or F32.
+ * Errors: HP_EINVAL for another dtype, N or K outside [1, 2^24], NULL bytes. */
 int hp_gemm_sym_workspace_bytes(int dtype, int64_t N, int64_t K, size_t* bytes);
 
 /* C = alpha A B + beta_identity I (N x N) for a product that the caller knows

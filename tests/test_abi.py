@@ -27,7 +27,8 @@ def test_header_declares_the_boundary():
                      "hp_batched_workspace_bytes", "hp_solve_batched", "hp_serve_create",
                      "hp_serve_submit", "hp_serve_step", "hp_serve_poll", "hp_serve_destroy",
                      "hp_autotune", "hp_tune_export", "hp_tune_import",
-                     "hp_residuals_workspace_bytes", "hp_residuals"):
+                     "hp_residuals_workspace_bytes", "hp_residuals", "hp_gemm_sym",
+                     "hp_gemm_sym_workspace_bytes"):
         assert required in names
 
 
@@ -116,3 +117,23 @@ def test_workspace_follows_the_plan():
     assert 7 * 4096 * 4096 * 8 < right
     assert wb(precision="fp32") < wb() < wb(precision="fp32_fp64") < wb(precision="mixed")
     assert hpw.workspace_bytes(hpw.make_params(), 8192, 8192) > 10 * 8192 * 8192 * 8
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
+def test_symmetric_product_argument_checks():
+    """hp_gemm_sym / hp_gemm_sym_workspace_bytes reject bad arguments before
+    any device work: FP64 and FP32 only, positive sizes, a handle."""
+    from paper_1604_07893_amd import hyperpower as hpw
+    lib = hpw.load_library()
+    nb = ctypes.c_size_t(7)
+    assert lib.hp_gemm_sym_workspace_bytes(2, 64, 64, ctypes.byref(nb)) == EINVAL   # 16-bit
+    assert lib.hp_gemm_sym_workspace_bytes(0, 0, 64, ctypes.byref(nb)) == EINVAL
+    assert lib.hp_gemm_sym_workspace_bytes(1, 64, -1, ctypes.byref(nb)) == EINVAL
+    assert lib.hp_gemm_sym_workspace_bytes(0, 64, 64, None) == EINVAL
+    # a valid request answers (no device here: nothing to share out, 0 bytes)
+    assert lib.hp_gemm_sym_workspace_bytes(0, 2048, 2048, ctypes.byref(nb)) == 0
+    assert lib.hp_gemm_sym(None, 0, 64, 64, 1.0, None, 64, None, 64, 0.0, None, 64, None, 0,
+                           None) == EINVAL
+    # the flag is accepted by the plan of every kind (Drazin simply ignores it)
+    for kw in (dict(symmetric=True), dict(symmetric=True, kind="drazin", l=2, alpha_rule="trace")):
+        assert hpw.workspace_bytes(hpw.make_params(**kw), 64, 64) > 0
