@@ -171,3 +171,28 @@ def test_staged_solves_with_symmetric_products(precision):
     assert i_f["gemms_sym"] == 0
     assert i_s["gemms_sym"] == 0
     assert es <= 1e-10 and es <= 2.0 * ef + 1e-11
+
+
+def test_complex_solve_with_symmetric_products():
+    """A complex full-rank 1100 x 1100 A: the real form (2200 x 2200) with
+    X0 = alpha times its transpose keeps X A symmetric, so HP_FLAG_SYMMETRIC
+    applies to hp_solve_complex too; same loops and the same inverse
+    (LAPACK's complex pseudo-inverse) as without it."""
+    hpw = need_gpu()
+    say("complex 1100 sym")
+    rng = np.random.default_rng(1100)
+    A = (rng.standard_normal((1100, 1100)) + 1j * rng.standard_normal((1100, 1100))) / 40.0
+    alpha = 1.0 / np.linalg.svd(A, compute_uv=False)[0] ** 2
+    Ad = torch.from_numpy(A).cuda()
+    kw = dict(alpha_rule="user", alpha=alpha, tol=1e-10)
+    Xs, i_s = hpw.solve_complex(Ad, symmetric=True, **kw)
+    Xf, i_f = hpw.solve_complex(Ad, **kw)
+    torch.cuda.synchronize()
+    P = np.linalg.pinv(A)
+    es, ef = rel(Xs.cpu().numpy(), P), rel(Xf.cpu().numpy(), P)
+    say(f"  iters {i_s['iters']} / {i_f['iters']}, sym launches {i_s['gemms_sym']}, "
+        f"err {es:.2e} vs {ef:.2e}")
+    assert i_s["status"] == i_f["status"] == "ok"
+    assert i_s["gemms_sym"] > 0 and i_f["gemms_sym"] == 0
+    assert i_s["iters"] == i_f["iters"]
+    assert es <= 1e-10 and es <= 2.0 * ef + 1e-11
