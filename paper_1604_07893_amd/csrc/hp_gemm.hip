@@ -19,6 +19,7 @@
 // optionally, per-block FP64 partial sums of (out_0 - ref)^2 and ref^2 for the
 // stopping test of Section 4.
 #include "hp_internal.h"
+#include "hp_symk.h"
 
 #include <type_traits>
 
@@ -512,25 +513,14 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_split(
                                                B + (int64_t)k0 * ldb, ldb, ep, tm, tn, t, split);
 }
 
-// Upper-triangle tile t (row-major: row 0 holds tiles (0, 0..nt-1), row 1
-// (1, 1..nt-1), ...) of an nt x nt tile grid.
-__device__ inline void tri_of(int t, int nt, int& tm, int& tn) {
-    int r = 0;
-    while (t >= nt - r) {
-        t -= nt - r;
-        ++r;
-    }
-    tm = r;
-    tn = r + t;
-}
-
 // Symmetric product (EpilogueT::sym) as one stream-K launch over the tiles on
 // and above the diagonal: the triangle's tiles * ipt K-steps (ipt = K-tiles
 // per tile), laid end to end, are cut into gridDim.x ranges of ipc steps, one
-// per block. A block walks its range tile by tile; a tile that lies wholly in
-// one range is finished there, one that spans several ranges (sk_np pieces)
-// by the last of their blocks to arrive. A block's first piece uses partial
-// slot 2b and its last slot 2b + 1, so 2 * gridDim.x slots suffice.
+// per block (the partition in hp_symk.h). A block walks its range tile by
+// tile; a tile that lies wholly in one range is finished there, one that
+// spans several ranges by the last of their blocks to arrive. A block's first
+// piece uses partial slot 2b and its last slot 2b + 1, so 2 * gridDim.x slots
+// suffice.
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
 __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN))
 __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_sym(
@@ -542,19 +532,14 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_sym(
     int64_t it = (int64_t)b * ipc;
     const int64_t end = min(it + (int64_t)ipc, total);
     while (it < end) {
-        const int t = (int)(it / ipt);
-        const int k0 = (int)(it - (int64_t)t * ipt);
-        const int k1 = (int)min((int64_t)ipt, k0 + (end - it));
-        const int64_t ts = (int64_t)t * ipt;
-        const int b0 = (int)(ts / ipc), b1 = (int)((ts + ipt - 1) / ipc);
-        const int slot0 = 2 * b0 + ((int64_t)b0 * ipc >= ts ? 0 : 1);
+        const SymPiece pc = sym_piece(it, end, ipt, ipc, b);
         int tm, tn;
-        tri_of(t, nt, tm, tn);
-        const int kb = k0 * BK, ke = min(K, k1 * BK);
+        sym_tile_of(pc.t, nt, tm, tn);
+        const int kb = pc.k0 * BK, ke = min(K, pc.k1 * BK);
         gemm_tile<T, BM, BN, BK, WM, WN, PF, -1, true>(N, N, ke - kb, A + kb, lda,
-                                                      B + (int64_t)kb * ldb, ldb, ep, tm, tn, t,
-                                                      b - b0, b1 - b0 + 1, slot0, b0);
-        it += k1 - k0;
+                                                      B + (int64_t)kb * ldb, ldb, ep, tm, tn, pc.t,
+                                                      pc.idx, pc.np, pc.slot0, pc.b0);
+        it += pc.k1 - pc.k0;
         __syncthreads();  // the next piece's staging reuses the LDS tiles
     }
 }
@@ -1229,9 +1214,7 @@ SymShape sym_shape(int64_t N, int64_t K) {
     sh.nt = (int)cdiv(N, BM);
     sh.tiles = sh.nt * (sh.nt + 1) / 2;
     sh.ipt = (int)cdiv(K, BK);
-    const int64_t total = (int64_t)sh.tiles * sh.ipt;
-    sh.ipc = (int)cdiv(total, g);
-    sh.grid = (int)cdiv(total, sh.ipc);
+    sym_layout(sh.tiles, sh.ipt, g, &sh.ipc, &sh.grid);
     return sh;
 }
 

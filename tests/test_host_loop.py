@@ -226,3 +226,20 @@ def test_symmetric_products_only_far_from_the_tolerance(tmp_path):
                     "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
+
+
+def test_symmetric_product_partition(tmp_path):
+    """The stream-K partition of the symmetric product (hp_symk.h, shared with
+    the kernel): every K-step once, pieces on consecutive blocks, whole tiles
+    on single blocks, distinct partial slots below 2 * grid
+    (tests/host/sym_partition_check.cpp)."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = tmp_path / "symk"
+    subprocess.run([gxx, "-std=c++17", "-O2", "-Wall",
+                    "-I", os.path.join(ROOT, "paper_1604_07893_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "sym_partition_check.cpp"),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
