@@ -138,22 +138,18 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area) {
                             hp::gemm_split_slots(hp::gemm_pick_tile(M, N, K, gt), M, N, K));
         pl.splitCnt = pl.splitSlots;
         // the symmetric launches of the loop's s x s products (K = s, or m or
-        // n for the residual and the stabilising middle product)
+        // n for the residual and the stabilising middle product); FP64 solves
+        // only (LoopState::sym_ok)
         pl.sym = p->kind == HP_KIND_MOORE_PENROSE && p->alpha_rule != HP_ALPHA_DIAG &&
-                 !(p->chop > 0.0) && (p->flags & HP_FLAG_SYMMETRIC);
+                 !(p->chop > 0.0) && p->precision == HP_PREC_FP64 &&
+                 (p->flags & HP_FLAG_SYMMETRIC);
         if (pl.sym) {
-            for (hp::GemmType gt : types) {
-                if (gt == hp::GT_F64 && fp32only) continue;
-                if (gt == hp::GT_F32 && !pl.has32) continue;
-                for (int64_t K : dims) {
-                    int64_t slots = 0, cnt = 0;
-                    hp::gemm_sym_scratch(hp::gemm_pick_tile(pl.s, pl.s, K, gt), gt, pl.s, &slots,
-                                         &cnt);
-                    // slots of 128 x 128 elements of the GEMM type, in FP64 tiles
-                    if (gt == hp::GT_F32) slots = (slots + 1) / 2;
-                    pl.splitSlots = std::max(pl.splitSlots, slots);
-                    pl.splitCnt = std::max(pl.splitCnt, cnt);
-                }
+            for (int64_t K : dims) {
+                int64_t slots = 0, cnt = 0;
+                hp::gemm_sym_scratch(hp::gemm_pick_tile(pl.s, pl.s, K, hp::GT_F64), hp::GT_F64,
+                                     pl.s, &slots, &cnt);
+                pl.splitSlots = std::max(pl.splitSlots, slots);
+                pl.splitCnt = std::max(pl.splitCnt, cnt);
             }
         }
         if (pl.splitSlots > 0) {
