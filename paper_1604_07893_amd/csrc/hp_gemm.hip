@@ -21,6 +21,7 @@
 #include "hp_internal.h"
 #include "hp_symk.h"
 
+#include <atomic>
 #include <type_traits>
 
 namespace hp {
@@ -1189,8 +1190,10 @@ hipError_t launch_split(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda
 // times blocks per unit): the stream-K grid. Queried once per kernel.
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
 int sym_grid() {
-    static int g = 0;
-    if (g == 0) {
+    // the same value whichever thread computes it first
+    static std::atomic<int> g{0};
+    int v = g.load(std::memory_order_relaxed);
+    if (v == 0) {
         int dev = 0, cus = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1198,9 +1201,10 @@ int sym_grid() {
                 &per, reinterpret_cast<const void*>(&k_gemm_sym<T, BM, BN, BK, WM, WN, PF>),
                 64 * (BM / WM) * (BN / WN), 0) != hipSuccess)
             return 0;
-        g = cus * std::max(per, 1);
+        v = cus * std::max(per, 1);
+        g.store(v, std::memory_order_relaxed);
     }
-    return g;
+    return v;
 }
 
 struct SymShape {
