@@ -205,3 +205,25 @@ def test_complex_solve_with_symmetric_products():
     assert i_s["gemms_sym"] > 0 and i_f["gemms_sym"] == 0
     assert i_s["iters"] == i_f["iters"]
     assert es <= 1e-10 and es <= 2.0 * ef + 1e-11
+
+
+def test_symmetric_products_with_gpu_alpha():
+    """X0 = alpha A^T with alpha from the GPU power iteration (sigma_max2) is
+    as symmetric as a given alpha: the same loops and the same inverse with and
+    without the symmetric products."""
+    hpw = need_gpu()
+    say("sym with sigma_max2 alpha")
+    d = inputs.lowrank_svd(2100, 2100, 2100, smin=1e-3, seed=77)
+    closed = (d.V / d.s) @ d.U.T
+    A = to_dev(d.A)
+    kw = dict(alpha_rule="sigma_max2", tol=1e-10)
+    Xs, i_s = hpw.solve(A, symmetric=True, **kw)
+    Xf, i_f = hpw.solve(A, **kw)
+    torch.cuda.synchronize()
+    es, ef = rel(Xs.cpu().numpy(), closed), rel(Xf.cpu().numpy(), closed)
+    say(f"  alpha {i_s['alpha']:.6f}, iters {i_s['iters']} / {i_f['iters']}, "
+        f"sym launches {i_s['gemms_sym']}, err {es:.2e} vs {ef:.2e}")
+    assert i_s["alpha"] == i_f["alpha"]
+    assert i_s["status"] == i_f["status"] == "ok"
+    assert i_s["gemms_sym"] > 0 and i_s["iters"] == i_f["iters"]
+    assert es <= 1e-10 and es <= 2.0 * ef + 1e-11
