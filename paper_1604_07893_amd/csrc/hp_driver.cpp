@@ -521,9 +521,14 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         r_ready = false;
         scheme = p->method;
         HIPCHK(reduce_pairs(bf.small, S.last_blocks, bf.scal, s));
-        const bool inf_now = want_inf && st.stage == 2;
-        if (inf_now)
+        // the inf-norm change in the precision the stage holds its iterates in
+        // (rule HP_STOP_ABS_INF reads it in whichever stage is final)
+        const bool inf_now = want_inf;
+        if (inf_now && st.stage == 2)
             HIPCHK(diff_norm_inf(bf.b64.X[st.in_], bf.b64.ldX, bf.b64.X[st.ik], bf.b64.ldX, n, m,
+                                 bf.small, bf.scal, s));
+        else if (inf_now)
+            HIPCHK(diff_norm_inf(bf.b32.X[st.in_], bf.b32.ldX, bf.b32.X[st.ik], bf.b32.ldX, n, m,
                                  bf.small, bf.scal, s));
         HIPCHK(hipMemcpyAsync(hs, bf.scal, sizeof(double) * SLOT_COUNT, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

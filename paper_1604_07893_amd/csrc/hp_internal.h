@@ -246,6 +246,8 @@ hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipSt
 // scal[SLOT_DINF] = max_i sum_j |X1[i][j] - X0[i][j]|. `tmp` needs M doubles.
 hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_t ld0,
                          int64_t M, int64_t N, double* tmp, double* scal, hipStream_t s);
+hipError_t diff_norm_inf(const float* X1, int64_t ld1, const float* X0, int64_t ld0,
+                         int64_t M, int64_t N, double* tmp, double* scal, hipStream_t s);
 
 // scal[slot] = sum of squares of the M x N matrix X (fixed order). `tmp`
 // needs M doubles.

@@ -320,13 +320,15 @@ __global__ __launch_bounds__(kThreads) void k_reduce_pairs(const double* __restr
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_diff_rowsum(const double* __restrict__ X1, int64_t ld1,
-                                                          const double* __restrict__ X0, int64_t ld0,
+// Row sums of |X1 - X0| (one block per row), accumulated in FP64.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_diff_rowsum(const T* __restrict__ X1, int64_t ld1,
+                                                          const T* __restrict__ X0, int64_t ld0,
                                                           int N, double* __restrict__ rows) {
     const int r = blockIdx.x;
     double s = 0.0;
     for (int c = threadIdx.x; c < N; c += kThreads)
-        s += fabs(X1[(int64_t)r * ld1 + c] - X0[(int64_t)r * ld0 + c]);
+        s += fabs((double)X1[(int64_t)r * ld1 + c] - (double)X0[(int64_t)r * ld0 + c]);
     s = block_sum(s);
     if (threadIdx.x == 0) rows[r] = s;
 }
@@ -570,12 +572,23 @@ hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipSt
     return hipGetLastError();
 }
 
-hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_t ld0, int64_t M,
-                         int64_t N, double* tmp, double* scal, hipStream_t s) {
-    hipLaunchKernelGGL(k_diff_rowsum, dim3((unsigned)M), dim3(kThreads), 0, s, X1, ld1, X0, ld0,
+template <typename T>
+static hipError_t diff_norm_inf_t(const T* X1, int64_t ld1, const T* X0, int64_t ld0, int64_t M,
+                                  int64_t N, double* tmp, double* scal, hipStream_t s) {
+    hipLaunchKernelGGL(k_diff_rowsum<T>, dim3((unsigned)M), dim3(kThreads), 0, s, X1, ld1, X0, ld0,
                        (int)N, tmp);
     hipLaunchKernelGGL(k_max_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal, (int)SLOT_DINF);
     return hipGetLastError();
+}
+
+hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_t ld0, int64_t M,
+                         int64_t N, double* tmp, double* scal, hipStream_t s) {
+    return diff_norm_inf_t(X1, ld1, X0, ld0, M, N, tmp, scal, s);
+}
+
+hipError_t diff_norm_inf(const float* X1, int64_t ld1, const float* X0, int64_t ld0, int64_t M,
+                         int64_t N, double* tmp, double* scal, hipStream_t s) {
+    return diff_norm_inf_t(X1, ld1, X0, ld0, M, N, tmp, scal, s);
 }
 
 }  // namespace hp

@@ -71,6 +71,24 @@ def test_stop_rules_and_coc_match_oracle():
         assert np.all(got[~big] <= floor)
 
 
+def test_fp32_loops_with_the_inf_norm_rule():
+    """Rule (Example 8.1) with FP32 loops: the inf-norm change is formed from
+    the FP32 iterates of the final stage, so the stop falls where the oracle's
+    does. (A stale value in its slot would stop the solve after one loop.)"""
+    say("fp32 abs_inf")
+    A = inputs.uniform(200, 100, seed=1001)
+    tol = 1e-4
+    ref = O.solve(A, kind="mp", stop="abs_inf", tol=tol)
+    assert ref.iters >= 4
+    X, info = run(A, precision="fp32", stop="abs_inf", tol=tol)
+    assert info["status"] == "ok" and info["iters"] == ref.iters
+    # the changes agree to FP32 rounding while they are above its floor
+    got, want = np.array(info["dinf_hist"]), np.array(ref.diff_inf_hist)
+    np.testing.assert_allclose(got[:-1], want[:len(got) - 1], rtol=1e-3)
+    assert got[-1] <= tol
+    assert rel(X, ref.X) <= 1e-4
+
+
 def test_user_alpha_and_given_x0():
     A = inputs.uniform(90, 60, seed=4)
     s1 = np.linalg.svd(A, compute_uv=False)[0]
