@@ -309,6 +309,28 @@ int hp_solve(hp_handle* h, const hp_params* p,
              void* workspace, size_t ws_bytes,
              void* stream, hp_result* out);
 
+/* hp_solve for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, with the workspace taken from a fixed array of
+ * HP_NOALLOC_SCRATCH_BYTES bytes that the library's device code object holds
+ * on each device it runs on, from the first hp_create on that device until
+ * the process ends. Arguments and results are those of hp_solve without
+ * `workspace`/`ws_bytes`; the caller still passes A, X0 and X. Allocates
+ * nothing (no hipMalloc, hipFree or allocating library call). Every call on
+ * one device shares that device's array: calls that overlap on a device
+ * (another stream, another host thread, another handle) race and must not
+ * be issued; a call leaves the array's contents behind, and the next call
+ * does not depend on them.
+ * Errors: as hp_solve; HP_EWORKSPACE when hp_workspace_bytes(p, m, n)
+ * exceeds HP_NOALLOC_SCRATCH_BYTES (e.g. 200 x 100 FP64 needs 1.2 MiB,
+ * 512 x 512 FP64 22 MiB, 1024 x 1024 FP64 121 MiB: too large). */
+#define HP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int hp_solve_noalloc(hp_handle* h, const hp_params* p,
+                     const double* A, int64_t m, int64_t n, int64_t lda,
+                     const double* X0, int64_t ldx0,
+                     double* X, int64_t ldx,
+                     void* stream, hp_result* out);
+
 /* Complex A (m x n, interleaved real and imaginary doubles, leading dimension
  * lda >= n in complex elements): X (n x m, interleaved, ldx >= m) ~ the
  * generalized inverse hp_solve defines, with G = A^* (conjugate transpose)

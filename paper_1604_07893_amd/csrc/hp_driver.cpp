@@ -657,6 +657,9 @@ int hp_create(hp_handle** out, int device) {
             return HP_EHIP;
         }
     }
+    // the fixed workspace of hp_solve_noalloc on this device (if this fails,
+    // that entry point tries again on its first call and reports HP_EHIP)
+    (void)hp::noalloc_init(device);
     *out = h;
     return HP_OK;
 }

@@ -94,6 +94,10 @@ struct PMConst {
 };
 PMConst pm_const();
 
+// Takes the device address of hp_solve_noalloc's fixed workspace on `device`
+// (which must be current) once per device; hp_create calls it.
+int noalloc_init(int device);
+
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t pad_ld(int64_t cols);

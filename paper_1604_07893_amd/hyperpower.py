@@ -37,6 +37,7 @@ LOWP = {"bf16": 0, "f16": 1, "fp16": 1}
 FLAG_TIME_KERNELS, FLAG_INF_NORM, FLAG_NO_GRAPH, FLAG_NO_RETRY, FLAG_SYMMETRIC = 1, 2, 4, 8, 16
 DTYPE = {torch.float64: 0, torch.float32: 1}
 HP_HIST = 128
+NOALLOC_SCRATCH_BYTES = 64 << 20  # HP_NOALLOC_SCRATCH_BYTES
 
 
 class HpParams(ctypes.Structure):
@@ -84,6 +85,9 @@ SIGNATURES = {
     "hp_solve": (c_int, [c_void_p, POINTER(HpParams), c_void_p, c_int64, c_int64, c_int64,
                          c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t, c_void_p,
                          POINTER(HpResult)]),
+    "hp_solve_noalloc": (c_int, [c_void_p, POINTER(HpParams), c_void_p, c_int64, c_int64, c_int64,
+                                 c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                 POINTER(HpResult)]),
     "hp_gemm": (c_int, [c_void_p, c_int, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
                         c_void_p, c_int64, c_double, c_void_p, c_int64, c_void_p]),
     "hp_autotune_scratch_bytes": (c_int, [c_int, c_int64, c_int64, c_int64, POINTER(c_size_t)]),
@@ -269,6 +273,32 @@ def solve(A: torch.Tensor, *, X0: torch.Tensor | None = None, out: torch.Tensor 
     if rc < 0:
         raise HyperpowerError(rc, "hp_solve")
     return out, result_dict(res)
+
+
+def solve_noalloc(A: torch.Tensor, out: torch.Tensor, *, X0: torch.Tensor | None = None,
+                  stream: torch.cuda.Stream | None = None, **kw) -> dict:
+    """hp_solve_noalloc: as solve(), with the library's fixed device workspace
+    (HP_NOALLOC_SCRATCH_BYTES per device) instead of caller memory; the
+    caller passes the output `out` (n x m). Returns info."""
+    _check_matrix(A, "A")
+    _check_matrix(out, "out")
+    m, n = A.shape
+    if tuple(out.shape) != (n, m):
+        raise ValueError("out must be n x m")
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    params = make_params(**kw)
+    x0p, ldx0 = None, 0
+    if X0 is not None:
+        _check_matrix(X0, "X0")
+        x0p, ldx0 = X0.data_ptr(), X0.stride(0)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    res = HpResult()
+    rc = load_library().hp_solve_noalloc(
+        handle(dev).ptr, ctypes.byref(params), A.data_ptr(), m, n, A.stride(0), x0p, ldx0,
+        out.data_ptr(), out.stride(0), s.cuda_stream, ctypes.byref(res))
+    if rc < 0:
+        raise HyperpowerError(rc, "hp_solve_noalloc")
+    return result_dict(res)
 
 
 def solve_complex(A: torch.Tensor, *, stream: torch.cuda.Stream | None = None,
