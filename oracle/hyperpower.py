@@ -18,7 +18,13 @@ Pins (what ties this file to something other than itself) live in
   * Drazin results: the Jordan-form closed form;
   * the iteration limit: classical order-2 Newton-Schulz reaches the same X;
   * Theorem 6.2 / 7.1: the E22 block grows 18x per plain loop and is removed by
-    the stabilising product.
+    the stabilising product;
+  * ``norm_1`` / ``norm_inf`` (the alpha of Section 4): hand-summed values and
+    numpy's matrix norms;
+  * ``penrose_residuals`` / ``drazin_residuals``: closed forms on iterates
+    with a known error built in the factors' bases.
+Parity unpinned: the (stopreliable) branch of ``solve`` (stop="paper_4_1"):
+the paper prints no outcome of that rule, so only its quantity is checked.
 """
 
 from __future__ import annotations
