@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define HP_ABI_VERSION 3
+#define HP_ABI_VERSION 4
 
 /* ---- status codes ------------------------------------------------------ */
 #define HP_OK 0
@@ -44,8 +44,15 @@ extern "C" {
                              in; X is the input of the loop that saw it
                              (Section 6: looping past convergence can diverge) */
 #define HP_DIVERGED 3     /* the relative change exceeded diverge_limit before
-                             convergence set in (alpha too large) */
-#define HP_NONFINITE 4    /* a NaN/Inf appeared; X is the last finite iterate */
+                             convergence set in (alpha too large, or rounding
+                             growing in a null-space block, Section 6); X is
+                             the best iterate before the blow-up: the input of
+                             the loop with the smallest relative change
+                             (hp_solve; batched and served solves return the
+                             input of the loop that detected it) */
+#define HP_NONFINITE 4    /* a NaN/Inf appeared; X is the best iterate as for
+                             HP_DIVERGED if no change below tau_switch had been
+                             seen, else the last finite iterate */
 #define HP_PENDING 5      /* serving: the request has not finished yet */
 #define HP_EINVAL (-1)    /* bad argument (shape, leading dim, alignment, enum) */
 #define HP_EWORKSPACE (-2)/* workspace NULL or smaller than hp_workspace_bytes */
@@ -162,6 +169,22 @@ extern "C" {
                            (an addition to the paper's method, from its third
                            and fourth Penrose equations). */
 
+#define HP_PREC_DELTA32 4 /* every loop in the delta form (an exact
+                           re-association of Section 2's products): the
+                           residual R = I - AX and the update
+                           X_{k+1} = X_k + X_k (W - I) in FP64, the products of
+                           the polynomial on R in FP32 (FP32 storage and MFMA),
+                           each product forming a b and its epilogue adding
+                           a + b for factors I + a, I + b, so that no value
+                           I + (small) is rounded to FP32. The FP32 error then
+                           enters W - I, not the update or R: on rank-deficient
+                           input the null-space block is not seeded by FP32
+                           rounding (it grows 18x per plain loop, Theorem 6.2,
+                           and all-FP32 loops diverge there), and the error
+                           floor is about u_fp32 * kappa-dependent growth of
+                           the off-diagonal blocks (not an FP64 tolerance on
+                           singular input). HP_METHOD_PM only; single solves */
+
 /* hp_params.low_dtype: operand type of the first mixed stage */
 #define HP_LOWP_BF16 0
 #define HP_LOWP_F16 1
@@ -198,6 +221,17 @@ extern "C" {
                                   rank(A) < s the forced symmetry feeds the
                                   null-space error block back into the
                                   range block: do not set it */
+
+#define HP_FLAG_FP64_POLY 32   /* HP_PREC_MIXED / HP_PREC_FP32_FP64 single
+                                  solves: run the FP64 stage's polynomial in
+                                  FP64 too. By default an FP64-stage loop whose
+                                  last known residual has ||R||_F < 0.5 (the
+                                  loops converge to R = 0: no null space on
+                                  the residual's side) runs in the delta form
+                                  of HP_PREC_DELTA32: R and the update in FP64,
+                                  the polynomial's products in FP32, whose
+                                  rounding then scales with ||R||; other FP64
+                                  loops form every product in FP64 */
 
 /* GEMM element type for hp_gemm */
 #define HP_DTYPE_F64 0 /* FP64 operands, v_mfma_f64_16x16x4f64, FP64 accumulate */
@@ -269,6 +303,11 @@ typedef struct hp_result {
     double gflop_sym;      /* their work, N*(N+1)*K per launch (included in gflop) */
     double gemm_ms_sym;    /* their kernel time (HP_FLAG_TIME_KERNELS; included
                               in gemm_ms) */
+    int32_t iters_delta;   /* loops whose polynomial ran in the delta form */
+    int32_t reserved_r2;
+    double gflop_engine[3];   /* executed GEMM work by MFMA path: 16-bit
+                                 operands, FP32, FP64 (included in gflop) */
+    double gemm_ms_engine[3]; /* their kernel time (HP_FLAG_TIME_KERNELS) */
 } hp_result;
 
 typedef struct hp_handle hp_handle;

@@ -323,6 +323,7 @@ class Result:
     bound_hist: list = field(default_factory=list)  # ||R||_F of "rel_fro_bound" checks
     fro_hist: list = field(default_factory=list)    # (||X_{k+1}-X_k||_F, ||X_k||_F) per loop
     method_hist: list = field(default_factory=list) # scheme run by each loop
+    returned_iter: int = 0      # k of the returned iterate X_k (X_0 = X0)
 
 
 def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1inf",
@@ -365,6 +366,10 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
     that does not decrease ends with "stagnated" and returns X_k, the input of
     that loop; a relative change above diverge_limit before then ends with
     "diverged"; max_iter loops end with "maxiter" (Section 8 uses 100).
+    On "diverged", and on "nonfinite" before some change below tau_switch has
+    been seen, the returned iterate is the best one before the blow-up: the
+    input of the loop with the smallest relative change so far (X_k itself if
+    no earlier loop qualifies).
     The returned iterate on success is X_{k+1}, and iters counts the loops run.
     """
     if not (isinstance(A, np.ndarray) and (A.dtype == object) == (ar is MP)):
@@ -391,6 +396,7 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
         res.switch_iter = 0
     converging = False
     next_method = None
+    best = None  # (d, k, X_k): the input of the loop with the smallest change
     for k in range(max_iter):
         use = next_method or method
         next_method = None
@@ -402,7 +408,10 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
             Xn = chop(Xn, chop_eps)
         res.iters = k + 1
         if not ar.isfinite(Xn):
-            res.status, res.X = "nonfinite", X
+            if best is not None and not converging:
+                res.status, res.X, res.returned_iter = "nonfinite", best[2], best[1]
+            else:
+                res.status, res.X, res.returned_iter = "nonfinite", X, k
             return res
         D = Xn - X
         nD, nX = norm_fro(D, ar), norm_fro(X, ar)
@@ -422,19 +431,24 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
             raise ValueError(f"unknown stop rule {stop!r}")
         res.stop_hist.append(sval)
         if passed:
-            res.status, res.X = "ok", Xn
+            res.status, res.X, res.returned_iter = "ok", Xn, k + 1
             return res
         if converging and d >= res.d_hist[-2]:
-            res.status, res.X = "stagnated", X
+            res.status, res.X, res.returned_iter = "stagnated", X, k
             return res
         if not converging and d > diverge_limit:
-            res.status, res.X = "diverged", X
+            if best is not None:
+                res.status, res.X, res.returned_iter = "diverged", best[2], best[1]
+            else:
+                res.status, res.X, res.returned_iter = "diverged", X, k
             return res
         if d < tau_switch:
             converging = True
             if variant == "stabilised" and not stabilising:
                 stabilising = True
                 res.switch_iter = k + 1
+        if not converging and (best is None or d < best[0]):
+            best = (d, k, X)
         if (stop == "rel_fro_bound" and not stabilising and k + 1 < max_iter
                 and d ** p < tol):
             # The next (plain) loop changes X by X (R + R^2 + ... + R^{p-1})
@@ -446,7 +460,7 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
             r = norm_fro(R, ar)
             res.bound_hist.append(r)
             if r < 1 and r / (1 - r) < tol:
-                res.status, res.X = "ok", Xn
+                res.status, res.X, res.returned_iter = "ok", Xn, k + 1
                 return res
             if method == "pm" and r < 1:
                 # the next loop's residual is R^q: an order q with r^q < tol/2
@@ -457,6 +471,7 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
                         break
         X = Xn
     res.X = X
+    res.returned_iter = res.iters
     return res
 
 

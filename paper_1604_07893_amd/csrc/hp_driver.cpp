@@ -50,7 +50,8 @@ static bool choose_left(const hp_params* p, int64_t m, int64_t n) {
     return m > n;
 }
 
-Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area) {
+Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool single) {
+    const bool split_area = single;
     Plan pl;
     pl.m = m;
     pl.n = n;
@@ -64,9 +65,9 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area) {
     pl.ldS32 = pad_ld(pl.s);
     const bool fp32only = p->precision == HP_PREC_FP32;
     pl.has32 = p->precision != HP_PREC_FP64;
-    pl.nX64 = fp32only ? 1 : 3;
+    pl.nX64 = fp32only ? 1 : (single ? 4 : 3);
     pl.nS64 = fp32only ? 0 : 7;
-    pl.nX32 = pl.has32 ? 3 : 0;
+    pl.nX32 = pl.has32 ? (single && fp32only ? 4 : 3) : 0;
     pl.nS32 = pl.has32 ? 7 : 0;
     // Drazin set-up forms A^l in two s x s buffers of the FP64 set
     if (fp32only && p->kind == HP_KIND_DRAZIN) pl.nS64 = 2;
@@ -81,7 +82,11 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area) {
         pl.offS[i] = off;
         off = align_up(off + sizeof(double) * (size_t)(pl.s * pl.ldS));
     }
-    pl.has_proj = pl.has32 && p->kind == HP_KIND_MOORE_PENROSE && p->precision != HP_PREC_FP32;
+    pl.has_proj = pl.has32 && p->kind == HP_KIND_MOORE_PENROSE &&
+                  (p->precision == HP_PREC_MIXED || p->precision == HP_PREC_FP32_FP64);
+    pl.delta = p->precision == HP_PREC_DELTA32 ||
+               ((p->precision == HP_PREC_MIXED || p->precision == HP_PREC_FP32_FP64) &&
+                !(p->flags & HP_FLAG_FP64_POLY));
     if (pl.has_proj) {
         pl.offAt = off;
         off = align_up(off + sizeof(double) * (size_t)(n * pl.ldX));
@@ -198,7 +203,7 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
     if (p->variant < HP_VARIANT_PLAIN || p->variant > HP_VARIANT_STAB_ALWAYS) return HP_EINVAL;
     if (p->side < HP_SIDE_AUTO || p->side > HP_SIDE_LEFT) return HP_EINVAL;
     if (p->stop_rule < HP_STOP_REL_FRO || p->stop_rule > HP_STOP_REL_FRO_BOUND) return HP_EINVAL;
-    if (p->precision < HP_PREC_FP64 || p->precision > HP_PREC_FP32_FP64) return HP_EINVAL;
+    if (p->precision < HP_PREC_FP64 || p->precision > HP_PREC_DELTA32) return HP_EINVAL;
     if (p->low_dtype != HP_LOWP_BF16 && p->low_dtype != HP_LOWP_F16) return HP_EINVAL;
     if (p->method < HP_METHOD_PM || p->method > HP_METHOD_HM) return HP_EINVAL;
     // the comparison methods run without precision stages (the stage exits
@@ -263,14 +268,17 @@ struct GemmTimer {
     double total_ms = 0.0;
     hipStream_t s;
     double sym_ms = 0.0;  // the part of total_ms spent in symmetric launches
+    double eng_ms[3] = {};  // ... by MFMA path: 16-bit, FP32, FP64
     bool is_sym[hp_handle::kEvents / 2] = {};
+    int eng[hp_handle::kEvents / 2] = {};
     void before() {
         if (on && used + 2 <= hp_handle::kEvents) (void)hipEventRecord(h->ev[used], s);
     }
-    void after(bool sym = false) {
+    void after(bool sym, int engine_idx) {
         if (on && used + 2 <= hp_handle::kEvents) {
             (void)hipEventRecord(h->ev[used + 1], s);
             is_sym[used / 2] = sym;
+            eng[used / 2] = engine_idx;
             used += 2;
         }
     }
@@ -280,6 +288,7 @@ struct GemmTimer {
             if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) {
                 total_ms += ms;
                 if (is_sym[i / 2]) sym_ms += ms;
+                eng_ms[eng[i / 2]] += ms;
             }
         }
         used = 0;
@@ -355,11 +364,12 @@ struct Solver {
                 e = gemm_h16(t16, eng == ENG_BF16 ? LOWP_BF16 : LOWP_F16, g.M, g.N, g.K, ca->h,
                              ca->ld, cb->ht, cb->ldt, ep, s);
                 last_blocks = gemm_blocks(t16, g.M, g.N);
-                timer.after();
+                timer.after(false, 0);
                 if (e != hipSuccess) return HP_EHIP;
                 const double gf = 2.0 * (double)g.M * (double)g.N * (double)g.K * 1e-9;
                 gflop += gf;
                 res->gflop_stage[stage] += gf;
+                res->gflop_engine[0] += gf;
                 ++gemms;
                 return HP_OK;
             } else {
@@ -367,7 +377,8 @@ struct Solver {
                               g.B, g.ldb, ep, s);
             }
         }
-        timer.after(sym_launch);
+        const int ei = eng == ENG_F64 ? 2 : eng == ENG_F32 ? 1 : 0;
+        timer.after(sym_launch, ei);
         last_blocks = gemm_blocks(t, g.M, g.N);
         if (e != hipSuccess) return HP_EHIP;
         // a symmetric launch forms N (N + 1) / 2 distinct elements
@@ -375,6 +386,7 @@ struct Solver {
                           (double)g.K * 1e-9;
         gflop += gf;
         res->gflop_stage[stage] += gf;
+        res->gflop_engine[ei] += gf;
         ++gemms;
         if (sym_launch) {
             gflop_sym += gf;
@@ -423,6 +435,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
 
     LoopState st;
     st.init(p, res, alpha);
+    st.keep_best = true;
     if (st.stage < 2) {
         HIPCHK(convert(bf.b64.A, bf.b64.ldA, m, n, bf.b32.A, bf.b32.ldA, s));
         HIPCHK(convert(bf.b64.X[0], bf.b64.ldX, n, m, bf.b32.X[0], bf.b32.ldX, s));
@@ -441,7 +454,50 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
     // already have run for the residual bound).
     // `scheme`: a plain final-stage loop after a residual check (first == 1) may run
     // a lower-order scheme (LoopState::scheme_for)
+    // The delta form (describe_delta_poly): R and the update in FP64, the
+    // polynomial's products in FP32. HP_PREC_DELTA32 runs every loop so;
+    // staged precisions run an FP64-stage loop so when the latest residual
+    // norm it knows (r_last) is below kDeltaR, i.e. R is going to 0: then
+    // the FP32 rounding of W - I is relative to ||R|| and costs no accuracy.
+    // With a null space on the residual's side R tends to a projector
+    // (||R||_F >= 1) and every product stays FP64.
+    constexpr double kDeltaR = 0.5;
+    const bool delta_all = p->precision == HP_PREC_DELTA32;
+    const bool track_r = pl.delta && !delta_all;  // ||R||_F of each FP64-stage loop
+    double r_last = INFINITY;
+    auto delta_now = [&]() { return pl.delta && (delta_all || r_last < kDeltaR); };
+    auto run_delta = [&](int first, int scheme) -> int {
+        S.sym_loop = false;
+        const int64_t sd = pl.s;
+        double* Xk = bf.b64.X[st.ik];
+        if (first == 0) {
+            GemmCall<double> c0[1];
+            describe_residual<double>(pl, bf.b64, Xk,
+                                      epilogue_plain(bf.b64.S[0], bf.b64.ldS, -1.0, 1.0), c0, 0);
+            CHK(S.gemm<double>(ENG_F64, c0[0]));
+            if (track_r)
+                HIPCHK(diffsq(bf.b64.S[0], bf.b64.ldS, nullptr, 0, 0.0, sd, sd, bf.small, bf.scal,
+                              SLOT_RNORM2, s));
+        }
+        const double* W64 = bf.b64.S[0];  // SM: W - I = R
+        if (scheme != HP_METHOD_SM) {
+            HIPCHK(convert(bf.b64.S[0], bf.b64.ldS, sd, sd, bf.b32.S[0], bf.b32.ldS, s));
+            GemmCall<float> calls[kMaxLoopGemms];
+            float* Wd = nullptr;
+            const int nc = describe_delta_poly<float>(scheme, pl, bf.b32, calls, &Wd);
+            for (int i = 0; i < nc; ++i) CHK(S.gemm<float>(ENG_F32, calls[i]));
+            HIPCHK(convert(Wd, bf.b32.ldS, sd, sd, bf.b64.S[1], bf.b64.ldS, s));
+            W64 = bf.b64.S[1];
+        }
+        GemmCall<double> u[3];
+        const int nu = describe_update<double>(pl, bf.b64, W64, Xk, bf.b64.X[st.in_], bf.b64.X[2],
+                                               st.stabilising, bf.small, bf.b64.S[2], u, 0, true);
+        for (int i = 0; i < nu; ++i) CHK(S.gemm<double>(ENG_F64, u[i]));
+        ++res->iters_delta;
+        return HP_OK;
+    };
     auto run_loop = [&](int first, int scheme) -> int {
+        if (st.stage == 2 && delta_now()) return run_delta(first, scheme);
         S.sym_loop = st.sym_ok();
         if (st.stage == 2) {
             GemmCall<double> calls[kMaxLoopGemms];
@@ -453,7 +509,12 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
                                             bf.b64.X[st.in_], bf.b64.X[2], st.stabilising,
                                             bf.small, calls);
             set_chop(calls, nc, bf.b64.X[st.in_], p->chop);
-            for (int i = first; i < nc; ++i) CHK(S.gemm<double>(ENG_F64, calls[i]));
+            for (int i = first; i < nc; ++i) {
+                CHK(S.gemm<double>(ENG_F64, calls[i]));
+                if (i == 0 && track_r)  // the residual's norm decides the next loop's form
+                    HIPCHK(diffsq(bf.b64.S[0], bf.b64.ldS, nullptr, 0, 0.0, pl.s, pl.s, bf.small,
+                                  bf.scal, SLOT_RNORM2, s));
+            }
         } else {
             GemmCall<float> calls[kMaxLoopGemms];
             const int nc =
@@ -503,6 +564,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         *settled = false;
         double r = 0.0;
         CHK(next_residual(&r));
+        if (track_r) r_last = r;
         if (std::isfinite(r) && r < 1.0 && r / (1.0 - r) < p->tol) {
             st.stop_bound(r / (1.0 - r));
             *settled = true;
@@ -517,6 +579,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         Range loop_range("loop %d stage %d%s", st.k + 1, st.stage,
                          st.stabilising ? " stabilised" : "");
         S.stage = st.stage;
+        const bool r_ready_prev = r_ready;
         CHK(run_loop(r_ready ? 1 : 0, scheme));
         r_ready = false;
         scheme = p->method;
@@ -534,7 +597,22 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         HIPCHK(hipStreamSynchronize(s));
         S.timer.harvest();
 
+        // (a loop that reused the bound check's R keeps the r_last of that check)
+        if (track_r && st.stage == 2 && !r_ready_prev) r_last = std::sqrt(hs[SLOT_RNORM2]);
         LoopState::Action a = st.step(hs[SLOT_DIFF2], hs[SLOT_REF2], hs[SLOT_DINF], inf_now);
+        if (st.save_best) {
+            // keep the input of this loop: the best iterate so far (the next
+            // loop overwrites its buffer)
+            const int b = LoopState::kBest;
+            if (st.stage == 2)
+                HIPCHK(hipMemcpy2DAsync(bf.b64.X[b], bf.b64.ldX * sizeof(double),
+                                        bf.b64.X[st.save_from], bf.b64.ldX * sizeof(double),
+                                        m * sizeof(double), n, hipMemcpyDeviceToDevice, s));
+            else
+                HIPCHK(hipMemcpy2DAsync(bf.b32.X[b], bf.b32.ldX * sizeof(float),
+                                        bf.b32.X[st.save_from], bf.b32.ldX * sizeof(float),
+                                        m * sizeof(float), n, hipMemcpyDeviceToDevice, s));
+        }
         if (a == LoopState::DONE) break;
         if (a == LoopState::CONTINUE && st.k < p->max_iter && st.probe) {
             double r = 0.0;
@@ -562,6 +640,17 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
             const int next = st.stage + 1;
             if (next == 2) {
                 HIPCHK(convert(bf.b32.X[st.from_idx], bf.b32.ldX, n, m, bf.b64.X[0], bf.b64.ldX, s));
+                if (track_r) {
+                    // the lower stage's last residual (of the iterate's
+                    // predecessor, or of the iterate itself after a probe)
+                    // decides the form of the first FP64 loop
+                    HIPCHK(sumsq(bf.b32.S[0], bf.b32.ldS, pl.s, pl.s, bf.small, bf.scal,
+                                 SLOT_RNORM2, s));
+                    HIPCHK(hipMemcpyAsync(hs + SLOT_RNORM2, bf.scal + SLOT_RNORM2, sizeof(double),
+                                          hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipStreamSynchronize(s));
+                    r_last = std::sqrt(hs[SLOT_RNORM2]);
+                }
                 bool proj = false;
                 CHK(needs_projection(pl, bf, hs, s, &proj));
                 // the projection assumes an iterate in the converging regime;
@@ -713,6 +802,7 @@ int hp_solve(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64
     res->gemms_sym = S.gemms_sym;
     res->gflop_sym = S.gflop_sym;
     res->gemm_ms_sym = S.timer.sym_ms;
+    for (int i = 0; i < 3; ++i) res->gemm_ms_engine[i] = S.timer.eng_ms[i];
     res->time_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return rc;

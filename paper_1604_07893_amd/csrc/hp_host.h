@@ -119,8 +119,8 @@ struct Plan {
     bool has16 = false;
     int64_t ldA16 = 0, ldAt16 = 0, ldX16 = 0, ldXt16 = 0, ldS16 = 0;
     size_t offA16 = 0, offAt16 = 0, offX16[3] = {}, offXt16[3] = {}, offS16[7] = {}, offSt16[7] = {};
-    size_t offA = 0, offX[3] = {}, offS[7] = {};
-    size_t offA32 = 0, offX32[3] = {}, offS32[7] = {};
+    size_t offA = 0, offX[4] = {}, offS[7] = {};
+    size_t offA32 = 0, offX32[4] = {}, offS32[7] = {};
     bool has_proj = false;      // A^T (n x m) and X^T (m x n) for the projection
     size_t offAt = 0, offXt = 0;
     // split-K scratch: splitSlots partial tiles (128 x 128 doubles), then
@@ -130,12 +130,18 @@ struct Plan {
     // the loop's s x s products may run symmetric (HP_FLAG_SYMMETRIC: X_k =
     // p(A^T A) A^T for a Moore-Penrose solve from alpha A^T without Chop)
     bool sym = false;
+    // FP64-stage loops may run in the delta form (HP_PREC_DELTA32, or staged
+    // precisions without HP_FLAG_FP64_POLY)
+    bool delta = false;
     size_t offSplit = 0, offSplitCnt = 0;
     size_t offSmall = 0, nSmall = 0, offScal = 0, total = 0;
 };
-// `split_area`: reserve the split-K scratch the default tile choice needs for
-// the solve's products (single solves; the grouped launches never split).
-Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool split_area = true);
+// `single`: a single solve, which reserves the split-K scratch the default
+// tile choice needs for its products (the grouped launches never split) and a
+// fourth iterate in the final stage's set for the best iterate kept before
+// convergence sets in (LoopState::kBest; batched and served solves return X_k
+// on divergence instead).
+Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool single = true);
 int validate(const hp_params* p, int64_t m, int64_t n);
 
 
@@ -143,7 +149,7 @@ int validate(const hp_params* p, int64_t m, int64_t n);
 template <typename T>
 struct Set {
     T* A = nullptr;
-    T* X[3] = {};
+    T* X[4] = {};  // X_k, X_{k+1}, X_{k+1/2}; [3]: the best iterate (single solves)
     T* S[7] = {};
     int64_t ldA = 0, ldX = 0, ldS = 0;
 };
@@ -234,7 +240,8 @@ constexpr int kMaxLoopGemms = 11;
 // X_{k+1/2} A X_{k+1/2} of (PM-modified), Section 7, follows, associated so
 // that the middle product is the smaller square (into `mid`, an s x s buffer
 // that is dead by then). Appends to out[c..]; returns the new count.
-// With `plus_x` (plain loops only) the product is X_k + X_k W (or X_k + W X_k).
+// With `plus_x` the product is X_k + X_k W (or X_k + W X_k) (with `stab`, that
+// is X_{k+1/2}).
 template <typename T>
 int describe_update(const Plan& pl, const Set<T>& b, const T* W, T* Xk, T* Xn, T* Xh, bool stab,
                     double* partials, T* mid, GemmCall<T>* out, int c, bool plus_x = false) {
@@ -424,6 +431,108 @@ int describe_after_residual(int method, const Plan& pl, const Set<T>& b, T* Xk, 
     e.sym = 1;
     out[c++] = {sd, sd, sd, S[0], ldS, S[0], ldS, e};
     return describe_update(pl, b, S[1], Xk, Xn, b.X[2], false, partials, S[2], out, c);
+}
+
+// The polynomial of one loop in the delta form, an exact re-association of
+// the products of Section 2: with R = I - A X_k (or I - X_k A) already in
+// S[0], it forms W' = W - I without rounding any value of the form
+// I + (small): (I + a)(I + b) = I + a + b + a b, so each product forms a b and
+// its epilogue adds a + b. For PM, with F1' = c1 R^2 + R^4 and
+// F2' = c2 R^2 + R^4 (F1 = I + F1', F2 = I + F2'):
+//   M' = F1' F2' + F1' + F2' = acc + (c1 + c2) R^2 + 2 R^4   (never stored),
+//   T' = M' + c3 R^2,   S' = M' + d1 R^2 + d2 R^4,
+//   V' = T' S' + T' + S' + mu R^2 + psi R^4 = T' S' + U,
+//   W' = (I + R)(I + V') - I = R V' + R + V',
+// where the M product's epilogue writes T', S' and U (in its accumulator and
+// R^2, R^4; U over R^4, which each element reads before it writes). Other
+// schemes: SM W' = R (no product); CM W' = R R + R; FM zeta' = R R + R,
+// upsilon = R^2 R^2 + R, W' = upsilon zeta' + upsilon. The update
+// X_{k+1} = X_k + X_k W' (or X_k + W' X_k) is the caller's. Appends to out;
+// returns the number of products; *Wd is the buffer holding W' (S[0] for SM).
+template <typename T>
+int describe_delta_poly(int method, const Plan& pl, const Set<T>& b, GemmCall<T>* out, T** Wd) {
+    const int64_t sd = pl.s, ldS = b.ldS;
+    T* const* S = b.S;
+    int c = 0;
+    auto sq = [&](const T* A, const T* B, const EpilogueT<T>& e) {
+        out[c++] = {sd, sd, sd, A, ldS, B, ldS, e};
+    };
+    auto out_to = [&](EpilogueT<T>& e, int o, T* buf, double acc, double g1, double g2) {
+        e.out[o] = buf; e.ldo[o] = ldS; e.acc_c[o] = acc; e.g1[o] = g1; e.g2[o] = g2;
+    };
+    T* R = S[0];
+    if (method == HP_METHOD_SM) {
+        *Wd = R;
+        return 0;
+    }
+    if (method == HP_METHOD_CM) {
+        EpilogueT<T> e{};
+        out_to(e, 0, S[1], 1.0, 1.0, 0.0);
+        e.D1 = R; e.ld1 = ldS;
+        sq(R, R, e);
+        *Wd = S[1];
+        return c;
+    }
+    if (method == HP_METHOD_FM) {
+        EpilogueT<T> e2{};
+        out_to(e2, 0, S[1], 1.0, 0.0, 0.0);   // R^2
+        out_to(e2, 1, S[2], 1.0, 1.0, 0.0);   // zeta' = R^2 + R
+        e2.D1 = R; e2.ld1 = ldS;
+        sq(R, R, e2);
+        EpilogueT<T> e4{};
+        out_to(e4, 0, S[3], 1.0, 1.0, 0.0);   // upsilon = R^4 + R
+        e4.D1 = R; e4.ld1 = ldS;
+        sq(S[1], S[1], e4);
+        EpilogueT<T> ew{};
+        out_to(ew, 0, S[4], 1.0, 1.0, 0.0);   // W' = upsilon zeta' + upsilon
+        ew.D1 = S[3]; ew.ld1 = ldS;
+        sq(S[3], S[2], ew);
+        *Wd = S[4];
+        return c;
+    }
+    // PM
+    const PMConst K = pm_const();
+    T* R2 = S[1];
+    T* R4 = S[2];
+    T* F1 = S[3];
+    T* F2 = S[4];
+    T* Tm = S[5];
+    T* Sm = S[6];
+    T* U = R4;  // written over R^4 by the product that last reads it
+    T* V = F1;  // F1', F2' are dead once T', S', U exist
+    T* W = F2;
+    sq(R, R, epilogue_plain(R2, ldS));
+    {
+        EpilogueT<T> e{};
+        out_to(e, 0, R4, 1.0, 0.0, 0.0);
+        out_to(e, 1, F1, 1.0, K.c1, 0.0);
+        out_to(e, 2, F2, 1.0, K.c2, 0.0);
+        e.D1 = R2; e.ld1 = ldS;
+        sq(R2, R2, e);
+    }
+    {
+        const double c12 = K.c1 + K.c2;
+        EpilogueT<T> e{};
+        out_to(e, 0, Tm, 1.0, c12 + K.c3, 2.0);
+        out_to(e, 1, Sm, 1.0, c12 + K.d1, 2.0 + K.d2);
+        out_to(e, 2, U, 2.0, 2.0 * c12 + K.c3 + K.d1 + K.mu, 4.0 + K.d2 + K.psi);
+        e.D1 = R2; e.ld1 = ldS; e.D2 = R4; e.ld2 = ldS;
+        sq(F1, F2, e);
+    }
+    {
+        EpilogueT<T> e{};
+        out_to(e, 0, V, 1.0, 1.0, 0.0);
+        e.D1 = U; e.ld1 = ldS;
+        sq(Tm, Sm, e);
+    }
+    {
+        EpilogueT<T> e{};
+        out_to(e, 0, W, 1.0, 1.0, 1.0);
+        e.D1 = R; e.ld1 = ldS; e.D2 = V; e.ld2 = ldS;
+        sq(R, V, e);
+    }
+    *Wd = W;
+    return c;
 }
 
 // Power-iteration steps of HP_ALPHA_SIGMA_MAX2.

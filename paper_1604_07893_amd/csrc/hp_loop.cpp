@@ -36,6 +36,11 @@ void LoopState::init(const hp_params* prm, hp_result* r, double a) {
     probe = false;
     exit_converged = false;
     proj_pending = false;
+    keep_best = false;
+    have_best = false;
+    save_best = false;
+    save_from = 0;
+    best_d = 0.0;
 }
 
 Engine LoopState::engine() const {
@@ -58,6 +63,7 @@ void LoopState::enter_stage(int next) {
 
 LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool have_dinf) {
     probe = false;
+    save_best = false;
     res->iters = k + 1;
     res->iters_stage[stage] += 1;
     const double d = std::sqrt(diff2) / std::sqrt(ref2);
@@ -110,9 +116,11 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         return CONTINUE;
     }
 
+    // before convergence sets in, a blow-up returns the best iterate seen
+    const int fallback = (keep_best && have_best && !converging) ? kBest : ik;
     if (!finite) {
         status = HP_NONFINITE;
-        result_idx = ik;
+        result_idx = fallback;
         return DONE;
     }
     double sval;
@@ -140,10 +148,16 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
     }
     if (!converging && d > p->diverge_limit) {
         status = HP_DIVERGED;
-        result_idx = ik;
+        result_idx = fallback;
         return DONE;
     }
     note_switch();
+    if (keep_best && !converging && (!have_best || d < best_d)) {
+        best_d = d;
+        have_best = true;
+        save_best = true;
+        save_from = ik;
+    }
     stage_first = false;
     d_prev = d;
     std::swap(ik, in_);

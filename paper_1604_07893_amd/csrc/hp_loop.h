@@ -40,6 +40,22 @@ struct LoopState {
     int result_idx = -1;  // iterate to return (index into the final stage's set)
     int from_idx = 0;     // NEXT_STAGE: iterate the next stage starts from
 
+    // The iterate returned on HP_DIVERGED, and on HP_NONFINITE before
+    // convergence sets in (Section 6 warns that the loops can diverge; the
+    // iterate just before the blow-up is already far off): the input of the
+    // final-stage loop with the smallest relative change among the loops
+    // before the change first fell below tau_switch. With keep_best (set by
+    // the caller after init) the caller keeps a copy of that iterate: after a
+    // step() that sets save_best it copies iterate save_from of the final
+    // stage's set to slot kBest before the next loop runs. Without keep_best
+    // those outcomes return X_k, the input of the loop that detected them.
+    static constexpr int kBest = 3;
+    bool keep_best = false;
+    bool have_best = false;
+    bool save_best = false;
+    int save_from = 0;
+    double best_d = 0.0;
+
     // Set by step() after the first loop of the FP32 stage (when the FP64
     // stage follows) if that loop changed X by less than kPredict: the caller
     // may then form the next loop's residual R = I - A X_{k+1} (its first

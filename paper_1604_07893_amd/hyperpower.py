@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhyperpower.so")
 
 # ---- constants mirrored from include/hyperpower.h ---------------------------
-HP_ABI_VERSION = 3
+HP_ABI_VERSION = 4
 HP_OK, HP_MAXITER, HP_STAGNATED, HP_DIVERGED, HP_NONFINITE, HP_PENDING = 0, 1, 2, 3, 4, 5
 HP_EINVAL, HP_EWORKSPACE, HP_EBUDGET, HP_EHIP, HP_EUNSUPPORTED = -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "ok", 1: "maxiter", 2: "stagnated", 3: "diverged", 4: "nonfinite", 5: "pending"}
@@ -32,9 +32,10 @@ STOP = {"rel_fro": 0, "paper_4_1": 1, "abs_inf": 2, "rel_fro_bound": 3}
 METHOD = {"pm": 0, "sm": 1, "cm": 2, "fm": 3, "hm": 4}
 METHOD_ORDER = {"pm": 18, "sm": 2, "cm": 3, "fm": 7, "hm": 18}
 METHOD_PRODUCTS = {"pm": 7, "sm": 2, "cm": 3, "fm": 5, "hm": 9}
-PREC = {"fp64": 0, "fp32": 1, "mixed": 2, "fp32_fp64": 3}
+PREC = {"fp64": 0, "fp32": 1, "mixed": 2, "fp32_fp64": 3, "delta32": 4}
 LOWP = {"bf16": 0, "f16": 1, "fp16": 1}
 FLAG_TIME_KERNELS, FLAG_INF_NORM, FLAG_NO_GRAPH, FLAG_NO_RETRY, FLAG_SYMMETRIC = 1, 2, 4, 8, 16
+FLAG_FP64_POLY = 32
 DTYPE = {torch.float64: 0, torch.float32: 1}
 HP_HIST = 128
 NOALLOC_SCRATCH_BYTES = 64 << 20  # HP_NOALLOC_SCRATCH_BYTES
@@ -61,6 +62,8 @@ class HpResult(ctypes.Structure):
         ("d_hist", c_double * HP_HIST), ("dinf_hist", c_double * HP_HIST),
         ("gemms_sym", c_int32), ("reserved_r", c_int32), ("gflop_sym", c_double),
         ("gemm_ms_sym", c_double),
+        ("iters_delta", c_int32), ("reserved_r2", c_int32),
+        ("gflop_engine", c_double * 3), ("gemm_ms_engine", c_double * 3),
     ]
 
 
@@ -182,7 +185,7 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
                 tol=1e-12, max_iter=100, stop="rel_fro", side="auto", precision="fp64",
                 diverge_limit=1e6, time_kernels=False, inf_norm=False,
                 low_dtype="bf16", graph=True, method="pm", chop=0.0, retry=True,
-                symmetric=False) -> HpParams:
+                symmetric=False, fp64_poly=False) -> HpParams:
     p = HpParams()
     load_library().hp_params_default(ctypes.byref(p))
     p.kind = KIND[kind]
@@ -204,7 +207,7 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
     p.chop = float(chop)
     p.flags = ((FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
                | (0 if graph else FLAG_NO_GRAPH) | (0 if retry else FLAG_NO_RETRY)
-               | (FLAG_SYMMETRIC if symmetric else 0))
+               | (FLAG_SYMMETRIC if symmetric else 0) | (FLAG_FP64_POLY if fp64_poly else 0))
     return p
 
 
@@ -237,6 +240,9 @@ def result_dict(r: HpResult) -> dict:
         "gflop_stage": list(r.gflop_stage), "queue_ms": r.queue_ms, "run_ms": r.run_ms,
         "d_hist": list(r.d_hist[:it]), "dinf_hist": list(r.dinf_hist[:it]),
         "gemms_sym": r.gemms_sym, "gflop_sym": r.gflop_sym, "gemm_ms_sym": r.gemm_ms_sym,
+        "iters_delta": r.iters_delta,
+        # by MFMA path: 16-bit operands, FP32, FP64
+        "gflop_engine": list(r.gflop_engine), "gemm_ms_engine": list(r.gemm_ms_engine),
     }
 
 

@@ -26,6 +26,11 @@ int main() {
     hp_result r{};
     hp::LoopState st;
     st.init(&p, &r, p.alpha);
+    st.keep_best = true;  // as the single-solve driver sets it
+    // which iterate X_j each buffer of the current stage's set holds (the
+    // driver's buffers: the loop writes X_{k+1} into in_; slot kBest takes a
+    // copy of save_from when asked; entering FP64 copies from_idx into 0)
+    int buf[4] = {0, -1, -1, -1};
     std::vector<int> actions;
     int projected_at = -1;
     bool returns_new = false, done = false;
@@ -35,7 +40,9 @@ int main() {
         const int got = std::sscanf(line, "%lf %lf %lf %lf", &diff2, &ref2, &dinf, &rnorm);
         if (got < 3) continue;
         const int newest = st.in_;
+        buf[st.in_] = st.k + 1;
         hp::LoopState::Action a = st.step(diff2, ref2, dinf, p.stop_rule == HP_STOP_ABS_INF);
+        if (st.save_best) buf[hp::LoopState::kBest] = buf[st.save_from];
         if (a == hp::LoopState::CONTINUE && st.k < p.max_iter && st.probe && got == 4 &&
             st.probe_exit(rnorm))
             a = hp::LoopState::NEXT_STAGE;
@@ -52,18 +59,26 @@ int main() {
                 if (st.exit_converged) projected_at = 0;
                 else st.proj_pending = true;
             }
+            const int from = buf[st.from_idx];
             st.enter_stage(st.stage + 1);
+            if (st.stage == 2) {
+                buf[0] = from;
+                buf[1] = buf[2] = buf[3] = -1;
+            }
         }
     }
     if (!done) {
         st.finish_maxiter();
         returns_new = true;  // after a CONTINUE the newest iterate is the current one
     }
+    const int returned = buf[st.result_idx];
     std::printf("{\"actions\": [");
     for (size_t i = 0; i < actions.size(); ++i) std::printf("%s%d", i ? ", " : "", actions[i]);
     std::printf("], \"status\": %d, \"iters\": %d, \"switch_iter\": %d, \"iters_stage\": [%d, %d, %d], "
-                "\"returns_new\": %s, \"stop_last\": %.17g, \"projected_at\": %d}\n",
+                "\"returns_new\": %s, \"returned\": %d, \"stop_last\": %.17g, "
+                "\"projected_at\": %d}\n",
                 st.status, r.iters, r.switch_iter, r.iters_stage[0], r.iters_stage[1],
-                r.iters_stage[2], returns_new ? "true" : "false", r.stop_last, projected_at);
+                r.iters_stage[2], returns_new ? "true" : "false", returned, r.stop_last,
+                projected_at);
     return 0;
 }

@@ -51,7 +51,7 @@ def test_host_only_calls():
     assert p.tol == 1e-12 and p.max_iter == 100 and abs(p.tau_switch - 0.1) < 1e-15
     # struct layouts mirror the header
     assert ctypes.sizeof(hpw.HpParams) == 96
-    assert ctypes.sizeof(hpw.HpResult) == 32 + 7 * 8 + 8 * 8 + 2 * 128 * 8 + 8 + 2 * 8
+    assert ctypes.sizeof(hpw.HpResult) == 32 + 7 * 8 + 8 * 8 + 2 * 128 * 8 + 8 + 2 * 8 + 8 + 6 * 8
     assert ctypes.sizeof(hpw.HpProblem) == 8 * 8
     # workspace sizes grow with the problem and reject bad arguments
     small = hpw.workspace_bytes(p, 200, 100)
@@ -77,6 +77,9 @@ EINVAL, EUNSUPPORTED = -1, -5
     (dict(alpha_rule="diag"), 12, 10, EINVAL),
     (dict(method="sm", precision="mixed"), 10, 10, EUNSUPPORTED),
     (dict(kind="drazin", l=2, precision="fp32"), 10, 10, EUNSUPPORTED),
+    (dict(kind="drazin", l=2, precision="delta32"), 10, 10, EUNSUPPORTED),
+    (dict(method="fm", precision="delta32"), 10, 10, EUNSUPPORTED),
+    (dict(chop=1e-5, precision="delta32"), 10, 10, EUNSUPPORTED),
     (dict(kind="drazin", l=2, alpha_rule="norm1inf"), 10, 10, EINVAL),
     (dict(tol=-1.0), 10, 10, EINVAL),
     (dict(max_iter=0), 10, 10, EINVAL),

@@ -63,7 +63,9 @@ def check_against_oracle(harness, res, **kw):
     assert STATUS[got["status"]] == res.status
     assert got["iters"] == res.iters
     assert got["switch_iter"] == res.switch_iter
-    # the oracle returns X_{k+1} on success and at the loop cap, X_k otherwise
+    # the same iterate is returned: X_{k+1} on success and at the loop cap,
+    # X_k on stagnation, the best one before the blow-up on divergence
+    assert got["returned"] == res.returned_iter
     assert got["returns_new"] == (res.status in ("ok", "maxiter"))
     assert got["actions"][-1] == (DONE if res.status != "maxiter" else CONTINUE)
     return got
@@ -117,10 +119,35 @@ def test_loop_cap(harness):
     check_against_oracle(harness, res, tol=1e-12, max_iter=3)
 
 
-def test_non_finite_change_returns_the_last_finite_iterate(harness):
+def test_non_finite_change_returns_the_best_iterate_before_it(harness):
     got = harness([(1.0, 1.0, 0.0), (float("nan"), 1.0, 0.0), (1e-30, 1.0, 0.0)])
     assert STATUS[got["status"]] == "nonfinite" and got["iters"] == 2
-    assert got["returns_new"] is False
+    assert got["returns_new"] is False and got["returned"] == 0
+    # after convergence set in (a change below tau_switch), the last finite one
+    got = harness(rel_loops([3.0, 0.05, 1e-3]) + [(float("nan"), 1.0, 0.0)])
+    assert STATUS[got["status"]] == "nonfinite" and got["returned"] == 3
+
+
+def test_divergence_returns_the_input_of_the_smallest_change(harness):
+    """A blow-up before convergence returns the iterate with the smallest
+    change seen, not the one the blow-up started from (Section 6)."""
+    got = harness(rel_loops([4.3, 3.7, 0.81, 0.14, 2.4, 15.9, 2e6]))
+    assert STATUS[got["status"]] == "diverged" and got["iters"] == 7
+    assert got["returned"] == 3  # X_3, the input of the loop that changed it by 0.14
+
+
+def test_fp32_emulation_of_the_rank_deficient_4096x2048_run(harness):
+    """The relative changes of the stabilised run on the 4096x2048 rank-1536
+    input with every product in FP32 (numpy float32 emulation of the GPU
+    loops): the null-space block, seeded by rounding, grows 18x per loop
+    (Theorem 6.2) before any change falls below tau_switch = 0.1; the guard
+    returns X_7 (error 8e-3 against the closed form in the emulation), not
+    X_12 (1.6e4)."""
+    ds = [4.285, 3.690, 3.655, 3.652, 3.625, 3.191, 0.810, 0.1355, 2.414, 15.85, 16.99, 18.21,
+          2.19e6]
+    got = harness(rel_loops(ds), variant="stabilised", tol=1e-10)
+    assert STATUS[got["status"]] == "diverged" and got["iters"] == 13
+    assert got["returned"] == 7 and got["switch_iter"] == -1
 
 
 # ---- precision stages (HP_PREC_MIXED = 2, HP_PREC_FP32 = 1) ------------------
