@@ -1,27 +1,43 @@
-"""Benchmark: Moore-Penrose inverses per second of the 18th-order hyperpower
-iteration on one MI355X.
+"""Benchmark: generalized inverses per second of the 18th-order hyperpower
+iteration on one MI355X, FP64 against the mixed-precision forms.
 
 Headline workload (one step = one complete inverse, inputs resident in HBM):
-rectangular rank-deficient A = U diag(s) V^T, 4096 x 2048, rank 1536, U and V
-Haar-orthogonal (seeded), nonzero s log-spaced in [1e-4, 1]; X0 = A^T /
-sigma_max^2 (sigma_max = 1 by construction); the stabilised variant (plain
-seven-product loops, then X <- X A X loops once the relative change drops below
-0.1); FP64; stop at relative Frobenius change < 1e-10.
+square nonsingular A = U diag(s) V^T, 8192 x 8192, U and V Haar-orthogonal
+(seeded, built on the GPU), s log-uniform in [1e-3, 1] with sigma_max = 1;
+X0 = A^T (alpha = 1/sigma_max^2 = 1); plain seven-product loops (Section 2);
+every product in FP64; stop at relative Frobenius change < 1e-10. `value` is
+its inverses/s.
 
-The same JSON line carries the roofline of the dominant kernel (the FP64 MFMA
-GEMM: executed 2MNK flops over its hipEvent-timed launches on the solve
-stream), a CPU baseline (the oracle on this host, bounded sample), and under
-"extras" the other workloads: the same input in FP32; a square 8192 x 8192
-(s log-uniform in [1e-3, 1]) in mixed precision against FP64; a 2048 x 2048
-Drazin input (index 3); and a served Poisson stream with p50/p99 latency.
+Beside it in the same JSON line:
+  * "mixed_vs_fp64": the same input with 16-bit (bf16) loops, then FP32, then
+    FP64 loops (the FP64 stage in the delta form: FP64 residual and update,
+    FP32 polynomial), with and without the residual-bound stop, the FP64
+    stage with an FP64 polynomial, and FP64 with the bound stop and the
+    symmetric products; inverses/s, loops and GFLOP per stage, error against
+    the closed form V diag(1/s) U^T, speed-ups over the FP64 value;
+  * "roofline": the dominant kernel of the headline (the FP64 MFMA GEMM,
+    8192^3 per launch): algorithmic 2*M*N*K flops per launch over its mean
+    launch time from hipEvents the library records on the solve stream;
+    "roofline_by_dtype": the same for the FP32 and the bf16 GEMM kernels in the
+    mixed run, and the bf16 kernel alone at 8192^3;
+  * "cpu_baseline": the oracle (numpy FP64) on this host, one loop of the
+    same 8192^2 input, scaled to the loops of one FP64 inverse;
+  * "extras": the 4096 x 2048 rank-1536 input (stabilised, FP64 / FP32 /
+    delta form), a 2048^2 Drazin input, the 200 x 100 latency case, the
+    comparison schemes and the Hilbert matrices of Example 8.2, the
+    preconditioners of Example 8.3, and the served Poisson stream.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline] [--no-extras]
-                    [--extras name,name,...]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+                    [--no-extras] [--extras name,name,...]
+    python bench.py --gemm-shapes 8192x8192x8192[,..] [--gemm-dtype f64|f32|bf16|f16|
+                    bf16s|f16s] [--gemm-reps 5] [--check]   # one GEMM kernel alone
+    python bench.py --copy-calibration   # a 512 MiB device copy, to scale counters
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,10 +50,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "inverses/s + GEMM TFLOP/s at rel. residual 1e-10, mixed vs FP64; p99 latency"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
-M, N, RANK, SMIN, SEED, TOL = 4096, 2048, 1536, 1e-4, 1002, 1e-10
-WORKLOAD = (f"moore-penrose {M}x{N} rank {RANK}, s log-spaced [{SMIN:g},1], Haar U/V seed {SEED}; "
-            f"X0=A^T/sigma_max^2; stabilised (switch at rel. change < 0.1); fp64; "
+NSQ, SMIN_SQ, SEED_SQ, TOL = 8192, 1e-3, 1003, 1e-10
+WORKLOAD = (f"moore-penrose {NSQ}x{NSQ} square, s log-uniform [{SMIN_SQ:g},1], Haar U/V "
+            f"(seed {SEED_SQ}, built on the GPU); X0=A^T (alpha=1/sigma_max^2=1); plain; fp64; "
             f"stop rel. Frobenius change < {TOL:g}")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_f64_square8192_traffic.json")
+GEMM_SRC = os.path.join(ROOT, "paper_1604_07893_amd", "csrc", "hp_gemm.hip")
 
 
 def log(*a):
@@ -46,6 +64,10 @@ def log(*a):
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def trel(torch, a, b):
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
 
 
 def timed_solves(hpw, torch, A, steps, warmup, **params):
@@ -66,117 +88,192 @@ def timed_solves(hpw, torch, A, steps, warmup, **params):
         _, info = hpw.solve(A, out=X, workspace=ws, stream=stream, **params)
         infos.append(info)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, infos, X
+    sec = (time.perf_counter() - t0) / steps
+    del ws
+    return sec, infos, X
+
+
+def engine_roofline(infos, engine: int, peak: float, kernel: str) -> dict | None:
+    """Executed flops over summed hipEvent time of one MFMA path's launches
+    (0: 16-bit operands, 1: FP32, 2: FP64) over the given solves."""
+    gf = sum(i["gflop_engine"][engine] for i in infos)
+    ms = sum(i["gemm_ms_engine"][engine] for i in infos)
+    if gf <= 0 or ms <= 0:
+        return None
+    a = gf / ms  # GFLOP/ms = TFLOP/s
+    return {"bound": "mfma", "kernel": kernel, "achieved": a, "peak": peak, "unit": "TFLOP/s",
+            "frac": a / peak, "gflop": gf / len(infos), "gemm_ms": ms / len(infos)}
 
 
 def measured_traffic():
     """HBM bytes per FP64 GEMM launch from the committed rocprofv3 counter
     summary, if it was taken on the current GEMM source (else None)."""
-    import hashlib
     try:
-        with open(os.path.join(ROOT, "profiles", "k_gemm_f64_lowrank4096x2048_traffic.json")) as f:
+        with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, "paper_1604_07893_amd", "csrc", "hp_gemm.hip"), "rb") as f:
+        with open(GEMM_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
-        return None
-    return rec["traffic_bytes_per_launch"] if rec.get("hp_gemm_hip_sha256") == sha else None
+        return None, None
+    if rec.get("hp_gemm_hip_sha256") != sha:
+        return None, "stale: taken on another hp_gemm.hip"
+    return rec["traffic_bytes_per_launch"], os.path.relpath(TRAFFIC_FILE, ROOT)
 
 
-def cpu_baseline(d, n_plain: int, n_stab: int) -> dict:
-    """The oracle (numpy FP64, OpenBLAS) timed on a bounded sample: one plain
-    and one stabilised loop on the full-size input, scaled by the loop counts
-    of a full inverse."""
-    import oracle as O
+def blas_threads() -> int:
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 0) for i in threadpool_info()
-                     if i.get("user_api") == "blas"] or [os.cpu_count()])
+        return max([i.get("num_threads", 0) for i in threadpool_info()
+                    if i.get("user_api") == "blas"] or [os.cpu_count()])
     except Exception:  # pragma: no cover
-        cores = os.cpu_count()
-    A = d.A
-    X0, _ = O.x0_moore_penrose(A, "user", 1.0)
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(A_host: np.ndarray, loops: int) -> dict:
+    """The oracle (numpy FP64, OpenBLAS) timed on a bounded sample: one loop
+    of (PM) on the full 8192^2 input from X0 = A^T, scaled by the loop count
+    of one FP64 inverse."""
+    import oracle as O
+    X0, _ = O.x0_moore_penrose(A_host, "user", 1.0)
     K = O.pm_constants()
     t0 = time.perf_counter()
-    X1 = O.pm_step(A, X0, K)
-    t_plain = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    X2 = O.stabilise(A, O.pm_step(A, X1, K))
-    t_stab = time.perf_counter() - t0
-    del X2
-    t_inv = n_plain * t_plain + n_stab * t_stab
-    return {"value": 1.0 / t_inv, "unit": "inverses/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"1 plain + 1 stabilised oracle loop on the full {M}x{N} input "
-                       f"({t_plain:.2f} s + {t_stab:.2f} s), scaled to {n_plain} plain + "
-                       f"{n_stab} stabilised loops per inverse")}
+    X1 = O.pm_step(A_host, X0, K)
+    t_loop = time.perf_counter() - t0
+    del X1
+    return {"value": 1.0 / (loops * t_loop), "unit": "inverses/s", "cores": int(blas_threads()),
+            "kind": "oracle",
+            "sample": (f"1 oracle loop of (PM) (7 products, numpy FP64) on the full {NSQ}x{NSQ} "
+                       f"input ({t_loop:.1f} s), scaled to the {loops} loops of one FP64 inverse")}
 
 
-def extra_fp32(hpw, torch, A, closed, steps):
-    sec, infos, X = timed_solves(hpw, torch, A, steps, 1, alpha_rule="user", alpha=1.0,
-                                 variant="stabilised", tol=TOL, precision="fp32")
-    return {"workload": "same 4096x2048 input, FP32 loops", "inverses_per_s": 1 / sec,
-            "status": infos[-1]["status"], "iters": infos[-1]["iters"],
-            "rel_err_vs_closed_form": rel(X.cpu().numpy(), closed),
-            "note": ("FP32 cannot reach 1e-10 at kappa = 1e4 on a rank-deficient input: "
-                     "rounding in the null-space block grows 18x per plain loop (Theorem 6.2) "
-                     "during the ~8 loops the small singular values need")}
-
-
-def extra_mixed(hpw, torch, steps):
-    from paper_1604_07893_amd import inputs
-    n = 8192
-    A, U, s, V = inputs.square_svd_device(n, smin=1e-3, seed=1003)
+def gemm_standalone(hpw, torch, M, N, K, dtype, reps, check=False) -> dict:
+    """One GEMM kernel alone: `reps` launches after one warm-up, timed with
+    events on the current stream. f64/f32: hp_gemm_ws with a split-K
+    workspace; bf16/f16: FP32 operands rounded while staged; bf16s/f16s:
+    16-bit operands in memory (A and B^T)."""
+    if dtype in ("bf16s", "f16s"):
+        h = torch.bfloat16 if dtype == "bf16s" else torch.float16
+        ldk = -(-K // 8) * 8
+        A = torch.randn(M, ldk, device="cuda").to(h)[:, :K]
+        Bt = torch.randn(N, ldk, device="cuda").to(h)[:, :K]
+        C = torch.empty(M, N, dtype=torch.float32, device="cuda")
+        run = lambda: hpw.gemm_bt(A, Bt, out=C)
+        ref = (lambda: A.double() @ Bt.double().t()) if check else None
+    else:
+        dt = torch.float64 if dtype == "f64" else torch.float32
+        ops = dtype if dtype in ("bf16", "f16") else None
+        vec = 2 if dt == torch.float64 else 4
+        lda, ldb = -(-K // vec) * vec, -(-N // vec) * vec
+        A = torch.randn(M, lda, dtype=dt, device="cuda")[:, :K]
+        B = torch.randn(K, ldb, dtype=dt, device="cuda")[:, :N]
+        C = torch.empty(M, N, dtype=dt, device="cuda")
+        tiles = -(-M // 128) * -(-N // 128)
+        ws = torch.empty(4 * tiles * 128 * 128 * 8 + 4 * 4 * tiles + 4096, dtype=torch.uint8,
+                         device="cuda")
+        run = lambda: hpw.gemm(A, B, out=C, operands=ops, workspace=ws)
+        ref = (lambda: A.double() @ B.double()) if check else None
+    run()
     torch.cuda.synchronize()
-    out = {"workload": f"square {n}x{n}, s log-uniform [1e-3,1], Haar U/V (seed 1003, built on "
-                       "the GPU); X0=A^T; plain; tol 1e-10"}
-    ref = None
-    # "*_bound": the same with the residual-bound stop (skips the loop that only
-    # confirms convergence: ||I - AX||_F / (1 - ||I - AX||_F) < tol)
-    # "*_sym": FP64 with HP_FLAG_SYMMETRIC (A is nonsingular): the loop's n x n
-    # products, symmetric for X0 = alpha A^T, formed once per pair i <= j
-    for prec, stop, sym in (("fp64", "rel_fro", False), ("mixed", "rel_fro", False),
-                            ("fp64_bound", "rel_fro_bound", False),
-                            ("mixed_bound", "rel_fro_bound", False),
-                            ("fp64_sym", "rel_fro", True), ("fp64_bound_sym", "rel_fro_bound", True)):
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        run()
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    rec = {"dtype": dtype, "M": M, "N": N, "K": K, "ms": ms,
+           "tflops": 2.0 * M * N * K / ms * 1e-9}
+    if ref is not None:
+        R = ref()
+        rec["max_rel_err"] = float((C.double() - R).abs().max() / R.abs().max())
+    return rec
+
+
+def copy_calibration(torch):
+    """A device copy of known size: a 64 Mi-element FP64 tensor (512 MiB)
+    copied three times with torch's copy kernel; each copy reads and writes
+    exactly 512 MiB, so the ratio of those bytes to what the FETCH_SIZE /
+    WRITE_SIZE counters report per copy scales them for the other kernels."""
+    a = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copied_bytes": a.numel() * 8, "copies": 3}), flush=True)
+
+
+def headline_mixed(hpw, torch, A, closed, steps) -> dict:
+    """The 8192^2 input in the mixed-precision forms and the fast FP64 forms."""
+    out = {}
+    for name, kw in (("mixed", dict(precision="mixed")),
+                     ("mixed_bound", dict(precision="mixed", stop="rel_fro_bound")),
+                     ("mixed_fp64_poly", dict(precision="mixed", fp64_poly=True)),
+                     ("mixed_bound_fp64_poly", dict(precision="mixed", stop="rel_fro_bound",
+                                                    fp64_poly=True)),
+                     ("fp64_bound", dict(precision="fp64", stop="rel_fro_bound")),
+                     ("fp64_bound_sym", dict(precision="fp64", stop="rel_fro_bound",
+                                             symmetric=True))):
         sec, infos, X = timed_solves(hpw, torch, A, steps, 1, alpha_rule="user", alpha=1.0,
-                                     tol=TOL, precision=prec.split("_")[0], stop=stop,
-                                     time_kernels=True, symmetric=sym)
+                                     tol=TOL, time_kernels=True, **kw)
         inf = infos[-1]
-        if ref is None:
-            # closed form V diag(1/s) U^T, on the GPU in FP64 (a reference, not the method)
-            ref = (V / s) @ U.T.contiguous()
-        err = float(torch.linalg.norm(X - ref) / torch.linalg.norm(ref))
-        gf = sum(i["gflop"] for i in infos) / len(infos)
-        out[prec] = {"inverses_per_s": 1 / sec, "ms_per_inverse": sec * 1e3, "status": inf["status"],
-                     "iters": inf["iters"], "iters_stage": inf["iters_stage"],
-                     "gflop_stage": inf["gflop_stage"], "gflop_per_inverse": gf,
-                     "gemm_tflops": gf / (sum(i["gemm_ms"] for i in infos) / len(infos)),
-                     "rel_err_vs_closed_form": err}
-        if sym:
-            ms_sym = sum(i["gemm_ms_sym"] for i in infos)
-            out[prec]["sym_launches_per_inverse"] = sum(i["gemms_sym"] for i in infos) / len(infos)
-            out[prec]["sym_gemm_tflops"] = (sum(i["gflop_sym"] for i in infos) / ms_sym
-                                            if ms_sym > 0 else 0.0)
-        if prec == "mixed":
+        rec = {"inverses_per_s": 1 / sec, "ms_per_inverse": sec * 1e3, "status": inf["status"],
+               "iters": inf["iters"], "iters_stage": inf["iters_stage"],
+               "iters_delta": inf["iters_delta"],
+               "gflop_stage": inf["gflop_stage"], "gflop_per_inverse": inf["gflop"],
+               "gflop_by_path": dict(zip(("bf16", "f32", "f64"), inf["gflop_engine"])),
+               "gemm_ms_by_path": dict(zip(("bf16", "f32", "f64"), inf["gemm_ms_engine"])),
+               "rel_err_vs_closed_form": trel(torch, X, closed)}
+        if kw.get("symmetric"):
+            rec["sym_launches_per_inverse"] = inf["gemms_sym"]
+        if name == "mixed":
             caps = np.cumsum(inf["iters_stage"])
             per_stage = []
             for cap in caps[:2]:
-                Xs, _ = hpw.solve(A, alpha_rule="user", alpha=1.0, tol=TOL, precision=prec,
+                Xs, _ = hpw.solve(A, alpha_rule="user", alpha=1.0, tol=TOL, precision="mixed",
                                   max_iter=int(cap))
-                per_stage.append(float(torch.linalg.norm(Xs - ref) / torch.linalg.norm(ref)))
+                per_stage.append(trel(torch, Xs, closed))
                 del Xs
-            per_stage.append(err)
-            out[prec]["rel_err_after_stage"] = per_stage
-        log(f"mixed-vs-fp64 {prec}: {out[prec]}")
-    out["speedup_mixed_vs_fp64"] = out["mixed"]["inverses_per_s"] / out["fp64"]["inverses_per_s"]
-    out["speedup_mixed_bound_vs_fp64"] = (out["mixed_bound"]["inverses_per_s"]
-                                          / out["fp64"]["inverses_per_s"])
-    out["speedup_fp64_sym_vs_fp64"] = (out["fp64_sym"]["inverses_per_s"]
-                                       / out["fp64"]["inverses_per_s"])
-    out["speedup_fp64_bound_sym_vs_fp64"] = (out["fp64_bound_sym"]["inverses_per_s"]
-                                             / out["fp64"]["inverses_per_s"])
-    del A, U, s, V, ref
-    torch.cuda.empty_cache()
+            per_stage.append(rec["rel_err_vs_closed_form"])
+            rec["rel_err_after_stage"] = per_stage
+            rec["_infos"] = infos
+        out[name] = rec
+        del X
+        log(f"8192^2 {name}: {1 / sec:.3f} inverses/s, stages {inf['iters_stage']}, "
+            f"delta loops {inf['iters_delta']}, err {rec['rel_err_vs_closed_form']:.2e}")
+    return out
+
+
+def extra_lowrank(hpw, torch, steps) -> dict:
+    """The rectangular rank-deficient input: 4096 x 2048, rank 1536, s
+    log-spaced in [1e-4, 1], Haar U/V (seed 1002); X0 = A^T/sigma_max^2; the
+    stabilised variant (switch at relative change < 0.1); tol 1e-10; FP64, all
+    FP32, and the delta form (FP64 residual and update, FP32 polynomial)."""
+    from paper_1604_07893_amd import inputs
+    d = inputs.lowrank_svd(4096, 2048, 1536, smin=1e-4, seed=1002)
+    A = torch.from_numpy(d.A).cuda()
+    closed = torch.from_numpy((d.V / d.s) @ d.U.T).cuda()
+    out = {"workload": "moore-penrose 4096x2048 rank 1536, s log-spaced [1e-4,1], Haar U/V seed "
+                       "1002; X0=A^T/sigma_max^2; stabilised; tol 1e-10"}
+    for prec in ("fp64", "fp32", "delta32"):
+        sec, infos, X = timed_solves(hpw, torch, A, steps, 1, alpha_rule="user", alpha=1.0,
+                                     variant="stabilised", tol=TOL, precision=prec,
+                                     time_kernels=True)
+        inf = infos[-1]
+        rec = {"inverses_per_s": 1 / sec, "ms_per_inverse": sec * 1e3, "status": inf["status"],
+               "iters": inf["iters"], "switch_iter": inf["switch_iter"], "side": inf["side"],
+               "rel_err_vs_closed_form": trel(torch, X, closed)}
+        if prec == "fp64":
+            rl = engine_roofline(infos, 2, PEAK_TFLOPS["f64"], "k_gemm<double> (FP64 MFMA)")
+            rec["gemm_roofline"] = rl
+            rec["gflop_per_launch"] = inf["gflop"] / max(inf["gemms"], 1)
+        if prec == "fp32":
+            rec["note"] = ("every product in FP32: rounding seeds the null-space block, which grows "
+                           "18x per plain loop (Theorem 6.2) before the change falls below "
+                           "tau_switch; the guard returns the best iterate before the blow-up")
+            rec["d_hist"] = inf["d_hist"]
+        out[prec] = rec
+        log(f"4096x2048 {prec}: {rec}")
+        del X
     return out
 
 
@@ -194,7 +291,8 @@ def extra_drazin(hpw, torch, steps):
         sec, infos, X = timed_solves(hpw, torch, A, steps, 1, kind="drazin", l=3, variant=variant,
                                      tol=TOL)
         out[variant] = {"inverses_per_s": 1 / sec, "status": infos[-1]["status"],
-                        "iters": infos[-1]["iters"], "rel_err_vs_closed_form": rel(X.cpu().numpy(), closed)}
+                        "iters": infos[-1]["iters"],
+                        "rel_err_vs_closed_form": rel(X.cpu().numpy(), closed)}
     return out
 
 
@@ -205,11 +303,13 @@ def extra_small(hpw, torch, steps):
     from paper_1604_07893_amd import inputs
     A64 = inputs.uniform(200, 100, seed=1001)
     A = torch.from_numpy(A64).cuda()
+    ref = np.linalg.pinv(A64)
+    out = {"workload": "moore-penrose 200x100, iid U[-1,1] (seed 1001); X0=A^T/(||A||_1||A||_inf); "
+                       "stop rel. Frobenius change < 1e-12"}
     sec, infos, X = timed_solves(hpw, torch, A, steps, 3, tol=1e-12)
-    return {"workload": "moore-penrose 200x100, iid U[-1,1] (seed 1001); X0=A^T/(||A||_1||A||_inf); "
-                        "stop rel. Frobenius change < 1e-12",
-            "us_per_inverse": sec * 1e6, "iters": infos[-1]["iters"], "status": infos[-1]["status"],
-            "rel_err_vs_lapack_pinv": rel(X.cpu().numpy(), np.linalg.pinv(A64))}
+    out.update({"us_per_inverse": sec * 1e6, "iters": infos[-1]["iters"],
+                "status": infos[-1]["status"], "rel_err_vs_lapack_pinv": rel(X.cpu().numpy(), ref)})
+    return out
 
 
 def extra_precond(hpw, torch, steps):
@@ -243,16 +343,17 @@ def extra_methods(hpw, torch, steps):
     PM) on (a) a square 4096^2 input with kappa = 1e3 (s log-uniform in
     [1e-3, 1], Haar U/V, built on the GPU; X0 = A^T, sigma_max = 1; relative
     Frobenius change < 1e-10) and (b) the Hilbert matrices of Example 8.2,
-    H_{m x (m-10)}, X0 = 2/(sigma_1^2 + sigma_r^2) H^T, rule (stopreliable)
-    with the Frobenius norm, eps = 1e-5, 1e-6, 1e-7. sigma_r is read as the
-    smallest singular value above sigma_1 * m * 2^-52 (the numerical rank)."""
+    H_{m x (m-10)} for m = 100, 200, ..., 1000 (the rows of Tables 2-4) and
+    2000, X0 = 2/(sigma_1^2 + sigma_r^2) H^T, rule (stopreliable) with the
+    Frobenius norm, eps = 1e-5, 1e-6, 1e-7. sigma_r is read as the smallest
+    singular value above sigma_1 * m * 2^-52 (the numerical rank)."""
     from paper_1604_07893_amd import inputs
     order = {"sm": 2, "cm": 3, "fm": 7, "hm": 18, "pm": 18}
     prods = {"sm": 2, "cm": 3, "fm": 5, "hm": 9, "pm": 7}
     out = {"square_4096": {"workload": "square 4096x4096, s log-uniform [1e-3,1], Haar U/V (seed 1006, "
                                        "built on the GPU); X0=A^T; plain FP64; tol 1e-10"}}
     A, U, s, V = inputs.square_svd_device(4096, smin=1e-3, seed=1006)
-    closed = (V / s) @ U.T
+    closed = (V / s) @ U.T.contiguous()
     for mth in ("sm", "cm", "fm", "hm", "pm"):
         sec, infos, X = timed_solves(hpw, torch, A, steps, 1, method=mth, alpha_rule="user",
                                      alpha=1.0, tol=TOL)
@@ -260,11 +361,12 @@ def extra_methods(hpw, torch, steps):
         out["square_4096"][mth] = {
             "inverses_per_s": 1 / sec, "iters": it, "products": infos[-1]["gemms"],
             "efficiency_index": order[mth] ** (1.0 / prods[mth]), "status": infos[-1]["status"],
-            "rel_err_vs_closed_form": float(torch.linalg.norm(X - closed) / torch.linalg.norm(closed))}
+            "rel_err_vs_closed_form": trel(torch, X, closed)}
     del A, U, s, V, closed
     hil = {"workload": "Hilbert H_{m x (m-10)} (Example 8.2), X0 = 2/(s1^2+sr^2) H^T, rule "
-                       "(stopreliable) Frobenius; ms per inverse and loops"}
-    for m in (1000, 2000):
+                       "(stopreliable) Frobenius; ms per inverse and loops (the paper's Tables 2-4 "
+                       "time the same rows in Mathematica on a 2.4 GHz laptop CPU: context only)"}
+    for m in list(range(100, 1001, 100)) + [2000]:
         H = torch.from_numpy(inputs.hilbert(m, m - 10)).cuda()
         sv = torch.linalg.svdvals(H)
         s1 = float(sv[0])
@@ -286,7 +388,7 @@ def extra_served(hpw, torch, n_req: int, warm: int):
     """Poisson stream of Moore-Penrose requests (m log-uniform in [64, 2048],
     n = m/r, r in {1,2,4}, N(0,1), 10% rank-deficient at half rank) through the
     continuous-batching server, FP32 loops then FP64 (with the Penrose
-    projection), at 80% of the measured saturation rate."""
+    projection), at 50/80/95% of the measured saturation rate."""
     from paper_1604_07893_amd import inputs
     kw = dict(variant="stabilised", tol=1e-10, precision="fp32_fp64")
     budget = 32 << 30
@@ -294,8 +396,13 @@ def extra_served(hpw, torch, n_req: int, warm: int):
     mats = [torch.from_numpy(r.A).cuda() for r in reqs]
     torch.cuda.synchronize()
 
-    # accuracy sample: requests after the warm-up with m <= 768 (pinv on the host)
-    sample = [i for i in range(warm, len(reqs)) if reqs[i].A.shape[0] <= 768][:12]
+    # accuracy sample after the warm-up: the 6 largest requests and 6 others,
+    # against torch's SVD pseudo-inverse on the GPU in FP64 (rank-deficient
+    # requests with rcond 1e-10)
+    after = list(range(warm, len(reqs)))
+    big = sorted(after, key=lambda i: -reqs[i].A.size)[:6]
+    rest = [i for i in after if i not in big][:: max(1, len(after) // 6)][:6]
+    sample = sorted(set(big + rest))
     kept = {}
 
     def run(arrivals):
@@ -321,19 +428,26 @@ def extra_served(hpw, torch, n_req: int, warm: int):
                     lat.append((i, t_now - arr))
                     res.append((i, r[1]))
                     if i in sample or r[1]["status"] != "ok":
-                        kept[i] = r[0].cpu().numpy()
+                        kept[i] = r[0].clone()
                     done += 1
         wall = time.perf_counter() - t0
         srv.close()
         return wall, lat, res
 
+    pinv_cache = {}
+
+    def pinv_gpu(i):
+        if i not in pinv_cache:
+            pinv_cache[i] = torch.linalg.pinv(mats[i], rtol=1e-10 if reqs[i].rank_deficient
+                                              else 0.0)
+        return pinv_cache[i]
+
     # saturation: everything arrives at t = 0
     wall0, _, res0 = run([0.0] * len(mats))
     sat = len(mats) / wall0
-    pinv = {i: np.linalg.pinv(reqs[i].A) for i in sample}
-    served_err = [rel(kept[i], pinv[i]) for i in sample]
-    # the requests that did not end "ok" (the stagnation guard): their error
-    not_ok = {i: (r["status"], rel(kept[i], np.linalg.pinv(reqs[i].A)), reqs[i].A.shape,
+    gflop_all = sum(r["gflop"] for _, r in res0)
+    served_err = {i: trel(torch, kept[i], pinv_gpu(i)) for i in sample}
+    not_ok = {i: (r["status"], trel(torch, kept[i], pinv_gpu(i)), reqs[i].A.shape,
                   reqs[i].rank_deficient)
               for i, r in res0 if r["status"] != "ok"}
     # the plain FP64 GPU method on the same requests, one hp_solve after another
@@ -347,7 +461,7 @@ def extra_served(hpw, torch, n_req: int, warm: int):
         X, info = hpw.solve(A, **kw64)
         seq_status.append(info["status"])
         if i in sample:
-            seq_err.append(rel(X.cpu().numpy(), pinv[i]))
+            seq_err.append(trel(torch, X, pinv_gpu(i)))
     torch.cuda.synchronize()
     seq_rate = len(mats) / (time.perf_counter() - t0)
     out = {"workload": (f"{n_req} Poisson requests (+{warm} warm-up), m log-uniform [64,2048], "
@@ -355,17 +469,21 @@ def extra_served(hpw, torch, n_req: int, warm: int):
                         "final loops in grouped launches; budget 32 GiB, 64 slots; offered at "
                         "50/80/95% of the saturation rate (headline: 80%)"),
            "saturation_req_per_s": sat,
+           "executed_tflops_at_saturation": gflop_all / wall0 * 1e-3,
            "plain_fp64_sequential": {
                "what": "the same requests solved one after another by hp_solve, FP64, stabilised, "
                        "tol 1e-10 (the plain FP64 GPU method)",
                "inverses_per_s": seq_rate,
                "ok_fraction": seq_status.count("ok") / len(seq_status),
                "rel_err_vs_pinv_max_sample": max(seq_err)},
-           "served_rel_err_vs_pinv_max_sample": max(served_err),
+           "served_rel_err_vs_pinv_max_sample": max(served_err.values()),
+           "served_rel_err_vs_pinv_largest": {
+               f"{reqs[i].A.shape[0]}x{reqs[i].A.shape[1]}": served_err[i] for i in big},
            "served_not_ok": [{"status": v[0], "rel_err_vs_pinv": v[1], "shape": list(v[2]),
                               "rank_deficient": bool(v[3])} for v in not_ok.values()],
-           "accuracy_sample": f"{len(sample)} requests with m <= 768, relative Frobenius error "
-                              "against numpy.linalg.pinv",
+           "accuracy_sample": (f"{len(sample)} requests after the warm-up (the 6 largest and "
+                               "6 spread over the trace), relative Frobenius error against "
+                               "torch.linalg.pinv (SVD, FP64, on the GPU)"),
            "speedup_saturation_vs_plain_fp64": sat / seq_rate}
     pct = lambda v, q: float(np.percentile(v, q))
     for frac in (0.5, 0.8, 0.95):
@@ -385,6 +503,7 @@ def extra_served(hpw, torch, n_req: int, warm: int):
                "ok_fraction": statuses.count("ok") / len(statuses),
                "status_counts": {k: statuses.count(k) for k in sorted(set(statuses))}}
         out[f"at_{int(frac * 100)}pct"] = rec
+        log(f"served at {int(frac * 100)}%: {rec}")
         if frac == 0.8:
             out.update({k: rec[k] for k in ("offered_qps", "inverses_per_s", "p50_ms", "p99_ms",
                                             "ok_fraction")})
@@ -398,8 +517,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision forms")
     ap.add_argument("--extras", default="",
                     help="comma-separated names of the extras to run (default: all)")
+    ap.add_argument("--gemm-shapes", default="", help="MxNxK list: time one GEMM kernel alone")
+    ap.add_argument("--gemm-dtype", default="f64",
+                    choices=["f64", "f32", "bf16", "f16", "bf16s", "f16s"])
+    ap.add_argument("--gemm-reps", type=int, default=5)
+    ap.add_argument("--check", action="store_true", help="--gemm-shapes: compare with torch FP64")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hyperpower "
@@ -411,23 +537,42 @@ def main() -> int:
     from paper_1604_07893_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    d = inputs.lowrank_svd(M, N, RANK, smin=SMIN, seed=SEED)
-    A = torch.from_numpy(d.A).to(dev)
-    closed = (d.V / d.s) @ d.U.T
-    params = dict(alpha_rule="user", alpha=1.0, variant="stabilised", tol=TOL)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return 0
+    if args.gemm_shapes:
+        for spec in args.gemm_shapes.split(","):
+            M, N, K = (int(v) for v in spec.lower().split("x"))
+            print(json.dumps(gemm_standalone(hpw, torch, M, N, K, args.gemm_dtype, args.gemm_reps,
+                                             args.check)), flush=True)
+        return 0
+
+    A, U, s, V = inputs.square_svd_device(NSQ, smin=SMIN_SQ, seed=SEED_SQ)
+    closed = (V / s) @ U.T.contiguous()  # V diag(1/s) U^T: a reference, not the method
+    del U, V, s
+    torch.cuda.synchronize()
+    params = dict(alpha_rule="user", alpha=1.0, tol=TOL, precision="fp64")
     sec, infos, X = timed_solves(hpw, torch, A, args.steps, args.warmup, time_kernels=True,
                                  **params)
-    err = rel(X.cpu().numpy(), closed)
-
-    gflop = sum(i["gflop"] for i in infos)
-    gemm_ms = sum(i["gemm_ms"] for i in infos)
-    launches = sum(i["gemms"] for i in infos)
-    achieved = gflop / gemm_ms if gemm_ms > 0 else 0.0  # GFLOP/ms = TFLOP/s
+    err = trel(torch, X, closed)
+    del X
     last = infos[-1]
-    n_stab = last["iters"] - last["switch_iter"] if last["switch_iter"] >= 0 else 0
-    n_plain = last["iters"] - n_stab
-
+    launches = sum(i["gemms"] for i in infos)
+    rl = engine_roofline(infos, 2, PEAK_TFLOPS["f64"],
+                         "k_gemm<double> (FP64 MFMA GEMM with the fused loop epilogue), "
+                         f"{NSQ}x{NSQ}x{NSQ} per launch")
+    traffic, traffic_src = measured_traffic()
+    roofline = {
+        "bound": "mfma", "kernel": rl["kernel"], "achieved": rl["achieved"],
+        "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s", "frac": rl["frac"],
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "traffic_source": traffic_src,
+        "gflop_per_launch": sum(i["gflop"] for i in infos) / max(launches, 1),
+        "avg_launch_ms": sum(i["gemm_ms"] for i in infos) / max(launches, 1),
+        "timing": "hipEvents recorded by the library around each GEMM launch on the solve "
+                  "stream, over the timed steps",
+    }
     line = {
         "metric": METRIC,
         "value": 1.0 / sec,
@@ -441,37 +586,50 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "m": M, "n": N, "rank": RANK, "variant": "stabilised",
-                   "side": last["side"], "precision": "fp64", "tol": TOL},
-        "roofline": {
-            "bound": "mfma",
-            "kernel": "k_gemm (FP64 MFMA GEMM with the fused loop epilogue)",
-            "achieved": achieved,
-            "peak": PEAK_TFLOPS["f64"],
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS["f64"],
-            "traffic": measured_traffic(),
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "gflop_per_launch": gflop / max(launches, 1),
-            "avg_launch_ms": gemm_ms / max(launches, 1),
-        },
-        "gemm_tflops_executed": gflop / (sec * args.steps * 1e3),
+        "config": {"workload": WORKLOAD, "m": NSQ, "n": NSQ, "smin": SMIN_SQ, "variant": "plain",
+                   "precision": "fp64", "tol": TOL},
+        "roofline": roofline,
         "iters": last["iters"],
-        "plain_loops": n_plain,
-        "stabilised_loops": n_stab,
         "status": last["status"],
         "rel_err_vs_closed_form": err,
+        "gemm_tflops_executed": last["gflop"] / (sec * 1e3),
     }
-    log(f"headline: {1 / sec:.2f} inverses/s, GEMM {achieved:.1f} TFLOP/s, err {err:.2e}")
+    log(f"headline: {1 / sec:.3f} inverses/s ({sec * 1e3:.1f} ms), {last['iters']} loops, "
+        f"FP64 GEMM {rl['achieved']:.1f} TFLOP/s, err {err:.2e}")
+    if not args.no_mixed:
+        mx = headline_mixed(hpw, torch, A, closed, 2)
+        minf = mx["mixed"].pop("_infos")
+        fp64_rate = 1.0 / sec
+        for k in list(mx):
+            mx[k]["speedup_vs_fp64"] = mx[k]["inverses_per_s"] / fp64_rate
+        line["mixed_vs_fp64"] = mx
+        bd = {"f64": {k: v for k, v in roofline.items() if k not in ("traffic", "traffic_unit",
+                                                                      "traffic_source", "timing")}}
+        bd["f32"] = engine_roofline(minf, 1, PEAK_TFLOPS["f32"],
+                                    "k_gemm<float> (FP32 MFMA), mixed run: FP32 stage and the "
+                                    "delta-form polynomials of the FP64 stage, 8192^3")
+        bd["bf16"] = engine_roofline(minf, 0, PEAK_TFLOPS["bf16"],
+                                     "k_gemm_h16_dma (bf16 operands, FP32 accumulate), mixed run's "
+                                     "16-bit stage, 8192^3")
+        alone = gemm_standalone(hpw, torch, NSQ, NSQ, NSQ, "bf16s", 5)
+        bd["bf16_alone"] = {"bound": "mfma", "kernel": "k_gemm_h16_dma alone, 8192^3",
+                            "achieved": alone["tflops"], "peak": PEAK_TFLOPS["bf16"],
+                            "unit": "TFLOP/s", "frac": alone["tflops"] / PEAK_TFLOPS["bf16"]}
+        line["roofline_by_dtype"] = bd
+    if not args.no_cpu_baseline:
+        A_host = A.cpu().numpy()
+        line["cpu_baseline"] = cpu_baseline(A_host, last["iters"])
+        del A_host
+    del A, closed
+    torch.cuda.empty_cache()
     if not args.no_extras:
         extras = {}
-        for name, fn in (("fp32_4096x2048", lambda: extra_fp32(hpw, torch, A, closed, 5)),
-                         ("mixed_vs_fp64_8192", lambda: extra_mixed(hpw, torch, 2)),
+        for name, fn in (("lowrank_4096x2048", lambda: extra_lowrank(hpw, torch, 5)),
                          ("drazin_2048", lambda: extra_drazin(hpw, torch, 3)),
                          ("small_200x100", lambda: extra_small(hpw, torch, 50)),
                          ("methods", lambda: extra_methods(hpw, torch, 2)),
                          ("preconditioner_example_8_3", lambda: extra_precond(hpw, torch, 20)),
-                         ("served_stream", lambda: extra_served(hpw, torch, 1000, 100))):
+                         ("served_stream", lambda: extra_served(hpw, torch, 2000, 200))):
             if args.extras and name not in args.extras.split(","):
                 continue
             t0 = time.perf_counter()
@@ -479,10 +637,9 @@ def main() -> int:
                 extras[name] = fn()
             except Exception as e:  # a failing extra must not hide the headline
                 extras[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
             log(f"extra {name} done in {time.perf_counter() - t0:.1f} s")
         line["extras"] = extras
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(d, n_plain, n_stab)
     print(json.dumps(line), flush=True)
     return 0
 
