@@ -21,8 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libhyperpower.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["hp_gemm.hip", "hp_kernels.hip", "hp_driver.cpp", "hp_batch.cpp", "hp_loop.cpp",
-           "hp_noalloc.hip"]
+SOURCES = ["hp_gemm.hip", "hp_gemm_h16.hip", "hp_tiles.cpp", "hp_kernels.hip", "hp_driver.cpp",
+           "hp_batch.cpp", "hp_loop.cpp", "hp_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
