@@ -309,6 +309,12 @@ def extra_small(hpw, torch, steps):
     sec, infos, X = timed_solves(hpw, torch, A, steps, 3, tol=1e-12)
     out.update({"us_per_inverse": sec * 1e6, "iters": infos[-1]["iters"],
                 "status": infos[-1]["status"], "rel_err_vs_lapack_pinv": rel(X.cpu().numpy(), ref)})
+    # the stop decisions on the device (hp_params.device_stop): loops enqueued
+    # in chunks (a captured graph of two loops replayed), no host read per loop
+    sec2, infos2, X2 = timed_solves(hpw, torch, A, steps, 3, tol=1e-12, device_stop=True)
+    out["device_stop"] = {"us_per_inverse": sec2 * 1e6, "iters": infos2[-1]["iters"],
+                          "status": infos2[-1]["status"],
+                          "bitwise_equal_to_host_loop": bool(torch.equal(X2, X))}
     return out
 
 

@@ -20,7 +20,8 @@
  *    write-only and must not alias inputs or the workspace.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
  *    device work is enqueued on it; hp_solve synchronises the stream once per
- *    loop to read the two stopping scalars.
+ *    loop to read the two stopping scalars (with hp_params.device_stop, once
+ *    per chunk of loops).
  *  - Return value: HP_OK (0); a positive numerical outcome (the output is
  *    still written); or a negative error (outputs untouched).
  *  - A handle is not thread-safe; use one handle per host thread.
@@ -194,9 +195,13 @@ extern "C" {
                                   solve stream; sums land in hp_result.gemm_ms */
 #define HP_FLAG_INF_NORM 2     /* also compute ||X_{k+1}-X_k||_inf each loop
                                   (implied by HP_STOP_ABS_INF); enables coc */
-#define HP_FLAG_NO_GRAPH 4     /* batched/served: launch each loop's kernels one
-                                  by one instead of replaying the captured
-                                  hipGraph of the loop */
+#define HP_FLAG_NO_GRAPH 4     /* batched/served, and hp_solve with
+                                  device_stop: launch each loop's kernels one
+                                  by one instead of replaying a captured
+                                  hipGraph of the loop (hp_solve caches a
+                                  graph of two loops per workspace, shape and
+                                  loop form in the handle; hp_solve_noalloc
+                                  and HP_FLAG_TIME_KERNELS never capture) */
 #define HP_FLAG_NO_RETRY 8     /* served: do not retry in FP64 a request whose
                                   lower-precision solve ended other than
                                   HP_OK (see hp_serve_step) */
@@ -264,7 +269,21 @@ typedef struct hp_params {
     int32_t method;        /* HP_METHOD_* (default PM). Methods other than PM
                               run in HP_PREC_FP64 or HP_PREC_FP32 in hp_solve
                               only (HP_EUNSUPPORTED otherwise) */
-    int32_t reserved0;     /* must be zero */
+    int32_t device_stop;   /* 1: hp_solve enqueues its loops without reading
+                              the stopping sums on the host after each
+                              loop: a one-thread kernel takes each loop's
+                              stop / switch / guard decision from the sums on
+                              the device, and every kernel of a later loop
+                              (or of the form of a loop not taken: plain or
+                              stabilised) reads that decision and returns at
+                              once; the host reads the decision state once
+                              per chunk of loops (the first 4, then 2 at a
+                              time). Same decisions, same iterates, bitwise,
+                              as with 0. HP_PREC_FP64 without
+                              HP_STOP_REL_FRO_BOUND, HP_FLAG_SYMMETRIC or
+                              chop (HP_EUNSUPPORTED otherwise); batched and
+                              served solves ignore it. 0: one host read per
+                              loop */
     double chop;           /* > 0: at the end of every loop, entries of X_{k+1}
                               with |x| < chop are set to zero before the
                               stopping test measures the change (the sparsity

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -177,6 +178,10 @@ Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool single) {
     off = align_up(off + sizeof(double) * (size_t)small);
     pl.offScal = off;
     off = align_up(off + sizeof(double) * hp::SLOT_COUNT);
+    pl.offDev = off;  // DevLoop and StepParams (hp_params.device_stop)
+    off = align_up(off + sizeof(hp::DevLoop));
+    pl.offStep = off;
+    off = align_up(off + sizeof(hp::StepParams));
     pl.total = off;
     return pl;
 }
@@ -212,7 +217,12 @@ int validate(const hp_params* p, int64_t m, int64_t n) {
         return HP_EUNSUPPORTED;
     if (p->max_iter < 1 || p->max_iter > 100000) return HP_EINVAL;
     if (!(p->tol >= 0.0) || !(p->tau_switch > 0.0) || !(p->diverge_limit > 0.0)) return HP_EINVAL;
-    if (p->reserved0 != 0 || p->reserved[0] != 0 || p->reserved[1] != 0) return HP_EINVAL;
+    if (p->reserved[0] != 0 || p->reserved[1] != 0) return HP_EINVAL;
+    if (p->device_stop != 0 && p->device_stop != 1) return HP_EINVAL;
+    // the device-side decision covers FP64 loops with the plain stopping rules
+    if (p->device_stop && (p->precision != HP_PREC_FP64 || p->stop_rule == HP_STOP_REL_FRO_BOUND ||
+                           (p->flags & HP_FLAG_SYMMETRIC) || p->chop > 0.0))
+        return HP_EUNSUPPORTED;
     return HP_OK;
 }
 
@@ -247,6 +257,8 @@ Buffers carve(const Plan& pl, char* ws) {
     }
     bf.small = d(pl.offSmall);
     bf.scal = d(pl.offScal);
+    bf.dev = reinterpret_cast<DevLoop*>(ws + pl.offDev);
+    bf.step = reinterpret_cast<StepParams*>(ws + pl.offStep);
     if (pl.splitSlots > 0) {
         bf.split_part = d(pl.offSplit);
         bf.split_cnt = reinterpret_cast<unsigned*>(ws + pl.offSplitCnt);
@@ -313,6 +325,7 @@ struct Solver {
     double* split_part = nullptr;  // split-K scratch of the workspace (Plan)
     unsigned* split_cnt = nullptr;
     const Buffers* bf = nullptr;   // for the 16-bit copies of the first mixed stage
+    bool may_allocate = true;      // false under hp_solve_noalloc
 
     template <typename T>
     int gemm(Engine eng, const GemmCall<T>& g, const CopyUse* use = nullptr) {
@@ -403,6 +416,233 @@ void set_chop(GemmCall<T>* calls, int nc, const T* Xn, double chop) {
     if (chop <= 0.0) return;
     for (int i = 0; i < nc; ++i)
         if (calls[i].ep.out[0] == Xn) calls[i].ep.chop = chop;
+}
+
+// hp_params.device_stop: the loops of an FP64 solve enqueued in chunks, each
+// loop's decision taken on the device by loop_step (LoopState::step's rules),
+// every kernel of the loop gated on it. A loop is enqueued in both forms --
+// the plain update (writing X_{k+1} with the stopping sums) and the
+// stabilised one (update into X_{k+1/2}, then X_{k+1/2} A X_{k+1/2} with the
+// sums) -- and the flag the previous decision left selects which runs, so the
+// iterates and decisions are those of run_solve, bitwise.
+int run_solve_device(Solver& S, char* ws, const double* A, int64_t lda, const double* X0,
+                     int64_t ldx0, double* X, int64_t ldx) {
+    const hp_params* p = S.p;
+    const Plan& pl = S.pl;
+    hipStream_t s = S.s;
+    hp_result* res = S.res;
+    const int64_t m = pl.m, n = pl.n;
+    const Buffers bf = carve(pl, ws);
+    double* hs = S.h->host_scal;
+    if (bf.split_cnt) {
+        HIPCHK(zero_u32(bf.split_cnt, pl.splitCnt, s));
+        S.split_part = bf.split_part;
+        S.split_cnt = bf.split_cnt;
+    }
+    S.sym = false;
+    S.bf = &bf;
+    S.stage = 2;
+    double alpha = 0.0;
+    {
+        Range setup_range("set-up X0");
+        CHK(setup_x0(p, pl, bf, A, lda, X0, ldx0, hs, s,
+                     [&](const GemmCall<double>& g) { return S.gemm<double>(ENG_F64, g); }, &alpha));
+    }
+    S.timer.harvest();
+    res->alpha = alpha;
+    const double gf_setup = S.gflop;
+    const int ng_setup = S.gemms;
+
+    DevLoop* L = bf.dev;
+    const int* gate = reinterpret_cast<const int*>(L);
+    HIPCHK(loop_init(L, p->variant == HP_VARIANT_STAB_ALWAYS ? 1 : 0, s));
+    const bool want_inf = (p->flags & HP_FLAG_INF_NORM) || p->stop_rule == HP_STOP_ABS_INF;
+    // the decision's parameters, staged through pinned memory (the stream
+    // reads them before the host touches that area again)
+    StepParams& P = *reinterpret_cast<StepParams*>(hs + SLOT_COUNT);
+    static_assert(sizeof(StepParams) <= sizeof(double) * hp_handle::kHostExtra, "staging");
+    P = StepParams{};
+    P.stop_rule = p->stop_rule;
+    P.variant = p->variant;
+    P.max_iter = p->max_iter;
+    P.have_dinf = want_inf ? 1 : 0;
+    P.keep_best = 1;
+    P.tol = p->tol;
+    P.tau = p->tau_switch;
+    P.diverge = p->diverge_limit;
+    P.alpha = alpha;
+    P.order = (double)method_order(p->method);
+    HIPCHK(hipMemcpyAsync(bf.step, &P, sizeof(StepParams), hipMemcpyHostToDevice, s));
+
+    // executed work of one loop in each form (the accounting after the solve)
+    double gf_plain = 0.0, gf_stab = 0.0;
+    int ng_plain = 0, ng_stab = 0;
+    auto flops = [](const GemmCall<double>& c) {
+        return 2.0 * (double)c.M * (double)c.N * (double)c.K * 1e-9;
+    };
+    auto gated = [&](GemmCall<double> c, int mode) {
+        c.ep.gate = gate;
+        c.ep.gate_mode = mode;
+        return S.gemm<double>(ENG_F64, c);
+    };
+    int calls_per_loop = 0;
+    auto enqueue = [&](int j) -> int {
+        const hipStream_t s = S.s;  // the solve stream, or the capture stream
+        Range loop_range("loop %d (device decision)", j + 1);
+        double* Xk = bf.b64.X[j & 1];
+        double* Xn = bf.b64.X[(j + 1) & 1];
+        GemmCall<double> cp[kMaxLoopGemms], cs[kMaxLoopGemms];
+        const int np = describe_loop<double>(p->method, pl, bf.b64, Xk, Xn, bf.b64.X[2], false,
+                                             bf.small, cp);
+        const int ns = describe_loop<double>(p->method, pl, bf.b64, Xk, Xn, bf.b64.X[2], true,
+                                             bf.small, cs);
+        const int common = np - 1;  // the products before the update
+        for (int i = 0; i < common; ++i) CHK(gated(cp[i], GATE_LIVE));
+        // a variant that never switches enqueues only the form it runs
+        int nb_plain = 0, nb_stab = 0;
+        if (p->variant != HP_VARIANT_STAB_ALWAYS) {
+            CHK(gated(cp[common], GATE_PLAIN));
+            nb_plain = S.last_blocks;
+        }
+        if (p->variant != HP_VARIANT_PLAIN) {
+            for (int i = common; i < ns; ++i) CHK(gated(cs[i], GATE_STAB));
+            nb_stab = S.last_blocks;
+        }
+        HIPCHK(reduce_pairs_gated(bf.small, nb_plain, nb_stab, bf.scal, L, s));
+        if (want_inf)
+            HIPCHK(diff_norm_inf_gated(Xn, bf.b64.ldX, Xk, bf.b64.ldX, n, m, bf.small, bf.scal, L,
+                                       s));
+        HIPCHK(loop_step(bf.scal, L, bf.step, s));
+        // the decision may ask to keep this loop's input as the best iterate
+        HIPCHK(copy_gated(Xk, bf.b64.ldX, bf.b64.X[LoopState::kBest], bf.b64.ldX, n, m, L,
+                          GATE_SAVE, s));
+        return HP_OK;
+    };
+    {
+        // the products of one loop in each form (host-side descriptions only)
+        GemmCall<double> cp[kMaxLoopGemms], cs[kMaxLoopGemms];
+        const int np = describe_loop<double>(p->method, pl, bf.b64, bf.b64.X[0], bf.b64.X[1],
+                                             bf.b64.X[2], false, bf.small, cp);
+        const int ns = describe_loop<double>(p->method, pl, bf.b64, bf.b64.X[0], bf.b64.X[1],
+                                             bf.b64.X[2], true, bf.small, cs);
+        const int common = np - 1;
+        for (int i = 0; i < np; ++i) gf_plain += flops(cp[i]);
+        for (int i = 0; i < common; ++i) gf_stab += flops(cp[i]);
+        for (int i = common; i < ns; ++i) gf_stab += flops(cs[i]);
+        ng_plain = np;
+        ng_stab = ns;
+        calls_per_loop = common + (p->variant != HP_VARIANT_STAB_ALWAYS ? 1 : 0) +
+                         (p->variant != HP_VARIANT_PLAIN ? ns - common : 0);
+    }
+
+    // Two loops (input X[0], then X[1]) captured once (on the handle's
+    // capture stream) as a graph per (workspace, shape, loop form) and
+    // replayed on the solve stream; without allocation (or with per-kernel
+    // timing, or HP_FLAG_NO_GRAPH) the loops are launched one by one instead.
+    hp_handle* h = S.h;
+    hipGraphExec_t exec = nullptr;
+    const bool use_graph = S.may_allocate && !S.timer.on && !(p->flags & HP_FLAG_NO_GRAPH);
+    if (use_graph) {
+        const std::array<int64_t, 10> key = {
+            (int64_t)reinterpret_cast<uintptr_t>(ws), m, n, pl.left ? 1 : 0, p->method,
+            p->variant, want_inf ? 1 : 0, h->tune_gen, h->forced_tile, (int64_t)pl.total};
+        for (auto& g : h->graphs)
+            if (g.key == key) {
+                g.used = ++h->graph_clock;
+                exec = g.exec;
+            }
+        if (!exec) {
+            if (!h->cap_stream)
+                HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+            Range cap_range("capture two loops");
+            HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            S.s = h->cap_stream;
+            int rc = enqueue(0);
+            if (rc == HP_OK) rc = enqueue(1);
+            S.s = s;
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+            if (rc != HP_OK || e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc != HP_OK ? rc : HP_EHIP;
+            }
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return HP_EHIP;
+            }
+            if ((int)h->graphs.size() >= hp_handle::kGraphs) {
+                auto lru = std::min_element(h->graphs.begin(), h->graphs.end(),
+                                            [](const auto& a, const auto& b) { return a.used < b.used; });
+                HIPCHK(hipStreamSynchronize(h->cap_stream));
+                (void)hipGraphExecDestroy(lru->exec);
+                (void)hipGraphDestroy(lru->graph);
+                h->graphs.erase(lru);
+            }
+            h->graphs.push_back({key, graph, exec, ++h->graph_clock});
+        }
+    }
+    // Chunks of loops between host reads of the decision state: 4 loops
+    // first; then one loop when the last change d, in the converging regime,
+    // has d^p < tol (the next loop is expected to pass the test), else two.
+    // A chunk starting at an even loop takes whole replays of the graph (on
+    // the solve stream); an odd remainder is launched loop by loop. Loops past
+    // max_iter find the solve done and return at once. (The event pairs of
+    // HP_FLAG_TIME_KERNELS bound a chunk too.)
+    const double order = (double)method_order(p->method);
+    int j = 0, chunk = std::min(p->max_iter, 4);
+    for (;;) {
+        int c = 0;
+        while (c < chunk && j < p->max_iter) {
+            if (exec && (j & 1) == 0 && chunk - c >= 2) {
+                HIPCHK(hipGraphLaunch(exec, s));
+                j += 2;
+                c += 2;
+            } else {
+                CHK(enqueue(j));
+                ++j;
+                ++c;
+            }
+        }
+        HIPCHK(hipMemcpyAsync(hs, L, offsetof(DevLoop, d_hist), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        S.timer.harvest();
+        const DevLoop& hl = *reinterpret_cast<const DevLoop*>(hs);
+        if (hl.done || j >= p->max_iter) break;
+        chunk = hl.converging && std::pow(hl.d_last, order) < p->tol ? 1 : 2;
+        if (S.timer.on && calls_per_loop > 0)
+            chunk = std::max(1, std::min(chunk, (hp_handle::kEvents / 2) / calls_per_loop));
+    }
+    DevLoop st{};
+    HIPCHK(hipMemcpyAsync(&st, L, sizeof(DevLoop), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int k = st.k;
+    res->iters = k;
+    res->iters_stage[2] = k;
+    res->switch_iter = st.switch_iter;
+    res->d_last = st.d_last;
+    res->d_stage[2] = st.d_last;
+    res->stop_last = st.stop_last;
+    const int it = std::min(k, HP_HIST);
+    for (int i = 0; i < it; ++i) {
+        res->d_hist[i] = st.d_hist[i];
+        if (want_inf) res->dinf_hist[i] = st.dinf_hist[i];
+    }
+    if (want_inf && it >= 3) {
+        const double e0 = res->dinf_hist[it - 3], e1 = res->dinf_hist[it - 2], e2 = res->dinf_hist[it - 1];
+        if (e0 > 0 && e1 > 0 && e2 > 0) res->coc = std::log(e2 / e1) / std::log(e1 / e0);
+    }
+    // work of the loops that ran (the gated-off launches did none)
+    const int n_stab = st.switch_iter >= 0 ? std::max(0, k - st.switch_iter) : 0;
+    const int n_plain = k - n_stab;
+    S.gflop = gf_setup + n_plain * gf_plain + n_stab * gf_stab;
+    S.gemms = ng_setup + n_plain * ng_plain + n_stab * ng_stab;
+    res->gflop_stage[2] = S.gflop;
+    res->gflop_engine[2] = S.gflop;
+    const int ri = st.result_idx >= 0 ? st.result_idx : (k & 1);
+    HIPCHK(hipMemcpy2DAsync(X, ldx * sizeof(double), bf.b64.X[ri], bf.b64.ldX * sizeof(double),
+                            m * sizeof(double), n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return st.done ? st.status : HP_MAXITER;
 }
 
 int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X0, int64_t ldx0,
@@ -735,7 +975,8 @@ int hp_create(hp_handle** out, int device) {
         const int v = std::atoi(t);
         if (v >= 0 && v < hp::TILE_COUNT) h->forced_tile = v;
     }
-    if (hipHostMalloc(reinterpret_cast<void**>(&h->host_scal), sizeof(double) * hp::SLOT_COUNT,
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->host_scal),
+                      sizeof(double) * (hp::SLOT_COUNT + hp_handle::kHostExtra),
                       hipHostMallocDefault) != hipSuccess) {
         delete h;
         return HP_EHIP;
@@ -756,6 +997,13 @@ int hp_create(hp_handle** out, int device) {
 int hp_destroy(hp_handle* h) {
     if (!h) return HP_EINVAL;
     (void)hipSetDevice(h->device);
+    if (h->cap_stream) (void)hipStreamSynchronize(h->cap_stream);
+    for (auto& g : h->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    h->graphs.clear();
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (int i = 0; i < hp_handle::kEvents; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
@@ -774,6 +1022,16 @@ int hp_workspace_bytes(const hp_params* p, int64_t m, int64_t n, size_t* bytes) 
 int hp_solve(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64_t n, int64_t lda,
              const double* X0, int64_t ldx0, double* X, int64_t ldx, void* workspace,
              size_t ws_bytes, void* stream, hp_result* out) {
+    return hp::solve_entry(h, p, A, m, n, lda, X0, ldx0, X, ldx, workspace, ws_bytes, stream, out,
+                           true);
+}
+
+}  // extern "C"
+
+int hp::solve_entry(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64_t n,
+                    int64_t lda, const double* X0, int64_t ldx0, double* X, int64_t ldx,
+                    void* workspace, size_t ws_bytes, void* stream, hp_result* out,
+                    bool may_allocate) {
     const auto t0 = std::chrono::steady_clock::now();
     if (!h || !A || !X) return HP_EINVAL;
     int rc = validate(p, m, n);
@@ -794,7 +1052,9 @@ int hp_solve(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64
     Solver S{h, p, reinterpret_cast<hipStream_t>(stream), pl, res,
              GemmTimer{h, (p->flags & HP_FLAG_TIME_KERNELS) != 0, 0, 0.0,
                        reinterpret_cast<hipStream_t>(stream)}};
-    rc = run_solve(S, static_cast<char*>(workspace), A, lda, X0, ldx0, X, ldx);
+    S.may_allocate = may_allocate;
+    rc = p->device_stop ? run_solve_device(S, static_cast<char*>(workspace), A, lda, X0, ldx0, X, ldx)
+                        : run_solve(S, static_cast<char*>(workspace), A, lda, X0, ldx0, X, ldx);
     res->status = rc;
     res->gflop = S.gflop;
     res->gemms = S.gemms;
@@ -807,6 +1067,8 @@ int hp_solve(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }
+
+extern "C" {
 
 // Split-K workspace of hp_gemm_ws: `slots` partial tiles of 128 x 128
 // elements of the dtype's storage type, then `slots` counters.
@@ -1244,6 +1506,7 @@ int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* 
     (void)hipEventDestroy(e1);
     if (best < 0) return HP_EHIP;
     h->tuned[{dtype, M, N, K}] = best;
+    ++h->tune_gen;
     *tile = best;
     *ms = best_ms;
     return HP_OK;
@@ -1271,6 +1534,7 @@ int hp_tune_import(hp_handle* h, const int64_t* rows, int count) {
             return HP_EINVAL;
         h->tuned[{r[0], r[1], r[2], r[3]}] = (int)r[4];
     }
+    ++h->tune_gen;
     return HP_OK;
 }
 

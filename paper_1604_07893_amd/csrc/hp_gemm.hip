@@ -465,6 +465,7 @@ template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
 __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm(
     int M, int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
     int64_t ldb, EpilogueT<T> ep, int tiles_m, int tiles_n) {
+    if (gate_closed(ep.gate, ep.gate_mode)) return;  // uniform over the launch
     int tm, tn;
     tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
     gemm_tile<T, BM, BN, BK, WM, WN, PF>(M, N, K, A, lda, B, ldb, ep, tm, tn, blockIdx.x);
@@ -477,6 +478,7 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN))
 __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_split(
     int M, int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
     int64_t ldb, EpilogueT<T> ep, int tiles_m, int tiles_n, int kchunk) {
+    if (gate_closed(ep.gate, ep.gate_mode)) return;  // uniform: no counter is touched
     const int p = xcd_contiguous(blockIdx.x, gridDim.x);
     const int t = p / SPLIT, split = p % SPLIT;
     int tm, tn;
@@ -500,6 +502,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_sym(
     int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     EpilogueT<T> ep, int nt, int tiles, int ipt, int ipc) {
     static_assert(BM == 128 && BN == 128, "partial slots hold 128 x 128 tiles");
+    if (gate_closed(ep.gate, ep.gate_mode)) return;  // uniform: no counter is touched
     const int b = xcd_contiguous(blockIdx.x, gridDim.x);
     const int64_t total = (int64_t)tiles * ipt;
     int64_t it = (int64_t)b * ipc;

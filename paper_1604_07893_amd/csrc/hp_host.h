@@ -10,6 +10,7 @@
 #include <map>
 #include <cstdint>
 #include <type_traits>
+#include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
@@ -25,9 +26,27 @@ struct hp_handle {
     int forced_tile = -1;         // HP_GEMM_TILE: one tile configuration for every product
     // autotuned tiles: (dtype, M, N, K) -> tile index
     std::map<std::array<int64_t, 4>, int> tuned;
-    double* host_scal = nullptr;  // pinned, hp::SLOT_COUNT doubles
+    int tune_gen = 0;             // bumped whenever `tuned` changes
+    // pinned: hp::SLOT_COUNT doubles, then kHostExtra doubles of staging
+    // (device_stop: the step parameters, and the head of the DevLoop state,
+    // which is read back over the slots)
+    double* host_scal = nullptr;
+    static constexpr int kHostExtra = 16;
     static constexpr int kEvents = 64;
     hipEvent_t ev[kEvents] = {};
+    // hp_params.device_stop: two loops of a solve captured (on cap_stream) as
+    // a hipGraph and replayed on the solve stream, cached per (workspace,
+    // shape, loop form); least recently used evicted.
+    struct LoopGraph {
+        std::array<int64_t, 10> key;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    static constexpr int kGraphs = 8;
+    std::vector<LoopGraph> graphs;
+    uint64_t graph_clock = 0;
+    hipStream_t cap_stream = nullptr;
 };
 
 #define HIPCHK(x)                              \
@@ -98,6 +117,14 @@ PMConst pm_const();
 // (which must be current) once per device; hp_create calls it.
 int noalloc_init(int device);
 
+// hp_solve's body; `may_allocate` false (hp_solve_noalloc) keeps it from
+// creating anything (the device_stop path then launches loop by loop
+// instead of capturing a graph).
+int solve_entry(hp_handle* h, const hp_params* p, const double* A, int64_t m, int64_t n,
+                int64_t lda, const double* X0, int64_t ldx0, double* X, int64_t ldx,
+                void* workspace, size_t ws_bytes, void* stream, hp_result* out,
+                bool may_allocate);
+
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t pad_ld(int64_t cols);
@@ -134,7 +161,7 @@ struct Plan {
     // precisions without HP_FLAG_FP64_POLY)
     bool delta = false;
     size_t offSplit = 0, offSplitCnt = 0;
-    size_t offSmall = 0, nSmall = 0, offScal = 0, total = 0;
+    size_t offSmall = 0, nSmall = 0, offScal = 0, offDev = 0, offStep = 0, total = 0;
 };
 // `single`: a single solve, which reserves the split-K scratch the default
 // tile choice needs for its products (the grouped launches never split) and a
@@ -181,6 +208,8 @@ struct Buffers {
     double* Xt = nullptr;  // m x n, ld b64.ldA
     double* small = nullptr;
     double* scal = nullptr;
+    DevLoop* dev = nullptr;  // loop control on the device (hp_params.device_stop)
+    StepParams* step = nullptr;  // its parameters
     double* split_part = nullptr;  // Plan::splitSlots tiles of 128 x 128 doubles
     unsigned* split_cnt = nullptr;
 };

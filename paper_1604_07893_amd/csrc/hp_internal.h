@@ -22,6 +22,42 @@ enum ScalarSlot : int {
     SLOT_COUNT = 8
 };
 
+// Loop control kept on the device (hp_params.device_stop): the stop, switch
+// and guard decisions of one FP64 solve, taken by k_loop_step from the
+// reduced stopping sums of each loop, so that loops can be enqueued without
+// the host reading those sums. The first three ints are what the kernels of a
+// loop read to decide whether to run (gate_closed).
+struct DevLoop {
+    int done;          // a decision ended the solve: every later kernel skips
+    int stabilising;   // the next loop runs the stabilising product
+    int save_best;     // copy this loop's input to the best-iterate slot
+    int status;        // HP_* outcome once done
+    int k;             // loops run
+    int converging;    // some change below tau_switch was seen
+    int switch_iter;   // first loop run stabilised (-1: none)
+    int result_idx;    // iterate to return (0, 1 or the best slot 3)
+    int have_best;
+    int pad[3];
+    double d_prev, best_d, stop_last, d_last;
+    double d_hist[128];     // HP_HIST
+    double dinf_hist[128];
+};
+
+// When a gated kernel runs (EpilogueT::gate_mode, and the gated elementwise
+// kernels): always; while the solve is live; in a live loop that is plain /
+// stabilised (the flag as the previous loop's decision left it); when the
+// last decision asked to keep the best iterate.
+enum GateMode : int { GATE_NONE = 0, GATE_LIVE = 1, GATE_PLAIN = 2, GATE_STAB = 3, GATE_SAVE = 4 };
+
+__host__ __device__ inline bool gate_closed(const int* g, int mode) {
+    if (mode == GATE_NONE || !g) return false;
+    if (mode == GATE_SAVE) return g[2] == 0;
+    if (g[0]) return true;
+    if (mode == GATE_PLAIN) return g[1] != 0;
+    if (mode == GATE_STAB) return g[1] == 0;
+    return false;
+}
+
 // Fused GEMM epilogue. For output o (0..2) with out[o] != nullptr:
 //   out[o][i][j] = id[o]*[i==j] + acc_c[o]*acc + g1[o]*D1[i][j] + g2[o]*D2[i][j]
 // If ref != nullptr, each block also writes FP64 partial sums
@@ -72,6 +108,10 @@ struct EpilogueT {
     // gemm_h16 only: nonzero skips the FP32 store of output o (when only its
     // 16-bit copies are read later); the stopping sums still use the value
     int skip32[3];
+    // FP64/FP32 kernels (gemm): with gate_mode != GATE_NONE the whole launch
+    // returns at once when gate_closed(gate, gate_mode) (a DevLoop's flags)
+    const int* gate;
+    int gate_mode;
 };
 using Epilogue = EpilogueT<double>;
 
@@ -242,6 +282,30 @@ hipError_t set_identity(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_
 
 // scal[SLOT_DIFF2], scal[SLOT_REF2] = fixed-order sums of the pair partials.
 hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipStream_t s);
+
+// Device-side loop control (hp_params.device_stop; hp_kernels.hip). Kept in
+// device memory (not a kernel argument), so that captured loops do not
+// depend on a solve's tolerance or alpha.
+struct StepParams {
+    int stop_rule, variant, max_iter, have_dinf, keep_best, pad;
+    double tol, tau, diverge, alpha, order;
+};
+// Reset *L for a new solve (a fill kernel).
+hipError_t loop_init(DevLoop* L, int stab_always, hipStream_t s);
+// reduce_pairs of whichever update ran this loop (nb_plain or nb_stab
+// partial pairs, by L->stabilising); skipped once the solve is done.
+hipError_t reduce_pairs_gated(const double* partials, int nb_plain, int nb_stab, double* scal,
+                              const DevLoop* L, hipStream_t s);
+// diff_norm_inf, skipped once the solve is done.
+hipError_t diff_norm_inf_gated(const double* X1, int64_t ld1, const double* X0, int64_t ld0,
+                               int64_t M, int64_t N, double* tmp, double* scal, const DevLoop* L,
+                               hipStream_t s);
+// One loop's stop / switch / guard decision (LoopState::step for an FP64
+// solve) from scal's sums; `ik` is the index (0 or 1) of the loop's input.
+hipError_t loop_step(const double* scal, DevLoop* L, const StepParams* P, hipStream_t s);
+// dst = src (rows x cols doubles) when the gate is open.
+hipError_t copy_gated(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                      int64_t cols, const DevLoop* L, int mode, hipStream_t s);
 
 // scal[SLOT_DINF] = max_i sum_j |X1[i][j] - X0[i][j]|. `tmp` needs M doubles.
 hipError_t diff_norm_inf(const double* X1, int64_t ld1, const double* X0, int64_t ld0,

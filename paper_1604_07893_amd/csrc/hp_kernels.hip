@@ -3,6 +3,7 @@
 // reductions of the stopping test and precision conversions. The hot kernel,
 // the MFMA GEMM with the fused loop epilogue, is in hp_gemm.hip.
 #include "hp_internal.h"
+#include "hyperpower.h"
 
 namespace hp {
 namespace {
@@ -324,7 +325,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce_pairs(const double* __restr
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_diff_rowsum(const T* __restrict__ X1, int64_t ld1,
                                                           const T* __restrict__ X0, int64_t ld0,
-                                                          int N, double* __restrict__ rows) {
+                                                          int N, double* __restrict__ rows,
+                                                          const int* gate) {
+    if (gate_closed(gate, GATE_LIVE)) return;
     const int r = blockIdx.x;
     double s = 0.0;
     for (int c = threadIdx.x; c < N; c += kThreads)
@@ -334,7 +337,9 @@ __global__ __launch_bounds__(kThreads) void k_diff_rowsum(const T* __restrict__ 
 }
 
 __global__ __launch_bounds__(kThreads) void k_max_to_slot(const double* __restrict__ v, int n,
-                                                          double* __restrict__ scal, int slot) {
+                                                          double* __restrict__ scal, int slot,
+                                                          const int* gate) {
+    if (gate_closed(gate, GATE_LIVE)) return;
     double m = 0.0;
     bool nan = false;
     for (int i = threadIdx.x; i < n; i += kThreads) {
@@ -574,10 +579,12 @@ hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipSt
 
 template <typename T>
 static hipError_t diff_norm_inf_t(const T* X1, int64_t ld1, const T* X0, int64_t ld0, int64_t M,
-                                  int64_t N, double* tmp, double* scal, hipStream_t s) {
+                                  int64_t N, double* tmp, double* scal, hipStream_t s,
+                                  const int* gate = nullptr) {
     hipLaunchKernelGGL(k_diff_rowsum<T>, dim3((unsigned)M), dim3(kThreads), 0, s, X1, ld1, X0, ld0,
-                       (int)N, tmp);
-    hipLaunchKernelGGL(k_max_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal, (int)SLOT_DINF);
+                       (int)N, tmp, gate);
+    hipLaunchKernelGGL(k_max_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, (int)M, scal,
+                       (int)SLOT_DINF, gate);
     return hipGetLastError();
 }
 
@@ -663,6 +670,176 @@ hipError_t asymsq(const double* P, int64_t ldp, int64_t n, double* tmp, double* 
     const int nt = (int)cdiv(n, 32);
     hipLaunchKernelGGL(k_asym_part, dim3(nt, nt), dim3(kThreads), 0, s, P, ldp, (int)n, tmp);
     hipLaunchKernelGGL(k_sum_to_slot, dim3(1), dim3(kThreads), 0, s, tmp, nt * nt, scal, slot);
+    return hipGetLastError();
+}
+
+}  // namespace hp
+
+// ---------------------------------------------------------------------------
+// Loop control on the device (hp_params.device_stop): the decisions of
+// LoopState::step for a solve whose every loop is FP64, taken from the
+// stopping sums the loop's update product left, so that the host can enqueue
+// loops without reading those sums; the kernels of a loop consult the flags
+// (gate_closed) and skip their work once the solve is done, or when they
+// belong to the other (plain / stabilised) form of the loop.
+// ---------------------------------------------------------------------------
+
+namespace hp {
+namespace {
+
+__global__ void k_loop_init(DevLoop* L, int stab_always) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    L->done = 0;
+    L->stabilising = stab_always;
+    L->save_best = 0;
+    L->status = HP_MAXITER;
+    L->k = 0;
+    L->converging = 0;
+    L->switch_iter = stab_always ? 0 : -1;
+    L->result_idx = -1;
+    L->have_best = 0;
+    L->d_prev = 0.0;
+    L->best_d = 0.0;
+    L->stop_last = 0.0;
+    L->d_last = 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_pairs_gated(const double* __restrict__ part,
+                                                                 int nb_plain, int nb_stab,
+                                                                 double* __restrict__ scal,
+                                                                 const DevLoop* L) {
+    if (L->done) return;
+    const int nb = L->stabilising ? nb_stab : nb_plain;
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) {
+        s0 += part[2 * b];
+        s1 += part[2 * b + 1];
+    }
+    s0 = block_sum(s0);
+    s1 = block_sum(s1);
+    if (threadIdx.x == 0) {
+        scal[SLOT_DIFF2] = s0;
+        scal[SLOT_REF2] = s1;
+    }
+}
+
+// The decision after loop k (its input iterate is index k % 2, its output
+// (k + 1) % 2), in the order and arithmetic of LoopState::step.
+__global__ void k_loop_step(const double* __restrict__ scal, DevLoop* L,
+                            const StepParams* __restrict__ Pp) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || L->done) return;
+    const StepParams P = *Pp;
+    L->save_best = 0;
+    const int k = L->k;
+    const int ik = k & 1, in_ = ik ^ 1;
+    const double diff2 = scal[SLOT_DIFF2], ref2 = scal[SLOT_REF2];
+    const double dinf = P.have_dinf ? scal[SLOT_DINF] : 0.0;
+    const double d = sqrt(diff2) / sqrt(ref2);
+    if (k < 128) {
+        L->d_hist[k] = d;
+        if (P.have_dinf) L->dinf_hist[k] = dinf;
+    }
+    L->d_last = d;
+    L->k = k + 1;
+    const bool finite = isfinite(d) && isfinite(diff2) && (!P.have_dinf || isfinite(dinf));
+    const int fallback = (P.keep_best && L->have_best && !L->converging) ? 3 : ik;
+    if (!finite) {
+        L->status = HP_NONFINITE;
+        L->result_idx = fallback;
+        L->done = 1;
+        return;
+    }
+    double sval;
+    bool passed;
+    if (P.stop_rule == HP_STOP_ABS_INF) {
+        sval = dinf;
+        passed = dinf <= P.tol;
+    } else if (P.stop_rule == HP_STOP_PAPER_4_1) {
+        sval = sqrt(diff2) / (pow(P.order, (double)k) * P.alpha);
+        passed = sval < P.tol;
+    } else {
+        sval = d;
+        passed = d < P.tol;
+    }
+    L->stop_last = sval;
+    if (passed) {
+        L->status = HP_OK;
+        L->result_idx = in_;
+        L->done = 1;
+        return;
+    }
+    if (L->converging && k > 0 && d >= L->d_prev) {
+        L->status = HP_STAGNATED;
+        L->result_idx = ik;
+        L->done = 1;
+        return;
+    }
+    if (!L->converging && d > P.diverge) {
+        L->status = HP_DIVERGED;
+        L->result_idx = fallback;
+        L->done = 1;
+        return;
+    }
+    if (d < P.tau) {
+        L->converging = 1;
+        if (P.variant == HP_VARIANT_STABILISED && !L->stabilising) {
+            L->stabilising = 1;
+            L->switch_iter = k + 1;
+        }
+    }
+    if (P.keep_best && !L->converging && (!L->have_best || d < L->best_d)) {
+        L->best_d = d;
+        L->have_best = 1;
+        L->save_best = 1;
+    }
+    L->d_prev = d;
+    if (k + 1 >= P.max_iter) {
+        L->status = HP_MAXITER;
+        L->result_idx = in_;
+        L->done = 1;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy_gated(const double* __restrict__ X, int64_t ldx,
+                                                         int M, int N, double* __restrict__ Y,
+                                                         int64_t ldy, const int* gate, int mode) {
+    if (gate_closed(gate, mode)) return;
+    const int r = blockIdx.y;
+    for (int c = blockIdx.x * kThreads + threadIdx.x; c < N; c += gridDim.x * kThreads)
+        Y[(int64_t)r * ldy + c] = X[(int64_t)r * ldx + c];
+}
+
+}  // namespace
+
+hipError_t loop_init(DevLoop* L, int stab_always, hipStream_t s) {
+    hipLaunchKernelGGL(k_loop_init, dim3(1), dim3(64), 0, s, L, stab_always);
+    return hipGetLastError();
+}
+
+hipError_t reduce_pairs_gated(const double* partials, int nb_plain, int nb_stab, double* scal,
+                              const DevLoop* L, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_pairs_gated, dim3(1), dim3(kThreads), 0, s, partials, nb_plain,
+                       nb_stab, scal, L);
+    return hipGetLastError();
+}
+
+hipError_t diff_norm_inf_gated(const double* X1, int64_t ld1, const double* X0, int64_t ld0,
+                               int64_t M, int64_t N, double* tmp, double* scal, const DevLoop* L,
+                               hipStream_t s) {
+    return diff_norm_inf_t(X1, ld1, X0, ld0, M, N, tmp, scal, s,
+                           reinterpret_cast<const int*>(L));
+}
+
+hipError_t loop_step(const double* scal, DevLoop* L, const StepParams* P, hipStream_t s) {
+    hipLaunchKernelGGL(k_loop_step, dim3(1), dim3(64), 0, s, scal, L, P);
+    return hipGetLastError();
+}
+
+hipError_t copy_gated(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                      int64_t cols, const DevLoop* L, int mode, hipStream_t s) {
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(cols, kThreads), 64);
+    hipLaunchKernelGGL(k_copy_gated, dim3(gx, (unsigned)rows), dim3(kThreads), 0, s, src, lds,
+                       (int)rows, (int)cols, dst, ldd, reinterpret_cast<const int*>(L), mode);
     return hipGetLastError();
 }
 

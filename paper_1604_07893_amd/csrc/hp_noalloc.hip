@@ -60,9 +60,10 @@ extern "C" int hp_solve_noalloc(hp_handle* h, const hp_params* p, const double* 
         std::lock_guard<std::mutex> lock(g_mu);
         ws = g_scratch[h->device];
     }
-    // hp_solve allocates nothing: it clears the split-K counters with a fill
-    // kernel and writes every other scratch value before reading it, so the
-    // previous call's contents do not matter
-    return hp_solve(h, p, A, m, n, lda, X0, ldx0, X, ldx, ws, (size_t)HP_NOALLOC_SCRATCH_BYTES,
-                    stream, out);
+    // the solve allocates nothing (no graph capture: with device_stop its
+    // loops are launched one by one); it clears the split-K counters with a
+    // fill kernel and writes every other scratch value before reading it, so
+    // the previous call's contents do not matter
+    return hp::solve_entry(h, p, A, m, n, lda, X0, ldx0, X, ldx, ws,
+                           (size_t)HP_NOALLOC_SCRATCH_BYTES, stream, out, false);
 }

@@ -47,7 +47,7 @@ class HpParams(ctypes.Structure):
         ("alpha", c_double), ("tau_switch", c_double), ("tol", c_double), ("diverge_limit", c_double),
         ("max_iter", c_int32), ("stop_rule", c_int32), ("side", c_int32), ("precision", c_int32),
         ("flags", c_int32), ("low_dtype", c_int32), ("method", c_int32),
-        ("reserved0", c_int32), ("chop", c_double), ("reserved", c_int32 * 2),
+        ("device_stop", c_int32), ("chop", c_double), ("reserved", c_int32 * 2),
     ]
 
 
@@ -185,7 +185,7 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
                 tol=1e-12, max_iter=100, stop="rel_fro", side="auto", precision="fp64",
                 diverge_limit=1e6, time_kernels=False, inf_norm=False,
                 low_dtype="bf16", graph=True, method="pm", chop=0.0, retry=True,
-                symmetric=False, fp64_poly=False) -> HpParams:
+                symmetric=False, fp64_poly=False, device_stop=False) -> HpParams:
     p = HpParams()
     load_library().hp_params_default(ctypes.byref(p))
     p.kind = KIND[kind]
@@ -205,6 +205,7 @@ def make_params(*, kind="mp", l=0, alpha_rule=None, alpha=0.0, variant="plain", 
     p.diverge_limit = float(diverge_limit)
     p.method = METHOD[method]
     p.chop = float(chop)
+    p.device_stop = 1 if device_stop else 0
     p.flags = ((FLAG_TIME_KERNELS if time_kernels else 0) | (FLAG_INF_NORM if inf_norm else 0)
                | (0 if graph else FLAG_NO_GRAPH) | (0 if retry else FLAG_NO_RETRY)
                | (FLAG_SYMMETRIC if symmetric else 0) | (FLAG_FP64_POLY if fp64_poly else 0))

@@ -80,6 +80,10 @@ EINVAL, EUNSUPPORTED = -1, -5
     (dict(kind="drazin", l=2, precision="delta32"), 10, 10, EUNSUPPORTED),
     (dict(method="fm", precision="delta32"), 10, 10, EUNSUPPORTED),
     (dict(chop=1e-5, precision="delta32"), 10, 10, EUNSUPPORTED),
+    (dict(device_stop=True, precision="fp32"), 10, 10, EUNSUPPORTED),
+    (dict(device_stop=True, stop="rel_fro_bound"), 10, 10, EUNSUPPORTED),
+    (dict(device_stop=True, symmetric=True), 10, 10, EUNSUPPORTED),
+    (dict(device_stop=True, chop=1e-5), 10, 10, EUNSUPPORTED),
     (dict(kind="drazin", l=2, alpha_rule="norm1inf"), 10, 10, EINVAL),
     (dict(tol=-1.0), 10, 10, EINVAL),
     (dict(max_iter=0), 10, 10, EINVAL),
@@ -97,11 +101,10 @@ def test_parameter_validation_on_the_host(kw, m, n, code):
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
 def test_reserved_fields_must_be_zero():
     from paper_1604_07893_amd import hyperpower as hpw
-    for field in ("reserved0",):
-        p = hpw.make_params()
-        setattr(p, field, 1)
-        with pytest.raises(hpw.HyperpowerError):
-            hpw.workspace_bytes(p, 10, 10)
+    p = hpw.make_params()
+    p.device_stop = 2  # a flag: 0 or 1
+    with pytest.raises(hpw.HyperpowerError):
+        hpw.workspace_bytes(p, 10, 10)
     p = hpw.make_params()
     p.reserved[1] = 7
     with pytest.raises(hpw.HyperpowerError):
