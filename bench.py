@@ -448,6 +448,34 @@ def extra_served(hpw, torch, n_req: int, warm: int):
                                               else 0.0)
         return pinv_cache[i]
 
+    pct = lambda v, q: float(np.percentile(v, q))
+
+    def offered(frac, sat):
+        qps = frac * sat
+        rng = np.random.default_rng(1005)
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(mats))).tolist()
+        wall, lat, res = run(arrivals)
+        lat_ms = np.array([l for i, l in sorted(lat) if i >= warm]) * 1e3
+        return qps, wall, lat_ms, res
+
+    # the grouped tile: the default (64 x 64) first, then the one hp_autotune
+    # picks per precision on the stream's work-weighted median product
+    g64, g32 = hpw.GEMM_DTYPES["grouped_f64"], hpw.GEMM_DTYPES["grouped_f32"]
+    hpw.import_tuning([(g64, 0, 0, 0, 0), (g32, 0, 0, 0, 0)])
+    wall_b, _, _ = run([0.0] * len(mats))
+    sat_b = len(mats) / wall_b
+    _, _, lat_b, _ = offered(0.8, sat_b)
+    dims = sorted(((min(r.A.shape), max(r.A.shape)) for r in reqs),
+                  key=lambda d: d[0] * d[0] * d[1])
+    w = np.cumsum([d[0] * d[0] * d[1] for d in dims])
+    s_med, k_med = dims[int(np.searchsorted(w, w[-1] / 2))]
+    tuned = {}
+    for name in ("grouped_f64", "grouped_f32"):
+        (_, _, _, t, ms), = hpw.autotune([(s_med, s_med, k_med)], dtype=name, reps=5)
+        tuned[name] = {"tile": hpw.GROUPED_TILES[t], "us_per_product": ms * 1e3}
+    log(f"grouped tile before: saturation {sat_b:.0f}/s p99@80% {pct(lat_b, 99):.1f} ms; "
+        f"autotuned on {s_med}x{s_med}x{k_med}: {tuned}")
+
     # saturation: everything arrives at t = 0
     wall0, _, res0 = run([0.0] * len(mats))
     sat = len(mats) / wall0
@@ -491,13 +519,8 @@ def extra_served(hpw, torch, n_req: int, warm: int):
                                "6 spread over the trace), relative Frobenius error against "
                                "torch.linalg.pinv (SVD, FP64, on the GPU)"),
            "speedup_saturation_vs_plain_fp64": sat / seq_rate}
-    pct = lambda v, q: float(np.percentile(v, q))
     for frac in (0.5, 0.8, 0.95):
-        qps = frac * sat
-        rng = np.random.default_rng(1005)
-        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(mats))).tolist()
-        wall, lat, res = run(arrivals)
-        lat_ms = np.array([l for i, l in sorted(lat) if i >= warm]) * 1e3
+        qps, wall, lat_ms, res = offered(frac, sat)
         rd = dict(res)
         q_ms = np.array([rd[i]["queue_ms"] for i in sorted(rd) if i >= warm])
         r_ms = np.array([rd[i]["run_ms"] for i in sorted(rd) if i >= warm])
@@ -513,6 +536,15 @@ def extra_served(hpw, torch, n_req: int, warm: int):
         if frac == 0.8:
             out.update({k: rec[k] for k in ("offered_qps", "inverses_per_s", "p50_ms", "p99_ms",
                                             "ok_fraction")})
+    out["grouped_tile"] = {
+        "what": ("tile of the grouped launches: the default 64x64 (before) and the one "
+                 "hp_autotune picks per precision on the stream's work-weighted median "
+                 f"product {s_med}x{s_med}x{k_med} (after; the rest of this record)"),
+        "autotuned": tuned,
+        "before": {"tile": "64x64", "saturation_req_per_s": sat_b,
+                   "p99_ms_at_80pct": pct(lat_b, 99)},
+        "after": {"saturation_req_per_s": sat, "p99_ms_at_80pct": out.get("p99_ms")}}
+    hpw.import_tuning([(g64, 0, 0, 0, 0), (g32, 0, 0, 0, 0)])
     return out
 
 

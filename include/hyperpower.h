@@ -249,6 +249,12 @@ extern "C" {
                            (ldb >= K); v_mfma_f32_16x16x32_bf16, FP32 accumulate
                            and C (float). lda, ldb multiples of 8 elements */
 #define HP_DTYPE_F16 5  /* as HP_DTYPE_BF16 with fp16 operands */
+/* hp_autotune only: the tile of the persistent grouped launch of batched and
+   served solves, FP64 or FP32 (returned tile: 0 = 64 x 64, 1 = 128 x 128,
+   2 = 32 x 32 with a 4x deeper K-tile), timed on a table of copies of an
+   M x N x K product; groups created afterwards use the fastest */
+#define HP_DTYPE_GROUPED_F64 6
+#define HP_DTYPE_GROUPED_F32 7
 
 typedef struct hp_params {
     int32_t kind;          /* HP_KIND_* */
@@ -501,7 +507,11 @@ int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* 
                 size_t scratch_bytes, int reps, void* stream, int* tile, double* ms);
 
 /* The handle's table as rows of 5 int64 (dtype, M, N, K, tile): export
- * copies up to `cap` rows and reports the count; import adds rows. */
+ * copies up to `cap` rows and reports the count; import adds rows (all are
+ * checked first: HP_EINVAL and nothing added if one has an unknown dtype or
+ * a tile out of range). A grouped row (HP_DTYPE_GROUPED_*) also sets the
+ * grouped tile of its precision for groups created afterwards, whatever its
+ * sizes; the latest grouped row imported or autotuned wins. */
 int hp_tune_export(hp_handle* h, int64_t* rows, int cap, int* count);
 int hp_tune_import(hp_handle* h, const int64_t* rows, int count);
 
@@ -526,8 +536,9 @@ int hp_batched_workspace_bytes(const hp_params* p, int count, const hp_problem* 
 
 /* Solve `count` problems of uneven shapes with the same params. Every loop
  * runs each product of all unfinished problems in one persistent grouped MFMA
- * launch (64x64 tiles walked from a device-side table); each problem stops on
- * its own test. A problem's result is bitwise the same whatever else is in
+ * launch (tiles walked from a device-side table; 64x64 unless hp_autotune or
+ * hp_tune_import chose another grouped tile for the precision); each problem
+ * stops on its own test. A problem's result is bitwise the same whatever else is in
  * the batch. Precision HP_PREC_FP64, HP_PREC_FP32 or HP_PREC_FP32_FP64;
  * stop rules REL_FRO and PAPER_4_1. outs: `count` results (may be NULL).
  * Returns HP_OK if the call ran (see each outs[i].status), else an error. */
@@ -551,11 +562,15 @@ int hp_serve_submit(hp_server* sv, const hp_problem* prob, uint64_t* ticket);
  * (either pointer may be NULL). A request whose solve with lower-precision
  * loops ends with a status other than HP_OK is run again once, from its X0,
  * in FP64 only (in its own arena space; its result then reports that run),
- * unless HP_FLAG_NO_RETRY is set. A negative return (HP_EHIP) leaves the
- * server's requests in an undefined state: destroy it. */
+ * unless HP_FLAG_NO_RETRY is set. A request whose set-up on admission (or on
+ * that rerun) fails is finished with the error, which hp_serve_poll then
+ * returns; its slot and memory are freed. A negative return is the first
+ * error of the step (the rest of the step still ran); after HP_EHIP the
+ * device may be unusable: destroy the server. */
 int hp_serve_step(hp_server* sv, int* active, int* waiting);
 /* HP_PENDING while the request is queued or running; afterwards its final
- * status (out filled, ticket released). HP_EINVAL for an unknown ticket. */
+ * status, or the negative error that ended it (out filled, ticket released).
+ * HP_EINVAL for an unknown ticket. */
 int hp_serve_poll(hp_server* sv, uint64_t ticket, hp_result* out);
 int hp_serve_destroy(hp_server* sv);
 

@@ -94,34 +94,48 @@ struct Tables {
     }
 };
 
+// One captured loop: the launches of the non-empty (precision, slot) tables
+// named by `mask` (bit prec * kSlots + slot).
+struct LoopGraph {
+    uint32_t mask = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+};
+
 struct Group {
     hp_handle* h = nullptr;
     hp_params prm{};
     hipStream_t s = nullptr;
     Tables tb;
     int grid = 1024;  // persistent grid of the grouped launches
-    // One loop's device work -- table upload, the 2 x 9 grouped launches, the
-    // per-problem reduction and the download of the sums -- captured once as
-    // a hipGraph and replayed every loop (every launch has a fixed grid and
-    // reads its sizes from the uploaded tables). No memset nodes.
+    int tile_cfg[2] = {GTILE_64, GTILE_64};  // grouped tile per precision (FP64, FP32)
+    // One loop's device work -- table upload, a grouped launch per non-empty
+    // (precision, product slot) table, the per-problem reduction and the
+    // download of the sums -- captured as a hipGraph per set of non-empty
+    // tables and replayed (every launch has a fixed grid and reads its sizes
+    // from the uploaded tables). No memset nodes.
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;  // capture needs a stream other than the null stream
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    static constexpr int kGraphs = 6;  // cached sets; the least recently used goes first
+    LoopGraph graphs[kGraphs];
+    uint64_t clock = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;  // order the replay against stream s
 };
 
 // Enqueue one loop's device work on stream s (used eagerly or under capture).
-int enqueue_loop(Group& g, hipStream_t s) {
+int enqueue_loop(Group& g, uint32_t mask, hipStream_t s) {
     Tables& tb = g.tb;
     HIPCHK(hipMemcpyAsync(tb.dev, tb.host, tb.off_out, hipMemcpyHostToDevice, s));
     for (int j = 0; j < kSlots; ++j) {
-        HIPCHK(gemm_grouped(reinterpret_cast<const GroupHeader*>(tb.dev + tb.off_hdr[0][j]),
-                            reinterpret_cast<const GroupEntry<double>*>(tb.dev + tb.off_ent[0][j]),
-                            g.grid, s));
-        HIPCHK(gemm_grouped(reinterpret_cast<const GroupHeader*>(tb.dev + tb.off_hdr[1][j]),
-                            reinterpret_cast<const GroupEntry<float>*>(tb.dev + tb.off_ent[1][j]),
-                            g.grid, s));
+        if (mask >> j & 1u)
+            HIPCHK(gemm_grouped(reinterpret_cast<const GroupHeader*>(tb.dev + tb.off_hdr[0][j]),
+                                reinterpret_cast<const GroupEntry<double>*>(tb.dev + tb.off_ent[0][j]),
+                                g.grid, g.tile_cfg[0], s));
+        if (mask >> (kSlots + j) & 1u)
+            HIPCHK(gemm_grouped(reinterpret_cast<const GroupHeader*>(tb.dev + tb.off_hdr[1][j]),
+                                reinterpret_cast<const GroupEntry<float>*>(tb.dev + tb.off_ent[1][j]),
+                                g.grid, g.tile_cfg[1], s));
     }
     HIPCHK(reduce_pairs_grouped(reinterpret_cast<const int*>(tb.dev + tb.off_cnt),
                                 reinterpret_cast<const ReduceEntry*>(tb.dev + tb.off_red), tb.cap,
@@ -131,25 +145,49 @@ int enqueue_loop(Group& g, hipStream_t s) {
     return HP_OK;
 }
 
-int run_loop_device(Group& g) {
-    if (!g.use_graph) return enqueue_loop(g, g.s);
-    if (!g.exec) {
+void drop_graph(LoopGraph& lg) {
+    if (lg.exec) (void)hipGraphExecDestroy(lg.exec);
+    if (lg.graph) (void)hipGraphDestroy(lg.graph);
+    lg = LoopGraph{};
+}
+
+int run_loop_device(Group& g, uint32_t mask) {
+    if (!g.use_graph) return enqueue_loop(g, mask, g.s);
+    LoopGraph* lg = nullptr;
+    for (LoopGraph& c : g.graphs)
+        if (c.exec && c.mask == mask) lg = &c;
+    if (!lg) {
         if (!g.cap_stream) HIPCHK(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
-        HIPCHK(hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming));
+        if (!g.ev_in) HIPCHK(hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming));
+        if (!g.ev_out) HIPCHK(hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming));
+        lg = &g.graphs[0];
+        for (LoopGraph& c : g.graphs)
+            if (!c.exec || c.used < lg->used) lg = &c;
+        if (lg->exec) {
+            // a replay of the evicted graph may still be running
+            HIPCHK(hipStreamSynchronize(g.cap_stream));
+            drop_graph(*lg);
+        }
         HIPCHK(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
-        const int rc = enqueue_loop(g, g.cap_stream);
+        const int rc = enqueue_loop(g, mask, g.cap_stream);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(g.cap_stream, &graph);
-        if (rc != HP_OK) return rc;
-        if (e != hipSuccess) return HP_EHIP;
-        g.graph = graph;
-        HIPCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+        if (rc != HP_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc != HP_OK ? rc : HP_EHIP;
+        }
+        lg->graph = graph;
+        if (hipGraphInstantiate(&lg->exec, lg->graph, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(*lg);
+            return HP_EHIP;
+        }
+        lg->mask = mask;
     }
+    lg->used = ++g.clock;
     // the graph runs on the capture stream, ordered after the group stream's work
     HIPCHK(hipEventRecord(g.ev_in, g.s));
     HIPCHK(hipStreamWaitEvent(g.cap_stream, g.ev_in, 0));
-    HIPCHK(hipGraphLaunch(g.exec, g.cap_stream));
+    HIPCHK(hipGraphLaunch(lg->exec, g.cap_stream));
     HIPCHK(hipEventRecord(g.ev_out, g.cap_stream));
     HIPCHK(hipStreamWaitEvent(g.s, g.ev_out, 0));
     return HP_OK;
@@ -160,12 +198,17 @@ void group_release(Group& g) {
     if (g.ev_in) (void)hipEventDestroy(g.ev_in);
     if (g.ev_out) (void)hipEventDestroy(g.ev_out);
     g.ev_in = g.ev_out = nullptr;
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (g.graph) (void)hipGraphDestroy(g.graph);
+    for (LoopGraph& c : g.graphs) drop_graph(c);
     if (g.cap_stream) (void)hipStreamDestroy(g.cap_stream);
-    g.exec = nullptr;
-    g.graph = nullptr;
     g.cap_stream = nullptr;
+}
+
+void group_init(Group& g, hp_handle* h, const hp_params* p, void* stream) {
+    g.h = h;
+    g.prm = *p;
+    g.s = reinterpret_cast<hipStream_t>(stream);
+    g.use_graph = (p->flags & HP_FLAG_NO_GRAPH) == 0;
+    for (int i = 0; i < 2; ++i) g.tile_cfg[i] = h->grouped_cfg[i];
 }
 
 // Products outside the loop (Drazin set-up, projection) run as single
@@ -183,7 +226,7 @@ auto single_gemm(Group& g, Problem& P) {
     };
 }
 
-int admit(Group& g, Problem& P) {
+int admit_setup(Group& g, Problem& P) {
     P.bf = carve(P.pl, P.ws);
     std::memset(&P.res, 0, sizeof(P.res));
     P.res.switch_iter = -1;
@@ -197,15 +240,28 @@ int admit(Group& g, Problem& P) {
         HIPCHK(convert(P.bf.b64.A, P.bf.b64.ldA, P.pl.m, P.pl.n, P.bf.b32.A, P.bf.b32.ldA, g.s));
         HIPCHK(convert(P.bf.b64.X[0], P.bf.b64.ldX, P.pl.n, P.pl.m, P.bf.b32.X[0], P.bf.b32.ldX, g.s));
     }
+    return HP_OK;
+}
+
+// Set a problem up from its X0. On failure it is finished with that error
+// (so neither a loop nor a poll sees a half-initialised state).
+int admit(Group& g, Problem& P) {
+    const int rc = admit_setup(g, P);
+    if (rc != HP_OK) {
+        P.res.status = rc;
+        P.finished = true;
+        return rc;
+    }
     P.finished = false;
     return HP_OK;
 }
 
 template <typename T>
-void append(Tables& tb, int prec, int slot, const GemmCall<T>& c, int* tiles_out) {
+void append(Tables& tb, int prec, int slot, int cfg, const GemmCall<T>& c, int* tiles_out) {
     GroupHeader* hdr = reinterpret_cast<GroupHeader*>(tb.host + tb.off_hdr[prec][slot]);
     GroupEntry<T>* ents = reinterpret_cast<GroupEntry<T>*>(tb.host + tb.off_ent[prec][slot]);
-    const int tn = (int)cdiv(c.N, grouped_tile_n()), tm = (int)cdiv(c.M, grouped_tile_m());
+    const int dim = grouped_tile_dim(cfg);
+    const int tn = (int)cdiv(c.N, dim), tm = (int)cdiv(c.M, dim);
     GroupEntry<T>& e = ents[hdr->count];
     e.M = (int)c.M;
     e.N = (int)c.N;
@@ -249,6 +305,7 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
     const int np = (int)act.size();
     *reinterpret_cast<int*>(tb.host + tb.off_cnt) = np;
     ReduceEntry* red = reinterpret_cast<ReduceEntry*>(tb.host + tb.off_red);
+    uint32_t mask = 0;  // the non-empty (precision, slot) tables
     for (int i = 0; i < np; ++i) {
         Problem& P = *act[i];
         LoopState& st = P.st;
@@ -258,9 +315,11 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
             const int nc = describe_loop<double>(HP_METHOD_PM, P.pl, P.bf.b64, P.bf.b64.X[st.ik],
                                                     P.bf.b64.X[st.in_], P.bf.b64.X[2],
                                                     st.stabilising, P.bf.small, calls);
+            if (nc > kSlots) return HP_EUNSUPPORTED;
             for (int j = 0; j < nc; ++j) {
                 if (!calls[j].A || !calls[j].B || !calls[j].ep.out[0]) return HP_EINVAL;
-                append(tb, 0, j, calls[j], &tiles);
+                append(tb, 0, j, g.tile_cfg[0], calls[j], &tiles);
+                mask |= 1u << j;
                 const double gf = 2.0 * (double)calls[j].M * calls[j].N * calls[j].K * 1e-9;
                 P.res.gflop += gf;
                 P.res.gflop_stage[2] += gf;
@@ -272,9 +331,11 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
             const int nc = describe_loop<float>(HP_METHOD_PM, P.pl, P.bf.b32, P.bf.b32.X[st.ik],
                                                    P.bf.b32.X[st.in_], P.bf.b32.X[2],
                                                    st.stabilising, P.bf.small, calls);
+            if (nc > kSlots) return HP_EUNSUPPORTED;
             for (int j = 0; j < nc; ++j) {
                 if (!calls[j].A || !calls[j].B || !calls[j].ep.out[0]) return HP_EINVAL;
-                append(tb, 1, j, calls[j], &tiles);
+                append(tb, 1, j, g.tile_cfg[1], calls[j], &tiles);
+                mask |= 1u << (kSlots + j);
                 const double gf = 2.0 * (double)calls[j].M * calls[j].N * calls[j].K * 1e-9;
                 P.res.gflop += gf;
                 P.res.gflop_stage[st.stage] += gf;
@@ -284,7 +345,7 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
         P.last_tiles = tiles;
         red[i] = ReduceEntry{P.bf.small, tiles, 0};
     }
-    CHK(run_loop_device(g));
+    CHK(run_loop_device(g, mask));
     HIPCHK(hipStreamSynchronize(g.s));
     const double* hout = reinterpret_cast<const double*>(tb.host + tb.off_out);
 
@@ -396,10 +457,7 @@ int hp_solve_batched(hp_handle* h, const hp_params* p, int count, const hp_probl
     if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
 
     Group g;
-    g.h = h;
-    g.prm = *p;
-    g.s = reinterpret_cast<hipStream_t>(stream);
-    g.use_graph = (p->flags & HP_FLAG_NO_GRAPH) == 0;
+    group_init(g, h, p, stream);
     char* ws = static_cast<char*>(workspace);
     // the tables live at the start of the workspace; staging is pinned host memory
     g.tb.cap = count;
@@ -446,10 +504,7 @@ int hp_serve_create(hp_handle* h, const hp_params* p, size_t hbm_budget, int max
     CHK(validate(p, 1, 1));
     if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
     hp_server* sv = new hp_server();
-    sv->g.h = h;
-    sv->g.prm = *p;
-    sv->g.s = reinterpret_cast<hipStream_t>(stream);
-    sv->g.use_graph = (p->flags & HP_FLAG_NO_GRAPH) == 0;
+    group_init(sv->g, h, p, stream);
     sv->budget = hbm_budget / kAlign * kAlign;
     sv->adm = Admission(sv->budget, max_slots);
     if (hipMalloc(reinterpret_cast<void**>(&sv->arena), sv->budget) != hipSuccess) {
@@ -487,46 +542,59 @@ int hp_serve_step(hp_server* sv, int* active, int* waiting) {
     if (!sv) return HP_EINVAL;
     Range range("hp_serve_step");
     if (hipSetDevice(sv->g.h->device) != hipSuccess) return HP_EHIP;
-    // admit in arrival order while a slot and memory are free
-    CHK(sv->adm.admit([&](uint64_t t, size_t off) {
-        Problem& P = sv->reqs[t];
-        P.ws_off = off;
-        P.ws = sv->arena + off;
-        P.t_admit = Clock::now();
-        return admit(sv->g, P);
-    }));
-    const std::vector<uint64_t> act_t = sv->adm.active();
-    if (!act_t.empty()) {
-        std::vector<Problem*> act;
-        for (uint64_t t : act_t) act.push_back(&sv->reqs[t]);
-        CHK(group_loop(sv->g, act));
-        for (uint64_t t : act_t) {
-            Problem& P = sv->reqs[t];
-            if (P.finished && P.res.status != HP_OK && !P.retried &&
-                P.prm.precision != HP_PREC_FP64 && !(sv->g.prm.flags & HP_FLAG_NO_RETRY)) {
-                // the lower precisions failed: once more from X0, FP64 only,
-                // in the same arena space (the FP64 plan needs less of it)
-                Problem& Q = P;
-                Q.retried = true;
-                Q.prm.precision = HP_PREC_FP64;
-                Q.pl = make_plan(&Q.prm, Q.pr.m, Q.pr.n, false);
-                if (align_up(Q.pl.total) <= Q.ws_bytes) {
-                    CHK(admit(sv->g, Q));
-                    continue;
-                }
-            }
-            if (P.finished) {
-                P.res.queue_ms = ms_between(P.t_submit, P.t_admit);
-                P.res.run_ms = ms_between(P.t_admit, P.t_finish);
-                P.res.time_ms = ms_between(P.t_submit, P.t_finish);
-                sv->adm.finish(t);
-                P.ws = nullptr;
-            }
+    // the GPU side of serve_step (hp_sched.h, which holds the bookkeeping)
+    struct Exec {
+        hp_server* sv;
+        Problem& req(uint64_t t) { return sv->reqs[t]; }
+        int enter(uint64_t t, size_t off) {
+            Problem& P = req(t);
+            P.ws_off = off;
+            P.ws = sv->arena + off;
+            P.t_admit = Clock::now();
+            return admit(sv->g, P);
         }
-    }
+        int run(const std::vector<uint64_t>& ts) {
+            std::vector<Problem*> act;
+            for (uint64_t t : ts) act.push_back(&req(t));
+            return group_loop(sv->g, act);
+        }
+        bool finished(uint64_t t) { return req(t).finished; }
+        // the lower precisions failed: once more from X0, FP64 only, in the
+        // same arena space (the FP64 plan needs less of it)
+        bool wants_retry(uint64_t t) {
+            Problem& P = req(t);
+            if (P.res.status == HP_OK || P.retried || P.prm.precision == HP_PREC_FP64 ||
+                (sv->g.prm.flags & HP_FLAG_NO_RETRY))
+                return false;
+            hp_params q = P.prm;
+            q.precision = HP_PREC_FP64;
+            return align_up(make_plan(&q, P.pr.m, P.pr.n, false).total) <= P.ws_bytes;
+        }
+        int reenter(uint64_t t) {
+            Problem& P = req(t);
+            P.retried = true;
+            P.prm.precision = HP_PREC_FP64;
+            P.pl = make_plan(&P.prm, P.pr.m, P.pr.n, false);
+            return admit(sv->g, P);
+        }
+        void fail(uint64_t t, int rc) {
+            Problem& P = req(t);
+            P.res.status = rc;
+            P.finished = true;
+            P.t_finish = Clock::now();
+        }
+        void settle(uint64_t t) {
+            Problem& P = req(t);
+            P.res.queue_ms = ms_between(P.t_submit, P.t_admit);
+            P.res.run_ms = ms_between(P.t_admit, P.t_finish);
+            P.res.time_ms = ms_between(P.t_submit, P.t_finish);
+            P.ws = nullptr;
+        }
+    } ex{sv};
+    const int rc = serve_step(sv->adm, ex);
     if (active) *active = (int)sv->adm.active_count();
     if (waiting) *waiting = (int)sv->adm.waiting();
-    return HP_OK;
+    return rc;
 }
 
 int hp_serve_poll(hp_server* sv, uint64_t ticket, hp_result* out) {

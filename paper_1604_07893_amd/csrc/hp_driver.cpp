@@ -1397,18 +1397,41 @@ int hp_residuals(hp_handle* h, int kind, int l, const double* A, int64_t m, int6
 }
 
 // Scratch of hp_autotune: operands and result, then split-K scratch for 4
-// partial tiles per output tile and as many counters.
+// partial tiles per output tile and as many counters. The grouped kinds hold
+// A, B and `entries` results instead, then the launch table.
 struct TuneLayout {
-    int64_t lda, ldb, ldc, slots;
+    int64_t lda, ldb, ldc, slots, entries;
     size_t ops, part, total;
 };
+static bool grouped_dtype(int dtype) {
+    return dtype == HP_DTYPE_GROUPED_F64 || dtype == HP_DTYPE_GROUPED_F32;
+}
 static size_t operand_bytes(int dtype) {
-    return dtype == HP_DTYPE_F64 ? 8 : (dtype == HP_DTYPE_BF16 || dtype == HP_DTYPE_F16) ? 2 : 4;
+    return (dtype == HP_DTYPE_F64 || dtype == HP_DTYPE_GROUPED_F64) ? 8
+           : (dtype == HP_DTYPE_BF16 || dtype == HP_DTYPE_F16)      ? 2
+                                                                     : 4;
 }
 
 static int tune_layout(int dtype, int64_t M, int64_t N, int64_t K, TuneLayout* L) {
-    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_F16) return HP_EINVAL;
+    if (dtype < HP_DTYPE_F64 || dtype > HP_DTYPE_GROUPED_F32) return HP_EINVAL;
     if (M < 1 || N < 1 || K < 1 || M > 65535 || N > 65535 || K > 65535) return HP_EINVAL;
+    if (grouped_dtype(dtype)) {
+        // as many copies of the product as fill about 4 Mi outputs (1 to 64),
+        // so that a table of small products is timed as the loop sees it
+        const size_t esz = operand_bytes(dtype);
+        const int64_t vec = 16 / (int64_t)esz;
+        L->lda = (K + vec - 1) / vec * vec;
+        L->ldb = L->ldc = (N + vec - 1) / vec * vec;
+        L->slots = 0;
+        L->entries = std::min<int64_t>(64, std::max<int64_t>(1, (int64_t(4) << 20) / (M * N)));
+        L->ops = hp::align_up(esz * (size_t)(M * L->lda + K * L->ldb + L->entries * M * L->ldc));
+        const size_t ent = dtype == HP_DTYPE_GROUPED_F64 ? sizeof(hp::GroupEntry<double>)
+                                                         : sizeof(hp::GroupEntry<float>);
+        L->part = hp::align_up(sizeof(hp::GroupHeader)) + ent * (size_t)L->entries;
+        L->total = L->ops + L->part;
+        return HP_OK;
+    }
+    L->entries = 0;
     const size_t esz = operand_bytes(dtype) == 2 ? 4 : operand_bytes(dtype);  // C is float
     const int64_t vec = 16 / (int64_t)operand_bytes(dtype);
     const bool h16 = operand_bytes(dtype) == 2;  // B held as B^T (N x K)
@@ -1430,11 +1453,97 @@ int hp_autotune_scratch_bytes(int dtype, int64_t M, int64_t N, int64_t K, size_t
     return HP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// hp_autotune of the grouped launch: every grouped tile on a table of
+// L.entries copies of the product (shared operands, distinct results).
+template <typename T>
+int autotune_grouped(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, const TuneLayout& L,
+                     char* base, int reps, hipStream_t s, int* tile, double* ms) {
+    T* A = reinterpret_cast<T*>(base);
+    T* B = A + M * L.lda;
+    T* C = B + K * L.ldb;
+    char* tab = base + L.ops;
+    auto* hdr_d = reinterpret_cast<hp::GroupHeader*>(tab);
+    auto* ents_d = reinterpret_cast<hp::GroupEntry<T>*>(tab + hp::align_up(sizeof(hp::GroupHeader)));
+    HIPCHK(hipMemsetAsync(A, 0, sizeof(T) * (size_t)(M * L.lda), s));
+    HIPCHK(hipMemsetAsync(B, 0, sizeof(T) * (size_t)(K * L.ldb), s));
+    std::vector<hp::GroupEntry<T>> ents((size_t)L.entries);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = -1;
+    double best_ms = 0.0;
+    for (int cfg = 0; cfg < hp::GTILE_COUNT; ++cfg) {
+        const int dim = hp::grouped_tile_dim(cfg);
+        const int tm = (int)((M + dim - 1) / dim), tn = (int)((N + dim - 1) / dim);
+        hp::GroupHeader hdr{(int)L.entries, (int)L.entries * tm * tn};
+        for (int64_t e = 0; e < L.entries; ++e) {
+            hp::GroupEntry<T>& g = ents[(size_t)e];
+            g = hp::GroupEntry<T>{};
+            g.M = (int)M;
+            g.N = (int)N;
+            g.K = (int)K;
+            g.tiles_n = tn;
+            g.tile_start = (int)e * tm * tn;
+            g.A = A;
+            g.lda = L.lda;
+            g.B = B;
+            g.ldb = L.ldb;
+            g.ep = hp::epilogue_plain(C + e * M * L.ldc, L.ldc);
+        }
+        // ordered after the previous configuration's launches on s
+        if (hipMemcpyAsync(hdr_d, &hdr, sizeof(hdr), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(ents_d, ents.data(), sizeof(hp::GroupEntry<T>) * ents.size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            break;
+        auto launch = [&]() { return hp::gemm_grouped(hdr_d, ents_d, 1024, cfg, s); };
+        if (launch() != hipSuccess) continue;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) (void)launch();
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float el = 0.f;
+        (void)hipEventElapsedTime(&el, e0, e1);
+        const double avg = el / reps / (double)L.entries;  // per product
+        if (best < 0 || avg < best_ms) {
+            best = cfg;
+            best_ms = avg;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best < 0) return HP_EHIP;
+    h->tuned[{dtype, M, N, K}] = best;
+    h->grouped_cfg[dtype - HP_DTYPE_GROUPED_F64] = best;
+    ++h->tune_gen;
+    *tile = best;
+    *ms = best_ms;
+    return HP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int hp_autotune(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, void* scratch,
                 size_t scratch_bytes, int reps, void* stream, int* tile, double* ms) {
     if (!h || !scratch || !tile || !ms || reps < 1) return HP_EINVAL;
     TuneLayout L;
     CHK(tune_layout(dtype, M, N, K, &L));
+    if (grouped_dtype(dtype)) {
+        if (scratch_bytes < L.total) return HP_EWORKSPACE;
+        if (reinterpret_cast<uintptr_t>(scratch) % 16) return HP_EINVAL;
+        if (hipSetDevice(h->device) != hipSuccess) return HP_EHIP;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        char* base = static_cast<char*>(scratch);
+        return dtype == HP_DTYPE_GROUPED_F64
+                   ? autotune_grouped<double>(h, dtype, M, N, K, L, base, reps, s, tile, ms)
+                   : autotune_grouped<float>(h, dtype, M, N, K, L, base, reps, s, tile, ms);
+    }
     const size_t esz = dtype == HP_DTYPE_F64 ? 8 : 4;  // 16-bit operands get 4-byte room
     const bool h16 = dtype == HP_DTYPE_BF16 || dtype == HP_DTYPE_F16;
     const int64_t lda = L.lda, ldb = L.ldb, ldc = L.ldc, slots = L.slots;
@@ -1530,9 +1639,14 @@ int hp_tune_import(hp_handle* h, const int64_t* rows, int count) {
     if (!h || count < 0 || (count > 0 && !rows)) return HP_EINVAL;
     for (int i = 0; i < count; ++i) {
         const int64_t* r = rows + 5 * i;
-        if (r[0] < HP_DTYPE_F64 || r[0] > HP_DTYPE_F16 || r[4] < 0 || r[4] >= hp::TILE_COUNT)
+        if (r[0] < HP_DTYPE_F64 || r[0] > HP_DTYPE_GROUPED_F32 || r[4] < 0 ||
+            r[4] >= (grouped_dtype((int)r[0]) ? hp::GTILE_COUNT : hp::TILE_COUNT))
             return HP_EINVAL;
+    }
+    for (int i = 0; i < count; ++i) {
+        const int64_t* r = rows + 5 * i;
         h->tuned[{r[0], r[1], r[2], r[3]}] = (int)r[4];
+        if (grouped_dtype((int)r[0])) h->grouped_cfg[r[0] - HP_DTYPE_GROUPED_F64] = (int)r[4];
     }
     ++h->tune_gen;
     return HP_OK;

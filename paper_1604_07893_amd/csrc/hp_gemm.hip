@@ -903,21 +903,32 @@ hipError_t dispatch_lp(GemmTile t, int64_t M, int64_t N, int64_t K, const float*
 
 }  // namespace
 
-int grouped_tile_m() { return 64; }
-int grouped_tile_n() { return 64; }
+int grouped_tile_dim(int cfg) { return cfg == GTILE_128 ? 128 : cfg == GTILE_32 ? 32 : 64; }
 
-hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<double>* ents, int grid,
-                        hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_grouped<double, 64, 64, 16, 32, 32>), dim3(grid), dim3(256), 0, s,
-                       hdr, ents);
+template <typename T>
+static hipError_t launch_grouped(const GroupHeader* hdr, const GroupEntry<T>* ents, int grid,
+                                 int cfg, hipStream_t s) {
+    constexpr int BKF = 16 * sizeof(double) / sizeof(T);  // 128-byte K-tile rows
+    if (cfg == GTILE_128)
+        hipLaunchKernelGGL((k_gemm_grouped<T, 128, 128, BKF, 64, 64>), dim3(grid), dim3(256), 0, s,
+                           hdr, ents);
+    else if (cfg == GTILE_32)
+        hipLaunchKernelGGL((k_gemm_grouped<T, 32, 32, 4 * BKF, 16, 16>), dim3(grid), dim3(256), 0,
+                           s, hdr, ents);
+    else
+        hipLaunchKernelGGL((k_gemm_grouped<T, 64, 64, BKF, 32, 32>), dim3(grid), dim3(256), 0, s,
+                           hdr, ents);
     return hipGetLastError();
 }
 
-hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<float>* ents, int grid,
+hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<double>* ents, int grid, int cfg,
                         hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_grouped<float, 64, 64, 32, 32, 32>), dim3(grid), dim3(256), 0, s,
-                       hdr, ents);
-    return hipGetLastError();
+    return launch_grouped(hdr, ents, grid, cfg, s);
+}
+
+hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<float>* ents, int grid, int cfg,
+                        hipStream_t s) {
+    return launch_grouped(hdr, ents, grid, cfg, s);
 }
 
 hipError_t gemm_lowp(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, const float* A,

@@ -27,6 +27,9 @@ struct hp_handle {
     // autotuned tiles: (dtype, M, N, K) -> tile index
     std::map<std::array<int64_t, 4>, int> tuned;
     int tune_gen = 0;             // bumped whenever `tuned` changes
+    // grouped-launch tile (GroupedTile) per precision (FP64, FP32) for groups
+    // created from now on: the latest autotuned or imported choice
+    int grouped_cfg[2] = {0, 0};
     // pinned: hp::SLOT_COUNT doubles, then kHostExtra doubles of staging
     // (device_stop: the step parameters, and the head of the DevLoop state,
     // which is read back over the slots)

@@ -192,7 +192,8 @@ hipError_t gemm(GemmTile t, int64_t M, int64_t N, int64_t K, const float* A, int
                 const float* B, int64_t ldb, const EpilogueT<float>& ep, hipStream_t s);
 
 // Grouped products: one persistent launch computes every entry of a device
-// table. Tiles are grouped_tile_m() x grouped_tile_n(); entry e covers tiles
+// table. Tiles are square, grouped_tile_dim(cfg) on a side, for the grouped
+// tile configuration cfg (GroupedTile); entry e covers tiles
 // [tile_start, tile_start + tiles_m * tiles_n) and writes its partial sums
 // (if ep.ref) to ep.partials[2*local_tile ...].
 struct GroupHeader {
@@ -209,11 +210,14 @@ struct GroupEntry {
     int64_t ldb;
     EpilogueT<T> ep;
 };
-int grouped_tile_m();
-int grouped_tile_n();
-hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<double>* ents, int grid,
+// Tile configurations of the grouped kernel (each a tile shape of the
+// single-launch kernel, 4 waves): 64 x 64 (the default), 128 x 128, and 32 x 32
+// with a K-tile four times as deep (small products).
+enum GroupedTile : int { GTILE_64 = 0, GTILE_128 = 1, GTILE_32 = 2, GTILE_COUNT = 3 };
+int grouped_tile_dim(int cfg);
+hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<double>* ents, int grid, int cfg,
                         hipStream_t s);
-hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<float>* ents, int grid,
+hipError_t gemm_grouped(const GroupHeader* hdr, const GroupEntry<float>* ents, int grid, int cfg,
                         hipStream_t s);
 
 // 16-bit MFMA product of FP32 matrices (operands rounded to nearest even while

@@ -65,8 +65,9 @@ public:
     void submit(uint64_t ticket, size_t bytes) { waiting_.push_back({ticket, bytes, 0}); }
     // Admits waiting requests in arrival order while a slot is free and the
     // first waiting one fits; enter(ticket, offset) places each admitted
-    // request (a nonzero return stops admission and is returned, the request
-    // staying admitted). Returns 0 otherwise.
+    // request. A nonzero return from enter takes that request back out (its
+    // slot and range are free again; it does not return to the queue),
+    // stops admission and is returned. Returns 0 otherwise.
     template <class Enter>
     int admit(Enter&& enter) {
         while (!waiting_.empty() && (int)active_.size() < slots_) {
@@ -75,7 +76,10 @@ public:
             waiting_.pop_front();
             active_.push_back(e);
             const int rc = enter(e.ticket, e.off);
-            if (rc != 0) return rc;
+            if (rc != 0) {
+                finish(e.ticket);
+                return rc;
+            }
         }
         return 0;
     }
@@ -108,5 +112,51 @@ private:
     std::deque<Entry> waiting_;
     std::vector<Entry> active_;
 };
+
+// One scheduling step of the server: admission, one loop of every active
+// request, then the bookkeeping of the requests that finished in it. Kept
+// apart from the GPU work (the executor) so that its error paths can be
+// checked on the CPU. Exec provides:
+//   int  enter(t, offset)  set up an admitted request in its arena range;
+//                          on failure it is out of the active set again
+//   int  run(active)       one loop of every active request (marks those
+//                          that finish; may fail after marking some)
+//   bool finished(t)
+//   bool wants_retry(t)    finished, failed, and may run again from its
+//                          start in its own range (once)
+//   int  reenter(t)        set that run up
+//   void fail(t, rc)       finish a request with error rc
+//   void settle(t)         record a finished request's times
+// A request whose set-up or rerun set-up fails is finished with that error
+// (its slot and range freed); every request that finished is settled and
+// its space freed even when the loop failed. Returns the first error (the
+// step's other work still done), else 0.
+template <class Exec>
+int serve_step(Admission& adm, Exec& ex) {
+    uint64_t failed = 0;
+    int rc = adm.admit([&](uint64_t t, size_t off) {
+        const int r = ex.enter(t, off);
+        if (r != 0) failed = t;
+        return r;
+    });
+    if (rc != 0) ex.fail(failed, rc);
+    const std::vector<uint64_t> act = adm.active();
+    if (act.empty()) return rc;
+    const int rl = ex.run(act);
+    if (rc == 0) rc = rl;
+    for (uint64_t t : act) {
+        if (ex.finished(t) && ex.wants_retry(t)) {
+            const int r = ex.reenter(t);
+            if (r == 0) continue;  // runs again from its start
+            ex.fail(t, r);
+            if (rc == 0) rc = r;
+        }
+        if (ex.finished(t)) {
+            ex.settle(t);
+            adm.finish(t);
+        }
+    }
+    return rc;
+}
 
 }  // namespace hp

@@ -572,12 +572,17 @@ class Server:
             pass
 
 
-GEMM_DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16s": 4, "f16s": 5}
+GEMM_DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16s": 4, "f16s": 5,
+               "grouped_f64": 6, "grouped_f32": 7}
+GROUPED_TILES = {0: "64x64", 1: "128x128", 2: "32x32 (4x deeper K-tile)"}
 
 
 def autotune(shapes, dtype: str = "f64", reps: int = 3, device: int | None = None) -> list:
     """Time every tile configuration on each (M, N, K) and keep the fastest in
-    the device's handle; returns [(M, N, K, tile, ms)]."""
+    the device's handle; returns [(M, N, K, tile, ms)]. With "grouped_f64" or
+    "grouped_f32" the grouped launch of batched and served solves is timed on
+    a table of copies of the product (ms per product) and groups created
+    afterwards use the chosen tile (GROUPED_TILES)."""
     dev = torch.cuda.current_device() if device is None else device
     h = handle(dev)
     code = GEMM_DTYPES[dtype]
@@ -618,9 +623,17 @@ def save_tuning(path: str, device: int | None = None):
 
 def load_tuning(path: str, device: int | None = None):
     import json
+    with open(path) as f:
+        import_tuning(json.load(f)["rows"], device)
+
+
+def import_tuning(rows, device: int | None = None):
+    """Add (dtype_code, M, N, K, tile) rows to the handle's table
+    (hp_tune_import); a grouped row also sets the grouped tile of its
+    precision for groups created afterwards."""
     dev = torch.cuda.current_device() if device is None else device
-    rows = json.load(open(path))["rows"]
-    flat = (c_int64 * (5 * max(len(rows), 1)))(*[int(x) for r in rows for x in r])
+    rows = [tuple(int(x) for x in r) for r in rows]
+    flat = (c_int64 * (5 * max(len(rows), 1)))(*[x for r in rows for x in r])
     rc = load_library().hp_tune_import(handle(dev).ptr, flat, len(rows))
     if rc != HP_OK:
         raise HyperpowerError(rc, "hp_tune_import")

@@ -66,10 +66,115 @@ static void arrival_order_and_slots() {
     adm.finish(5);
     adm.finish(6);
     CHECK(adm.active_count() == 0 && adm.arena().free_ranges().size() == 1);
-    // a failing placement is reported and stops admission
+    // a failing placement is reported, stops admission and is taken back out
+    // (its slot and range free again)
     adm.submit(7, 10);
     adm.submit(8, 10);
     CHECK(adm.admit([](uint64_t, size_t) { return -4; }) == -4 && adm.waiting() == 1);
+    CHECK(adm.active_count() == 0 && adm.arena().free_ranges().size() == 1 &&
+          adm.arena().free_ranges().begin()->second == 1000);
+}
+
+// hp::serve_step's error paths with a fake executor: a request whose set-up
+// fails, one whose rerun set-up fails, a loop that fails after finishing some
+// requests, and a successful rerun.
+struct FakeReq {
+    int loops = 1, done = 0, status = 0;
+    bool finished = false, retried = false, settled = false;
+    bool fail_enter = false, fail_reenter = false, fails_first_run = false;
+};
+struct FakeExec {
+    std::map<uint64_t, FakeReq>& reqs;
+    int loop_error = 0;  // returned by run() after its bookkeeping
+    int enter(uint64_t t, size_t) {
+        FakeReq& r = reqs[t];
+        if (r.fail_enter) {
+            r.status = -4;
+            r.finished = true;
+            return -4;
+        }
+        r.finished = false;
+        return 0;
+    }
+    int run(const std::vector<uint64_t>& act) {
+        for (uint64_t t : act) {
+            FakeReq& r = reqs[t];
+            CHECK(!r.finished);  // no loop on a finished or half-set-up request
+            if (++r.done >= r.loops) {
+                r.finished = true;
+                r.status = (r.fails_first_run && !r.retried) ? 2 : 0;
+            }
+        }
+        return loop_error;
+    }
+    bool finished(uint64_t t) { return reqs[t].finished; }
+    bool wants_retry(uint64_t t) { return reqs[t].status > 0 && !reqs[t].retried; }
+    int reenter(uint64_t t) {
+        FakeReq& r = reqs[t];
+        r.retried = true;
+        r.done = 0;
+        if (r.fail_reenter) {
+            r.status = -4;
+            r.finished = true;
+            return -4;
+        }
+        r.status = 0;
+        r.finished = false;
+        return 0;
+    }
+    void fail(uint64_t t, int rc) {
+        reqs[t].status = rc;
+        reqs[t].finished = true;
+    }
+    void settle(uint64_t t) { reqs[t].settled = true; }
+};
+
+static void serve_step_error_paths() {
+    std::map<uint64_t, FakeReq> reqs;
+    hp::Admission adm(1000, 4);
+    FakeExec ex{reqs};
+    reqs[1].loops = 2;
+    reqs[2].fail_enter = true;
+    reqs[3].loops = 1;
+    for (uint64_t t = 1; t <= 3; ++t) adm.submit(t, 300);
+    // step 1: 2's set-up fails: it ends with the error, out of the active set,
+    // its range free; admission stopped there (3 waits); 1 runs a loop
+    CHECK(hp::serve_step(adm, ex) == -4);
+    CHECK(reqs[2].finished && reqs[2].status == -4 && !reqs[2].settled);
+    CHECK(adm.active_count() == 1 && adm.waiting() == 1);
+    // step 2: 3 is admitted into 2's range; 1 and 3 finish
+    CHECK(hp::serve_step(adm, ex) == 0);
+    CHECK(reqs[1].settled && reqs[3].settled && reqs[1].status == 0 && reqs[3].status == 0);
+    CHECK(adm.active_count() == 0 && adm.arena().free_ranges().begin()->second == 1000);
+
+    // a failed solve is rerun; a rerun whose set-up fails ends with the error
+    reqs[4].fails_first_run = true;
+    reqs[5].fails_first_run = true;
+    reqs[5].fail_reenter = true;
+    adm.submit(4, 300);
+    adm.submit(5, 300);
+    CHECK(hp::serve_step(adm, ex) == -4);
+    CHECK(!reqs[4].finished && reqs[4].retried && !reqs[4].settled);      // rerunning
+    CHECK(reqs[5].finished && reqs[5].status == -4 && reqs[5].settled);   // not "ok"
+    CHECK(adm.active_count() == 1);
+    CHECK(hp::serve_step(adm, ex) == 0);
+    CHECK(reqs[4].finished && reqs[4].status == 0 && reqs[4].settled);
+    CHECK(adm.active_count() == 0 && adm.arena().free_ranges().begin()->second == 1000);
+
+    // a loop that fails after finishing a request: that request is still
+    // settled and its space freed; the error is returned
+    reqs[6].loops = 1;
+    reqs[7].loops = 3;
+    adm.submit(6, 300);
+    adm.submit(7, 300);
+    ex.loop_error = -4;
+    CHECK(hp::serve_step(adm, ex) == -4);
+    CHECK(reqs[6].settled && adm.active_count() == 1);
+    ex.loop_error = 0;
+    CHECK(hp::serve_step(adm, ex) == 0 && hp::serve_step(adm, ex) == 0);
+    CHECK(reqs[7].settled && adm.active_count() == 0);
+    CHECK(adm.arena().free_ranges().size() == 1 &&
+          adm.arena().free_ranges().begin()->second == 1000);
 }
 
 // Poisson-like replay: random sizes and loop counts; the invariants of the
@@ -140,6 +245,7 @@ static void replay(unsigned seed) {
 int main() {
     first_fit();
     arrival_order_and_slots();
+    serve_step_error_paths();
     for (unsigned s = 1; s <= 20; ++s) replay(s);
     std::printf("ok\n");
     return 0;

@@ -64,6 +64,17 @@ def test_host_only_calls():
         hpw.workspace_bytes(hpw.make_params(kind="drazin", l=0), 10, 10)
     with pytest.raises(hpw.HyperpowerError):
         hpw.workspace_bytes(hpw.make_params(alpha_rule="user", alpha=-1.0), 10, 10)
+    # autotune scratch: the grouped kinds hold A, B and a table of copies of
+    # the result (1 to 64 of them, about 4 Mi outputs in all)
+    def tune_bytes(code, M, N, K):
+        nb = ctypes.c_size_t()
+        rc = lib.hp_autotune_scratch_bytes(code, M, N, K, ctypes.byref(nb))
+        return rc, nb.value
+    rc, b = tune_bytes(hpw.GEMM_DTYPES["grouped_f64"], 64, 64, 64)
+    assert rc == 0 and b >= 8 * (2 * 64 * 64 + 64 * 64 * 64)
+    rc, b = tune_bytes(hpw.GEMM_DTYPES["grouped_f32"], 4096, 4096, 64)
+    assert rc == 0 and 4 * 4096 * 4096 <= b < 2 * 4 * 4096 * 4096 + (1 << 20)
+    assert tune_bytes(8, 64, 64, 64)[0] == EINVAL
 
 
 EINVAL, EUNSUPPORTED = -1, -5

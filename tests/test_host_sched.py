@@ -3,7 +3,9 @@ arrival-order admission under a slot cap and an HBM budget, first-fit
 placement with a coalescing free list), compiled for the CPU with g++ and
 exercised by tests/host/sched_check.cpp with a fake executor (each request
 finishes after its own number of loops): placement and coalescing cases,
-head-of-line blocking, and 20 random replays of 400 requests checking the
+head-of-line blocking, the error paths of the serving step (hp::serve_step:
+a failed set-up, a failed rerun set-up, a loop that fails after finishing
+some requests, a successful rerun), and 20 random replays of 400 requests checking the
 slot cap, the budget, disjoint placements, arrival order, completion and a
 fully coalesced arena at the end. No GPU."""
 
