@@ -30,13 +30,14 @@ Beside it in the same JSON line:
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
                     [--no-extras] [--extras name,name,...]
     python bench.py --gemm-shapes 8192x8192x8192[,..] [--gemm-dtype f64|f32|bf16|f16|
-                    bf16s|f16s] [--gemm-reps 5] [--check]   # one GEMM kernel alone
+                    bf16s|f16s|f64sym|f32sym] [--gemm-reps 5] [--check]   # one GEMM kernel alone
     python bench.py --copy-calibration   # a 512 MiB device copy, to scale counters
 """
 
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -150,8 +151,25 @@ def gemm_standalone(hpw, torch, M, N, K, dtype, reps, check=False) -> dict:
     """One GEMM kernel alone: `reps` launches after one warm-up, timed with
     events on the current stream. f64/f32: hp_gemm_ws with a split-K
     workspace; bf16/f16: FP32 operands rounded while staged; bf16s/f16s:
-    16-bit operands in memory (A and B^T)."""
-    if dtype in ("bf16s", "f16s"):
+    16-bit operands in memory (A and B^T); f64sym/f32sym: hp_gemm_sym on
+    C = G G^T (G random N x K; the symmetric launch forms the upper triangle's
+    tiles and mirrors them), algorithmic flops N (N + 1) K."""
+    if dtype in ("f64sym", "f32sym"):
+        dt = torch.float64 if dtype == "f64sym" else torch.float32
+        vec = 2 if dt == torch.float64 else 4
+        ldk = -(-K // vec) * vec
+        G = torch.randn(N, ldk, dtype=dt, device="cuda")[:, :K]
+        Gt = G.t().contiguous()
+        C = torch.empty(N, N, dtype=dt, device="cuda")
+        nb = ctypes.c_size_t()
+        if hpw.load_library().hp_gemm_sym_workspace_bytes(hpw.DTYPE[dt], N, K,
+                                                          ctypes.byref(nb)) != 0:
+            raise RuntimeError("hp_gemm_sym_workspace_bytes")
+        ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
+        run = lambda: hpw.gemm_sym(G, Gt, out=C, workspace=ws)
+        ref = (lambda: G.double() @ G.double().t()) if check else None
+        flops = float(N) * (N + 1) * K
+    elif dtype in ("bf16s", "f16s"):
         h = torch.bfloat16 if dtype == "bf16s" else torch.float16
         ldk = -(-K // 8) * 8
         A = torch.randn(M, ldk, device="cuda").to(h)[:, :K]
@@ -172,6 +190,8 @@ def gemm_standalone(hpw, torch, M, N, K, dtype, reps, check=False) -> dict:
                          device="cuda")
         run = lambda: hpw.gemm(A, B, out=C, operands=ops, workspace=ws)
         ref = (lambda: A.double() @ B.double()) if check else None
+    if dtype not in ("f64sym", "f32sym"):
+        flops = 2.0 * M * N * K
     run()
     torch.cuda.synchronize()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -182,7 +202,7 @@ def gemm_standalone(hpw, torch, M, N, K, dtype, reps, check=False) -> dict:
     torch.cuda.synchronize()
     ms = s.elapsed_time(e) / reps
     rec = {"dtype": dtype, "M": M, "N": N, "K": K, "ms": ms,
-           "tflops": 2.0 * M * N * K / ms * 1e-9}
+           "tflops": flops / ms * 1e-9}
     if ref is not None:
         R = ref()
         rec["max_rel_err"] = float((C.double() - R).abs().max() / R.abs().max())
@@ -560,7 +580,7 @@ def main() -> int:
                     help="comma-separated names of the extras to run (default: all)")
     ap.add_argument("--gemm-shapes", default="", help="MxNxK list: time one GEMM kernel alone")
     ap.add_argument("--gemm-dtype", default="f64",
-                    choices=["f64", "f32", "bf16", "f16", "bf16s", "f16s"])
+                    choices=["f64", "f32", "bf16", "f16", "bf16s", "f16s", "f64sym", "f32sym"])
     ap.add_argument("--gemm-reps", type=int, default=5)
     ap.add_argument("--check", action="store_true", help="--gemm-shapes: compare with torch FP64")
     ap.add_argument("--copy-calibration", action="store_true")

@@ -103,7 +103,11 @@ template <typename T, int TI, int TJ, int WAVES, bool SYM = false>
 __device__ __attribute__((always_inline)) inline void tile_epilogue(
     typename Mfma<T>::acc_t (&acc)[TI][TJ], const EpilogueT<T>& ep, int M, int N, int bm, int bn,
     int wm, int wn, int part, double (*red)[WAVES]) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int tid = threadIdx.x;
+    // in the stream-K loop, values derived from the thread index would
+    // otherwise be computed once before the loop and held through it
+    if constexpr (SYM) asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
     const int fr = lane & 15, fg = lane >> 4;
     double s_diff = 0.0, s_ref = 0.0;
 #pragma unroll
@@ -118,14 +122,13 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(
                     const T a = acc[i][j][r];
                     const T d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : T(0);
                     const T d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : T(0);
-                    const T idv = (row == col) ? T(1) : T(0);
 #pragma unroll
                     for (int o = 0; o < 3; ++o) {
                         if (ep.out[o]) {
                             T v = T(ep.acc_c[o]) * a;
-                            if (ep.id[o] != 0.0) v += T(ep.id[o]) * idv;
-                            if (ep.g1[o] != 0.0) v += T(ep.g1[o]) * d1;
-                            if (ep.g2[o] != 0.0) v += T(ep.g2[o]) * d2;
+                            if (row == col && ep.id[o] != 0.0) v += T(ep.id[o]);
+                            if (ep.D1 && ep.g1[o] != 0.0) v += T(ep.g1[o]) * d1;
+                            if (ep.D2 && ep.g2[o] != 0.0) v += T(ep.g2[o]) * d2;
                             if (o == 0 && ep.chop > 0.0 && fabs((double)v) < ep.chop) v = T(0);
                             ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
                             if (SYM && row != col) ep.out[o][(int64_t)col * ep.ldo[o] + row] = v;
@@ -179,7 +182,8 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
     __shared__ __attribute__((aligned(16))) T Bs[2][BK][C::LDB_S];
     __shared__ double red[2][C::WAVES];
 
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    if constexpr (SPLIT < 0) asm volatile("" : "+v"(tid));  // as in tile_epilogue
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int bm = tm * BM, bn = tn * BN;
@@ -488,33 +492,45 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_split(
                                                B + (int64_t)k0 * ldb, ldb, ep, tm, tn, t, split);
 }
 
-// Symmetric product (EpilogueT::sym) as one stream-K launch over the tiles on
-// and above the diagonal: the triangle's tiles * ipt K-steps (ipt = K-tiles
-// per tile), laid end to end, are cut into gridDim.x ranges of ipc steps, one
-// per block (the partition in hp_symk.h). A block walks its range tile by
-// tile; a tile that lies wholly in one range is finished there, one that
-// spans several ranges by the last of their blocks to arrive. A block's first
-// piece uses partial slot 2b and its last slot 2b + 1, so 2 * gridDim.x slots
-// suffice.
+// Symmetric product (EpilogueT::sym) as one launch over the tiles on and
+// above the diagonal (the partition in hp_symk.h): first `dp` tiles taken
+// whole, gridDim.x at a time, then the rest as stream-K: their tiles * ipt
+// K-steps (ipt = K-tiles per tile), laid end to end, cut into gridDim.x
+// ranges of ipc steps, one per block. A block walks its range tile by tile;
+// a tile that lies wholly in one range is finished there, one that spans
+// several ranges by the last of their blocks to arrive. A block's first
+// piece uses partial slot 2b and its last slot 2b + 1, so 2 * gridDim.x
+// slots suffice.
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
-__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN))
-__attribute__((amdgpu_waves_per_eu(4))) void k_gemm_sym(
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_sym(
     int N, int K, const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
-    EpilogueT<T> ep, int nt, int tiles, int ipt, int ipc) {
+    EpilogueT<T> ep, int nt, int tiles, int ipt, int ipc, int dp) {
     static_assert(BM == 128 && BN == 128, "partial slots hold 128 x 128 tiles");
     if (gate_closed(ep.gate, ep.gate_mode)) return;  // uniform: no counter is touched
     const int b = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int64_t total = (int64_t)tiles * ipt;
+    for (int t = b; t < dp; t += gridDim.x) {
+        int nt_p = nt;
+        asm volatile("" : "+s"(nt_p));  // as below
+        int tm, tn;
+        sym_tile_of(t, nt_p, tm, tn);
+        gemm_tile<T, BM, BN, BK, WM, WN, PF, -1, true>(N, N, K, A, lda, B, ldb, ep, tm, tn, t);
+        __syncthreads();  // the next tile's staging reuses the LDS tiles
+    }
+    const int64_t total = (int64_t)(tiles - dp) * ipt;
     int64_t it = (int64_t)b * ipc;
     const int64_t end = min(it + (int64_t)ipc, total);
     while (it < end) {
-        const SymPiece pc = sym_piece(it, end, ipt, ipc, b);
+        // the divisions below are redone per piece instead of keeping their
+        // reciprocals in vector registers through the loop
+        int ipt_p = ipt, ipc_p = ipc, nt_p = nt;
+        asm volatile("" : "+s"(ipt_p), "+s"(ipc_p), "+s"(nt_p));
+        const SymPiece pc = sym_piece(it, end, ipt_p, ipc_p, b);
         int tm, tn;
-        sym_tile_of(pc.t, nt, tm, tn);
+        sym_tile_of(dp + pc.t, nt_p, tm, tn);
         const int kb = pc.k0 * BK, ke = min(K, pc.k1 * BK);
         gemm_tile<T, BM, BN, BK, WM, WN, PF, -1, true>(N, N, ke - kb, A + kb, lda,
-                                                      B + (int64_t)kb * ldb, ldb, ep, tm, tn, pc.t,
-                                                      pc.idx, pc.np, pc.slot0, pc.b0);
+                                                      B + (int64_t)kb * ldb, ldb, ep, tm, tn,
+                                                      dp + pc.t, pc.idx, pc.np, pc.slot0, pc.b0);
         it += pc.k1 - pc.k0;
         __syncthreads();  // the next piece's staging reuses the LDS tiles
     }
@@ -797,7 +813,7 @@ int sym_grid() {
 }
 
 struct SymShape {
-    int grid, nt, tiles, ipt, ipc;
+    int grid, nt, tiles, ipt, ipc, dp;
 };
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF>
 SymShape sym_shape(int64_t N, int64_t K) {
@@ -807,7 +823,7 @@ SymShape sym_shape(int64_t N, int64_t K) {
     sh.nt = (int)cdiv(N, BM);
     sh.tiles = sh.nt * (sh.nt + 1) / 2;
     sh.ipt = (int)cdiv(K, BK);
-    sym_layout(sh.tiles, sh.ipt, g, &sh.ipc, &sh.grid);
+    sym_layout(sh.tiles, sh.ipt, g, &sh.ipc, &sh.grid, &sh.dp);
     return sh;
 }
 
@@ -828,7 +844,8 @@ bool launch_sym(int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64
     const SymShape sh = sym_shape<T, BM, BN, BK, WM, WN, PF>(N, K);
     if (!sym_fits(sh, ep)) return false;
     hipLaunchKernelGGL((k_gemm_sym<T, BM, BN, BK, WM, WN, PF>), dim3(sh.grid), dim3(C::NT), 0, s,
-                       (int)N, (int)K, A, lda, B, ldb, ep, sh.nt, sh.tiles, sh.ipt, sh.ipc);
+                       (int)N, (int)K, A, lda, B, ldb, ep, sh.nt, sh.tiles, sh.ipt, sh.ipc,
+                       sh.dp);
     *err = hipGetLastError();
     return true;
 }

@@ -4,12 +4,19 @@
 // of its invariants (tests/host/sym_partition_check.cpp).
 //
 // The t_count = nt (nt + 1) / 2 tiles on and above the diagonal of an
-// nt x nt tile grid are numbered row by row; tile t's K-steps (ipt of them)
-// occupy the global step range [t ipt, (t + 1) ipt). Block b takes the steps
-// [b ipc, min((b + 1) ipc, t_count ipt)). A tile covered by one block is
-// finished there; one covered by several (its pieces, in K order, on
-// consecutive blocks b0..b1) is finished by the last of them to arrive. A
-// block's first piece uses partial slot 2 b and its last slot 2 b + 1.
+// nt x nt tile grid are numbered row by row. With at least one tile per
+// block, the first dp tiles are taken whole in rounds (round r gives tile
+// r grid + b to block b, so the tiles in flight at once are neighbours in
+// the numbering and share operand panels in L2); dp is the multiple of the
+// grid that leaves between one and two tiles per block to the stream-K part
+// (nothing when the grid divides the tile count). The remaining tiles
+// dp .. t_count-1 are split by K-steps: tile
+// dp + u's steps (ipt of them) occupy the stream-K step range
+// [u ipt, (u + 1) ipt), and block b takes the steps [b ipc, min((b + 1) ipc,
+// (t_count - dp) ipt)). A tile covered by one block is finished there; one
+// covered by several (its pieces, in K order, on consecutive blocks b0..b1)
+// is finished by the last of them to arrive. A block's first piece uses
+// partial slot 2 b and its last slot 2 b + 1.
 #pragma once
 
 #include <stdint.h>
@@ -22,12 +29,16 @@
 
 namespace hp {
 
-// Steps per block (ipc) and blocks (grid <= g) for t_count tiles of ipt
-// K-steps on a launch of at most g resident blocks.
-HP_SYMK_FN void sym_layout(int t_count, int ipt, int g, int* ipc, int* grid) {
-    const int64_t total = (int64_t)t_count * ipt;
-    *ipc = (int)((total + g - 1) / g);
-    *grid = (int)((total + *ipc - 1) / *ipc);
+// Blocks (grid <= g), whole tiles (dp) and stream-K steps per block (ipc)
+// for t_count tiles of ipt K-steps on a launch of at most g resident blocks.
+HP_SYMK_FN void sym_layout(int t_count, int ipt, int g, int* ipc, int* grid, int* dp) {
+    const int q = t_count / g, r = t_count % g;
+    // the remainder goes to stream-K with the last round, so that no tile is
+    // cut into many small pieces (each piece costs a partial tile's round trip)
+    *dp = q == 0 ? 0 : r == 0 ? q * g : (q - 1) * g;
+    const int64_t total = (int64_t)(t_count - *dp) * ipt;
+    *ipc = total > 0 ? (int)((total + g - 1) / g) : 1;
+    *grid = *dp > 0 ? g : (int)((total + *ipc - 1) / *ipc);
 }
 
 // Upper-triangle tile t (row-major: row 0 holds tiles (0, 0..nt-1), row 1
@@ -42,10 +53,10 @@ HP_SYMK_FN void sym_tile_of(int t, int nt, int& tm, int& tn) {
     tn = r + t;
 }
 
-// The piece that a block whose range ends at `end` takes from global step
-// `it` on: tile t, its K-steps [k0, k1), the tile's piece count np, this
-// piece's index, and the slot of the tile's piece 0 (pieces i > 0 are in
-// slot 2 (b0 + i)).
+// The piece that a block whose range ends at `end` takes from stream-K step
+// `it` on: stream-K tile t (tile dp + t of the triangle), its K-steps
+// [k0, k1), the tile's piece count np, this piece's index, and the slot of
+// the tile's piece 0 (pieces i > 0 are in slot 2 (b0 + i)).
 struct SymPiece {
     int t, k0, k1, np, idx, slot0, b0;
 };
