@@ -288,8 +288,9 @@ def extra_lowrank(hpw, torch, steps) -> dict:
             rec["gflop_per_launch"] = inf["gflop"] / max(inf["gemms"], 1)
         if prec == "fp32":
             rec["note"] = ("every product in FP32: rounding seeds the null-space block, which grows "
-                           "18x per plain loop (Theorem 6.2) before the change falls below "
-                           "tau_switch; the guard returns the best iterate before the blow-up")
+                           "18x per plain loop (Theorem 6.2); an FP32 solve switches to the "
+                           "stabilised loops (Theorem 7.1) below a change of 0.25 instead of 0.1, "
+                           "before that block outgrows X, and ends at its FP32 floor")
             rec["d_hist"] = inf["d_hist"]
         out[prec] = rec
         log(f"4096x2048 {prec}: {rec}")

@@ -263,7 +263,13 @@ typedef struct hp_params {
     int32_t variant;       /* HP_VARIANT_* */
     double alpha;          /* used with HP_ALPHA_USER */
     double tau_switch;     /* relative change that starts the stabilised loops
-                              and arms the stagnation guard (default 0.1) */
+                              and arms the stagnation guard (default 0.1; a
+                              solve whose last stage is FP32 uses at least
+                              0.25: its rounding-seeded null-space block
+                              outgrows X a loop earlier, Theorem 6.2). The
+                              first stabilised loop after the switch is not
+                              tested for stagnation (its change also removes
+                              the null-space block, Theorem 7.1) */
     double tol;            /* stopping tolerance (default 1e-12) */
     double diverge_limit;  /* relative change treated as divergence (1e6) */
     int32_t max_iter;      /* loop cap (default 100, as in Section 8) */

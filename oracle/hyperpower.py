@@ -364,7 +364,9 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
     diverge): a non-finite iterate ends with "nonfinite" and the last finite
     iterate; once some relative change below tau_switch has been seen, a change
     that does not decrease ends with "stagnated" and returns X_k, the input of
-    that loop; a relative change above diverge_limit before then ends with
+    that loop (the first stabilised loop after the switch is exempt: its change
+    also removes the null-space block of Theorem 7.1, which no plain loop
+    measured); a relative change above diverge_limit before then ends with
     "diverged"; max_iter loops end with "maxiter" (Section 8 uses 100).
     On "diverged", and on "nonfinite" before some change below tau_switch has
     been seen, the returned iterate is the best one before the blow-up: the
@@ -433,7 +435,11 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
         if passed:
             res.status, res.X, res.returned_iter = "ok", Xn, k + 1
             return res
-        if converging and d >= res.d_hist[-2]:
+        # the first stabilised loop after the switch is not compared: its
+        # change includes the removal of the null-space block (Theorem 7.1),
+        # which the plain loops before it did not measure
+        first_stab = variant == "stabilised" and res.switch_iter == k
+        if converging and not first_stab and d >= res.d_hist[-2]:
             res.status, res.X, res.returned_iter = "stagnated", X, k
             return res
         if not converging and d > diverge_limit:

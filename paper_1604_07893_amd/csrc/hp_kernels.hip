@@ -768,7 +768,10 @@ __global__ void k_loop_step(const double* __restrict__ scal, DevLoop* L,
         L->done = 1;
         return;
     }
-    if (L->converging && k > 0 && d >= L->d_prev) {
+    // the first stabilised loop after the switch is not compared (LoopState)
+    const bool first_stab = P.variant == HP_VARIANT_STABILISED && L->switch_iter > 0 &&
+                            k == L->switch_iter;
+    if (L->converging && k > 0 && !first_stab && d >= L->d_prev) {
         L->status = HP_STAGNATED;
         L->result_idx = ik;
         L->done = 1;

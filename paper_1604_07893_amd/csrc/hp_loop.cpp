@@ -76,7 +76,7 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
     ++k;
     const bool finite = std::isfinite(d) && std::isfinite(diff2) && (!have_dinf || std::isfinite(dinf));
     auto note_switch = [&]() {
-        if (d < p->tau_switch) {
+        if (d < tau_switch()) {
             converging = true;
             if (p->variant == HP_VARIANT_STABILISED && !stabilising) {
                 stabilising = true;
@@ -141,7 +141,11 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         result_idx = in_;
         return DONE;
     }
-    if (converging && !stage_first && d >= d_prev) {
+    // the first stabilised loop after the switch is not compared: its change
+    // also removes the null-space block (Theorem 7.1)
+    const bool first_stab = p->variant == HP_VARIANT_STABILISED && res->switch_iter > 0 &&
+                            k == res->switch_iter + 1;
+    if (converging && !stage_first && !first_stab && d >= d_prev) {
         status = HP_STAGNATED;
         result_idx = ik;
         return DONE;

@@ -50,6 +50,17 @@ struct LoopState {
     // stage's set to slot kBest before the next loop runs. Without keep_best
     // those outcomes return X_k, the input of the loop that detected them.
     static constexpr int kBest = 3;
+
+    // The change below which the stabilised loops start (and the stagnation
+    // guard is armed): hp_params.tau_switch, but at least kTauFp32 when the
+    // last stage is FP32. FP32 rounding seeds the null-space block of a
+    // rank-deficient input 2^29 times above FP64's and it grows 18x per plain
+    // loop (Theorem 6.2), so FP32 must switch a loop earlier (measured on the
+    // 4096 x 2048 rank-1536 input: changes 0.81, 0.20, then 3.5 and growing).
+    static constexpr double kTauFp32 = 0.25;
+    double tau_switch() const {
+        return final_stage == 1 && p->tau_switch < kTauFp32 ? kTauFp32 : p->tau_switch;
+    }
     bool keep_best = false;
     bool have_best = false;
     bool save_best = false;

@@ -169,12 +169,13 @@ def test_staged_rank_deficient_keeps_the_fp64_polynomial():
 def test_rank_deficient_4096x2048_fp32_and_delta32():
     """The 4096 x 2048 rank-1536 workload (s log-spaced in [1e-4, 1]),
     stabilised, tol 1e-10, at full size. Every product in FP32: rounding seeds
-    the null-space block, which grows 18x per plain loop (Theorem 6.2) before
-    any change falls below tau_switch; the guard ends the run and returns the
-    best iterate before the blow-up (a CPU float32 emulation of these loops
-    gives X_7, error 8e-3, against 1.6e4 for the last one). The delta form
-    (FP64 R and update, FP32 polynomial) keeps that block's seed at FP64
-    rounding: it switches, and ends at its floor, never diverging."""
+    the null-space block, which grows 18x per plain loop (Theorem 6.2); with
+    the FP64 switch threshold 0.1 it outgrows X before any change gets there
+    (changes 0.81, 0.20, 3.5, ...), so an FP32 solve switches below 0.25 and
+    the stabilised loops (Theorem 7.1) hold it: the run ends at its FP32 floor
+    ("stagnated" or "ok", error about 2e-3 in a CPU float32 emulation), never
+    "diverged". The delta form (FP64 R and update, FP32 polynomial) keeps that
+    block's seed at FP64 rounding: it switches at 0.1, and ends at its floor."""
     hpw = need_gpu()
     d = inputs.lowrank_svd(4096, 2048, 1536, smin=1e-4, seed=1002)
     closed = (d.V / d.s) @ d.U.T
@@ -190,10 +191,7 @@ def test_rank_deficient_4096x2048_fp32_and_delta32():
     say("4096x2048 fp32")
     X, info = run(d.A, precision="fp32", **kw)
     err = rel(X, closed)
-    say(f"  fp32 {info['status']} iters {info['iters']} err {err:.2e} d {info['d_hist']}")
-    assert np.all(np.isfinite(X))
-    if info["status"] in ("diverged", "nonfinite"):
-        # the best iterate before the blow-up, not the last one
-        assert err <= 0.1
-    else:
-        assert info["status"] in ("ok", "stagnated") and err <= 1e-2
+    say(f"  fp32 {info['status']} iters {info['iters']} switch {info['switch_iter']} "
+        f"err {err:.2e} d {info['d_hist']}")
+    assert info["status"] in ("ok", "stagnated") and info["switch_iter"] > 0
+    assert err <= 1e-2

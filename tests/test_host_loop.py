@@ -137,17 +137,49 @@ def test_divergence_returns_the_input_of_the_smallest_change(harness):
 
 
 def test_fp32_emulation_of_the_rank_deficient_4096x2048_run(harness):
-    """The relative changes of the stabilised run on the 4096x2048 rank-1536
+    """The relative changes of the plain loops on the 4096x2048 rank-1536
     input with every product in FP32 (numpy float32 emulation of the GPU
     loops): the null-space block, seeded by rounding, grows 18x per loop
-    (Theorem 6.2) before any change falls below tau_switch = 0.1; the guard
-    returns X_7 (error 8e-3 against the closed form in the emulation), not
-    X_12 (1.6e4)."""
+    (Theorem 6.2) before any change falls below 0.1. With that threshold
+    (the FP64 default) the loops never switch and the guard returns X_7
+    (error 8e-3 against the closed form in the emulation), not X_12 (1.6e4)."""
     ds = [4.285, 3.690, 3.655, 3.652, 3.625, 3.191, 0.810, 0.1355, 2.414, 15.85, 16.99, 18.21,
           2.19e6]
     got = harness(rel_loops(ds), variant="stabilised", tol=1e-10)
     assert STATUS[got["status"]] == "diverged" and got["iters"] == 13
     assert got["returned"] == 7 and got["switch_iter"] == -1
+
+
+def test_fp32_solve_switches_before_the_null_space_block_grows(harness):
+    """The same input solved in FP32 (precision 1): the switch threshold is at
+    least 0.25, so the change 0.1355 of loop 8 starts the stabilised loops.
+    Changes from the emulation of that run: loop 9, the first stabilised one,
+    changes X by 0.142 (more than loop 8: it also removes the null-space
+    block, Theorem 7.1) and is not tested for stagnation; loops 10-12 settle
+    at the FP32 floor and loop 13's change rises, so the solve ends
+    "stagnated" with X_12 (error 2.2e-3 against the closed form in the
+    emulation)."""
+    ds = [4.285, 3.690, 3.655, 3.652, 3.625, 3.191, 0.810, 0.1355, 0.142, 1.022e-3, 9.236e-4,
+          9.230e-4, 9.258e-4]
+    got = harness(rel_loops(ds), precision=1, variant="stabilised", tol=1e-10)
+    assert got["switch_iter"] == 8
+    assert STATUS[got["status"]] == "stagnated" and got["iters"] == 13
+    assert got["returned"] == 12
+    # an explicit threshold above 0.25 is kept: 0.9 switches after loop 7
+    got = harness(rel_loops(ds[:8]), precision=1, variant="stabilised", tau=0.9, tol=1e-10)
+    assert got["switch_iter"] == 7
+
+
+def test_first_stabilised_loop_is_not_tested_for_stagnation(harness):
+    """FP64: the loop right after the switch may change X more than the loop
+    that triggered it; the next loops are tested again."""
+    got = harness(rel_loops([3.0, 0.05, 0.08, 1e-3, 2e-3]), variant="stabilised", tol=1e-12)
+    assert got["switch_iter"] == 2
+    assert STATUS[got["status"]] == "stagnated" and got["iters"] == 5
+    assert got["returned"] == 4
+    # without the switch (plain variant) loop 3 is tested: 0.08 >= 0.05
+    got = harness(rel_loops([3.0, 0.05, 0.08]), variant="plain", tol=1e-12)
+    assert STATUS[got["status"]] == "stagnated" and got["iters"] == 3
 
 
 # ---- precision stages (HP_PREC_MIXED = 2, HP_PREC_FP32 = 1) ------------------
