@@ -585,6 +585,9 @@ def main() -> int:
     ap.add_argument("--gemm-reps", type=int, default=5)
     ap.add_argument("--check", action="store_true", help="--gemm-shapes: compare with torch FP64")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--host-input", action="store_true",
+                    help="build the 8192^2 input with numpy on the host (same recipe, other "
+                         "draws): torch's GPU QR does not run under rocprofv3 counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hyperpower "
@@ -606,9 +609,15 @@ def main() -> int:
                                              args.check)), flush=True)
         return 0
 
-    A, U, s, V = inputs.square_svd_device(NSQ, smin=SMIN_SQ, seed=SEED_SQ)
-    closed = (V / s) @ U.T.contiguous()  # V diag(1/s) U^T: a reference, not the method
-    del U, V, s
+    if args.host_input:
+        d = inputs.square_svd(NSQ, smin=SMIN_SQ, seed=SEED_SQ)
+        A = torch.from_numpy(d.A).cuda()
+        closed = torch.from_numpy((d.V / d.s) @ d.U.T).cuda()
+        del d
+    else:
+        A, U, s, V = inputs.square_svd_device(NSQ, smin=SMIN_SQ, seed=SEED_SQ)
+        closed = (V / s) @ U.T.contiguous()  # V diag(1/s) U^T: a reference, not the method
+        del U, V, s
     torch.cuda.synchronize()
     params = dict(alpha_rule="user", alpha=1.0, tol=TOL, precision="fp64")
     sec, infos, X = timed_solves(hpw, torch, A, args.steps, args.warmup, time_kernels=True,
@@ -645,7 +654,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "m": NSQ, "n": NSQ, "smin": SMIN_SQ, "variant": "plain",
+        "config": {"workload": WORKLOAD + (" (built on the host)" if args.host_input else ""),
+                   "m": NSQ, "n": NSQ, "smin": SMIN_SQ, "variant": "plain",
                    "precision": "fp64", "tol": TOL},
         "roofline": roofline,
         "iters": last["iters"],
