@@ -147,7 +147,7 @@ def cpu_baseline(A_host: np.ndarray, loops: int) -> dict:
                        f"input ({t_loop:.1f} s), scaled to the {loops} loops of one FP64 inverse")}
 
 
-def gemm_standalone(hpw, torch, M, N, K, dtype, reps, check=False) -> dict:
+def gemm_standalone(hpw, torch, M, N, K, dtype, reps, check=False, ref_blas=False) -> dict:
     """One GEMM kernel alone: `reps` launches after one warm-up, timed with
     events on the current stream. f64/f32: hp_gemm_ws with a split-K
     workspace; bf16/f16: FP32 operands rounded while staged; bf16s/f16s:
@@ -192,17 +192,37 @@ def gemm_standalone(hpw, torch, M, N, K, dtype, reps, check=False) -> dict:
         ref = (lambda: A.double() @ B.double()) if check else None
     if dtype not in ("f64sym", "f32sym"):
         flops = 2.0 * M * N * K
-    run()
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        run()
-    e.record()
-    torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / reps
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps
+
+    ms = timed(run)
     rec = {"dtype": dtype, "M": M, "N": N, "K": K, "ms": ms,
            "tflops": flops / ms * 1e-9}
+    if ref_blas:
+        # the platform BLAS on the same operands (a reference point, not this
+        # library's path): torch.matmul in the operands' dtype
+        if dtype in ("bf16s", "f16s"):
+            Ac, Bc = A.contiguous(), Bt.t().contiguous()
+            blas = lambda: torch.matmul(Ac, Bc)
+        elif dtype in ("f64sym", "f32sym"):
+            blas = lambda: torch.matmul(G, Gt)
+        elif dtype in ("f64", "f32"):
+            Ac, Bc = A.contiguous(), B.contiguous()
+            blas = lambda: torch.matmul(Ac, Bc)
+        else:
+            blas = None
+        if blas is not None:
+            bms = timed(blas)
+            rec["torch_matmul_ms"] = bms
+            rec["torch_matmul_tflops"] = 2.0 * M * N * K / bms * 1e-9
     if ref is not None:
         R = ref()
         rec["max_rel_err"] = float((C.double() - R).abs().max() / R.abs().max())
@@ -584,6 +604,9 @@ def main() -> int:
                     choices=["f64", "f32", "bf16", "f16", "bf16s", "f16s", "f64sym", "f32sym"])
     ap.add_argument("--gemm-reps", type=int, default=5)
     ap.add_argument("--check", action="store_true", help="--gemm-shapes: compare with torch FP64")
+    ap.add_argument("--gemm-ref", action="store_true",
+                    help="--gemm-shapes: also time torch.matmul (the platform's BLAS) on the same "
+                         "operands and dtype, for reference only")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--host-input", action="store_true",
                     help="build the 8192^2 input with numpy on the host (same recipe, other "
@@ -606,7 +629,7 @@ def main() -> int:
         for spec in args.gemm_shapes.split(","):
             M, N, K = (int(v) for v in spec.lower().split("x"))
             print(json.dumps(gemm_standalone(hpw, torch, M, N, K, args.gemm_dtype, args.gemm_reps,
-                                             args.check)), flush=True)
+                                             args.check, args.gemm_ref)), flush=True)
         return 0
 
     if args.host_input:
