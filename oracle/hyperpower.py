@@ -180,7 +180,10 @@ def x0_moore_penrose(A, rule: str = "norm1inf", alpha=None, ar: Arith = F64):
     Returns (X0, alpha).
     """
     if rule == "norm1inf":
-        alpha = 1 / (norm_1(A) * norm_inf(A))
+        # A = 0: the rule's denominator vanishes; X0 = alpha A^* = 0 for any
+        # alpha (G = 0, so the outer inverse with range R(G) = {0} is 0)
+        den = norm_1(A) * norm_inf(A)
+        alpha = 1 / den if den != 0 else den * 0
     elif rule in ("sigma_max2", "sigma_opt"):
         s = np.linalg.svd(np.asarray(A, dtype=np.complex128 if np.iscomplexobj(A) else np.float64),
                           compute_uv=False)
@@ -417,7 +420,15 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
             return res
         D = Xn - X
         nD, nX = norm_fro(D, ar), norm_fro(X, ar)
-        d = nD / nX
+        # alpha = 0 (A = 0 under the rule of Section 4, or a user's 0): X0 = 0 is
+        # the outer inverse with range R(X0) = {0}; X_k = X_{k+1} = 0 is read as
+        # no change. Any other zero iterate leaves the change undefined.
+        if nX != 0:
+            d = nD / nX
+        elif nD == 0 and alpha == 0:
+            d = nD
+        else:
+            d = ar.num(np.nan)
         res.fro_hist.append((nD, nX))
         res.d_hist.append(d)
         res.diff_inf_hist.append(norm_inf(D))
@@ -427,11 +438,14 @@ def solve(A, *, kind: str = "mp", l: int | None = None, alpha_rule: str = "norm1
             sval = res.diff_inf_hist[-1]
             passed = sval <= tol
         elif stop == "paper_4_1":
-            sval = norm_fro(D, ar) / (ar.num(p) ** k * alpha)
+            sval = nD / (ar.num(p) ** k * alpha) if nD != 0 else nD
             passed = sval < tol
         else:
             raise ValueError(f"unknown stop rule {stop!r}")
         res.stop_hist.append(sval)
+        if not (bool(np.isfinite(d)) if ar.name == "f64" else mpmath.isfinite(d)):
+            res.status, res.X, res.returned_iter = "nonfinite", X, k
+            return res
         if passed:
             res.status, res.X, res.returned_iter = "ok", Xn, k + 1
             return res

@@ -92,7 +92,8 @@ __global__ __launch_bounds__(kThreads) void k_alpha_norm1inf(const double* __res
     if (threadIdx.x == 0) {
         scal[SLOT_NORM1] = m1;
         scal[SLOT_NORMINF] = mi;
-        scal[SLOT_ALPHA] = 1.0 / (m1 * mi);
+        // A = 0: X0 = alpha A^T = 0 whatever alpha (the zero matrix's inverse)
+        scal[SLOT_ALPHA] = m1 * mi > 0.0 ? 1.0 / (m1 * mi) : 0.0;
     }
 }
 
@@ -734,7 +735,9 @@ __global__ void k_loop_step(const double* __restrict__ scal, DevLoop* L,
     const int ik = k & 1, in_ = ik ^ 1;
     const double diff2 = scal[SLOT_DIFF2], ref2 = scal[SLOT_REF2];
     const double dinf = P.have_dinf ? scal[SLOT_DINF] : 0.0;
-    const double d = sqrt(diff2) / sqrt(ref2);
+    // a zero iterate from alpha = 0 (A = 0): no change, as in LoopState
+    const double d = (diff2 == 0.0 && ref2 == 0.0 && P.alpha == 0.0) ? 0.0
+                                                                   : sqrt(diff2) / sqrt(ref2);
     if (k < 128) {
         L->d_hist[k] = d;
         if (P.have_dinf) L->dinf_hist[k] = dinf;
@@ -755,7 +758,7 @@ __global__ void k_loop_step(const double* __restrict__ scal, DevLoop* L,
         sval = dinf;
         passed = dinf <= P.tol;
     } else if (P.stop_rule == HP_STOP_PAPER_4_1) {
-        sval = sqrt(diff2) / (pow(P.order, (double)k) * P.alpha);
+        sval = diff2 == 0.0 ? 0.0 : sqrt(diff2) / (pow(P.order, (double)k) * P.alpha);
         passed = sval < P.tol;
     } else {
         sval = d;

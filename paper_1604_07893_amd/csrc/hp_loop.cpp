@@ -66,7 +66,12 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
     save_best = false;
     res->iters = k + 1;
     res->iters_stage[stage] += 1;
-    const double d = std::sqrt(diff2) / std::sqrt(ref2);
+    // alpha = 0 (A = 0 under the norm rule, or a caller's 0): X0 = 0 is the
+    // outer inverse with range {0}, and X_k = X_{k+1} = 0 is no change. Any
+    // other zero iterate (e.g. X0 below FP32's range) leaves 0/0: non-finite.
+    const double d = (diff2 == 0.0 && ref2 == 0.0 && alpha == 0.0)
+                         ? 0.0
+                         : std::sqrt(diff2) / std::sqrt(ref2);
     if (k < HP_HIST) {
         res->d_hist[k] = d;
         if (have_dinf) res->dinf_hist[k] = dinf;
@@ -132,7 +137,9 @@ LoopState::Action LoopState::step(double diff2, double ref2, double dinf, bool h
         sval = dinf;
         passed = dinf <= p->tol;
     } else {
-        sval = std::sqrt(diff2) / (std::pow((double)method_order(p->method), (double)(k - 1)) * alpha);
+        sval = diff2 == 0.0 ? 0.0
+                            : std::sqrt(diff2) /
+                                  (std::pow((double)method_order(p->method), (double)(k - 1)) * alpha);
         passed = sval < p->tol;
     }
     res->stop_last = sval;

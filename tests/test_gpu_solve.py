@@ -55,6 +55,35 @@ def test_ragged_shapes_match_oracle(m, n):
     assert abs(info["iters"] - ref.iters) <= 1
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "mixed", "delta32"])
+def test_zero_matrix_gives_zero(precision):
+    """A = 0 (Section 4's alpha has a zero denominator; X0 = 0 and 0 is the
+    inverse): status ok after one loop and X exactly 0, in every precision,
+    square and not, with each stopping rule; the same in a batch beside a
+    normal problem, and with the decisions on the device."""
+    hpw = need_gpu()
+    for shape in ((1, 1), (64, 32), (33, 130)):
+        A = np.zeros(shape)
+        for stop in ("rel_fro", "paper_4_1"):
+            X, info = run(A, precision=precision, stop=stop, tol=1e-12)
+            say(f"zero {shape} {precision} {stop}: {info['status']} iters {info['iters']}")
+            assert info["status"] == "ok"
+            assert np.array_equal(X, np.zeros(shape[::-1]))
+    if precision in ("fp64", "fp32", "mixed"):
+        B = inputs.uniform(40, 24, seed=5)
+        Xs, infos = hpw.solve_batched([to_dev(np.zeros((40, 24))), to_dev(B)],
+                                      precision="fp32_fp64" if precision == "mixed" else precision,
+                                      tol=1e-12)
+        torch.cuda.synchronize()
+        assert infos[0]["status"] == "ok" and torch.count_nonzero(Xs[0]).item() == 0
+        ref = O.solve(B, kind="mp", tol=1e-12)
+        assert rel(Xs[1].cpu().numpy(), ref.X) <= (TOL if precision != "fp32" else 1e-5)
+    if precision == "fp64":
+        X, info = hpw.solve(to_dev(np.zeros((64, 32))), device_stop=True, tol=1e-12)
+        torch.cuda.synchronize()
+        assert info["status"] == "ok" and torch.count_nonzero(X).item() == 0
+
+
 def test_stop_rules_and_coc_match_oracle():
     A = inputs.uniform(120, 80, seed=3)
     for stop, tol in (("paper_4_1", 1e-6), ("abs_inf", 1e-9)):

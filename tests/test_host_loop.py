@@ -170,6 +170,22 @@ def test_fp32_solve_switches_before_the_null_space_block_grows(harness):
     assert got["switch_iter"] == 7
 
 
+def test_zero_iterate_reads_as_no_change(harness):
+    """A = 0 gives alpha = 0, X0 = 0 and zero stopping sums: the change 0/0 is
+    read as 0, so the first loop passes (the zero matrix's inverse is 0), as
+    the oracle decides. With alpha > 0 a zero iterate (X0 below a precision's
+    range) is not a result: 0/0 is non-finite."""
+    got = harness([(0.0, 0.0, 0.0)], tol=1e-12, alpha=0.0)
+    assert STATUS[got["status"]] == "ok" and got["iters"] == 1 and got["returns_new"]
+    got = harness([(0.0, 0.0, 0.0)], stop="paper_4_1", tol=1e-12, alpha=0.0)
+    assert STATUS[got["status"]] == "ok" and got["iters"] == 1
+    got = harness([(0.0, 0.0, 0.0)], tol=1e-12, alpha=1e-90)
+    assert STATUS[got["status"]] == "nonfinite"
+    res = O.solve(np.zeros((4, 3)), kind="mp", tol=1e-12)
+    assert res.alpha == 0
+    check_against_oracle(harness, res, tol=1e-12, alpha=0.0)
+
+
 def test_first_stabilised_loop_is_not_tested_for_stagnation(harness):
     """FP64: the loop right after the switch may change X more than the loop
     that triggered it; the next loops are tested again."""

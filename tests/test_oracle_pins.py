@@ -671,3 +671,20 @@ def test_complex_moore_penrose_vs_lapack(m, n, rank):
     E = np.block([[A.real, -A.imag], [A.imag, A.real]])
     XE = np.block([[res.X.real, -res.X.imag], [res.X.imag, res.X.real]])
     assert np.linalg.norm(XE - np.linalg.pinv(E)) / np.linalg.norm(XE) < 1e-11
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 2), (2, 5)])
+def test_zero_matrix_inverse_is_zero(shape):
+    """A = 0: the rule of Section 4 has a zero denominator, but X0 = alpha A^T
+    is 0 for any alpha, and 0 is the Moore-Penrose inverse of the zero matrix
+    (LAPACK's pinv agrees); the first loop changes nothing and the solve ends
+    there."""
+    A = np.zeros(shape)
+    for stop in ("rel_fro", "paper_4_1", "abs_inf"):
+        res = O.solve(A, kind="mp", tol=1e-12, stop=stop)
+        assert res.status == "ok" and res.iters == 1
+        assert np.array_equal(res.X, np.zeros(shape[::-1]))
+        assert np.array_equal(res.X, np.linalg.pinv(A))
+    # a zero X0 that is not from alpha = 0 is not a result
+    res = O.solve(np.ones(shape), kind="mp", X0=np.zeros(shape[::-1]), alpha=1.0, tol=1e-12)
+    assert res.status == "nonfinite"
