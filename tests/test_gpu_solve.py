@@ -84,6 +84,23 @@ def test_zero_matrix_gives_zero(precision):
         assert info["status"] == "ok" and torch.count_nonzero(X).item() == 0
 
 
+@pytest.mark.parametrize("m,n", [(65535, 3), (3, 65535), (65535, 1)])
+def test_largest_dimension(m, n):
+    """The largest dimension the boundary takes (65535; 65536 is rejected on
+    the host), on the narrow side's form: tall input on the left form (3 x 3
+    residual), wide input on the right form. Against LAPACK's pseudo-inverse
+    and the FP64 oracle's loop count; for tall input the oracle runs on A^T
+    (its right form there has the same iterates, transposed, as the left form
+    here, and an m x m residual would not fit in memory)."""
+    A = inputs.uniform(m, n, seed=m + 7 * n)
+    ref = O.solve(A if m <= n else np.ascontiguousarray(A.T), kind="mp", tol=1e-12)
+    X, info = run(A, tol=1e-12)
+    say(f"max {m}x{n}: {info['status']} iters {info['iters']} side {info['side']}")
+    assert info["status"] == ref.status == "ok"
+    assert abs(info["iters"] - ref.iters) <= 1
+    assert rel(X, np.linalg.pinv(A)) <= 1e-12
+
+
 def test_stop_rules_and_coc_match_oracle():
     A = inputs.uniform(120, 80, seed=3)
     for stop, tol in (("paper_4_1", 1e-6), ("abs_inf", 1e-9)):
