@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
@@ -425,6 +426,25 @@ void set_chop(GemmCall<T>* calls, int nc, const T* Xn, double chop) {
 // stabilised one (update into X_{k+1/2}, then X_{k+1/2} A X_{k+1/2} with the
 // sums) -- and the flag the previous decision left selects which runs, so the
 // iterates and decisions are those of run_solve, bitwise.
+// Spins for at most kPollUs microseconds until *flag (pinned host memory that
+// a kernel writes) equals `want`. Returns false when the time is up (the
+// caller then waits for the stream).
+bool poll_host(const double* flag, double want) {
+    constexpr double kPollUs = 300.0;
+    const auto t0 = std::chrono::steady_clock::now();
+    const volatile double* f = flag;
+    for (int i = 0;; ++i) {
+        if (*f == want) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return true;
+        }
+        if ((i & 63) == 63 &&
+            std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0)
+                    .count() > kPollUs)
+            return false;
+    }
+}
+
 int run_solve_device(Solver& S, char* ws, const double* A, int64_t lda, const double* X0,
                      int64_t ldx0, double* X, int64_t ldx) {
     const hp_params* p = S.p;
@@ -823,18 +843,26 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
         CHK(run_loop(r_ready ? 1 : 0, scheme));
         r_ready = false;
         scheme = p->method;
-        HIPCHK(reduce_pairs(bf.small, S.last_blocks, bf.scal, s));
         // the inf-norm change in the precision the stage holds its iterates in
         // (rule HP_STOP_ABS_INF reads it in whichever stage is final)
         const bool inf_now = want_inf;
+        // without it, the reduction itself hands the scalars to the host
+        double* direct = inf_now ? nullptr : S.h->host_sums_dev;
+        const double seq = (double)++S.h->sums_seq;
+        HIPCHK(reduce_pairs(bf.small, S.last_blocks, bf.scal, s, direct, seq));
         if (inf_now && st.stage == 2)
             HIPCHK(diff_norm_inf(bf.b64.X[st.in_], bf.b64.ldX, bf.b64.X[st.ik], bf.b64.ldX, n, m,
                                  bf.small, bf.scal, s));
         else if (inf_now)
             HIPCHK(diff_norm_inf(bf.b32.X[st.in_], bf.b32.ldX, bf.b32.X[st.ik], bf.b32.ldX, n, m,
                                  bf.small, bf.scal, s));
-        HIPCHK(hipMemcpyAsync(hs, bf.scal, sizeof(double) * SLOT_COUNT, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        if (!direct)
+            HIPCHK(hipMemcpyAsync(hs, bf.scal, sizeof(double) * SLOT_COUNT, hipMemcpyDeviceToHost, s));
+        // a short loop's sums arrive within microseconds: poll for them rather
+        // than sleep in the stream wait (kernel timing needs the wait)
+        if (!direct || S.timer.on || !poll_host(S.h->host_sums + SLOT_COUNT, seq))
+            HIPCHK(hipStreamSynchronize(s));
+        if (direct) std::memcpy(hs, S.h->host_sums, sizeof(double) * SLOT_COUNT);
         S.timer.harvest();
 
         // (a loop that reused the bound check's R keeps the r_last of that check)
@@ -981,6 +1009,12 @@ int hp_create(hp_handle** out, int device) {
         delete h;
         return HP_EHIP;
     }
+    // (without it the loop falls back to a copy of the device scalars)
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->host_sums), sizeof(double) * (hp::SLOT_COUNT + 1),
+                      hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess &&
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&h->host_sums_dev), h->host_sums, 0) !=
+            hipSuccess)
+        h->host_sums_dev = nullptr;
     for (int i = 0; i < hp_handle::kEvents; ++i) {
         if (hipEventCreate(&h->ev[i]) != hipSuccess) {
             hp_destroy(h);
@@ -1007,6 +1041,7 @@ int hp_destroy(hp_handle* h) {
     for (int i = 0; i < hp_handle::kEvents; ++i)
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
+    if (h->host_sums) (void)hipHostFree(h->host_sums);
     delete h;
     return HP_OK;
 }

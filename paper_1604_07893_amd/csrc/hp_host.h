@@ -34,6 +34,15 @@ struct hp_handle {
     // (device_stop: the step parameters, and the head of the DevLoop state,
     // which is read back over the slots)
     double* host_scal = nullptr;
+    // SLOT_COUNT doubles of fine-grained pinned memory that the end-of-loop
+    // reduction writes directly (device address host_sums_dev), in place of
+    // a device-to-host copy per loop
+    // Slot SLOT_COUNT holds the number of the last loop whose sums arrived
+    // (sums_seq counts them), so that the host can poll it instead of waiting
+    // for the stream.
+    double* host_sums = nullptr;
+    double* host_sums_dev = nullptr;
+    uint64_t sums_seq = 0;
     static constexpr int kHostExtra = 16;
     static constexpr int kEvents = 64;
     hipEvent_t ev[kEvents] = {};

@@ -285,7 +285,11 @@ hipError_t extract_complex(const double* E, int64_t lde, int64_t N, int64_t M, d
 hipError_t set_identity(double* Y, int64_t ldy, int64_t M, int64_t N, hipStream_t s);
 
 // scal[SLOT_DIFF2], scal[SLOT_REF2] = fixed-order sums of the pair partials.
-hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipStream_t s);
+// With `host` (a device-visible address of SLOT_COUNT + 1 doubles of pinned
+// host memory), also writes all SLOT_COUNT scalars there and then `seq` to
+// host[SLOT_COUNT], each write visible to the host in that order.
+hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipStream_t s,
+                        double* host = nullptr, double seq = 0.0);
 
 // Device-side loop control (hp_params.device_stop; hp_kernels.hip). Kept in
 // device memory (not a kernel argument), so that captured loops do not

@@ -308,7 +308,9 @@ __global__ __launch_bounds__(kThreads) void k_zero_u32(unsigned* __restrict__ p,
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce_pairs(const double* __restrict__ part, int nb,
-                                                           double* __restrict__ scal) {
+                                                           double* __restrict__ scal,
+                                                           double* __restrict__ host,
+                                                           double seq) {
     double s0 = 0.0, s1 = 0.0;
     for (int b = threadIdx.x; b < nb; b += kThreads) {
         s0 += part[2 * b];
@@ -319,6 +321,15 @@ __global__ __launch_bounds__(kThreads) void k_reduce_pairs(const double* __restr
     if (threadIdx.x == 0) {
         scal[SLOT_DIFF2] = s0;
         scal[SLOT_REF2] = s1;
+        if (host) {
+            // the other slots were written by earlier launches on this stream
+            for (int i = 0; i < SLOT_COUNT; ++i)
+                host[i] = i == SLOT_DIFF2 ? s0 : i == SLOT_REF2 ? s1 : scal[i];
+            __threadfence_system();
+            // last: the host polls this number before reading the sums
+            host[SLOT_COUNT] = seq;
+            __threadfence_system();
+        }
     }
 }
 
@@ -573,8 +584,10 @@ hipError_t zero_u32(unsigned* p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kThreads), 0, s, partials, nblocks, scal);
+hipError_t reduce_pairs(const double* partials, int nblocks, double* scal, hipStream_t s,
+                        double* host, double seq) {
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kThreads), 0, s, partials, nblocks, scal,
+                       host, seq);
     return hipGetLastError();
 }
 
