@@ -30,6 +30,10 @@ struct ReduceEntry {
 // grid >= *count blocks; blocks past *count exit at once
 hipError_t reduce_pairs_grouped(const int* count, const ReduceEntry* ents, int grid, double* out,
                                 hipStream_t s);
+// Adds one to *counter (device memory) and writes the new value to *flag
+// (pinned host memory, device address) after everything before it on the
+// stream: the host polls it for the end of a grouped loop (hp_kernels.hip).
+hipError_t signal_host(unsigned long long* counter, double* flag, hipStream_t s);
 
 }  // namespace hp
 
@@ -69,7 +73,7 @@ struct Tables {
     size_t bytes = 0;
     size_t off_hdr[2][kSlots] = {};
     size_t off_ent[2][kSlots] = {};
-    size_t off_cnt = 0, off_red = 0, off_out = 0;
+    size_t off_cnt = 0, off_red = 0, off_out = 0, off_sig = 0;
     char* dev = nullptr;
     char* host = nullptr;
 
@@ -90,6 +94,8 @@ struct Tables {
         off = align_up(off + sizeof(ReduceEntry) * (size_t)cap);
         if (t) t->off_out = off;
         off = align_up(off + 2 * sizeof(double) * (size_t)cap);
+        if (t) t->off_sig = off;  // loops signalled so far (device counter)
+        off = align_up(off + sizeof(unsigned long long));
         return off;
     }
 };
@@ -121,6 +127,13 @@ struct Group {
     LoopGraph graphs[kGraphs];
     uint64_t clock = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;  // order the replay against stream s
+    // The per-problem sums land in fine-grained pinned host memory (2 per
+    // problem, then the loop number): the reduction writes them and a signal
+    // kernel the number, which the host polls instead of a copy and a stream
+    // wait. Null when that memory is unavailable (copy and wait instead).
+    double* sums = nullptr;
+    double* sums_dev = nullptr;
+    uint64_t signals = 0;
 };
 
 // Enqueue one loop's device work on stream s (used eagerly or under capture).
@@ -136,6 +149,14 @@ int enqueue_loop(Group& g, uint32_t mask, hipStream_t s) {
             HIPCHK(gemm_grouped(reinterpret_cast<const GroupHeader*>(tb.dev + tb.off_hdr[1][j]),
                                 reinterpret_cast<const GroupEntry<float>*>(tb.dev + tb.off_ent[1][j]),
                                 g.grid, g.tile_cfg[1], s));
+    }
+    if (g.sums_dev) {
+        HIPCHK(reduce_pairs_grouped(reinterpret_cast<const int*>(tb.dev + tb.off_cnt),
+                                    reinterpret_cast<const ReduceEntry*>(tb.dev + tb.off_red),
+                                    tb.cap, g.sums_dev, s));
+        HIPCHK(signal_host(reinterpret_cast<unsigned long long*>(tb.dev + tb.off_sig),
+                           g.sums_dev + 2 * tb.cap, s));
+        return HP_OK;
     }
     HIPCHK(reduce_pairs_grouped(reinterpret_cast<const int*>(tb.dev + tb.off_cnt),
                                 reinterpret_cast<const ReduceEntry*>(tb.dev + tb.off_red), tb.cap,
@@ -195,6 +216,9 @@ int run_loop_device(Group& g, uint32_t mask) {
 
 void group_release(Group& g) {
     if (g.cap_stream) (void)hipStreamSynchronize(g.cap_stream);
+    if (g.s) (void)hipStreamSynchronize(g.s);
+    if (g.sums) (void)hipHostFree(g.sums);
+    g.sums = g.sums_dev = nullptr;
     if (g.ev_in) (void)hipEventDestroy(g.ev_in);
     if (g.ev_out) (void)hipEventDestroy(g.ev_out);
     g.ev_in = g.ev_out = nullptr;
@@ -209,6 +233,26 @@ void group_init(Group& g, hp_handle* h, const hp_params* p, void* stream) {
     g.s = reinterpret_cast<hipStream_t>(stream);
     g.use_graph = (p->flags & HP_FLAG_NO_GRAPH) == 0;
     for (int i = 0; i < 2; ++i) g.tile_cfg[i] = h->grouped_cfg[i];
+}
+
+// Once the tables exist: the host area for the sums and a zero loop counter
+// (a plain memset: no graph is being captured yet).
+int group_sums_init(Group& g) {
+    const size_t bytes = sizeof(double) * (2 * (size_t)g.tb.cap + 1);
+    if (hipHostMalloc(reinterpret_cast<void**>(&g.sums), bytes,
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        g.sums = nullptr;
+        return HP_OK;  // copy and wait instead
+    }
+    std::memset(g.sums, 0, bytes);
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&g.sums_dev), g.sums, 0) != hipSuccess) {
+        (void)hipHostFree(g.sums);
+        g.sums = g.sums_dev = nullptr;
+        return HP_OK;
+    }
+    g.signals = 0;
+    HIPCHK(hipMemsetAsync(g.tb.dev + g.tb.off_sig, 0, sizeof(unsigned long long), g.s));
+    return HP_OK;
 }
 
 // Products outside the loop (Drazin set-up, projection) run as single
@@ -346,8 +390,16 @@ int group_loop(Group& g, std::vector<Problem*>& act) {
         red[i] = ReduceEntry{P.bf.small, tiles, 0};
     }
     CHK(run_loop_device(g, mask));
-    HIPCHK(hipStreamSynchronize(g.s));
     const double* hout = reinterpret_cast<const double*>(tb.host + tb.off_out);
+    if (g.sums) {
+        // a grouped loop takes from tens of microseconds to tens of
+        // milliseconds: poll for its signal, then wait for the stream
+        const double want = (double)++g.signals;
+        if (!poll_host(g.sums + 2 * tb.cap, want, 20000.0)) HIPCHK(hipStreamSynchronize(g.s));
+        hout = g.sums;
+    } else {
+        HIPCHK(hipStreamSynchronize(g.s));
+    }
 
     bool any_done = false;
     for (int i = 0; i < np; ++i) {
@@ -465,6 +517,10 @@ int hp_solve_batched(hp_handle* h, const hp_params* p, int count, const hp_probl
     g.tb.dev = ws;
     if (hipHostMalloc(reinterpret_cast<void**>(&g.tb.host), g.tb.bytes, hipHostMallocDefault) != hipSuccess)
         return HP_EHIP;
+    if (group_sums_init(g) != HP_OK) {
+        (void)hipHostFree(g.tb.host);
+        return HP_EHIP;
+    }
     std::vector<Problem> P(count);
     size_t off = align_up(g.tb.bytes);
     int rc = HP_OK;
@@ -511,7 +567,8 @@ int hp_serve_create(hp_handle* h, const hp_params* p, size_t hbm_budget, int max
         delete sv;
         return HP_EHIP;
     }
-    if (tables_alloc(sv->g.tb, max_slots) != HP_OK) {
+    if (tables_alloc(sv->g.tb, max_slots) != HP_OK || group_sums_init(sv->g) != HP_OK) {
+        group_release(sv->g);
         (void)hipFree(sv->arena);
         tables_free(sv->g.tb);
         delete sv;

@@ -426,11 +426,15 @@ void set_chop(GemmCall<T>* calls, int nc, const T* Xn, double chop) {
 // stabilised one (update into X_{k+1/2}, then X_{k+1/2} A X_{k+1/2} with the
 // sums) -- and the flag the previous decision left selects which runs, so the
 // iterates and decisions are those of run_solve, bitwise.
-// Spins for at most kPollUs microseconds until *flag (pinned host memory that
+}  // namespace
+
+namespace hp {
+
+// Spins for at most max_us microseconds until *flag (pinned host memory that
 // a kernel writes) equals `want`. Returns false when the time is up (the
 // caller then waits for the stream).
-bool poll_host(const double* flag, double want) {
-    constexpr double kPollUs = 300.0;
+bool poll_host(const double* flag, double want, double max_us) {
+    const double kPollUs = max_us;
     const auto t0 = std::chrono::steady_clock::now();
     const volatile double* f = flag;
     for (int i = 0;; ++i) {
@@ -444,6 +448,10 @@ bool poll_host(const double* flag, double want) {
             return false;
     }
 }
+
+}  // namespace hp
+
+namespace {
 
 int run_solve_device(Solver& S, char* ws, const double* A, int64_t lda, const double* X0,
                      int64_t ldx0, double* X, int64_t ldx) {
@@ -860,7 +868,7 @@ int run_solve(Solver& S, char* ws, const double* A, int64_t lda, const double* X
             HIPCHK(hipMemcpyAsync(hs, bf.scal, sizeof(double) * SLOT_COUNT, hipMemcpyDeviceToHost, s));
         // a short loop's sums arrive within microseconds: poll for them rather
         // than sleep in the stream wait (kernel timing needs the wait)
-        if (!direct || S.timer.on || !poll_host(S.h->host_sums + SLOT_COUNT, seq))
+        if (!direct || S.timer.on || !poll_host(S.h->host_sums + SLOT_COUNT, seq, 300.0))
             HIPCHK(hipStreamSynchronize(s));
         if (direct) std::memcpy(hs, S.h->host_sums, sizeof(double) * SLOT_COUNT);
         S.timer.harvest();

@@ -181,6 +181,9 @@ struct Plan {
 // convergence sets in (LoopState::kBest; batched and served solves return X_k
 // on divergence instead).
 Plan make_plan(const hp_params* p, int64_t m, int64_t n, bool single = true);
+// Spins for at most max_us microseconds until *flag (pinned host memory that
+// a kernel writes) equals `want`; false when the time is up.
+bool poll_host(const double* flag, double want, double max_us);
 int validate(const hp_params* p, int64_t m, int64_t n);
 
 

@@ -328,7 +328,6 @@ __global__ __launch_bounds__(kThreads) void k_reduce_pairs(const double* __restr
             __threadfence_system();
             // last: the host polls this number before reading the sums
             host[SLOT_COUNT] = seq;
-            __threadfence_system();
         }
     }
 }
@@ -453,7 +452,21 @@ __global__ __launch_bounds__(kThreads) void k_reduce_pairs_grouped(const int* __
     if (threadIdx.x == 0) {
         out[2 * blockIdx.x] = s0;
         out[2 * blockIdx.x + 1] = s1;
+        // (`out` may be pinned host memory: the signal launched after this
+        // kernel orders these writes before its flag)
     }
+}
+
+// One more loop signalled: the device counter, then its value in `flag`
+// (pinned host memory), which the host polls.
+__global__ void k_signal_host(unsigned long long* __restrict__ counter, double* __restrict__ flag) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long v = *counter + 1;
+    *counter = v;
+    // the earlier launches' writes to host memory are complete; one system
+    // fence per loop orders them before the flag
+    __threadfence_system();
+    *flag = (double)v;
 }
 
 // Elementwise precision conversion of an M x N matrix (round to nearest even
@@ -646,6 +659,11 @@ struct ReduceEntry {
     int pad;
 };
 static_assert(sizeof(ReduceEntry) == sizeof(ReduceEntryDev), "reduce table layout");
+
+hipError_t signal_host(unsigned long long* counter, double* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_signal_host, dim3(1), dim3(64), 0, s, counter, flag);
+    return hipGetLastError();
+}
 
 hipError_t reduce_pairs_grouped(const int* count, const ReduceEntry* ents, int grid, double* out,
                                 hipStream_t s) {
