@@ -631,8 +631,16 @@ int run_solve_device(Solver& S, char* ws, const double* A, int64_t lda, const do
                 ++c;
             }
         }
-        HIPCHK(hipMemcpyAsync(hs, L, offsetof(DevLoop, d_hist), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        double* direct = S.h->host_loop_dev;
+        const double seq = (double)++S.h->loop_seq;
+        if (direct)
+            CHK(loop_report(L, direct, seq, s));
+        else
+            HIPCHK(hipMemcpyAsync(hs, L, offsetof(DevLoop, d_hist), hipMemcpyDeviceToHost, s));
+        if (!direct || S.timer.on ||
+            !poll_host(S.h->host_loop + kLoopReportDoubles, seq, 1000.0))
+            HIPCHK(hipStreamSynchronize(s));
+        if (direct) std::memcpy(hs, S.h->host_loop, offsetof(DevLoop, d_hist));
         S.timer.harvest();
         const DevLoop& hl = *reinterpret_cast<const DevLoop*>(hs);
         if (hl.done || j >= p->max_iter) break;
@@ -1023,6 +1031,12 @@ int hp_create(hp_handle** out, int device) {
         hipHostGetDevicePointer(reinterpret_cast<void**>(&h->host_sums_dev), h->host_sums, 0) !=
             hipSuccess)
         h->host_sums_dev = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->host_loop),
+                      sizeof(double) * (hp::kLoopReportDoubles + 1),
+                      hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess &&
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&h->host_loop_dev), h->host_loop, 0) !=
+            hipSuccess)
+        h->host_loop_dev = nullptr;
     for (int i = 0; i < hp_handle::kEvents; ++i) {
         if (hipEventCreate(&h->ev[i]) != hipSuccess) {
             hp_destroy(h);
@@ -1050,6 +1064,7 @@ int hp_destroy(hp_handle* h) {
         if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
     if (h->host_sums) (void)hipHostFree(h->host_sums);
+    if (h->host_loop) (void)hipHostFree(h->host_loop);
     delete h;
     return HP_OK;
 }

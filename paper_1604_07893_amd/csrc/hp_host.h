@@ -43,6 +43,12 @@ struct hp_handle {
     double* host_sums = nullptr;
     double* host_sums_dev = nullptr;
     uint64_t sums_seq = 0;
+    // device_stop: the head of the DevLoop state, written by the device at
+    // the end of each chunk of loops, then the chunk's number (loop_seq)
+    // after it, which the host polls in place of a copy and a stream wait
+    double* host_loop = nullptr;
+    double* host_loop_dev = nullptr;
+    uint64_t loop_seq = 0;
     static constexpr int kHostExtra = 16;
     static constexpr int kEvents = 64;
     hipEvent_t ev[kEvents] = {};

@@ -311,6 +311,12 @@ hipError_t diff_norm_inf_gated(const double* X1, int64_t ld1, const double* X0, 
 // One loop's stop / switch / guard decision (LoopState::step for an FP64
 // solve) from scal's sums; `ik` is the index (0 or 1) of the loop's input.
 hipError_t loop_step(const double* scal, DevLoop* L, const StepParams* P, hipStream_t s);
+// Copies the decision fields of *L (the bytes before d_hist) to `host` (the
+// device address of pinned host memory with room for them and one more
+// double), then writes `seq` into that last double: the host polls it.
+hipError_t loop_report(const DevLoop* L, double* host, double seq, hipStream_t s);
+constexpr int kLoopReportDoubles = (int)(offsetof(DevLoop, d_hist) / sizeof(double));
+static_assert(offsetof(DevLoop, d_hist) % sizeof(double) == 0, "DevLoop header in whole doubles");
 // dst = src (rows x cols doubles) when the gate is open.
 hipError_t copy_gated(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
                       int64_t cols, const DevLoop* L, int mode, hipStream_t s);

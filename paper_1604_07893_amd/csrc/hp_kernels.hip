@@ -457,6 +457,16 @@ __global__ __launch_bounds__(kThreads) void k_reduce_pairs_grouped(const int* __
     }
 }
 
+// The decision fields of the device loop (the doubles before its change
+// history) to pinned host memory, then `seq` after them.
+__global__ void k_loop_report(const double* __restrict__ L, double* __restrict__ host, int n,
+                              double seq) {
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < n; ++i) host[i] = L[i];
+    __threadfence_system();
+    host[n] = seq;
+}
+
 // One more loop signalled: the device counter, then its value in `flag`
 // (pinned host memory), which the host polls.
 __global__ void k_signal_host(unsigned long long* __restrict__ counter, double* __restrict__ flag) {
@@ -659,6 +669,12 @@ struct ReduceEntry {
     int pad;
 };
 static_assert(sizeof(ReduceEntry) == sizeof(ReduceEntryDev), "reduce table layout");
+
+hipError_t loop_report(const DevLoop* L, double* host, double seq, hipStream_t s) {
+    hipLaunchKernelGGL(k_loop_report, dim3(1), dim3(64), 0, s, reinterpret_cast<const double*>(L),
+                       host, kLoopReportDoubles, seq);
+    return hipGetLastError();
+}
 
 hipError_t signal_host(unsigned long long* counter, double* flag, hipStream_t s) {
     hipLaunchKernelGGL(k_signal_host, dim3(1), dim3(64), 0, s, counter, flag);
