@@ -303,7 +303,8 @@ def extra_lowrank(hpw, torch, steps) -> dict:
                "iters": inf["iters"], "switch_iter": inf["switch_iter"], "side": inf["side"],
                "rel_err_vs_closed_form": trel(torch, X, closed)}
         if prec == "fp64":
-            rl = engine_roofline(infos, 2, PEAK_TFLOPS["f64"], "k_gemm<double> (FP64 MFMA)")
+            rl = engine_roofline(infos, 2, PEAK_TFLOPS["f64"], "FP64 MFMA GEMMs (k_gemm_w4dma from "
+                                 "512 output tiles, k_gemm<double> below)")
             rec["gemm_roofline"] = rl
             rec["gflop_per_launch"] = inf["gflop"] / max(inf["gemms"], 1)
         if prec == "fp32":
@@ -650,8 +651,8 @@ def main() -> int:
     last = infos[-1]
     launches = sum(i["gemms"] for i in infos)
     rl = engine_roofline(infos, 2, PEAK_TFLOPS["f64"],
-                         "k_gemm<double> (FP64 MFMA GEMM with the fused loop epilogue), "
-                         f"{NSQ}x{NSQ}x{NSQ} per launch")
+                         "k_gemm_w4dma (FP64 MFMA GEMM, 4 waves of 64x64, load-to-LDS tiles, "
+                         f"with the fused loop epilogue), {NSQ}x{NSQ}x{NSQ} per launch")
     traffic, traffic_src = measured_traffic()
     roofline = {
         "bound": "mfma", "kernel": rl["kernel"], "achieved": rl["achieved"],

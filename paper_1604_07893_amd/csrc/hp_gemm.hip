@@ -13,6 +13,9 @@
 // over 2 or 4 blocks per tile; the last block of a tile to finish adds the
 // partial tiles in a fixed order, so the result does not depend on which
 // block finishes last.
+// Large FP64 products (from 512 output tiles) run instead on k_gemm_w4dma:
+// 4 waves of 64 x 64 per 128 x 128 tile, tiles brought to LDS by the
+// load-to-LDS instruction, two blocks per CU.
 // The epilogue forms up to three outputs
 //     out_o = id_o * I + acc_o * (A B) + g1_o * D1 + g2_o * D2
 // (the linear combinations of one loop of iteration (PM), Section 2) and,
@@ -758,6 +761,119 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_lp(
 }
 
 
+// FP64 on 128 x 128 tiles of 4 waves (2 x 2), each wave a 64 x 64 sub-tile
+// (16 accumulators, 128 VGPRs), K-tile 16, two blocks per CU. The tiles come
+// to LDS by the load-to-LDS instruction (global_load_lds_dwordx4: a wave's
+// instruction fills 1 KB, 16 bytes per lane in lane order), two stages, with
+// no staging registers and no LDS store instructions. Per K-tile a wave reads
+// all its fragments (8 reads of 16 bytes of A, 8 paired reads of B), then
+// issues the next K-tile's loads into the other stage (so that no LDS read
+// waits behind a load in flight), then runs its 64 MFMAs; one barrier per
+// K-tile. Each block keeps one wave per SIMD, so the other block's MFMAs fill
+// the matrix pipe while a block reads fragments or waits at its barrier.
+// A stage: 128 rows of 16 elements; row r's 16-byte chunk c sits in slot
+// c ^ (r % 8), so the lanes of a fragment read that share a cycle hit distinct
+// banks. B stage: 16 rows of 128 elements as in memory. Rows beyond M and
+// columns beyond N are read from the last row (column pair) and feed only
+// outputs that are not stored. Needs N, lda, ldb even, K % 16 == 0 and A, B
+// 16-byte aligned (w4dma_fits).
+__global__ __launch_bounds__(256, 2) void k_gemm_w4dma(
+    int M, int N, int K, const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+    int64_t ldb, EpilogueT<double> ep, int tiles_m, int tiles_n) {
+    constexpr int BM = 128, BN = 128, BK = 16, WAVES = 4, TI = 4, TJ = 4;
+    if (gate_closed(ep.gate, ep.gate_mode)) return;  // uniform over the launch
+    __shared__ __attribute__((aligned(16))) double As[2][BM * BK];
+    __shared__ __attribute__((aligned(16))) double Bs[2][BK * BN];
+    __shared__ double red[2][WAVES];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int tm, tn;
+    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    const int bm = tm * BM, bn = tn * BN;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    // the wave's instruction d fills A tile rows 8 (wave + 4 d) .. + 7 (lane
+    // l: row 8 (wave + 4 d) + l / 8, chunk (l % 8) ^ (row % 8)) and B tile row
+    // wave + 4 d (lane l: columns 2 l, 2 l + 1)
+    const double* a_src[4];
+    const double* b_src[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int r = 8 * (wave + 4 * d) + (lane >> 3);
+        a_src[d] = A + (int64_t)min(bm + r, M - 1) * lda + 2 * ((lane & 7) ^ (r & 7));
+        b_src[d] = B + (int64_t)(wave + 4 * d) * ldb + min(bn + 2 * lane, N - 2);
+    }
+    // (the builtin takes an LDS address-space pointer, which exists only in
+    // the device compilation; the host pass sees an empty body)
+    auto issue = [&](int st, int k0) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            __builtin_amdgcn_global_load_lds(a_src[d] + k0, &As[st][8 * (wave + 4 * d) * BK], 16, 0, 0);
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            __builtin_amdgcn_global_load_lds(b_src[d] + (int64_t)k0 * ldb, &Bs[st][(wave + 4 * d) * BN],
+                                             16, 0, 0);
+#else
+        (void)st;
+        (void)k0;
+#endif
+    };
+    dbl4 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = dbl4{};
+    const int fr = lane & 15, fg = lane >> 4;
+    typedef double dbl2 __attribute__((ext_vector_type(2)));
+    dbl2 fa[2][TI];
+    double fb[2][TJ][2];
+    const int nk = K / BK;
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        const int st = t & 1;
+        // lane group fg supplies k = 4 fg + 2 g + e of the K-tile: chunk
+        // 2 fg + g of an A row, rows 4 fg + 2 g + e of B
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int c = 2 * fg + g;
+#pragma unroll
+            for (int i = 0; i < TI; ++i) {
+                const int r = wm + 16 * i + fr;
+                fa[g][i] = *reinterpret_cast<const dbl2*>(&As[st][r * BK + 2 * (c ^ (r & 7))]);
+            }
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) fb[g][j][e] = Bs[st][(2 * c + e) * BN + wn + 16 * j + fr];
+        }
+        // issued on every K-tile (the last one re-reads its own K-range into
+        // the stage nobody reads again), so that no branch lets the compiler
+        // move the MFMAs above it; the scheduling barriers keep the loads
+        // ahead of the MFMAs and the MFMAs ahead of the closing wait
+        issue(st ^ 1, (t + 1 < nk ? t + 1 : t) * BK);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j)
+                        acc[i][j] = Mfma<double>::mma(fa[g][i][e], fb[g][j][e], acc[i][j]);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next K-tile
+        __syncthreads();                // everyone's, and every read of this stage
+    }
+    tile_epilogue<double, TI, TJ, WAVES>(acc, ep, M, N, bm, bn, wm, wn, blockIdx.x, red);
+}
+
+bool w4dma_fits(int64_t N, int64_t K, int64_t lda, int64_t ldb, const void* A, const void* B) {
+    return N >= 2 && N % 2 == 0 && K > 0 && K % 16 == 0 && lda % 2 == 0 && ldb % 2 == 0 &&
+           (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+}
+
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1>
 hipError_t launch(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
                   int64_t ldb, const EpilogueT<T>& ep, hipStream_t s) {
@@ -857,7 +973,7 @@ hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int
     constexpr int BKF = 16 * sizeof(double) / sizeof(T);  // 128-byte K-tile rows
     if (ep.sym && M == N && !ep.ref) {
         hipError_t e = hipSuccess;
-        if (t == TILE_128x128_W16_K2_P2 &&
+        if ((t == TILE_128x128_W16_K2_P2 || t == TILE_128x128_W4_DMA) &&
             launch_sym<T, 128, 128, 2 * BKF, 32, 32, 2>(N, K, A, lda, B, ldb, ep, s, &e))
             return e;
         if (t == TILE_128x128_W8 && launch_sym<T, 128, 128, BKF, 64, 32, 1>(N, K, A, lda, B, ldb, ep, s, &e))
@@ -879,6 +995,19 @@ hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int
         case TILE_128x128_W8_S4: return launch_split<T, BKF, 4>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_128x128_W16_K2_P2: return launch<T, 128, 128, 2 * BKF, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
         case TILE_32x32_W4_K4: return launch<T, 32, 32, 4 * BKF, 16, 16>(M, N, K, A, lda, B, ldb, ep, s);
+        case TILE_128x128_W4_DMA:
+            if constexpr (std::is_same<T, double>::value) {
+                // otherwise the 16-wave kernel on the same 128 x 128 tiles
+                // (the same blocks, so the same partial-sum slots)
+                if (!w4dma_fits(N, K, lda, ldb, A, B))
+                    return launch<T, 128, 128, 2 * BKF, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
+                const int tm = (int)cdiv(M, 128), tn = (int)cdiv(N, 128);
+                hipLaunchKernelGGL(k_gemm_w4dma, dim3(tm * tn), dim3(256), 0, s, (int)M, (int)N,
+                                   (int)K, A, lda, B, ldb, ep, tm, tn);
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;
+            }
         default: return hipErrorInvalidValue;
     }
 }
@@ -961,7 +1090,7 @@ template <typename T>
 static bool sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<T>& ep) {
     constexpr int BKF = 16 * sizeof(double) / sizeof(T);
     if (!ep.sym || M != N || ep.ref || K <= 0) return false;
-    if (t == TILE_128x128_W16_K2_P2)
+    if (t == TILE_128x128_W16_K2_P2 || t == TILE_128x128_W4_DMA)
         return sym_fits(sym_shape<T, 128, 128, 2 * BKF, 32, 32, 2>(N, K), ep);
     if (t == TILE_128x128_W8) return sym_fits(sym_shape<T, 128, 128, BKF, 64, 32, 1>(N, K), ep);
     return false;
@@ -974,7 +1103,9 @@ bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const Epilog
 }
 
 bool gemm_sym_runs(GemmTile t, GemmType gt) {
-    return (gt == GT_F64 || gt == GT_F32) && (t == TILE_128x128_W16_K2_P2 || t == TILE_128x128_W8);
+    // (the load-to-LDS tile's symmetric products run on the 16-wave kernel)
+    return ((gt == GT_F64 || gt == GT_F32) && (t == TILE_128x128_W16_K2_P2 || t == TILE_128x128_W8)) ||
+           (gt == GT_F64 && t == TILE_128x128_W4_DMA);
 }
 
 void gemm_sym_scratch(GemmTile t, GemmType gt, int64_t n, int64_t* slots, int64_t* counters) {

@@ -33,6 +33,7 @@ constexpr TileShape kShapes[] = {
     {256, 256},  // TILE_256x256_W8_DMA (16-bit-operand kernel, load-to-LDS)
     {256, 256},  // TILE_256x256_W16_DMA (16-bit-operand kernel, load-to-LDS)
     {32, 32},    // TILE_32x32_W4_K4: 4 waves of 16x16, 4x deeper K-tile
+    {128, 128},  // TILE_128x128_W4_DMA: 4 waves of 64x64, load-to-LDS (FP64)
 };
 static_assert(sizeof(kShapes) / sizeof(kShapes[0]) == TILE_COUNT, "tile table");
 
@@ -57,7 +58,9 @@ bool gemm_runs(GemmTile t, GemmType gt) {
                    t == TILE_256x256_W8 || t == TILE_256x256_W16 || t == TILE_128x128_W16 ||
                    t == TILE_128x128_W8;
         case GT_LOWP: return t <= TILE_128x128_W16_K2_P2;
-        default: return t <= TILE_128x128_W16_K2_P2 || t == TILE_32x32_W4_K4;
+        default:
+            return t <= TILE_128x128_W16_K2_P2 || t == TILE_32x32_W4_K4 ||
+                   (gt == GT_F64 && t == TILE_128x128_W4_DMA);
     }
 }
 
@@ -71,7 +74,9 @@ GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow
     // below. With fewer tiles than CUs and a long K, splitting K four ways
     // fills the chip (FP64 1024x1024x2048: 33.6 TFLOP/s against 14.6 unsplit
     // and 27.7 on 64x64 tiles); short K or the FP32 1536^2 case favour 64x64
-    // tiles. The 16-bit kernel does not split.
+    // tiles. The 16-bit kernel does not split. FP64 from two 128x128 tiles per
+    // CU: the 4-wave 64x64-per-wave tile filled by load-to-LDS, two blocks
+    // per CU (8192^3: 71.8 TFLOP/s against 65.5; 4096^3: 65.0 against 59-65).
     const int64_t tiles = cdiv(M, 128) * cdiv(N, 128);
     if (gt == GT_H16) {
         // 16-bit operands in memory: 256x256 tiles filled by load-to-LDS from
@@ -93,6 +98,7 @@ GemmTile gemm_pick_tile(int64_t M, int64_t N, int64_t K, GemmType gt, bool allow
     // 39.7; 768^3: 52.5 against 56.8; 1024^3 favours 64x64 again).
     const bool small = cdiv(M, 64) * cdiv(N, 64) <= 144 && K <= 1024;
     if (gt == GT_F64) {
+        if (tiles >= 512) return TILE_128x128_W4_DMA;
         if (tiles >= 256) return TILE_128x128_W16_K2_P2;
         if (small) return TILE_32x32_W4_K4;
         if (allow_split && K >= 1024) return TILE_128x128_W8_S4;

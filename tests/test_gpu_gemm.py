@@ -263,3 +263,62 @@ def test_gemm_16bit_operands_in_memory(dt, M, N, K, tile, tmp_path):
     err = np.abs(C.cpu().numpy().astype(np.float64) - ref)
     assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
 
+
+
+# The 4-wave FP64 tile filled by load-to-LDS (tile 19), forced through the
+# tuning table: ragged M and N, a single K-tile, N = 2, and two shapes it hands
+# to the 16-wave kernel on the same tiles (K not a multiple of 16, odd N).
+DMA_TILE = 19
+
+
+@pytest.mark.parametrize("M,N,K", [(256, 256, 16), (300, 260, 48), (130, 2, 32), (1000, 1002, 1024),
+                                   (512, 384, 100), (300, 259, 64)])
+def test_gemm_f64_load_to_lds_tile(M, N, K, tmp_path):
+    import json
+    hpw = need_gpu()
+    say(f"gemm f64 load-to-LDS tile M={M} N={N} K={K}")
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"rows": [[0, M, N, K, DMA_TILE]]}))
+    hpw.load_tuning(str(path))
+    rng = np.random.default_rng(M + 13 * N + 17 * K)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    Ad, Bd = _dev_pad(A, torch.float64), _dev_pad(B, torch.float64)
+    C1 = hpw.gemm(Ad, Bd)
+    C2 = hpw.gemm(Ad, Bd, alpha=-1.0, beta_identity=1.0)
+    torch.cuda.synchronize()
+    ref = A @ B
+    bound = (np.abs(A) @ np.abs(B)) * (2 * K + 4) * U64
+    err = np.abs(C1.cpu().numpy() - ref)
+    assert np.all(err <= bound + 1e-300), float((err / (bound + 1e-300)).max())
+    # the epilogue's identity and scale on the same tile: exactly I - C1
+    assert torch.equal(C2, torch.eye(M, N, dtype=torch.float64, device="cuda:0") - C1)
+
+
+def test_solve_on_the_load_to_lds_tile_matches_the_16_wave_tile(tmp_path):
+    """A 3072^2 FP64 solve (576 tiles per product: the load-to-LDS tile by
+    default) against the same solve with the 16-wave tile forced: same loop
+    count, X equal to rounding, and A X = I to 1e-10."""
+    import json
+    hpw = need_gpu()
+    n = 3072
+    say(f"solve f64 {n}^2 load-to-LDS tile vs 16-wave tile")
+    g = torch.Generator(device="cuda:0").manual_seed(3072)
+    A = torch.randn((n, n), dtype=torch.float64, device="cuda:0", generator=g) / n**0.5
+    A += 2.0 * torch.eye(n, dtype=torch.float64, device="cuda:0")   # singular values in ~[1, 3]
+    X1, info1 = hpw.solve(A, tol=1e-12)
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"rows": [[0, n, n, n, 13]]}))
+    hpw.load_tuning(str(path))
+    try:
+        X2, info2 = hpw.solve(A, tol=1e-12)
+    finally:
+        path.write_text(json.dumps({"rows": [[0, n, n, n, DMA_TILE]]}))
+        hpw.load_tuning(str(path))
+    torch.cuda.synchronize()
+    assert info1["status"] == info2["status"] == "ok"
+    assert info1["iters"] == info2["iters"]
+    scale = float(X2.abs().max())
+    assert float((X1 - X2).abs().max()) <= 1e-12 * scale
+    I = torch.eye(n, dtype=torch.float64, device="cuda:0")
+    assert float((A @ X1 - I).abs().max()) <= 1e-10
