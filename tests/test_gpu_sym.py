@@ -227,3 +227,26 @@ def test_symmetric_products_with_gpu_alpha():
     assert i_s["status"] == i_f["status"] == "ok"
     assert i_s["gemms_sym"] > 0 and i_s["iters"] == i_f["iters"]
     assert es <= 1e-10 and es <= 2.0 * ef + 1e-11
+
+
+def test_solve_symmetric_beside_the_load_to_lds_tile():
+    """3072^2 (576 tiles per product: full products on the load-to-LDS tile,
+    symmetric ones on the 16-wave stream-K kernel) with HP_FLAG_SYMMETRIC
+    against the same solve with full products: same loops, both at the
+    closed-form inverse to 1e-10."""
+    hpw = need_gpu()
+    say("solve sym vs full 3072^2 load-to-LDS tile")
+    d = inputs.lowrank_svd(3072, 3072, 3072, smin=1e-3, seed=3072)
+    closed = (d.V / d.s) @ d.U.T
+    A = to_dev(d.A)
+    kw = dict(alpha_rule="user", alpha=1.0, tol=1e-10)
+    Xs, i_s = hpw.solve(A, symmetric=True, **kw)
+    Xf, i_f = hpw.solve(A, **kw)
+    torch.cuda.synchronize()
+    assert i_s["status"] == i_f["status"] == "ok"
+    assert i_s["gemms_sym"] > 0 and i_f["gemms_sym"] == 0
+    assert i_s["iters"] == i_f["iters"]
+    xs, xf = Xs.cpu().numpy(), Xf.cpu().numpy()
+    es, ef = rel(xs, closed), rel(xf, closed)
+    say(f"  iters {i_s['iters']}: err sym {es:.2e}, full {ef:.2e}")
+    assert es <= 1e-10 and ef <= 1e-10 and es <= 2.0 * ef + 1e-11
