@@ -15,7 +15,8 @@
 // block finishes last.
 // Large FP64 products (from 512 output tiles) run instead on k_gemm_w4dma:
 // 4 waves of 64 x 64 per 128 x 128 tile, tiles brought to LDS by the
-// load-to-LDS instruction, two blocks per CU.
+// load-to-LDS instruction, two blocks per CU; large FP32 products (from 256
+// tiles of 256 x 256) on k_gemm_w4dma_f32, 4 waves of 128 x 128 per tile.
 // The epilogue forms up to three outputs
 //     out_o = id_o * I + acc_o * (A B) + g1_o * D1 + g2_o * D2
 // (the linear combinations of one loop of iteration (PM), Section 2) and,
@@ -113,33 +114,47 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(
     const int lane = tid & 63, wave = tid >> 6;
     const int fr = lane & 15, fg = lane >> 4;
     double s_diff = 0.0, s_ref = 0.0;
+    // Per 16 x 16 accumulator, the reads of its 4 elements (D1, D2 and the
+    // stopping test's reference) are all issued before any of its stores, so
+    // that a lane waits once per accumulator rather than once per element.
+    // An element reads those inputs only at its own position, so reading them
+    // ahead of the other elements' stores changes no value.
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
 #pragma unroll
         for (int j = 0; j < TJ; ++j) {
+            const int col = bn + wn + j * 16 + fr;
+            T d1[4], d2[4];
+            double x0[4];
+            bool ok[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = bm + wm + i * 16 + Mfma<T>::row(fg, r);
-                const int col = bn + wn + j * 16 + fr;
-                if (row < M && col < N && (!SYM || row <= col)) {
+                ok[r] = row < M && col < N && (!SYM || row <= col);
+                d1[r] = ok[r] && ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : T(0);
+                d2[r] = ok[r] && ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : T(0);
+                x0[r] = !SYM && ok[r] && ep.ref && ep.out[0] ? (double)ep.ref[(int64_t)row * ep.ldref + col]
+                                                            : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = bm + wm + i * 16 + Mfma<T>::row(fg, r);
+                if (ok[r]) {
                     const T a = acc[i][j][r];
-                    const T d1 = ep.D1 ? ep.D1[(int64_t)row * ep.ld1 + col] : T(0);
-                    const T d2 = ep.D2 ? ep.D2[(int64_t)row * ep.ld2 + col] : T(0);
 #pragma unroll
                     for (int o = 0; o < 3; ++o) {
                         if (ep.out[o]) {
                             T v = T(ep.acc_c[o]) * a;
                             if (row == col && ep.id[o] != 0.0) v += T(ep.id[o]);
-                            if (ep.D1 && ep.g1[o] != 0.0) v += T(ep.g1[o]) * d1;
-                            if (ep.D2 && ep.g2[o] != 0.0) v += T(ep.g2[o]) * d2;
+                            if (ep.D1 && ep.g1[o] != 0.0) v += T(ep.g1[o]) * d1[r];
+                            if (ep.D2 && ep.g2[o] != 0.0) v += T(ep.g2[o]) * d2[r];
                             if (o == 0 && ep.chop > 0.0 && fabs((double)v) < ep.chop) v = T(0);
                             ep.out[o][(int64_t)row * ep.ldo[o] + col] = v;
                             if (SYM && row != col) ep.out[o][(int64_t)col * ep.ldo[o] + row] = v;
                             if (!SYM && o == 0 && ep.ref) {
-                                const double x0 = (double)ep.ref[(int64_t)row * ep.ldref + col];
-                                const double df = (double)v - x0;
+                                const double df = (double)v - x0[r];
                                 s_diff += df * df;
-                                s_ref += x0 * x0;
+                                s_ref += x0[r] * x0[r];
                             }
                         }
                     }
@@ -874,6 +889,115 @@ bool w4dma_fits(int64_t N, int64_t K, int64_t lda, int64_t ldb, const void* A, c
            (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
 }
 
+// FP32 on 256 x 256 tiles of 4 waves (2 x 2), each wave a 128 x 128
+// sub-tile: 64 accumulators in the 256 AGPRs, one wave per SIMD, K-tile 32,
+// two LDS stages of 64 KB. The structure of k_gemm_w4dma (tiles brought in
+// by load-to-LDS; per K-tile all fragment reads, then the next K-tile's
+// loads, then the MFMAs, then one barrier), with 512 MFMAs per wave per
+// K-tile against 48 LDS reads: the larger wave tile makes up for the single
+// wave per SIMD. A rows as in k_gemm_w4dma (16-byte chunk c of row r in slot
+// c ^ (r % 8)); B rows keep their 16-byte chunks with chunk q of row k in slot
+// q ^ (4 ((k / 8) % 2)), so that the two lane groups of a 4-byte fragment read
+// that share an LDS cycle (rows k and k + 8) use different banks. Needs N,
+// lda, ldb multiples of 4, K of 32, 16-byte aligned operands
+// (w4dma_f32_fits).
+__global__ __launch_bounds__(256, 1) void k_gemm_w4dma_f32(
+    int M, int N, int K, const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+    int64_t ldb, EpilogueT<float> ep, int tiles_m, int tiles_n) {
+    constexpr int BM = 256, BN = 256, BK = 32, WAVES = 4, TI = 8, TJ = 8;
+    if (gate_closed(ep.gate, ep.gate_mode)) return;  // uniform over the launch
+    __shared__ __attribute__((aligned(16))) float As[2][BM * BK];
+    __shared__ __attribute__((aligned(16))) float Bs[2][BK * BN];
+    __shared__ double red[2][WAVES];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int tm, tn;
+    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    const int bm = tm * BM, bn = tn * BN;
+    const int wm = (wave >> 1) * 128, wn = (wave & 1) * 128;
+    // the wave's instruction d fills A tile rows 8 (wave + 4 d) .. + 7 and B
+    // tile row wave + 4 d (1 KB each)
+    const float* a_src[8];
+    const float* b_src[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const int r = 8 * (wave + 4 * d) + (lane >> 3);
+        a_src[d] = A + (int64_t)min(bm + r, M - 1) * lda + 4 * ((lane & 7) ^ (r & 7));
+        const int k = wave + 4 * d;
+        b_src[d] = B + (int64_t)k * ldb + min(bn + 4 * (lane ^ (4 * ((k >> 3) & 1))), N - 4);
+    }
+    auto issue = [&](int st, int k0) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            __builtin_amdgcn_global_load_lds(a_src[d] + k0, &As[st][8 * (wave + 4 * d) * BK], 16, 0, 0);
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            __builtin_amdgcn_global_load_lds(b_src[d] + (int64_t)k0 * ldb, &Bs[st][(wave + 4 * d) * BN],
+                                             16, 0, 0);
+#else
+        (void)st;
+        (void)k0;
+#endif
+    };
+    flt4 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = flt4{};
+    const int fr = lane & 15, fg = lane >> 4;
+    typedef float flt4v_ __attribute__((ext_vector_type(4)));
+    flt4v_ fa[2][TI];
+    float fb[2][TJ][4];
+    const int nk = K / BK;
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int t = 0; t < nk; ++t) {
+        const int st = t & 1;
+        // lane group fg supplies k = 8 fg + 4 g + e: chunk 2 fg + g of an A
+        // row, rows 4 (2 fg + g) + e of B
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int c = 2 * fg + g;
+#pragma unroll
+            for (int i = 0; i < TI; ++i) {
+                const int r = wm + 16 * i + fr;
+                fa[g][i] = *reinterpret_cast<const flt4v_*>(&As[st][r * BK + 4 * (c ^ (r & 7))]);
+            }
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) {
+                const int col = wn + 16 * j + fr;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 4 * c + e;
+                    fb[g][j][e] = Bs[st][k * BN + 4 * ((col >> 2) ^ (4 * ((k >> 3) & 1))) + (col & 3)];
+                }
+            }
+        }
+        // as in k_gemm_w4dma: loads on every K-tile, order pinned
+        issue(st ^ 1, (t + 1 < nk ? t + 1 : t) * BK);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j)
+                        acc[i][j] = Mfma<float>::mma(fa[g][i][e], fb[g][j][e], acc[i][j]);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+    tile_epilogue<float, TI, TJ, WAVES>(acc, ep, M, N, bm, bn, wm, wn, blockIdx.x, red);
+}
+
+bool w4dma_f32_fits(int64_t N, int64_t K, int64_t lda, int64_t ldb, const void* A, const void* B) {
+    return N >= 4 && N % 4 == 0 && K > 0 && K % 32 == 0 && lda % 4 == 0 && ldb % 4 == 0 &&
+           (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+}
+
 template <typename T, int BM, int BN, int BK, int WM, int WN, int PF = 1>
 hipError_t launch(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
                   int64_t ldb, const EpilogueT<T>& ep, hipStream_t s) {
@@ -1003,6 +1127,19 @@ hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int
                     return launch<T, 128, 128, 2 * BKF, 32, 32, 2>(M, N, K, A, lda, B, ldb, ep, s);
                 const int tm = (int)cdiv(M, 128), tn = (int)cdiv(N, 128);
                 hipLaunchKernelGGL(k_gemm_w4dma, dim3(tm * tn), dim3(256), 0, s, (int)M, (int)N,
+                                   (int)K, A, lda, B, ldb, ep, tm, tn);
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;
+            }
+        case TILE_256x256_W4_DMA:
+            if constexpr (std::is_same<T, float>::value) {
+                // otherwise a register-staged kernel on the same 256 x 256
+                // tiles (the same blocks, so the same partial-sum slots)
+                if (!w4dma_f32_fits(N, K, lda, ldb, A, B))
+                    return launch<T, 256, 256, BKF, 128, 64>(M, N, K, A, lda, B, ldb, ep, s);
+                const int tm = (int)cdiv(M, 256), tn = (int)cdiv(N, 256);
+                hipLaunchKernelGGL(k_gemm_w4dma_f32, dim3(tm * tn), dim3(256), 0, s, (int)M, (int)N,
                                    (int)K, A, lda, B, ldb, ep, tm, tn);
                 return hipGetLastError();
             } else {

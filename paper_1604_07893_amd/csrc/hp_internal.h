@@ -147,7 +147,8 @@ enum GemmTile : int {
     TILE_256x256_W16_DMA = 17,  // TILE_256x256_W16 with load-to-LDS tiles (K % 64 == 0)
     TILE_32x32_W4_K4 = 18,  // 4 waves, 16x16 each, K-tile four times as deep (small products)
     TILE_128x128_W4_DMA = 19,  // FP64 only: 4 waves of 64x64, load-to-LDS tiles (K % 16 == 0)
-    TILE_COUNT = 20
+    TILE_256x256_W4_DMA = 20,  // FP32 only: 4 waves of 128x128, load-to-LDS tiles (K % 32 == 0)
+    TILE_COUNT = 21
 };
 
 // Blocks (and partial-sum pairs) a launch with this tile uses for M x N.

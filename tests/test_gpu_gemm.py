@@ -322,3 +322,33 @@ def test_solve_on_the_load_to_lds_tile_matches_the_16_wave_tile(tmp_path):
     assert float((X1 - X2).abs().max()) <= 1e-12 * scale
     I = torch.eye(n, dtype=torch.float64, device="cuda:0")
     assert float((A @ X1 - I).abs().max()) <= 1e-10
+
+
+# The 4-wave FP32 tile of 128 x 128 per wave (tile 20, 256 x 256 tiles,
+# load-to-LDS), forced through the tuning table: a single K-tile, ragged M and
+# N, and shapes it hands to a register-staged kernel on the same tiles (N not a
+# multiple of 4, K not a multiple of 32).
+F32_DMA_TILE = 20
+
+
+@pytest.mark.parametrize("M,N,K", [(256, 256, 32), (300, 260, 64), (520, 1000, 96), (1000, 1004, 1024),
+                                   (300, 258, 64), (512, 384, 100)])
+def test_gemm_f32_load_to_lds_tile(M, N, K, tmp_path):
+    import json
+    hpw = need_gpu()
+    say(f"gemm f32 load-to-LDS tile M={M} N={N} K={K}")
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"rows": [[1, M, N, K, F32_DMA_TILE]]}))
+    hpw.load_tuning(str(path))
+    rng = np.random.default_rng(M + 19 * N + 23 * K)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    Ad, Bd = _dev_pad(A.astype(np.float64), torch.float32), _dev_pad(B.astype(np.float64), torch.float32)
+    C1 = hpw.gemm(Ad, Bd)
+    C2 = hpw.gemm(Ad, Bd, alpha=-1.0, beta_identity=1.0)
+    torch.cuda.synchronize()
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    bound = (np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64)) * (2 * K + 4) * 2.0**-24
+    err = np.abs(C1.cpu().numpy().astype(np.float64) - ref)
+    assert np.all(err <= bound + 1e-30), float((err / (bound + 1e-30)).max())
+    assert torch.equal(C2, torch.eye(M, N, dtype=torch.float32, device="cuda:0") - C1)
