@@ -699,7 +699,8 @@ def main() -> int:
         bd = {"f64": {k: v for k, v in roofline.items() if k not in ("traffic", "traffic_unit",
                                                                       "traffic_source", "timing")}}
         bd["f32"] = engine_roofline(minf, 1, PEAK_TFLOPS["f32"],
-                                    "k_gemm<float> (FP32 MFMA), mixed run: FP32 stage and the "
+                                    "k_gemm_w4dma_f32 (FP32 MFMA, 4 waves of 128x128 per 256x256 tile, "
+                                    "load-to-LDS), mixed run: FP32 stage and the "
                                     "delta-form polynomials of the FP64 stage, 8192^3")
         bd["bf16"] = engine_roofline(minf, 0, PEAK_TFLOPS["bf16"],
                                      "k_gemm_h16_dma (bf16 operands, FP32 accumulate), mixed run's "
