@@ -62,6 +62,18 @@ def test_drazin_plain_and_stabilised(variant, n, nb):
     same(X0, i0, X1, i1)
 
 
+def test_large_products_on_the_load_to_lds_tile():
+    """3072^2 (576 tiles of 128^2): the products run on the load-to-LDS FP64
+    tile, whose launches are gated like the others. Decisions and X bitwise
+    those of the host loop."""
+    d = inputs.square_svd(3072, smin=1e-3, seed=3073)
+    X0, i0, X1, i1 = both(d.A, alpha_rule="user", alpha=1.0, tol=1e-10)
+    say(f"3072^2: {i1['status']} iters {i1['iters']}")
+    same(X0, i0, X1, i1)
+    closed = (d.V / d.s) @ d.U.T
+    assert i1["status"] == "ok" and rel(X1.cpu().numpy(), closed) <= 1e-10
+
+
 def test_guards_and_loop_cap():
     A = inputs.uniform(90, 60, seed=4)
     s1 = np.linalg.svd(A, compute_uv=False)[0]
