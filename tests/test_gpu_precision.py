@@ -106,6 +106,27 @@ def test_mixed_8192_full_size_matches_closed_form(stop):
     torch.cuda.empty_cache()
 
 
+def test_fp64_8192_full_size_headline_matches_closed_form():
+    """The headline workload as the benchmark runs it (8192^2, plain (PM) in
+    FP64, X0 = A^T with alpha = 1 = 1/sigma_1^2, tol 1e-10; its products on the
+    load-to-LDS FP64 tile): 7 loops, X equals V diag(1/s) U^T within 1e-10,
+    and the sampled rows of X A X equal those of X."""
+    hpw = need_gpu()
+    say("fp64 8192^2 headline")
+    A, U, s, V = inputs.square_svd_device(8192, smin=1e-3, seed=1003)
+    X, info = hpw.solve(A, alpha_rule="user", alpha=1.0, tol=1e-10)
+    closed = (V / s) @ U.T.contiguous()
+    err = float(torch.linalg.norm(X - closed) / torch.linalg.norm(closed))
+    rows = torch.from_numpy(np.random.default_rng(8192).choice(8192, 16, replace=False)).cuda()
+    XA = X[rows] @ A
+    pen = float(torch.linalg.norm(XA @ X - X[rows]) / torch.linalg.norm(X[rows]))
+    say(f"  {info['status']} iters {info['iters']} err {err:.2e} XAX rows {pen:.2e}")
+    assert info["status"] == "ok" and info["iters"] == 7
+    assert err <= 1e-10 and pen <= 1e-10
+    del A, U, V, X, closed
+    torch.cuda.empty_cache()
+
+
 # ---- the delta form: R and the update in FP64, the polynomial in FP32 -------
 
 @pytest.mark.parametrize("m,n", [(384, 384), (200, 100), (100, 200)])
