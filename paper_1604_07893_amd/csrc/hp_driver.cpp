@@ -345,7 +345,7 @@ struct Solver {
         if (!(sym && sym_loop)) ep.sym = 0;
         const GemmTile t = choose_tile(h, dt, g.M, g.N, g.K, ep.split_slots);
         const bool sym_launch = eng == ENG_F64 || eng == ENG_F32
-                                    ? gemm_sym_launches(t, g.M, g.N, g.K, ep)
+                                    ? gemm_sym_launches(t, g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, ep)
                                     : false;
         timer.before();
         hipError_t e;
@@ -1210,7 +1210,7 @@ int hp_gemm(hp_handle* h, int dtype, int64_t M, int64_t N, int64_t K, double alp
 static void gemm_sym_ws(int dtype, int64_t N, int64_t* slots, int64_t* cnt) {
     *slots = *cnt = 0;
     const hp::GemmType gt = hp::gemm_type(dtype);
-    for (hp::GemmTile t : {hp::TILE_128x128_W16_K2_P2, hp::TILE_128x128_W8}) {
+    for (hp::GemmTile t : {hp::TILE_128x128_W16_K2_P2, hp::TILE_128x128_W8, hp::TILE_128x128_W4_DMA}) {
         int64_t sl = 0, c = 0;
         hp::gemm_sym_scratch(t, gt, N, &sl, &c);
         *slots = std::max(*slots, sl);

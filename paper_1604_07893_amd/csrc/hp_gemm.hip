@@ -181,6 +181,59 @@ __device__ __attribute__((always_inline)) inline void tile_epilogue(
     }
 }
 
+// Stream-K: the block holds piece `split` (in K order) of the sk_np pieces of
+// output tile `part`; piece 0's partial tile is slot sk_slot0 of
+// ep.split_part and piece i > 0's is slot 2 (sk_b0 + i). As the split-K path
+// of gemm_tile, with a tile-dependent piece count: every piece is stored, and
+// the last block to arrive reads them all back and adds them in K order (the
+// same bits whichever block is last) into acc and returns true; the other
+// blocks return false (uniformly over the block). A tile in one piece
+// returns true at once.
+template <typename T, int TI, int TJ, int NT, int TILE>
+__device__ inline bool streamk_gather(typename Mfma<T>::acc_t (&acc)[TI][TJ], const EpilogueT<T>& ep,
+                                      int tid, int part, int split, int sk_np, int sk_slot0, int sk_b0) {
+    if (sk_np <= 1) return true;
+    static_assert(TILE == TI * TJ * 4 * NT, "partial layout");
+    auto slot = [&](int i) {
+        return ep.split_part + (int64_t)(i == 0 ? sk_slot0 : 2 * (sk_b0 + i)) * TILE;
+    };
+    __shared__ unsigned sk_arrived;
+    T* mine = slot(split);
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) mine[((i * TJ + j) * 4 + r) * NT + tid] = acc[i][j][r];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        sk_arrived = __hip_atomic_fetch_add(&ep.split_cnt[part], 1u, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (sk_arrived != (unsigned)(sk_np - 1)) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = ((i * TJ + j) * 4 + r) * NT + tid;
+                T v = slot(0)[e];
+                for (int q = 1; q < sk_np; ++q) v += slot(q)[e];
+                asm volatile("" : "+v"(v));
+                acc[i][j][r] = v;
+            }
+        }
+    if (tid == 0) __hip_atomic_store(&ep.split_cnt[part], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
 // One BM x BN output tile (tm, tn) of C = epilogue(A * B); the block's
 // partial sums (if any) go to pair `part` of ep.partials. SPLIT < 0 (the
 // stream-K launch): the block holds piece `split` (in K order) of the
@@ -431,53 +484,9 @@ __device__ inline void gemm_tile(int M, int N, int K, const T* __restrict__ A, i
     }
 
     if constexpr (SPLIT < 0) {
-        // ---- stream-K: a piece of a tile shared with other blocks ----
-        // As the split-K path above, with a tile-dependent piece count: every
-        // piece is stored, and the last block to arrive reads them all back
-        // and adds them in K order (the same bits whichever block is last).
-        if (sk_np > 1) {
-            constexpr int TILE = BM * BN;
-            static_assert(TILE == C::TI * C::TJ * 4 * C::NT, "partial layout");
-            auto slot = [&](int i) {
-                return ep.split_part + (int64_t)(i == 0 ? sk_slot0 : 2 * (sk_b0 + i)) * TILE;
-            };
-            __shared__ unsigned sk_arrived;
-            T* mine = slot(split);
-#pragma unroll
-            for (int i = 0; i < C::TI; ++i)
-#pragma unroll
-                for (int j = 0; j < C::TJ; ++j)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        mine[((i * C::TJ + j) * 4 + r) * C::NT + tid] = acc[i][j][r];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __syncthreads();
-            if (tid == 0) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                sk_arrived = __hip_atomic_fetch_add(&ep.split_cnt[part], 1u, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            __syncthreads();
-            if (sk_arrived != (unsigned)(sk_np - 1)) return;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-#pragma unroll
-            for (int i = 0; i < C::TI; ++i)
-#pragma unroll
-                for (int j = 0; j < C::TJ; ++j) {
-                    asm volatile("" ::: "memory");
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int e = ((i * C::TJ + j) * 4 + r) * C::NT + tid;
-                        T v = slot(0)[e];
-                        for (int q = 1; q < sk_np; ++q) v += slot(q)[e];
-                        asm volatile("" : "+v"(v));
-                        acc[i][j][r] = v;
-                    }
-                }
-            if (tid == 0)
-                __hip_atomic_store(&ep.split_cnt[part], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (!streamk_gather<T, C::TI, C::TJ, C::NT, BM * BN>(acc, ep, tid, part, split, sk_np, sk_slot0,
+                                                             sk_b0))
+            return;
     }
 
     tile_epilogue<T, C::TI, C::TJ, C::WAVES, SYM>(acc, ep, M, N, bm, bn, wm, wn, part, red);
@@ -777,34 +786,37 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN)) void k_gemm_lp(
 
 
 // FP64 on 128 x 128 tiles of 4 waves (2 x 2), each wave a 64 x 64 sub-tile
-// (16 accumulators, 128 VGPRs), K-tile 16, two blocks per CU. The tiles come
-// to LDS by the load-to-LDS instruction (global_load_lds_dwordx4: a wave's
-// instruction fills 1 KB, 16 bytes per lane in lane order), two stages, with
-// no staging registers and no LDS store instructions. Per K-tile a wave reads
-// all its fragments (8 reads of 16 bytes of A, 8 paired reads of B), then
-// issues the next K-tile's loads into the other stage (so that no LDS read
-// waits behind a load in flight), then runs its 64 MFMAs; one barrier per
-// K-tile. Each block keeps one wave per SIMD, so the other block's MFMAs fill
-// the matrix pipe while a block reads fragments or waits at its barrier.
+// (16 accumulators, 128 VGPRs), K-tile 16, two blocks per CU (launch bounds:
+// at least two waves per SIMD). The tiles come to LDS by the load-to-LDS
+// instruction (global_load_lds_dwordx4: a wave's instruction fills 1 KB, 16
+// bytes per lane in lane order), two stages, with no staging registers and no
+// LDS store instructions. Per K-tile a wave reads all its fragments (8 reads
+// of 16 bytes of A, 8 paired reads of B), then issues the next K-tile's loads
+// into the other stage (so that no LDS read waits behind a load in flight),
+// then runs its 64 MFMAs; one barrier per K-tile. Each block keeps one wave
+// per SIMD, so the other block's MFMAs fill the matrix pipe while a block
+// reads fragments or waits at its barrier.
 // A stage: 128 rows of 16 elements; row r's 16-byte chunk c sits in slot
 // c ^ (r % 8), so the lanes of a fragment read that share a cycle hit distinct
 // banks. B stage: 16 rows of 128 elements as in memory. Rows beyond M and
 // columns beyond N are read from the last row (column pair) and feed only
 // outputs that are not stored. Needs N, lda, ldb even, K % 16 == 0 and A, B
 // 16-byte aligned (w4dma_fits).
-__global__ __launch_bounds__(256, 2) void k_gemm_w4dma(
-    int M, int N, int K, const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
-    int64_t ldb, EpilogueT<double> ep, int tiles_m, int tiles_n) {
-    constexpr int BM = 128, BN = 128, BK = 16, WAVES = 4, TI = 4, TJ = 4;
-    if (gate_closed(ep.gate, ep.gate_mode)) return;  // uniform over the launch
-    __shared__ __attribute__((aligned(16))) double As[2][BM * BK];
+//
+// The K loop of one tile: acc = A[bm.., 0..K) B[0..K, bn..) for the wave's
+// 64 x 64 sub-tile at (wm, wn). All threads of the block call it; it returns
+// with every load landed and every wave past its last LDS read, so the LDS
+// stages can be filled again at once.
+__device__ inline void w4dma_mainloop(dbl4 (&acc)[4][4], int M, int N, int K, const double* A,
+                                      int64_t lda, const double* B, int64_t ldb, int bm, int bn,
+                                      int wm, int wn, int wave, int lane) {
+    constexpr int BN = 128, BK = 16, TI = 4, TJ = 4;
+    __shared__ __attribute__((aligned(16))) double As[2][128 * BK];
     __shared__ __attribute__((aligned(16))) double Bs[2][BK * BN];
-    __shared__ double red[2][WAVES];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int tm, tn;
-    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
-    const int bm = tm * BM, bn = tn * BN;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    // opaque per call: in the symmetric kernel's loops over tiles and pieces
+    // the addresses derived from them would otherwise be computed once and
+    // held through both loops (and spilled)
+    asm volatile("" : "+v"(lane), "+v"(wave), "+v"(wm), "+v"(wn));
     // the wave's instruction d fills A tile rows 8 (wave + 4 d) .. + 7 (lane
     // l: row 8 (wave + 4 d) + l / 8, chunk (l % 8) ^ (row % 8)) and B tile row
     // wave + 4 d (lane l: columns 2 l, 2 l + 1)
@@ -832,7 +844,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_w4dma(
         (void)k0;
 #endif
     };
-    dbl4 acc[TI][TJ];
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -881,7 +892,77 @@ __global__ __launch_bounds__(256, 2) void k_gemm_w4dma(
         __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next K-tile
         __syncthreads();                // everyone's, and every read of this stage
     }
-    tile_epilogue<double, TI, TJ, WAVES>(acc, ep, M, N, bm, bn, wm, wn, blockIdx.x, red);
+}
+
+__global__ __launch_bounds__(256, 2) void k_gemm_w4dma(
+    int M, int N, int K, const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+    int64_t ldb, EpilogueT<double> ep, int tiles_m, int tiles_n) {
+    if (gate_closed(ep.gate, ep.gate_mode)) return;  // uniform over the launch
+    __shared__ double red[2][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int tm, tn;
+    tile_of(xcd_contiguous(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    const int bm = tm * 128, bn = tn * 128;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    dbl4 acc[4][4];
+    w4dma_mainloop(acc, M, N, K, A, lda, B, ldb, bm, bn, wm, wn, wave, lane);
+    tile_epilogue<double, 4, 4, 4>(acc, ep, M, N, bm, bn, wm, wn, blockIdx.x, red);
+}
+
+// The symmetric product (EpilogueT::sym) on the same tile: the partition of
+// k_gemm_sym (hp_symk.h) over the blocks the device holds at once (two per
+// CU): whole upper-triangle tiles in rounds, then the rest split by K-steps
+// of 16, pieces of a tile combined by streamk_gather.
+__global__ __launch_bounds__(256, 2) void k_gemm_w4dma_sym(
+    int N, int K, const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+    int64_t ldb, EpilogueT<double> ep, int nt, int tiles, int ipt, int ipc, int dp) {
+    if (gate_closed(ep.gate, ep.gate_mode)) return;  // uniform: no counter is touched
+    __shared__ double red[2][4];
+    int tid = threadIdx.x;
+    // as in gemm_tile: values derived from the thread index are recomputed
+    // per piece instead of being held through the loops
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int b = xcd_contiguous(blockIdx.x, gridDim.x);
+    // one loop over the block's whole tiles (b, b + grid, ... below dp) and
+    // then its stream-K pieces, so that the K loop and the epilogue are
+    // compiled once
+    int t_whole = b;
+    const int64_t total = (int64_t)(tiles - dp) * ipt;
+    int64_t it = (int64_t)b * ipc;
+    const int64_t end = min(it + (int64_t)ipc, total);
+    for (;;) {
+        int ipt_p = ipt, ipc_p = ipc, nt_p = nt;
+        asm volatile("" : "+s"(ipt_p), "+s"(ipc_p), "+s"(nt_p));
+        int t, kb, ke, idx = 0, np = 1, slot0 = 0, b0 = 0;
+        if (t_whole < dp) {
+            t = t_whole;
+            kb = 0;
+            ke = K;
+            t_whole += gridDim.x;
+        } else if (it < end) {
+            const SymPiece pc = sym_piece(it, end, ipt_p, ipc_p, b);
+            t = dp + pc.t;
+            kb = pc.k0 * 16;
+            ke = min(K, pc.k1 * 16);
+            idx = pc.idx;
+            np = pc.np;
+            slot0 = pc.slot0;
+            b0 = pc.b0;
+            it += pc.k1 - pc.k0;
+        } else {
+            break;
+        }
+        int tm, tn;
+        sym_tile_of(t, nt_p, tm, tn);
+        dbl4 acc[4][4];
+        w4dma_mainloop(acc, N, N, ke - kb, A + kb, lda, B + (int64_t)kb * ldb, ldb, tm * 128, tn * 128,
+                       wm, wn, wave, lane);
+        if (streamk_gather<double, 4, 4, 256, 128 * 128>(acc, ep, tid, t, idx, np, slot0, b0))
+            tile_epilogue<double, 4, 4, 4, true>(acc, ep, N, N, tm * 128, tn * 128, wm, wn, t, red);
+        __syncthreads();  // the next tile's loads refill the LDS stages
+    }
 }
 
 bool w4dma_fits(int64_t N, int64_t K, int64_t lda, int64_t ldb, const void* A, const void* B) {
@@ -1090,6 +1171,51 @@ bool launch_sym(int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64
     return true;
 }
 
+// The same for k_gemm_w4dma_sym (K-steps of 16, two blocks per CU).
+int sym_grid_w4dma() {
+    static std::atomic<int> g{0};
+    int v = g.load(std::memory_order_relaxed);
+    if (v == 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per, reinterpret_cast<const void*>(&k_gemm_w4dma_sym), 256, 0) != hipSuccess)
+            return 0;
+        v = cus * std::max(per, 1);
+        g.store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+SymShape sym_shape_w4dma(int64_t N, int64_t K) {
+    SymShape sh{};
+    const int g = sym_grid_w4dma();
+    if (g <= 0) return sh;
+    sh.nt = (int)cdiv(N, 128);
+    sh.tiles = sh.nt * (sh.nt + 1) / 2;
+    sh.ipt = (int)cdiv(K, 16);
+    sym_layout(sh.tiles, sh.ipt, g, &sh.ipc, &sh.grid, &sh.dp);
+    return sh;
+}
+
+// Which symmetric launch a call on the load-to-LDS tile takes: 1 for
+// k_gemm_w4dma_sym (operands fit, scratch for its grid, and at least three
+// rounds of whole tiles: 8192^3 8.44 ms against 8.68-8.75 for the 16-wave
+// kernel, but 4096^3, one round, 1.37 against 1.16), 2 for the 16-wave
+// stream-K kernel (otherwise, with scratch for it), 0 for none (the full
+// product).
+template <typename T>
+int w4dma_sym_choice(int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
+                     const EpilogueT<T>& ep) {
+    constexpr int BKF = 16 * sizeof(double) / sizeof(T);
+    if constexpr (std::is_same<T, double>::value) {
+        const SymShape sh = sym_shape_w4dma(N, K);
+        if (w4dma_fits(N, K, lda, ldb, A, B) && sym_fits(sh, ep) && sh.tiles >= 3 * sh.grid) return 1;
+    }
+    return sym_fits(sym_shape<T, 128, 128, 2 * BKF, 32, 32, 2>(N, K), ep) ? 2 : 0;
+}
+
 
 template <typename T>
 hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
@@ -1097,6 +1223,14 @@ hipError_t dispatch(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int
     constexpr int BKF = 16 * sizeof(double) / sizeof(T);  // 128-byte K-tile rows
     if (ep.sym && M == N && !ep.ref) {
         hipError_t e = hipSuccess;
+        if constexpr (std::is_same<T, double>::value) {
+            if (t == TILE_128x128_W4_DMA && K > 0 && w4dma_sym_choice(N, K, A, lda, B, ldb, ep) == 1) {
+                const SymShape sh = sym_shape_w4dma(N, K);
+                hipLaunchKernelGGL(k_gemm_w4dma_sym, dim3(sh.grid), dim3(256), 0, s, (int)N, (int)K, A,
+                                   lda, B, ldb, ep, sh.nt, sh.tiles, sh.ipt, sh.ipc, sh.dp);
+                return hipGetLastError();
+            }
+        }
         if ((t == TILE_128x128_W16_K2_P2 || t == TILE_128x128_W4_DMA) &&
             launch_sym<T, 128, 128, 2 * BKF, 32, 32, 2>(N, K, A, lda, B, ldb, ep, s, &e))
             return e;
@@ -1224,23 +1358,28 @@ hipError_t gemm_lowp(GemmTile t, LowPrec lp, int64_t M, int64_t N, int64_t K, co
 
 
 template <typename T>
-static bool sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<T>& ep) {
+static bool sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
+                         const T* B, int64_t ldb, const EpilogueT<T>& ep) {
     constexpr int BKF = 16 * sizeof(double) / sizeof(T);
     if (!ep.sym || M != N || ep.ref || K <= 0) return false;
-    if (t == TILE_128x128_W16_K2_P2 || t == TILE_128x128_W4_DMA)
+    if (t == TILE_128x128_W4_DMA) return w4dma_sym_choice(N, K, A, lda, B, ldb, ep) != 0;
+    if (t == TILE_128x128_W16_K2_P2)
         return sym_fits(sym_shape<T, 128, 128, 2 * BKF, 32, 32, 2>(N, K), ep);
     if (t == TILE_128x128_W8) return sym_fits(sym_shape<T, 128, 128, BKF, 64, 32, 1>(N, K), ep);
     return false;
 }
-bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<double>& ep) {
-    return sym_launches(t, M, N, K, ep);
+bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                       const double* B, int64_t ldb, const EpilogueT<double>& ep) {
+    return sym_launches(t, M, N, K, A, lda, B, ldb, ep);
 }
-bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<float>& ep) {
-    return sym_launches(t, M, N, K, ep);
+bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, const EpilogueT<float>& ep) {
+    return sym_launches(t, M, N, K, A, lda, B, ldb, ep);
 }
 
 bool gemm_sym_runs(GemmTile t, GemmType gt) {
-    // (the load-to-LDS tile's symmetric products run on the 16-wave kernel)
+    // (the load-to-LDS tile's symmetric products run on k_gemm_w4dma_sym, or
+    // on the 16-wave kernel where its operands or scratch do not fit)
     return ((gt == GT_F64 || gt == GT_F32) && (t == TILE_128x128_W16_K2_P2 || t == TILE_128x128_W8)) ||
            (gt == GT_F64 && t == TILE_128x128_W4_DMA);
 }
@@ -1251,8 +1390,9 @@ void gemm_sym_scratch(GemmTile t, GemmType gt, int64_t n, int64_t* slots, int64_
     // the grid is at most the resident block count, whatever K is
     int g = 0;
     if (gt == GT_F64)
-        g = t == TILE_128x128_W8 ? sym_grid<double, 128, 128, 16, 64, 32, 1>()
-                                 : sym_grid<double, 128, 128, 32, 32, 32, 2>();
+        g = t == TILE_128x128_W8       ? sym_grid<double, 128, 128, 16, 64, 32, 1>()
+            : t == TILE_128x128_W4_DMA ? std::max(sym_grid_w4dma(), sym_grid<double, 128, 128, 32, 32, 32, 2>())
+                                       : sym_grid<double, 128, 128, 32, 32, 32, 2>();
     else
         g = t == TILE_128x128_W8 ? sym_grid<float, 128, 128, 32, 64, 32, 1>()
                                  : sym_grid<float, 128, 128, 64, 32, 32, 2>();

@@ -179,9 +179,12 @@ bool gemm_sym_runs(GemmTile t, GemmType gt);
 void gemm_sym_scratch(GemmTile t, GemmType gt, int64_t n, int64_t* slots, int64_t* counters);
 // Whether gemm() runs this call as the symmetric launch (ep.sym set, M == N,
 // no stopping sums, a tile with that launch and enough scratch); it runs the
-// full product otherwise.
-bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<double>& ep);
-bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const EpilogueT<float>& ep);
+// full product otherwise. The operands decide whether the load-to-LDS tile's
+// symmetric kernel applies.
+bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                       const double* B, int64_t ldb, const EpilogueT<double>& ep);
+bool gemm_sym_launches(GemmTile t, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, const EpilogueT<float>& ep);
 
 // Zero n unsigned counters (a fill kernel: safe inside stream capture).
 hipError_t zero_u32(unsigned* p, int64_t n, hipStream_t s);

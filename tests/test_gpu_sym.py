@@ -229,11 +229,45 @@ def test_symmetric_products_with_gpu_alpha():
     assert es <= 1e-10 and es <= 2.0 * ef + 1e-11
 
 
+@pytest.mark.parametrize("N,K", [
+    (7000, 512),    # 55 x 55 tiles (1540 >= 3 rounds of 512 blocks): k_gemm_w4dma_sym,
+                    # 2 rounds of whole tiles, the ragged rest split by K-steps
+    (300, 208),     # 6 triangle tiles, under 3 rounds: the 16-wave stream-K launch
+    (2100, 1024),   # 153 triangle tiles: likewise
+    (512, 100),     # K not a multiple of 16: likewise
+])
+def test_sym_product_on_the_load_to_lds_tile(N, K, tmp_path):
+    """Symmetric products with the 4-wave load-to-LDS tile chosen (tile 19,
+    forced through the tuning table): its stream-K form where the triangle
+    fills three rounds of the device's blocks, the 16-wave stream-K kernel
+    otherwise. Exactly symmetric, within the product's bound of the host
+    product, to rounding the full product; two calls in a row give the same
+    bits."""
+    import json
+    hpw = need_gpu()
+    say(f"gemm_sym load-to-LDS tile N={N} K={K}")
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"rows": [[0, N, N, K, 19]]}))
+    hpw.load_tuning(str(path))
+    g, G, Gt = gram(N, K, 7000 + N, torch.float64)
+    C = hpw.gemm_sym(G, Gt, alpha=0.5, beta_identity=2.0)
+    C2 = hpw.gemm_sym(G, Gt, alpha=0.5, beta_identity=2.0)
+    F = hpw.gemm(G, Gt, alpha=0.5, beta_identity=2.0)
+    torch.cuda.synchronize()
+    assert torch.equal(C, C2)
+    c, f = C.cpu().numpy(), F.cpu().numpy()
+    assert np.array_equal(c, c.T)
+    ref = 0.5 * (g @ g.T) + 2.0 * np.eye(N)
+    tol = 1e-14 * np.sqrt(K) * np.abs(ref).max()
+    assert np.abs(c - ref).max() <= tol
+    assert np.abs(np.triu(c) - np.triu(f)).max() <= tol
+
+
 def test_solve_symmetric_beside_the_load_to_lds_tile():
     """3072^2 (576 tiles per product: full products on the load-to-LDS tile,
-    symmetric ones on the 16-wave stream-K kernel) with HP_FLAG_SYMMETRIC
-    against the same solve with full products: same loops, both at the
-    closed-form inverse to 1e-10."""
+    symmetric ones on its stream-K form) with HP_FLAG_SYMMETRIC against the
+    same solve with full products: same loops, both at the closed-form
+    inverse to 1e-10."""
     hpw = need_gpu()
     say("solve sym vs full 3072^2 load-to-LDS tile")
     d = inputs.lowrank_svd(3072, 3072, 3072, smin=1e-3, seed=3072)
