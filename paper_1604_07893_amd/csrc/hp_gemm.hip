@@ -1388,16 +1388,22 @@ void gemm_sym_scratch(GemmTile t, GemmType gt, int64_t n, int64_t* slots, int64_
     *slots = *counters = 0;
     if (!gemm_sym_runs(t, gt) || n <= 0) return;
     // the grid is at most the resident block count, whatever K is
+    const int64_t nt = cdiv(n, 128);
     int g = 0;
-    if (gt == GT_F64)
-        g = t == TILE_128x128_W8       ? sym_grid<double, 128, 128, 16, 64, 32, 1>()
-            : t == TILE_128x128_W4_DMA ? std::max(sym_grid_w4dma(), sym_grid<double, 128, 128, 32, 32, 32, 2>())
-                                       : sym_grid<double, 128, 128, 32, 32, 32, 2>();
-    else
+    if (gt == GT_F64) {
+        g = t == TILE_128x128_W8 ? sym_grid<double, 128, 128, 16, 64, 32, 1>()
+                                 : sym_grid<double, 128, 128, 32, 32, 32, 2>();
+        // the load-to-LDS tile's own symmetric kernel (a larger grid) runs
+        // only on a triangle of at least three rounds (w4dma_sym_choice)
+        if (t == TILE_128x128_W4_DMA) {
+            const int gd = sym_grid_w4dma();
+            if (nt * (nt + 1) / 2 >= 3 * (int64_t)gd) g = std::max(g, gd);
+        }
+    } else {
         g = t == TILE_128x128_W8 ? sym_grid<float, 128, 128, 32, 64, 32, 1>()
                                  : sym_grid<float, 128, 128, 64, 32, 32, 2>();
+    }
     if (g <= 0) return;
-    const int64_t nt = cdiv(n, 128);
     *slots = 2 * (int64_t)g;
     *counters = nt * (nt + 1) / 2;
 }
